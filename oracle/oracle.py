@@ -1,0 +1,195 @@
+"""Python front-end of the serial FP64 CPU oracle (swe_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline call this module; the GPU library never does.  It takes problems
+from the shared seeded input generators (plain numpy arrays) and shares no
+arithmetic with the GPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "swe_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+FLAG_NAN, FLAG_CLIPPED, FLAG_BADDT = 1, 2, 4
+NTRACE, NSCALAR = 47, 16
+#: names of the traced arrays, in order, with the sub-step that writes them
+TRACE_NAMES = (
+    ["S1.eta", "S1.qx", "S1.qy", "S2.h", "S2.r", "S2.u", "S2.v", "S3.nux", "S3.nuy",
+     "S4.Deta", "S4.Dqx", "S4.Dqy", "S5.Fm", "S5.Fx", "S5.Fy", "S5.Px",
+     "S6.Gm", "S6.Gx", "S6.Gy", "S6.Py", "S7.eta", "S7.qx", "S7.qy",
+     "S9.h", "S9.r", "S9.u", "S9.v", "S10.Fm", "S10.Fx", "S10.Fy", "S10.Px",
+     "S11.Gm", "S11.Gx", "S11.Gy", "S11.Py", "S12.eta", "S12.qx", "S12.qy",
+     "S13.eta", "S13.qx", "S13.qy", "S14.eta", "S14.qx", "S14.qy",
+     "S15.eta", "S15.qx", "S15.qy"])
+SCALAR_NAMES = ["qin_n", "qin_n1", "rx", "ry", "defect_depth", "lam_max", "dt_next",
+                "volume", "flags", "sigma", "t_next"]
+
+
+def build(force: bool = False) -> str:
+    """Compile swe_oracle.c with gcc (no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("bc", ctypes.c_int32 * 4), ("in_lo", ctypes.c_int32 * 4),
+                ("in_hi", ctypes.c_int32 * 4), ("hydro_len", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)] + [
+                (f, ctypes.c_double) for f in
+                ("dx", "dy", "g", "cfl", "h_dry", "kappa", "eps_max", "dt_max", "dt_fixed")] + [
+                ("hydro_t", ctypes.POINTER(ctypes.c_double)),
+                ("hydro_q", ctypes.POINTER(ctypes.c_double))]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("bad_step", ctypes.c_int64),
+                ("flags", ctypes.c_uint32), ("pad_", ctypes.c_uint32)] + [
+                (f, ctypes.c_double) for f in
+                ("t", "dt", "dt_min", "dt_max", "volume", "defect", "lambda_max")]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc_run.argtypes = [ctypes.POINTER(_Cfg), dp, dp, dp, dp, dp, dp,
+                              ctypes.POINTER(ctypes.c_int64), dp, ctypes.c_int64, ctypes.c_double,
+                              ctypes.POINTER(_Stats)]
+        L.orc_run.restype = ctypes.c_int
+        L.orc_trace.argtypes = [ctypes.POINTER(_Cfg), dp, dp, dp, dp, dp, ctypes.c_double,
+                                ctypes.c_int64, ctypes.c_double, dp, dp]
+        L.orc_trace.restype = ctypes.c_int
+        L.orc_initial_dt.argtypes = [ctypes.POINTER(_Cfg), dp, dp, dp, dp, dp, dp]
+        L.orc_initial_dt.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _cfg(p, keep):
+    c = _Cfg()
+    c.nx, c.ny = p.nx, p.ny
+    for k in range(4):
+        c.bc[k] = int(p.bc[k])
+        c.in_lo[k] = int(p.inflow_lo[k])
+        c.in_hi[k] = int(p.inflow_hi[k])
+    ht = np.ascontiguousarray(p.hydro_t, dtype=np.float64)
+    hq = np.ascontiguousarray(p.hydro_q, dtype=np.float64)
+    keep += [ht, hq]
+    c.hydro_len = len(ht)
+    c.hydro_t = _ptr(ht) if len(ht) else None
+    c.hydro_q = _ptr(hq) if len(hq) else None
+    for f in ("dx", "dy", "g", "cfl", "h_dry", "kappa", "eps_max", "dt_max", "dt_fixed"):
+        setattr(c, f, float(getattr(p, f)))
+    return c
+
+
+@dataclasses.dataclass
+class Stats:
+    steps: int
+    bad_step: int
+    flags: int
+    t: float
+    dt: float
+    dt_min: float
+    dt_max: float
+    volume: float
+    defect: float
+    lambda_max: float
+    step: int = 0
+
+
+class State:
+    """Oracle state of one problem: (eta, qx, qy), t^n, n and dt^n."""
+
+    def __init__(self, problem, t0: float = 0.0, step0: int = 0):
+        self.p = problem
+        self.eta, self.qx, self.qy = problem.state()
+        self.t = float(t0)
+        self.step = int(step0)
+        self.dt = initial_dt(problem, self.eta, self.qx, self.qy)
+
+    def run(self, nsteps: int, t_end: float = math.inf) -> Stats:
+        keep = []
+        c = _cfg(self.p, keep)
+        t = ctypes.c_double(self.t)
+        n = ctypes.c_int64(self.step)
+        dt = ctypes.c_double(self.dt)
+        st = _Stats()
+        rc = lib().orc_run(ctypes.byref(c), _ptr(self.eta), _ptr(self.qx), _ptr(self.qy),
+                           _ptr(self.p.z), _ptr(self.p.n), ctypes.byref(t), ctypes.byref(n),
+                           ctypes.byref(dt), int(nsteps), float(t_end), ctypes.byref(st))
+        if rc < 0:
+            raise ValueError("oracle rejected its arguments")
+        self.t, self.step, self.dt = t.value, n.value, dt.value
+        return Stats(st.steps, st.bad_step, st.flags, st.t, st.dt, st.dt_min, st.dt_max,
+                     st.volume, st.defect, st.lambda_max, self.step)
+
+    def trace(self):
+        """One step with every intermediate: (dict name -> (ny+2, nx+2) array,
+        dict name -> scalar).  Advances the state."""
+        keep = []
+        c = _cfg(self.p, keep)
+        P, Q = self.p.nx + 2, self.p.ny + 2
+        arrays = np.zeros((NTRACE, Q, P))
+        scal = np.zeros(NSCALAR)
+        rc = lib().orc_trace(ctypes.byref(c), _ptr(self.eta), _ptr(self.qx), _ptr(self.qy),
+                             _ptr(self.p.z), _ptr(self.p.n), self.t, self.step, self.dt,
+                             _ptr(arrays), _ptr(scal))
+        if rc < 0:
+            raise ValueError("oracle rejected its arguments")
+        self.t = scal[10]
+        self.dt = scal[6]
+        self.step += 1
+        return ({nm: arrays[k] for k, nm in enumerate(TRACE_NAMES)},
+                {nm: scal[k] for k, nm in enumerate(SCALAR_NAMES)})
+
+
+def initial_dt(problem, eta=None, qx=None, qy=None):
+    keep = []
+    c = _cfg(problem, keep)
+    eta = problem.eta if eta is None else eta
+    qx = problem.qx if qx is None else qx
+    qy = problem.qy if qy is None else qy
+    return lib().orc_initial_dt(ctypes.byref(c), _ptr(eta), _ptr(qx), _ptr(qy), _ptr(problem.z),
+                                None, None)
+
+
+def volume_and_lambda(problem, eta, qx, qy):
+    keep = []
+    c = _cfg(problem, keep)
+    lam = ctypes.c_double()
+    vol = ctypes.c_double()
+    lib().orc_initial_dt(ctypes.byref(c), _ptr(eta), _ptr(qx), _ptr(qy), _ptr(problem.z),
+                         ctypes.byref(lam), ctypes.byref(vol))
+    return vol.value, lam.value
+
+
+def run(problem, nsteps: int, t_end: float = math.inf):
+    """Convenience: fresh state, nsteps steps; returns (State, Stats)."""
+    s = State(problem)
+    st = s.run(nsteps, t_end)
+    return s, st

@@ -1,0 +1,694 @@
+/*
+ * swe_oracle.c -- serial FP64 reference of one explicit 2D predictor-corrector
+ * MacCormack time step of the shallow-water mass and momentum equations.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct checker
+ * for the GPU library.  Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it.  It shares no source with the GPU path:
+ * no headers, no helpers, no constant tables.
+ *
+ * What the paper fixes (Seitz et al., "A GPU Implementation for
+ * Two-Dimensional Shallow Water Modeling", 2013):
+ *   - the method: a 2D predictor-corrector MacCormack scheme solving for the
+ *     water elevation and the two velocity components every time step (§1);
+ *   - explicitness: a step depends only on the previous step's values (§1);
+ *   - the step is split into 16 dependent sub-steps, each needing neighbour
+ *     values produced by the sub-step before it, while inside a sub-step every
+ *     cell is independent, so any cell order gives the same result (§1, §6.1);
+ *   - a variable time step computed after each step from the new data (§3.1);
+ *   - the scheme cannot handle dry cells (§6.2).
+ * The paper defers the equations themselves to Ransom's thesis, which is not
+ * available, so the discrete scheme below is our reading of the standard
+ * MacCormack form for open-channel flow.  Every expression is written with its
+ * evaluation order fixed so that an independent implementation doing the same
+ * correctly rounded operations (+ - * / sqrt) reproduces it bit for bit; the
+ * only libm call besides sqrt is one cbrt per wet cell in the friction step.
+ *
+ * PDEs (conservative, surface-gradient pressure form), unknowns eta (water
+ * surface elevation) and q = (qx, qy) (unit discharges), h = eta - z:
+ *   d(eta)/dt + d(qx)/dx + d(qy)/dy = 0
+ *   d(qx)/dt + d(qx u)/dx + d(qy u)/dy + g h d(eta)/dx = -m qx |u| h^(-4/3)
+ *   d(qy)/dt + d(qx v)/dx + d(qy v)/dy + g h d(eta)/dy = -m qy |u| h^(-4/3)
+ *   u = qx/h, v = qy/h, m = g n^2 (n: Manning coefficient field).
+ *
+ * One step (U^n = (eta, qx, qy), t^n, dt = dt^n, sigma = +1 for even n and -1
+ * for odd n) is the sixteen sweeps S1..S16 below, in order.  Arrays are
+ * cell-centred, row-major with x fastest, padded with a one-cell ghost ring
+ * (index i in [-1, nx], j in [-1, ny]); the four ghost corners are never read.
+ *   S1  BC(U^n, t^n): ghost ring of U^n.  eta_g = eta of the adjacent cell for
+ *       every kind.  WALL: normal discharge mirrored, tangential copied.  OPEN:
+ *       both copied.  INFLOW: normal discharge = q_in(t) pointing into the
+ *       domain, tangential 0.  An INFLOW edge acts as WALL outside its face
+ *       band [lo, hi).  z of a ghost = z of the adjacent cell.
+ *   S2  PRIM(U^n): h = eta - z; wet <=> h > h_dry; r = wet ? 1/h : 0;
+ *       u = qx*r; v = qy*r.  Over every padded cell.
+ *   S3  SWITCH: nu_x = 0.25*(|(eta_E - eta_C) - (eta_C - eta_W)| * r_C), nu_y
+ *       likewise with N/S.  Interior cells.
+ *   S4  DISS: face coefficient eps = (wet_L && wet_R) ?
+ *       min(kappa*max(nu_L, nu_R), eps_max) : 0 on interior faces, 0 on
+ *       boundary faces; for each of eta, qx, qy:
+ *       D = (eps_E*(U_E - U_C) - eps_W*(U_C - U_W))
+ *         + (eps_N*(U_N - U_C) - eps_S*(U_C - U_S)).
+ *   S5  XFLUX(U^n, sigma), every x-face between cells L = i and R = i+1:
+ *       WALL face: all four terms 0.  Otherwise donor d = sigma > 0 ? R : L
+ *       (INFLOW face: d = the ghost cell); fm = wet_d ? qx_d : 0 (INFLOW face:
+ *       fm = qx_d unconditionally); Fm = fm, Fx = fm*u_d, Fy = fm*v_d.
+ *       Pressure Px = (g*(0.5*(h+_L + h+_R)))*(eta_R - eta_L) on interior
+ *       faces (h+ = max(h, 0)), 0 on boundary faces and on dry-bank faces
+ *       (one side not wet and its z above the other side's eta).
+ *   S6  YFLUX(U^n, sigma): S5 with x and y exchanged (Gm = fm from qy,
+ *       Gx = fm*u_d, Gy = fm*v_d, Py from eta_N - eta_S).
+ *   S7  PRED: rx = dt/dx, ry = dt/dy, P_x = sigma > 0 ? Px_E : Px_W (same in y)
+ *       eta* = (eta - rx*(Fm_E - Fm_W)) - ry*(Gm_N - Gm_S)
+ *       qx*  = (qx - rx*((Fx_E - Fx_W) + P_x)) - ry*(Gx_N - Gx_S)
+ *       qy*  = (qy - rx*(Fy_E - Fy_W)) - ry*((Gy_N - Gy_S) + P_y)
+ *   S8  BC(U*, t^n + dt): S1 applied to U*.
+ *   S9  PRIM(U*).
+ *   S10 XFLUX(U*, -sigma).   S11 YFLUX(U*, -sigma).
+ *   S12 CORR: with the S10/S11 faces and -sigma for the pressure side, the S7
+ *       expressions applied to U* give a; U^c = 0.5*(U^n + a).
+ *   S13 ADD-DISS: U^d = U^c + D.
+ *   S14 FRIC (point-implicit Manning), wet cells of U^d only:
+ *       r = 1/h; s = sqrt(qx*qx + qy*qy)*r; k = r*cbrt(r) (= h^(-4/3));
+ *       phi = 1 + ((dt*m)*s)*k; psi = 1/phi; qx = qx*psi; qy = qy*psi.
+ *   S15 DRY-FIX: h = eta - z; if h < 0: defect += (0 - h), eta = z.  Then if
+ *       eta - z is not > h_dry: qx = qy = 0.  A non-finite value raises the
+ *       NaN flag.
+ *   S16 CFL: over wet cells of U^{n+1}: r = 1/h, u = qx*r, v = qy*r,
+ *       c = sqrt(g*h), lam = (|u| + c)*(1/dx) + (|v| + c)*(1/dy); lam_max is
+ *       the maximum.  dt^{n+1} = dt_fixed if dt_fixed > 0, else
+ *       min(cfl/lam_max, dt_max) if lam_max > 0, else dt_max.
+ *       t^{n+1} = t^n + dt^n.  dt^0 is S16 applied to U^0.
+ * q_in(t) is the piecewise-linear hydrograph (t_k, q_k), held constant before
+ * its first and after its last point:
+ *   q_in = q_k + ((t - t_k)/(t_{k+1} - t_k))*(q_{k+1} - q_k).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { BC_WALL = 0, BC_OPEN = 1, BC_INFLOW = 2, FACE_INTERIOR = 3 };
+enum { EDGE_W = 0, EDGE_E = 1, EDGE_S = 2, EDGE_N = 3 };
+enum { ORC_FLAG_NAN = 1u, ORC_FLAG_CLIPPED = 2u, ORC_FLAG_BADDT = 4u };
+
+/* Number of padded arrays one traced step exposes, and scalar slots. */
+#define ORC_NTRACE 47
+#define ORC_NSCALAR 16
+
+typedef struct orc_cfg {
+    int32_t nx, ny;
+    int32_t bc[4];      /* W, E, S, N: BC_WALL, BC_OPEN or BC_INFLOW */
+    int32_t in_lo[4];   /* INFLOW face band [lo, hi) along each edge */
+    int32_t in_hi[4];
+    int32_t hydro_len;  /* number of hydrograph points (0: q_in = 0) */
+    int32_t pad_;
+    double dx, dy, g, cfl, h_dry, kappa, eps_max, dt_max, dt_fixed;
+    const double *hydro_t, *hydro_q;
+} orc_cfg;
+
+typedef struct orc_stats {
+    int64_t steps;      /* steps taken by the call */
+    int64_t bad_step;   /* global index of the step that raised a flag, -1 none */
+    uint32_t flags;
+    uint32_t pad_;
+    double t, dt;       /* time and next time step after the call */
+    double dt_min, dt_max;  /* extremes of the time steps used */
+    double volume;      /* sum of h dx dy over the final state */
+    double defect;      /* clipped volume added during the call */
+    double lambda_max;  /* lam_max of the final state */
+} orc_stats;
+
+/* ---------------------------------------------------------------- helpers */
+
+typedef struct {
+    int nx, ny, P;      /* P = nx + 2: padded row length */
+} Grid;
+
+static inline size_t at(const Grid* G, int i, int j) {
+    return (size_t)(j + 1) * (size_t)G->P + (size_t)(i + 1);
+}
+
+static int face_kind(const orc_cfg* c, int edge, int k) {
+    int kind = c->bc[edge];
+    if (kind == BC_INFLOW && !(k >= c->in_lo[edge] && k < c->in_hi[edge])) return BC_WALL;
+    return kind;
+}
+
+static double q_inflow(const orc_cfg* c, double t) {
+    int L = c->hydro_len;
+    if (L <= 0) return 0.0;
+    if (t <= c->hydro_t[0]) return c->hydro_q[0];
+    if (t >= c->hydro_t[L - 1]) return c->hydro_q[L - 1];
+    int k = 0;
+    while (k + 1 < L && !(t < c->hydro_t[k + 1])) ++k;
+    double w = (t - c->hydro_t[k]) / (c->hydro_t[k + 1] - c->hydro_t[k]);
+    return c->hydro_q[k] + w * (c->hydro_q[k + 1] - c->hydro_q[k]);
+}
+
+static inline double pos(double h) { return h > 0.0 ? h : 0.0; }
+static inline double dmax(double a, double b) { return a > b ? a : b; }
+static inline double dmin(double a, double b) { return a < b ? a : b; }
+
+/* Work arrays of one step, in trace order; each is a padded (ny+2) x (nx+2)
+ * array.  Face arrays store the face between cells i and i+1 (x) or j and j+1
+ * (y) in the slot of cell i (resp. j), so faces -1/2 sit in the ghost slot. */
+typedef struct {
+    double *Un[3];          /* S1   */
+    double *h, *r, *u, *v;  /* S2   */
+    double *nux, *nuy;      /* S3   */
+    double *D[3];           /* S4   */
+    double *F[4];           /* S5: Fm, Fx, Fy, Px */
+    double *G[4];           /* S6: Gm, Gx, Gy, Py */
+    double *Us[3];          /* S7 interior + S8 ghosts */
+    double *hs, *rs, *us, *vs;  /* S9 */
+    double *Fs[4];          /* S10  */
+    double *Gs[4];          /* S11  */
+    double *Uc[3];          /* S12  */
+    double *Ud[3];          /* S13  */
+    double *Uf[3];          /* S14  */
+    double *Unew[3];        /* S15  */
+    double *zp, *mp;        /* padded bed and m = g n^2 */
+    const double* z;        /* unpadded bed, pitch nx */
+    double *block;
+    int owns;
+} Work;
+
+static int work_init(Work* w, const Grid* G, double* external) {
+    size_t N = (size_t)G->P * (size_t)(G->ny + 2);
+    double* b = external;
+    w->owns = 0;
+    if (!b) {
+        b = (double*)calloc((size_t)(ORC_NTRACE + 2) * N, sizeof(double));
+        if (!b) return -1;
+        w->owns = 1;
+    } else {
+        memset(b, 0, (size_t)ORC_NTRACE * N * sizeof(double));
+    }
+    w->block = b;
+    double* p[ORC_NTRACE];
+    for (int k = 0; k < ORC_NTRACE; ++k) p[k] = b + (size_t)k * N;
+    int k = 0;
+    for (int a = 0; a < 3; ++a) w->Un[a] = p[k++];
+    w->h = p[k++]; w->r = p[k++]; w->u = p[k++]; w->v = p[k++];
+    w->nux = p[k++]; w->nuy = p[k++];
+    for (int a = 0; a < 3; ++a) w->D[a] = p[k++];
+    for (int a = 0; a < 4; ++a) w->F[a] = p[k++];
+    for (int a = 0; a < 4; ++a) w->G[a] = p[k++];
+    for (int a = 0; a < 3; ++a) w->Us[a] = p[k++];
+    w->hs = p[k++]; w->rs = p[k++]; w->us = p[k++]; w->vs = p[k++];
+    for (int a = 0; a < 4; ++a) w->Fs[a] = p[k++];
+    for (int a = 0; a < 4; ++a) w->Gs[a] = p[k++];
+    for (int a = 0; a < 3; ++a) w->Uc[a] = p[k++];
+    for (int a = 0; a < 3; ++a) w->Ud[a] = p[k++];
+    for (int a = 0; a < 3; ++a) w->Uf[a] = p[k++];
+    for (int a = 0; a < 3; ++a) w->Unew[a] = p[k++];
+    return 0;
+}
+
+static void work_free(Work* w) {
+    if (w->owns) free(w->block);
+    w->block = NULL;
+}
+
+/* Padded copies of the static fields: z and m = g n^2, ghosts = adjacent. */
+static void static_fields(const orc_cfg* c, const Grid* G, const double* z,
+                          const double* nman, double* zp, double* mp) {
+    int nx = G->nx, ny = G->ny;
+    for (int j = -1; j <= ny; ++j)
+        for (int i = -1; i <= nx; ++i) {
+            int ii = i < 0 ? 0 : (i >= nx ? nx - 1 : i);
+            int jj = j < 0 ? 0 : (j >= ny ? ny - 1 : j);
+            int corner = (i < 0 || i >= nx) && (j < 0 || j >= ny);
+            size_t s = (size_t)jj * (size_t)nx + (size_t)ii;
+            double nn = nman[s];
+            zp[at(G, i, j)] = corner ? 0.0 : z[s];
+            mp[at(G, i, j)] = corner ? 0.0 : c->g * (nn * nn);
+        }
+}
+
+/* ------------------------------------------------------------- sub-steps */
+
+/* S1 / S8: ghost ring of (eta, qx, qy) for the boundary kinds at time t. */
+static void fill_ghosts(const orc_cfg* c, const Grid* G, double qin, double* eta,
+                        double* qx, double* qy) {
+    int nx = G->nx, ny = G->ny;
+    for (int j = 0; j < ny; ++j) {
+        for (int side = 0; side < 2; ++side) {
+            int edge = side == 0 ? EDGE_W : EDGE_E;
+            size_t g = side == 0 ? at(G, -1, j) : at(G, nx, j);
+            size_t a = side == 0 ? at(G, 0, j) : at(G, nx - 1, j);
+            int kind = face_kind(c, edge, j);
+            eta[g] = eta[a];
+            if (kind == BC_OPEN) {
+                qx[g] = qx[a];
+                qy[g] = qy[a];
+            } else if (kind == BC_INFLOW) {
+                qx[g] = side == 0 ? qin : -qin;
+                qy[g] = 0.0;
+            } else {
+                qx[g] = -qx[a];
+                qy[g] = qy[a];
+            }
+        }
+    }
+    for (int i = 0; i < nx; ++i) {
+        for (int side = 0; side < 2; ++side) {
+            int edge = side == 0 ? EDGE_S : EDGE_N;
+            size_t g = side == 0 ? at(G, i, -1) : at(G, i, ny);
+            size_t a = side == 0 ? at(G, i, 0) : at(G, i, ny - 1);
+            int kind = face_kind(c, edge, i);
+            eta[g] = eta[a];
+            if (kind == BC_OPEN) {
+                qx[g] = qx[a];
+                qy[g] = qy[a];
+            } else if (kind == BC_INFLOW) {
+                qy[g] = side == 0 ? qin : -qin;
+                qx[g] = 0.0;
+            } else {
+                qy[g] = -qy[a];
+                qx[g] = qx[a];
+            }
+        }
+    }
+}
+
+/* S2 / S9: primitive variables over every padded cell. */
+static void prim(const orc_cfg* c, const Grid* G, double* const U[3], const double* zp,
+                 double* h, double* r, double* u, double* v) {
+    size_t N = (size_t)G->P * (size_t)(G->ny + 2);
+    for (size_t s = 0; s < N; ++s) {
+        double hh = U[0][s] - zp[s];
+        double rr = hh > c->h_dry ? 1.0 / hh : 0.0;
+        h[s] = hh;
+        r[s] = rr;
+        u[s] = U[1][s] * rr;
+        v[s] = U[2][s] * rr;
+    }
+}
+
+/* S3: dissipation switch from the curvature of the water surface. */
+static void switch_nu(const Grid* G, const double* eta, const double* r, double* nux,
+                      double* nuy) {
+    for (int j = 0; j < G->ny; ++j)
+        for (int i = 0; i < G->nx; ++i) {
+            size_t C = at(G, i, j);
+            double ax = eta[at(G, i + 1, j)] - eta[C];
+            double bx = eta[C] - eta[at(G, i - 1, j)];
+            double ay = eta[at(G, i, j + 1)] - eta[C];
+            double by = eta[C] - eta[at(G, i, j - 1)];
+            nux[C] = 0.25 * (fabs(ax - bx) * r[C]);
+            nuy[C] = 0.25 * (fabs(ay - by) * r[C]);
+        }
+}
+
+/* Face coefficient of S4 between cells a and b (interior faces only). */
+static double eps_face(const orc_cfg* c, const double* h, const double* nu, size_t a,
+                       size_t b) {
+    if (!(h[a] > c->h_dry && h[b] > c->h_dry)) return 0.0;
+    return dmin(c->kappa * dmax(nu[a], nu[b]), c->eps_max);
+}
+
+/* S4: switched second-difference dissipation of U^n. */
+static void dissipation(const orc_cfg* c, const Grid* G, double* const U[3],
+                        const double* h, const double* nux, const double* nuy,
+                        double* D[3]) {
+    int nx = G->nx, ny = G->ny;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            size_t C = at(G, i, j), E = at(G, i + 1, j), W = at(G, i - 1, j);
+            size_t N = at(G, i, j + 1), S = at(G, i, j - 1);
+            double eE = i + 1 < nx ? eps_face(c, h, nux, C, E) : 0.0;
+            double eW = i > 0 ? eps_face(c, h, nux, W, C) : 0.0;
+            double eN = j + 1 < ny ? eps_face(c, h, nuy, C, N) : 0.0;
+            double eS = j > 0 ? eps_face(c, h, nuy, S, C) : 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double* q = U[a];
+                double dxq = eE * (q[E] - q[C]) - eW * (q[C] - q[W]);
+                double dyq = eN * (q[N] - q[C]) - eS * (q[C] - q[S]);
+                D[a][C] = dxq + dyq;
+            }
+        }
+}
+
+/* One face of S5/S6/S10/S11.  L and R are the cells on the low and high side
+ * of the face, gL/gR say which of them is a ghost, kind is the face kind,
+ * qn is the discharge normal to the face, and the outputs are (mass, x-momentum,
+ * y-momentum, pressure). */
+static void face_flux(const orc_cfg* c, int sigma, int kind, size_t L, size_t R, int ghost_is_R,
+                      const double* eta, const double* qn, const double* h, const double* u,
+                      const double* v, const double* zp, double out[4]) {
+    if (kind == BC_WALL) {
+        out[0] = out[1] = out[2] = out[3] = 0.0;
+        return;
+    }
+    size_t d;
+    double fm;
+    if (kind == BC_INFLOW) {
+        d = ghost_is_R ? R : L;
+        fm = qn[d];
+    } else {
+        d = sigma > 0 ? R : L;
+        fm = h[d] > c->h_dry ? qn[d] : 0.0;
+    }
+    out[0] = fm;
+    out[1] = fm * u[d];
+    out[2] = fm * v[d];
+    if (kind != FACE_INTERIOR) {
+        out[3] = 0.0;
+        return;
+    }
+    int wetL = h[L] > c->h_dry, wetR = h[R] > c->h_dry;
+    int bank = (!wetL && zp[L] > eta[R]) || (!wetR && zp[R] > eta[L]);
+    out[3] = bank ? 0.0 : (c->g * (0.5 * (pos(h[L]) + pos(h[R])))) * (eta[R] - eta[L]);
+}
+
+/* S5 / S10: fluxes through every x-face (i = -1 .. nx-1). */
+static void xflux(const orc_cfg* c, const Grid* G, int sigma, double* const U[3],
+                  const double* h, const double* u, const double* v, const double* zp,
+                  double* F[4]) {
+    int nx = G->nx, ny = G->ny;
+    for (int j = 0; j < ny; ++j)
+        for (int i = -1; i < nx; ++i) {
+            int kind = i == -1 ? face_kind(c, EDGE_W, j)
+                               : (i == nx - 1 ? face_kind(c, EDGE_E, j) : FACE_INTERIOR);
+            double o[4];
+            face_flux(c, sigma, kind, at(G, i, j), at(G, i + 1, j), i == nx - 1, U[0], U[1], h,
+                      u, v, zp, o);
+            size_t s = at(G, i, j);
+            for (int a = 0; a < 4; ++a) F[a][s] = o[a];
+        }
+}
+
+/* S6 / S11: fluxes through every y-face (j = -1 .. ny-1). */
+static void yflux(const orc_cfg* c, const Grid* G, int sigma, double* const U[3],
+                  const double* h, const double* u, const double* v, const double* zp,
+                  double* Gf[4]) {
+    int nx = G->nx, ny = G->ny;
+    for (int j = -1; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            int kind = j == -1 ? face_kind(c, EDGE_S, i)
+                               : (j == ny - 1 ? face_kind(c, EDGE_N, i) : FACE_INTERIOR);
+            double o[4];
+            face_flux(c, sigma, kind, at(G, i, j), at(G, i, j + 1), j == ny - 1, U[0], U[2], h,
+                      u, v, zp, o);
+            size_t s = at(G, i, j);
+            for (int a = 0; a < 4; ++a) Gf[a][s] = o[a];
+        }
+}
+
+/* S7 (base = U^n, out = U*) and the inner part of S12 (base = U*): the flux
+ * divergence update base - L_sigma with the pressure on the sigma-side face. */
+static void flux_update(const Grid* G, int sigma, double rx, double ry, double* const base[3],
+                        double* const F[4], double* const Gf[4], double* out[3]) {
+    for (int j = 0; j < G->ny; ++j)
+        for (int i = 0; i < G->nx; ++i) {
+            size_t C = at(G, i, j), W = at(G, i - 1, j), S = at(G, i, j - 1);
+            double px = sigma > 0 ? F[3][C] : F[3][W];
+            double py = sigma > 0 ? Gf[3][C] : Gf[3][S];
+            out[0][C] = (base[0][C] - rx * (F[0][C] - F[0][W])) - ry * (Gf[0][C] - Gf[0][S]);
+            out[1][C] = (base[1][C] - rx * ((F[1][C] - F[1][W]) + px)) - ry * (Gf[1][C] - Gf[1][S]);
+            out[2][C] = (base[2][C] - rx * (F[2][C] - F[2][W])) - ry * ((Gf[2][C] - Gf[2][S]) + py);
+        }
+}
+
+/* S12: U^c = 0.5*(U^n + (U* - L_{-sigma}(U*))). */
+static void corrector(const Grid* G, int sigma, double rx, double ry, double* const Un[3],
+                      double* const Us[3], double* const Fs[4], double* const Gs[4],
+                      double* Uc[3]) {
+    flux_update(G, -sigma, rx, ry, Us, Fs, Gs, Uc);
+    for (int j = 0; j < G->ny; ++j)
+        for (int i = 0; i < G->nx; ++i) {
+            size_t C = at(G, i, j);
+            for (int a = 0; a < 3; ++a) Uc[a][C] = 0.5 * (Un[a][C] + Uc[a][C]);
+        }
+}
+
+/* S13 */
+static void add_diss(const Grid* G, double* const Uc[3], double* const D[3], double* Ud[3]) {
+    for (int j = 0; j < G->ny; ++j)
+        for (int i = 0; i < G->nx; ++i) {
+            size_t C = at(G, i, j);
+            for (int a = 0; a < 3; ++a) Ud[a][C] = Uc[a][C] + D[a][C];
+        }
+}
+
+/* S14: point-implicit Manning friction on wet cells. */
+static void friction(const orc_cfg* c, const Grid* G, double dt, double* const Ud[3],
+                     const double* zp, const double* mp, double* Uf[3]) {
+    for (int j = 0; j < G->ny; ++j)
+        for (int i = 0; i < G->nx; ++i) {
+            size_t C = at(G, i, j);
+            double eta = Ud[0][C], qx = Ud[1][C], qy = Ud[2][C];
+            double h = eta - zp[C];
+            if (h > c->h_dry) {
+                double r = 1.0 / h;
+                double s = sqrt(qx * qx + qy * qy) * r;
+                double k = r * cbrt(r);
+                double phi = 1.0 + ((dt * mp[C]) * s) * k;
+                double psi = 1.0 / phi;
+                qx = qx * psi;
+                qy = qy * psi;
+            }
+            Uf[0][C] = eta;
+            Uf[1][C] = qx;
+            Uf[2][C] = qy;
+        }
+}
+
+/* S15: clip negative depth (volume recorded), zero the discharge of dry
+ * cells, raise the NaN flag on non-finite values.  Returns sum of (0 - h). */
+static double dry_fix(const orc_cfg* c, const Grid* G, double* const Uf[3], const double* zp,
+                      double* Un1[3], uint32_t* flags) {
+    double defect = 0.0;
+    for (int j = 0; j < G->ny; ++j)
+        for (int i = 0; i < G->nx; ++i) {
+            size_t C = at(G, i, j);
+            double eta = Uf[0][C], qx = Uf[1][C], qy = Uf[2][C];
+            double h = eta - zp[C];
+            if (h < 0.0) {
+                defect += 0.0 - h;
+                eta = zp[C];
+                *flags |= ORC_FLAG_CLIPPED;
+            }
+            if (!(eta - zp[C] > c->h_dry)) {
+                qx = 0.0;
+                qy = 0.0;
+            }
+            if (!isfinite(eta) || !isfinite(qx) || !isfinite(qy)) *flags |= ORC_FLAG_NAN;
+            Un1[0][C] = eta;
+            Un1[1][C] = qx;
+            Un1[2][C] = qy;
+        }
+    return defect;
+}
+
+/* S16 on an unpadded state (pitch nx): lam_max and the volume sum of h. */
+static void cfl_scan(const orc_cfg* c, int nx, int ny, const double* eta, const double* qx,
+                     const double* qy, const double* z, double* lam_max, double* hsum) {
+    double idx = 1.0 / c->dx, idy = 1.0 / c->dy;
+    double lmax = 0.0, vs = 0.0;
+    size_t N = (size_t)nx * (size_t)ny;
+    for (size_t s = 0; s < N; ++s) {
+        double h = eta[s] - z[s];
+        vs += h;
+        if (h > c->h_dry) {
+            double r = 1.0 / h;
+            double u = qx[s] * r, v = qy[s] * r;
+            double cc = sqrt(c->g * h);
+            double lam = (fabs(u) + cc) * idx + (fabs(v) + cc) * idy;
+            if (!(lam <= lmax)) lmax = lam;  /* a NaN lam propagates */
+        }
+    }
+    *lam_max = lmax;
+    *hsum = vs;
+}
+
+static double next_dt(const orc_cfg* c, double lam_max) {
+    if (c->dt_fixed > 0.0) return c->dt_fixed;
+    if (lam_max > 0.0) return dmin(c->cfl / lam_max, c->dt_max);
+    return c->dt_max;
+}
+
+/* ------------------------------------------------------------ one step */
+
+typedef struct {
+    double qin_n, qin_n1, rx, ry, defect, lam_max, dt_next, volume, t_next;
+    uint32_t flags;
+} StepOut;
+
+static void one_step(const orc_cfg* c, const Grid* G, Work* w, double* eta, double* qx,
+                     double* qy, double t, int64_t n, double dt, StepOut* o) {
+    int nx = G->nx, ny = G->ny;
+    int sigma = (n & 1) ? -1 : 1;
+    double rx = dt / c->dx, ry = dt / c->dy;
+    double qin0 = q_inflow(c, t);
+    double qin1 = q_inflow(c, t + dt);
+    /* S1: copy U^n into the padded arrays and build its ghost ring. */
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            size_t s = (size_t)j * (size_t)nx + (size_t)i;
+            w->Un[0][at(G, i, j)] = eta[s];
+            w->Un[1][at(G, i, j)] = qx[s];
+            w->Un[2][at(G, i, j)] = qy[s];
+        }
+    fill_ghosts(c, G, qin0, w->Un[0], w->Un[1], w->Un[2]);
+    prim(c, G, w->Un, w->zp, w->h, w->r, w->u, w->v);                       /* S2 */
+    switch_nu(G, w->Un[0], w->r, w->nux, w->nuy);                           /* S3 */
+    dissipation(c, G, w->Un, w->h, w->nux, w->nuy, w->D);                   /* S4 */
+    xflux(c, G, sigma, w->Un, w->h, w->u, w->v, w->zp, w->F);               /* S5 */
+    yflux(c, G, sigma, w->Un, w->h, w->u, w->v, w->zp, w->G);               /* S6 */
+    flux_update(G, sigma, rx, ry, w->Un, w->F, w->G, w->Us);                /* S7 */
+    fill_ghosts(c, G, qin1, w->Us[0], w->Us[1], w->Us[2]);                  /* S8 */
+    prim(c, G, w->Us, w->zp, w->hs, w->rs, w->us, w->vs);                   /* S9 */
+    xflux(c, G, -sigma, w->Us, w->hs, w->us, w->vs, w->zp, w->Fs);          /* S10 */
+    yflux(c, G, -sigma, w->Us, w->hs, w->us, w->vs, w->zp, w->Gs);          /* S11 */
+    corrector(G, sigma, rx, ry, w->Un, w->Us, w->Fs, w->Gs, w->Uc);         /* S12 */
+    add_diss(G, w->Uc, w->D, w->Ud);                                        /* S13 */
+    friction(c, G, dt, w->Ud, w->zp, w->mp, w->Uf);                         /* S14 */
+    uint32_t flags = 0;
+    double defect = dry_fix(c, G, w->Uf, w->zp, w->Unew, &flags);           /* S15 */
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            size_t s = (size_t)j * (size_t)nx + (size_t)i;
+            eta[s] = w->Unew[0][at(G, i, j)];
+            qx[s] = w->Unew[1][at(G, i, j)];
+            qy[s] = w->Unew[2][at(G, i, j)];
+        }
+    /* S16, on the unpadded new state. */
+    double lam, hsum;
+    cfl_scan(c, nx, ny, eta, qx, qy, w->z, &lam, &hsum);
+    double dtn = next_dt(c, lam);
+    if (!isfinite(lam)) flags |= ORC_FLAG_NAN;
+    if (!(dtn > 0.0) || !isfinite(dtn)) flags |= ORC_FLAG_BADDT;
+    o->qin_n = qin0;
+    o->qin_n1 = qin1;
+    o->rx = rx;
+    o->ry = ry;
+    o->defect = defect;
+    o->lam_max = lam;
+    o->dt_next = dtn;
+    o->volume = hsum * (c->dx * c->dy);
+    o->t_next = t + dt;
+    o->flags = flags;
+}
+
+static int check_cfg(const orc_cfg* c) {
+    if (c->nx < 1 || c->ny < 1) return -1;
+    if (!(c->dx > 0.0) || !(c->dy > 0.0)) return -1;
+    if (c->hydro_len > 0 && (!c->hydro_t || !c->hydro_q)) return -1;
+    for (int k = 0; k < 4; ++k)
+        if (c->bc[k] < BC_WALL || c->bc[k] > BC_INFLOW) return -1;
+    return 0;
+}
+
+/* ------------------------------------------------------------ public API */
+
+int orc_ntrace(void) { return ORC_NTRACE; }
+int orc_nscalar(void) { return ORC_NSCALAR; }
+
+/* dt^0 of a state (S16) and its volume.  Returns dt; lam_max and volume are
+ * written through the pointers when they are not NULL. */
+double orc_initial_dt(const orc_cfg* c, const double* eta, const double* qx, const double* qy,
+                      const double* z, double* lam_max, double* volume) {
+    double lam, hsum;
+    cfl_scan(c, c->nx, c->ny, eta, qx, qy, z, &lam, &hsum);
+    if (lam_max) *lam_max = lam;
+    if (volume) *volume = hsum * (c->dx * c->dy);
+    return next_dt(c, lam);
+}
+
+/* Advance the state in place by up to nsteps steps, stopping early once
+ * t >= t_end or when a step raises the NaN or bad-dt flag.  *t, *step and *dt
+ * hold t^n, n and dt^n on entry (a *dt <= 0 means: compute dt^0 from the
+ * state) and the values after the last step on return.  Returns 0 on success,
+ * 1 when a step raised a fatal flag, -1 on bad arguments or allocation. */
+int orc_run(const orc_cfg* c, double* eta, double* qx, double* qy, const double* z,
+            const double* nman, double* t, int64_t* step, double* dt, int64_t nsteps,
+            double t_end, orc_stats* st) {
+    if (check_cfg(c) || !eta || !qx || !qy || !z || !nman || !t || !step || !dt) return -1;
+    Grid G = {c->nx, c->ny, c->nx + 2};
+    Work w;
+    if (work_init(&w, &G, NULL)) return -1;
+    size_t N = (size_t)G.P * (size_t)(G.ny + 2);
+    w.zp = w.block + (size_t)ORC_NTRACE * N;
+    w.mp = w.zp + N;
+    w.z = z;
+    static_fields(c, &G, z, nman, w.zp, w.mp);
+    if (!(*dt > 0.0)) *dt = orc_initial_dt(c, eta, qx, qy, z, NULL, NULL);
+    orc_stats S;
+    memset(&S, 0, sizeof S);
+    S.bad_step = -1;
+    S.dt_min = INFINITY;
+    S.dt_max = 0.0;
+    double lam = 0.0, vol;
+    orc_initial_dt(c, eta, qx, qy, z, &lam, &vol);
+    S.volume = vol;
+    S.lambda_max = lam;
+    int rc = 0;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        if (!(*t < t_end)) break;
+        StepOut o;
+        one_step(c, &G, &w, eta, qx, qy, *t, *step, *dt, &o);
+        S.dt_min = dmin(S.dt_min, *dt);
+        S.dt_max = dmax(S.dt_max, *dt);
+        S.defect += o.defect * (c->dx * c->dy);
+        S.flags |= o.flags;
+        S.volume = o.volume;
+        S.lambda_max = o.lam_max;
+        S.steps += 1;
+        *t = o.t_next;
+        *dt = o.dt_next;
+        *step += 1;
+        if (o.flags & (ORC_FLAG_NAN | ORC_FLAG_BADDT)) {
+            S.bad_step = *step - 1;
+            rc = 1;
+            break;
+        }
+    }
+    S.t = *t;
+    S.dt = *dt;
+    if (st) *st = S;
+    work_free(&w);
+    return rc;
+}
+
+/* One step with every intermediate exposed.  `arrays` receives ORC_NTRACE
+ * padded (ny+2) x (nx+2) arrays in the order S1 (eta, qx, qy), S2 (h, r, u, v),
+ * S3 (nu_x, nu_y), S4 (D_eta, D_qx, D_qy), S5 (Fm, Fx, Fy, Px), S6 (Gm, Gx,
+ * Gy, Py), S7+S8 (eta*, qx*, qy*), S9 (h*, r*, u*, v*), S10 (4), S11 (4),
+ * S12 (3), S13 (3), S14 (3), S15 (3).  `scalars` receives ORC_NSCALAR
+ * values: q_in(t^n), q_in(t^n + dt), rx, ry, sum of clipped depth, lam_max,
+ * dt^{n+1}, volume, flags, sigma, t^{n+1}; the rest 0.  The state is advanced
+ * in place.  Returns 0, or -1 on bad arguments. */
+int orc_trace(const orc_cfg* c, double* eta, double* qx, double* qy, const double* z,
+              const double* nman, double t, int64_t step, double dt, double* arrays,
+              double* scalars) {
+    if (check_cfg(c) || !arrays || !scalars) return -1;
+    Grid G = {c->nx, c->ny, c->nx + 2};
+    Work w;
+    work_init(&w, &G, arrays);
+    size_t N = (size_t)G.P * (size_t)(G.ny + 2);
+    double* zm = (double*)calloc(2 * N, sizeof(double));
+    if (!zm) return -1;
+    w.zp = zm;
+    w.mp = zm + N;
+    w.z = z;
+    static_fields(c, &G, z, nman, w.zp, w.mp);
+    StepOut o;
+    one_step(c, &G, &w, eta, qx, qy, t, step, dt, &o);
+    free(zm);
+    for (int k = 0; k < ORC_NSCALAR; ++k) scalars[k] = 0.0;
+    scalars[0] = o.qin_n;
+    scalars[1] = o.qin_n1;
+    scalars[2] = o.rx;
+    scalars[3] = o.ry;
+    scalars[4] = o.defect;
+    scalars[5] = o.lam_max;
+    scalars[6] = o.dt_next;
+    scalars[7] = o.volume;
+    scalars[8] = (double)o.flags;
+    scalars[9] = (step & 1) ? -1.0 : 1.0;
+    scalars[10] = o.t_next;
+    return 0;
+}

@@ -1,0 +1,258 @@
+"""Seeded synthetic inputs for the shallow-water step.
+
+This module only builds problem definitions: grids, bed elevation, Manning
+field, initial state, boundary kinds and the inflow hydrograph.  It holds none
+of the solver's arithmetic, so both the GPU library and the CPU oracle can be
+fed from it.
+
+The paper's five data sets (Table 1) are not published; every input here is a
+synthetic stand-in with the shape and structure of the workloads the solver is
+measured on: a wet-bed dam break on a flat bed, a reservoir released onto
+seeded hilly terrain, and small still-water and wave cases that have closed
+forms.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional, Sequence
+
+import numpy as np
+
+WALL, OPEN, INFLOW = 0, 1, 2
+EDGE_W, EDGE_E, EDGE_S, EDGE_N = 0, 1, 2, 3
+
+#: default switched-dissipation coefficient and its per-direction cap
+KAPPA = 0.5
+EPS_MAX = 0.25
+
+
+@dataclasses.dataclass
+class Problem:
+    """One shallow-water problem: parameters plus float64 host arrays (ny, nx)."""
+
+    nx: int
+    ny: int
+    dx: float
+    dy: float
+    z: np.ndarray
+    n: np.ndarray
+    eta: np.ndarray
+    qx: np.ndarray
+    qy: np.ndarray
+    g: float = 9.81
+    cfl: float = 0.5
+    h_dry: float = 1e-3
+    kappa: float = KAPPA
+    eps_max: float = EPS_MAX
+    dt_max: float = 1.0
+    dt_fixed: float = 0.0
+    bc: tuple = (WALL, WALL, WALL, WALL)
+    inflow_lo: tuple = (0, 0, 0, 0)
+    inflow_hi: Optional[tuple] = None
+    hydro_t: Sequence[float] = ()
+    hydro_q: Sequence[float] = ()
+    name: str = ""
+
+    def __post_init__(self):
+        if self.inflow_hi is None:
+            self.inflow_hi = (self.ny, self.ny, self.nx, self.nx)
+        for a in ("z", "n", "eta", "qx", "qy"):
+            arr = np.ascontiguousarray(getattr(self, a), dtype=np.float64)
+            if arr.shape != (self.ny, self.nx):
+                raise ValueError(f"{a} has shape {arr.shape}, expected {(self.ny, self.nx)}")
+            setattr(self, a, arr)
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny
+
+    def copy(self) -> "Problem":
+        p = dataclasses.replace(self)
+        for a in ("z", "n", "eta", "qx", "qy"):
+            setattr(p, a, getattr(self, a).copy())
+        return p
+
+    def state(self):
+        return self.eta.copy(), self.qx.copy(), self.qy.copy()
+
+
+# --------------------------------------------------------------------------
+# Stoker wet-bed dam break: 128 x 128, dx = dy = 1 m, flat bed, walls,
+# h = 1.0 m for x < 64 m and 0.5 m beyond, n = 0, g = 9.81, CFL 0.5.
+
+def stoker(nx: int = 128, ny: int = 128, dx: float = 1.0, x_dam: float = 64.0,
+           h_left: float = 1.0, h_right: float = 0.5, axis: str = "x") -> Problem:
+    """Dam break along x (or along y with axis='y').  Cell centres sit at
+    (i + 1/2) dx, so the dam lies on the face at x_dam when x_dam/dx is whole."""
+    n_along = nx if axis == "x" else ny
+    xc = (np.arange(n_along) + 0.5) * dx
+    prof = np.where(xc < x_dam, h_left, h_right)
+    if axis == "x":
+        h = np.broadcast_to(prof[None, :], (ny, nx)).copy()
+    else:
+        h = np.broadcast_to(prof[:, None], (ny, nx)).copy()
+    z = np.zeros((ny, nx))
+    return Problem(nx=nx, ny=ny, dx=dx, dy=dx, z=z, n=np.zeros((ny, nx)), eta=h,
+                   qx=np.zeros((ny, nx)), qy=np.zeros((ny, nx)), name=f"stoker{nx}x{ny}")
+
+
+# --------------------------------------------------------------------------
+# Terrain: a sum of Gaussian hills plus a 1/f fractal layer.
+
+def gaussian_hills(nx: int, ny: int, dx: float, dy: float, rng: np.random.Generator,
+                   count: int, height: tuple, sigma: tuple) -> np.ndarray:
+    """Sum of `count` Gaussian hills with centres uniform over the domain,
+    heights U(height) and widths U(sigma) (metres).  Each hill is separable, so
+    the sum is one (ny x K) @ (K x nx) product."""
+    Lx, Ly = nx * dx, ny * dy
+    cx = rng.uniform(0.0, Lx, count)
+    cy = rng.uniform(0.0, Ly, count)
+    a = rng.uniform(height[0], height[1], count)
+    s = rng.uniform(sigma[0], sigma[1], count)
+    xc = (np.arange(nx) + 0.5) * dx
+    yc = (np.arange(ny) + 0.5) * dy
+    gx = np.exp(-0.5 * ((xc[None, :] - cx[:, None]) / s[:, None]) ** 2)  # K x nx
+    gy = np.exp(-0.5 * ((yc[:, None] - cy[None, :]) / s[None, :]) ** 2)  # ny x K
+    return (gy * a[None, :]) @ gx
+
+
+def fractal_noise(nx: int, ny: int, rng: np.random.Generator, amplitude: float) -> np.ndarray:
+    """1/f noise by spectral synthesis: amplitude proportional to 1/|k|, random
+    phases, zero mean, scaled so that max |noise| = amplitude."""
+    kx = np.fft.rfftfreq(nx)
+    ky = np.fft.fftfreq(ny)
+    kk = np.sqrt(kx[None, :] ** 2 + ky[:, None] ** 2)
+    kk[0, 0] = np.inf
+    spec = (1.0 / kk) * np.exp(2j * np.pi * rng.uniform(0.0, 1.0, kk.shape))
+    spec[0, 0] = 0.0
+    f = np.fft.irfft2(spec, s=(ny, nx))
+    f -= f.mean()
+    m = np.abs(f).max()
+    return f * (amplitude / m) if m > 0 else f
+
+
+def reservoir_release(nx: int = 4096, ny: int = 4096, dx: float = 5.0, seed: int = 1001,
+                      hills: int = 200, hill_height=(0.0, 20.0), hill_sigma=(50.0, 400.0),
+                      noise_amp: float = 1.0, surface: float = 25.0, dam_frac: float = 0.2,
+                      manning: float = 0.035, h_dry: float = 1e-3) -> Problem:
+    """Reservoir released onto seeded hilly terrain.  The default is the
+    4096 x 4096, dx = 5 m workload: 200 Gaussian hills (height 0-20 m, sigma
+    50-400 m) plus 1/f noise of amplitude 1 m; water surface at 25 m for cell
+    centres with x < 0.2 L, dry land beyond (h = 0 there); uniform Manning
+    n = 0.035; open east edge, walls elsewhere.  Smaller grids keep the
+    physical recipe (hill sizes in metres) at the given dx."""
+    rng = np.random.default_rng(seed)
+    z = gaussian_hills(nx, ny, dx, dx, rng, hills, hill_height, hill_sigma)
+    z += fractal_noise(nx, ny, rng, noise_amp)
+    L = nx * dx
+    xc = (np.arange(nx) + 0.5) * dx
+    behind = (xc < dam_frac * L)[None, :]
+    eta = np.where(behind, np.maximum(surface, z), z)
+    return Problem(nx=nx, ny=ny, dx=dx, dy=dx, z=z, n=np.full((ny, nx), manning), eta=eta,
+                   qx=np.zeros((ny, nx)), qy=np.zeros((ny, nx)), h_dry=h_dry,
+                   bc=(WALL, OPEN, WALL, WALL), name=f"reservoir{nx}x{ny}")
+
+
+# --------------------------------------------------------------------------
+# Cases with closed forms or exact invariants.
+
+def lake_at_rest(nx: int, ny: int, seed: int, level: float = 1.0, dry_banks: bool = True,
+                 dx: float = 1.0) -> Problem:
+    """Still water at elevation `level` over a random bed; with dry_banks the
+    bed rises above the surface in places (those cells are dry, h = 0)."""
+    rng = np.random.default_rng(seed)
+    z = gaussian_hills(nx, ny, dx, dx, rng, max(4, (nx * ny) // 200), (0.0, 1.6 if dry_banks else 0.8),
+                       (2.0 * dx, 0.25 * min(nx, ny) * dx))
+    z -= 0.2
+    eta = np.maximum(level, z)
+    n = rng.uniform(0.01, 0.05, (ny, nx))
+    return Problem(nx=nx, ny=ny, dx=dx, dy=dx, z=z, n=n, eta=eta, qx=np.zeros((ny, nx)),
+                   qy=np.zeros((ny, nx)), name=f"lake{nx}x{ny}")
+
+
+def smooth_wet(nx: int, ny: int, seed: int, dx: float = 1.0, manning: float = 0.03,
+               amp: float = 0.2, vel: float = 0.3) -> Problem:
+    """A random smooth, everywhere-wet moving state over a hilly bed (depth
+    stays above ~0.5 m), used for conservation and parity checks."""
+    rng = np.random.default_rng(seed)
+    z = gaussian_hills(nx, ny, dx, dx, rng, 12, (0.0, 0.5), (0.1 * nx * dx, 0.3 * nx * dx))
+    surf = 1.5 + gaussian_hills(nx, ny, dx, dx, rng, 6, (-amp, amp), (0.1 * nx * dx, 0.25 * nx * dx))
+    h = np.maximum(surf - z, 0.5)
+    eta = z + h
+    u = gaussian_hills(nx, ny, dx, dx, rng, 6, (-vel, vel), (0.15 * nx * dx, 0.3 * nx * dx))
+    v = gaussian_hills(nx, ny, dx, dx, rng, 6, (-vel, vel), (0.15 * nx * dx, 0.3 * nx * dx))
+    n = rng.uniform(0.5 * manning, 1.5 * manning, (ny, nx))
+    return Problem(nx=nx, ny=ny, dx=dx, dy=dx, z=z, n=n, eta=eta, qx=u * h, qy=v * h,
+                   name=f"smooth{nx}x{ny}")
+
+
+def gaussian_hump(nx: int = 2048, ny: int = 8, dx: float = 1.0, h0: float = 1.0,
+                  amp: float = 1e-4, width: float = 20.0, dt_fixed: float = 0.1) -> Problem:
+    """Small Gaussian hump on still water of depth h0 in a walled channel."""
+    xc = (np.arange(nx) + 0.5) * dx
+    x0 = 0.5 * nx * dx
+    prof = h0 + amp * np.exp(-0.5 * ((xc - x0) / width) ** 2)
+    eta = np.broadcast_to(prof[None, :], (ny, nx)).copy()
+    return Problem(nx=nx, ny=ny, dx=dx, dy=dx, z=np.zeros((ny, nx)), n=np.zeros((ny, nx)),
+                   eta=eta, qx=np.zeros((ny, nx)), qy=np.zeros((ny, nx)), dt_fixed=dt_fixed,
+                   kappa=0.0, name="hump")
+
+
+def seiche(nx: int = 200, ny: int = 6, dx: float = 1.0, h0: float = 1.0, amp: float = 1e-4,
+           dt_fixed: float = 0.05) -> Problem:
+    """First closed-basin mode: eta = h0 + amp cos(pi x / L)."""
+    L = nx * dx
+    xc = (np.arange(nx) + 0.5) * dx
+    prof = h0 + amp * np.cos(np.pi * xc / L)
+    eta = np.broadcast_to(prof[None, :], (ny, nx)).copy()
+    return Problem(nx=nx, ny=ny, dx=dx, dy=dx, z=np.zeros((ny, nx)), n=np.zeros((ny, nx)),
+                   eta=eta, qx=np.zeros((ny, nx)), qy=np.zeros((ny, nx)), dt_fixed=dt_fixed,
+                   kappa=0.0, name="seiche")
+
+
+def uniform_flow(nx: int, ny: int, h: float, q: float, manning: float, dt_fixed: float,
+                 dx: float = 1.0) -> Problem:
+    """Uniform depth h and discharge (q, 0) on a flat bed with open edges."""
+    eta = np.full((ny, nx), h)
+    return Problem(nx=nx, ny=ny, dx=dx, dy=dx, z=np.zeros((ny, nx)),
+                   n=np.full((ny, nx), manning), eta=eta, qx=np.full((ny, nx), q),
+                   qy=np.zeros((ny, nx)), dt_fixed=dt_fixed, bc=(OPEN, OPEN, OPEN, OPEN),
+                   name="uniform")
+
+
+def inflow_channel(nx: int, ny: int, seed: int, q_peak: float = 2.0, dry: bool = True,
+                   dx: float = 2.0, t_peak: float = 20.0, t_end: float = 60.0) -> Problem:
+    """Sloping channel fed by a triangular inflow hydrograph on the west edge
+    (0 at t = 0, q_peak at t_peak, 0 again at t_end), open east edge, walls
+    north and south; initially dry unless dry=False."""
+    rng = np.random.default_rng(seed)
+    xc = (np.arange(nx) + 0.5) * dx
+    z = np.broadcast_to((1e-3 * (nx * dx - xc))[None, :], (ny, nx)).copy()
+    z += gaussian_hills(nx, ny, dx, dx, rng, 6, (0.0, 0.3), (0.05 * nx * dx, 0.2 * nx * dx))
+    eta = z.copy() if dry else z + 0.5
+    n = rng.uniform(0.02, 0.06) * np.ones((ny, nx))
+    return Problem(nx=nx, ny=ny, dx=dx, dy=dx, z=z, n=n, eta=eta, qx=np.zeros((ny, nx)),
+                   qy=np.zeros((ny, nx)), bc=(INFLOW, OPEN, WALL, WALL),
+                   hydro_t=(0.0, t_peak, t_end), hydro_q=(0.0, q_peak, 0.0), name="inflow")
+
+
+def random_valid_state(nx: int, ny: int, seed: int, dry_fraction: float = 0.2,
+                       dx: float = 1.0) -> Problem:
+    """Rough random state with wet, thin and dry cells, banks and every
+    boundary kind, for sub-step-by-sub-step parity checks."""
+    rng = np.random.default_rng(seed)
+    z = rng.uniform(0.0, 0.6, (ny, nx))
+    h = rng.uniform(0.05, 1.0, (ny, nx))
+    dry = rng.uniform(0.0, 1.0, (ny, nx)) < dry_fraction
+    thin = rng.uniform(0.0, 1.0, (ny, nx)) < 0.05
+    h = np.where(dry, 0.0, h)
+    h = np.where(thin, rng.uniform(0.0, 2e-3, (ny, nx)), h)
+    eta = z + h
+    qx = rng.normal(0.0, 0.3, (ny, nx)) * (h > 1e-3)
+    qy = rng.normal(0.0, 0.3, (ny, nx)) * (h > 1e-3)
+    n = rng.uniform(0.0, 0.06, (ny, nx))
+    return Problem(nx=nx, ny=ny, dx=dx, dy=1.25 * dx, z=z, n=n, eta=eta, qx=qx, qy=qy,
+                   bc=(INFLOW, OPEN, WALL, INFLOW), inflow_lo=(1, 0, 0, 2),
+                   inflow_hi=(ny - 1, ny, nx, nx - 3), hydro_t=(0.0, 0.05, 10.0),
+                   hydro_q=(0.1, 0.4, 0.0), name=f"random{nx}x{ny}")
