@@ -1,0 +1,202 @@
+/*
+ * swe.h -- C ABI of libswe.so, the MI355X (gfx950) shallow-water library.
+ *
+ * The library advances the 2D shallow-water mass and momentum equations with
+ * the explicit predictor-corrector MacCormack scheme (Seitz et al., 2013, §1):
+ * each time step is sixteen dependent sub-steps, every one a cell-independent
+ * stencil sweep, with a variable time step computed after every step from the
+ * new state (§3.1).  Unknowns are the water-surface elevation eta and the unit
+ * discharges qx, qy; the bed elevation z and a Manning coefficient field n are
+ * static.  Dry cells (depth <= h_dry), which the paper lists as unsupported
+ * (§6.2), are handled by a thin-film rule: zero velocity, no dissipation or
+ * pressure across dry banks, negative depth clipped with the clipped volume
+ * recorded.
+ *
+ * Conventions shared by every entry point:
+ *   - Fields are 2D, row-major with x fastest: element (i, j) of a field sits
+ *     at index j*pitch + i, 0 <= i < nx, 0 <= j < ny, pitch >= nx (elements).
+ *     Every field of one handle has the same pitch and element type
+ *     (float for SWE_F32, double for SWE_F64).
+ *   - Device pointers are GPU memory of the device current at swe_create.  The
+ *     caller owns them (typically PyTorch tensors); they must outlive the
+ *     handle.  The library never frees caller memory.
+ *   - All device work is enqueued on the stream given at create (NULL: the
+ *     null stream).  A handle is not thread-safe.
+ *   - Return values: SWE_OK (0) or a negative swe_status.  No C++ exception and
+ *     no abort crosses this interface; the message of the last failure is
+ *     available from swe_last_error.
+ */
+#ifndef SWE_H
+#define SWE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SWE_ABI_VERSION 1
+
+typedef enum swe_status {
+    SWE_OK = 0,
+    SWE_EINVAL = -1,       /* bad argument; nothing was enqueued */
+    SWE_ENOMEM = -2,       /* device or host allocation failed */
+    SWE_EDEVICE = -3,      /* no usable GPU, or a HIP call failed (text in last_error) */
+    SWE_EUNSTABLE = -4,    /* a step produced NaN/Inf or an invalid time step */
+    SWE_EUNSUPPORTED = -5  /* valid request this build does not implement */
+} swe_status;
+
+typedef enum swe_dtype { SWE_F32 = 1, SWE_F64 = 2 } swe_dtype;
+
+/* Boundary kind of an edge.  WALL: reflective, no flux.  OPEN: zero-gradient
+ * outflow (ghost = copy of the edge cell).  INFLOW: prescribed normal unit
+ * discharge q_in(t) into the domain (the hydrograph), acting as WALL outside
+ * the edge's face band [inflow_lo, inflow_hi). */
+typedef enum swe_bc { SWE_BC_WALL = 0, SWE_BC_OPEN = 1, SWE_BC_INFLOW = 2 } swe_bc;
+typedef enum swe_edge { SWE_EDGE_W = 0, SWE_EDGE_E = 1, SWE_EDGE_S = 2, SWE_EDGE_N = 3 } swe_edge;
+
+/* Execution path.  FUSED: one kernel per time step (all sixteen sub-steps on
+ * an LDS/register-resident tile, the default).  UNFUSED: one kernel per
+ * sub-step with every intermediate in device memory; bitwise equal results,
+ * kept as the parity ladder and as the one-kernel-per-sub-step comparison
+ * point (the paper's own structure, §3.1). */
+typedef enum swe_path { SWE_PATH_FUSED = 0, SWE_PATH_UNFUSED = 1 } swe_path;
+
+/* Flag bits reported in swe_stats.flags. */
+enum {
+    SWE_FLAG_NAN = 1,      /* a non-finite value appeared (fatal) */
+    SWE_FLAG_CLIPPED = 2,  /* a negative depth was clipped (informational) */
+    SWE_FLAG_BADDT = 4     /* the next time step is not finite and positive (fatal) */
+};
+
+/* Problem definition.  Fill with swe_config_init, then set the fields. */
+typedef struct swe_config {
+    int32_t nx, ny;          /* cells in x and y, each >= 5 */
+    int32_t dtype;           /* SWE_F32 or SWE_F64: element type of every field */
+    int32_t path;            /* swe_path */
+    int32_t bc[4];           /* swe_bc per edge, indexed by swe_edge */
+    int32_t inflow_lo[4];    /* INFLOW face band along each edge: faces k with */
+    int32_t inflow_hi[4];    /*   lo <= k < hi (k = j on W/E, k = i on S/N) */
+    int32_t hydro_len;       /* points of the hydrograph, 0..4096 (0: q_in = 0) */
+    int32_t tile_rows;       /* rows per workgroup of the fused kernel, 0 = auto */
+    int64_t pitch;           /* row pitch of every field in elements, >= nx */
+    double dx, dy;           /* cell size (m), > 0 */
+    double g;                /* gravity (m/s^2), > 0 */
+    double cfl;              /* Courant number of the adaptive step, (0, 1] */
+    double h_dry;            /* dry-depth threshold (m), >= 0; wet <=> h > h_dry */
+    double kappa;            /* dissipation coefficient, [0, 4] */
+    double eps_max;          /* cap of the per-face dissipation coefficient, [0, 0.25] */
+    double dt_max;           /* upper bound of the time step (s), > 0 */
+    double dt_fixed;         /* > 0: use this time step every step; <= 0: adaptive */
+    double t0;               /* start time (s) */
+    const double* hydro_t;   /* host, hydro_len increasing times (s); copied */
+    const double* hydro_q;   /* host, hydro_len unit discharges (m^2/s); copied */
+    const void* z;           /* device: bed elevation (m) */
+    const void* n;           /* device: Manning coefficient (s m^-1/3); read once */
+    void* eta;               /* device, in/out: water-surface elevation (m) */
+    void* qx;                /* device, in/out: unit discharge along x (m^2/s) */
+    void* qy;                /* device, in/out: unit discharge along y (m^2/s) */
+    void* stream;            /* hipStream_t, or NULL */
+} swe_config;
+
+/* Progress and diagnostics of a handle. */
+typedef struct swe_stats {
+    int64_t step;            /* global step index n of the current state */
+    int64_t steps;           /* steps taken by the call that filled this */
+    int64_t bad_step;        /* step that raised a fatal flag, or -1 */
+    uint32_t flags;          /* OR of all flags raised since create */
+    uint32_t pad_;
+    double t;                /* t^n of the current state (s) */
+    double dt;               /* dt^n, the step the next swe_step will take (s) */
+    double dt_min, dt_max;   /* extremes of the steps taken by the call (s) */
+    double volume;           /* sum of (eta - z) dx dy over the state (m^3) */
+    double defect;           /* clipped volume added since create (m^3) */
+    double lambda_max;       /* max over wet cells of (|u|+c)/dx + (|v|+c)/dy */
+} swe_stats;
+
+/* Scalars needed to resume a run bitwise: the caller saves its own eta, qx,
+ * qy arrays next to this record. */
+typedef struct swe_checkpoint {
+    int64_t step;
+    uint32_t flags;
+    uint32_t pad_;
+    double t, dt, defect;
+} swe_checkpoint;
+
+typedef struct swe_handle swe_handle;
+
+/* SWE_ABI_VERSION of the loaded library. */
+int swe_abi_version(void);
+
+/* Fill *cfg with defaults: g = 9.81, cfl = 0.5, h_dry = 1e-3, kappa = 0.5,
+ * eps_max = 0.25, dt_max = 1, dt_fixed = 0, t0 = 0, dtype = SWE_F64, path =
+ * FUSED, all edges WALL with full inflow bands, every pointer NULL.  No-op on
+ * NULL. */
+void swe_config_init(swe_config* cfg);
+
+/* Validate cfg, take host copies of the hydrograph, allocate the library's
+ * device scratch (second state buffer, m = g n^2, control block, reduction
+ * partials) and compute dt^0 from the initial state (sub-step 16 on U^0).
+ * Enqueues on cfg->stream and synchronises it once.  On success *out owns the
+ * scratch; on failure *out is NULL and swe_last_error(NULL) says why.
+ * Errors: SWE_EINVAL (NULL pointer, sizes, ranges, pitch < nx, unknown enum),
+ * SWE_EDEVICE (no GPU, or a pointer that is not device memory of the current
+ * device), SWE_ENOMEM. */
+int swe_create(const swe_config* cfg, swe_handle** out);
+
+/* Free the library's scratch (never caller memory).  NULL is a no-op. */
+void swe_destroy(swe_handle* h);
+
+/* One time step (sub-steps 1..16), asynchronous on the handle's stream; the
+ * new state is in the caller's eta/qx/qy when the stream reaches it.  With
+ * dt_used != NULL the call synchronises and stores the step taken.  Errors:
+ * SWE_EINVAL, SWE_EDEVICE, SWE_EUNSTABLE (only detected when dt_used != NULL). */
+int swe_step(swe_handle* h, double* dt_used);
+
+/* Up to nsteps steps, stopping early once t >= t_end (pass +INFINITY for no
+ * limit) or after a step raises a fatal flag; steps past the stop become
+ * no-ops on the device, so the host enqueues all launches without waiting.
+ * Synchronises once at the end, leaves the final state in the caller's
+ * arrays and fills *out (may be NULL).  Returns SWE_EUNSTABLE if a fatal flag
+ * was raised (out->bad_step names the step). */
+int swe_run(swe_handle* h, int64_t nsteps, double t_end, swe_stats* out);
+
+/* Synchronise the stream and report the current statistics. */
+int swe_get_stats(swe_handle* h, swe_stats* out);
+
+/* One time step on the UNFUSED path that also copies every intermediate out:
+ * `arrays` (device, `bytes` >= swe_trace_bytes(h)) receives 47 arrays of
+ * (ny+2) x (nx+2) elements of the handle's dtype, each padded with a one-cell
+ * ghost ring (element (i, j) at (j+1)*(nx+2) + (i+1), i in [-1, nx], j in
+ * [-1, ny]), in the order: S1 eta, qx, qy (with ghosts); S2 h, r, u, v;
+ * S3 nu_x, nu_y; S4 D_eta, D_qx, D_qy; S5 Fm, Fx, Fy, Px; S6 Gm, Gx, Gy, Py;
+ * S7/S8 eta*, qx*, qy*; S9 h*, r*, u*, v*; S10 (4); S11 (4); S12 (3);
+ * S13 (3); S14 (3); S15 (3).  Face arrays keep the face between cells k and
+ * k+1 in the slot of cell k.  `scalars` (host, 16 doubles) receives q_in(t^n),
+ * q_in(t^n + dt), dt/dx, dt/dy, the clipped depth sum, lambda_max, dt^{n+1},
+ * volume, flags of the step, sigma, t^{n+1}, then zeros.  Synchronises. */
+int swe_trace_step(swe_handle* h, void* arrays, size_t bytes, double* scalars);
+
+/* Bytes of the `arrays` buffer swe_trace_step needs. */
+size_t swe_trace_bytes(const swe_handle* h);
+
+/* Copy the handle's scalars to *ck (synchronises), or restore them from *ck
+ * after the caller has restored its eta/qx/qy arrays. */
+int swe_save(swe_handle* h, swe_checkpoint* ck);
+int swe_load(swe_handle* h, const swe_checkpoint* ck);
+
+/* Message of the handle's last failure, or of the last failed swe_create
+ * when h is NULL.  Never NULL; valid until the next call on that handle. */
+const char* swe_last_error(const swe_handle* h);
+
+/* Plain device-to-device copy kernel of `bytes` bytes (multiple of 16, both
+ * pointers 16-byte aligned) on `stream`: the bandwidth probe the HBM traffic
+ * counters are calibrated against.  Asynchronous.  SWE_EINVAL on misuse. */
+int swe_probe_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWE_H */

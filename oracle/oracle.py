@@ -59,7 +59,8 @@ class _Stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("bad_step", ctypes.c_int64),
                 ("flags", ctypes.c_uint32), ("pad_", ctypes.c_uint32)] + [
                 (f, ctypes.c_double) for f in
-                ("t", "dt", "dt_min", "dt_max", "volume", "defect", "lambda_max")]
+                ("t", "dt", "dt_min", "dt_max", "volume", "defect", "lambda_max",
+                 "loop_seconds")]
 
 
 _lib = None
@@ -119,6 +120,7 @@ class Stats:
     volume: float
     defect: float
     lambda_max: float
+    loop_seconds: float = 0.0
     step: int = 0
 
 
@@ -146,7 +148,7 @@ class State:
             raise ValueError("oracle rejected its arguments")
         self.t, self.step, self.dt = t.value, n.value, dt.value
         return Stats(st.steps, st.bad_step, st.flags, st.t, st.dt, st.dt_min, st.dt_max,
-                     st.volume, st.defect, st.lambda_max, self.step)
+                     st.volume, st.defect, st.lambda_max, st.loop_seconds, self.step)
 
     def trace(self):
         """One step with every intermediate: (dict name -> (ny+2, nx+2) array,

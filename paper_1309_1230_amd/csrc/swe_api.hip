@@ -1,0 +1,530 @@
+// swe_api.hip -- the extern "C" interface of libswe.so (declared in swe.h):
+// argument validation, ownership of the library's device scratch, the
+// asynchronous step loop and error reporting.  No C++ exception crosses the
+// interface.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "swe.h"
+#include "swe_internal.hpp"
+
+using swe::Ctl;
+using swe::Params;
+
+struct swe_handle {
+    Params P{};
+    int dtype = SWE_F64;
+    int path = SWE_PATH_FUSED;
+    int H = 0, gy = 0;
+    size_t elem = 8;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    void* eta = nullptr;       // caller's state (buffer A)
+    void* qx = nullptr;
+    void* qy = nullptr;
+    const void* z = nullptr;
+    void* buf = nullptr;       // library: state buffer B (3 fields) + m
+    Ctl* ctl = nullptr;
+    double* part = nullptr;    // 2 * nparts
+    int nparts = 0;
+    double* hydro = nullptr;   // device copy of (t, q)
+    void* trace = nullptr;     // unfused scratch: 47 padded arrays + zp + mp
+    long long step_host = 0;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_create_err = "no error";
+
+const char* hip_text(hipError_t e) { return hipGetErrorString(e); }
+
+int fail(swe_handle* h, int code, const std::string& msg) {
+    if (h)
+        h->err = msg;
+    else
+        g_create_err = msg;
+    return code;
+}
+
+int hip_fail(swe_handle* h, hipError_t e, const char* what) {
+    return fail(h, SWE_EDEVICE, std::string(what) + ": " + hip_text(e));
+}
+
+size_t field_bytes(const swe_handle* h) {
+    return (size_t)h->P.ny * (size_t)h->P.pitch * h->elem;
+}
+
+void* bufB(const swe_handle* h, int k) {  // k = 0 eta, 1 qx, 2 qy, 3 m
+    return (char*)h->buf + (size_t)k * field_bytes(h);
+}
+
+void* bufA(const swe_handle* h, int k) {
+    return k == 0 ? h->eta : (k == 1 ? h->qx : h->qy);
+}
+
+size_t padded_elems(const swe_handle* h) {
+    return (size_t)(h->P.nx + 2) * (size_t)(h->P.ny + 2);
+}
+
+template <typename T>
+__global__ void k_copy_back(const Ctl* ctl, T* a0, T* a1, T* a2, const T* b0, const T* b1,
+                            const T* b2, size_t n) {
+    if (!(ctl->call_steps & 1)) return;
+    size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; k < n; k += stride) {
+        a0[k] = b0[k];
+        a1[k] = b1[k];
+        a2[k] = b2[k];
+    }
+}
+
+// If the steps of the current call ended in buffer B, copy it back to the
+// caller's arrays (decided on the device, so the host never waits).
+template <typename T>
+hipError_t copy_back(swe_handle* h) {
+    // the last row ends at nx: a pitched caller view may own nothing beyond it
+    const size_t n = (size_t)(h->P.ny - 1) * (size_t)h->P.pitch + (size_t)h->P.nx;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_copy_back<T>, dim3((unsigned)blocks), dim3(256), 0, h->stream, h->ctl,
+                       (T*)bufA(h, 0), (T*)bufA(h, 1), (T*)bufA(h, 2), (const T*)bufB(h, 0),
+                       (const T*)bufB(h, 1), (const T*)bufB(h, 2), n);
+    return hipGetLastError();
+}
+
+// Enqueue the k-th step of a call: sigma follows the global step index, and
+// even k read the caller's arrays (A) and write the library's (B).
+template <typename T>
+hipError_t enqueue_step(swe_handle* h, int64_t k, double t_end, bool unfused) {
+    const int sigma = ((h->step_host + k) & 1) ? -1 : 1;
+    const int s = k & 1;  // 0: A -> B, 1: B -> A
+    const T* src[3];
+    T* dst[3];
+    for (int v = 0; v < 3; ++v) {
+        src[v] = (const T*)(s ? bufB(h, v) : bufA(h, v));
+        dst[v] = (T*)(s ? bufA(h, v) : bufB(h, v));
+    }
+    if (unfused) {
+        swe::UnfusedArgs<T> a;
+        a.P = h->P;
+        a.ctl = h->ctl;
+        a.t_end = t_end;
+        a.eta = src[0]; a.qx = src[1]; a.qy = src[2];
+        a.z = (const T*)h->z;
+        a.eta1 = dst[0]; a.qx1 = dst[1]; a.qy1 = dst[2];
+        a.trace = (T*)h->trace;
+        a.zp = (const T*)h->trace + (size_t)swe::kTraceArrays * padded_elems(h);
+        a.mp = a.zp + padded_elems(h);
+        a.part_def = h->part;
+        a.part_vol = h->part + h->nparts;
+        return swe::launch_unfused_step<T>(a, sigma, h->stream);
+    }
+    swe::FusedArgs<T> a;
+    a.P = h->P;
+    a.ctl = h->ctl;
+    a.t_end = t_end;
+    a.eta = src[0]; a.qx = src[1]; a.qy = src[2];
+    a.z = (const T*)h->z;
+    a.m = (const T*)bufB(h, 3);
+    a.eta1 = dst[0]; a.qx1 = dst[1]; a.qy1 = dst[2];
+    a.part_def = h->part;
+    a.part_vol = h->part + h->nparts;
+    a.gy = h->gy;
+    a.H = h->H;
+    return swe::launch_fused<T>(a, sigma, h->stream);
+}
+
+hipError_t enqueue(swe_handle* h, int64_t k, double t_end, bool unfused) {
+    return h->dtype == SWE_F32 ? enqueue_step<float>(h, k, t_end, unfused)
+                               : enqueue_step<double>(h, k, t_end, unfused);
+}
+
+hipError_t enqueue_copy_back(swe_handle* h) {
+    return h->dtype == SWE_F32 ? copy_back<float>(h) : copy_back<double>(h);
+}
+
+int ensure_trace(swe_handle* h) {
+    if (h->trace) return SWE_OK;
+    const size_t bytes = (size_t)(swe::kTraceArrays + 2) * padded_elems(h) * h->elem;
+    hipError_t e = hipMalloc(&h->trace, bytes);
+    if (e != hipSuccess) {
+        h->trace = nullptr;
+        return fail(h, SWE_ENOMEM, std::string("hipMalloc of the unfused scratch failed: ") +
+                                       hip_text(e));
+    }
+    e = hipMemsetAsync(h->trace, 0, bytes, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "hipMemsetAsync");
+    void* zp = (char*)h->trace + (size_t)swe::kTraceArrays * padded_elems(h) * h->elem;
+    void* mp = (char*)zp + padded_elems(h) * h->elem;
+    e = h->dtype == SWE_F32
+            ? swe::launch_pad_static<float>(h->P, (const float*)h->z, (const float*)bufB(h, 3),
+                                            (float*)zp, (float*)mp, h->stream)
+            : swe::launch_pad_static<double>(h->P, (const double*)h->z,
+                                             (const double*)bufB(h, 3), (double*)zp, (double*)mp,
+                                             h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "padding the static fields");
+    return SWE_OK;
+}
+
+int fill_stats(swe_handle* h, swe_stats* out) {
+    Ctl c;
+    hipError_t e = hipMemcpyAsync(&c, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "reading the control block");
+    h->step_host = c.step;
+    if (out) {
+        std::memset(out, 0, sizeof(*out));
+        out->step = c.step;
+        out->steps = c.call_steps;
+        out->bad_step = c.bad_step;
+        out->flags = c.flags;
+        out->t = c.t;
+        out->dt = c.dt;
+        out->dt_min = c.call_steps > 0 ? c.dt_min : 0.0;
+        out->dt_max = c.dt_max_used;
+        out->volume = c.volume;
+        out->defect = c.defect;
+        out->lambda_max = c.lam_max;
+    }
+    if (c.flags & swe::FLAG_FATAL) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "unstable: flags 0x%x raised at step %lld", c.flags,
+                      (long long)c.bad_step);
+        return fail(h, SWE_EUNSTABLE, buf);
+    }
+    return SWE_OK;
+}
+
+bool is_device_ptr(const void* p, int device) {
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice && at.device == device;
+}
+
+int validate(const swe_config* c, std::string& why) {
+    auto bad = [&](const char* m) {
+        why = m;
+        return SWE_EINVAL;
+    };
+    if (!c) return bad("config is NULL");
+    if (c->nx < 5 || c->ny < 5) return bad("nx and ny must be >= 5");
+    if ((long long)c->nx * (long long)c->ny > (1ll << 31)) return bad("grid larger than 2^31 cells");
+    if (c->dtype != SWE_F32 && c->dtype != SWE_F64) return bad("dtype must be SWE_F32 or SWE_F64");
+    if (c->path != SWE_PATH_FUSED && c->path != SWE_PATH_UNFUSED) return bad("unknown path");
+    if (c->pitch < c->nx) return bad("pitch must be >= nx");
+    if (!(c->dx > 0) || !(c->dy > 0) || !std::isfinite(c->dx) || !std::isfinite(c->dy))
+        return bad("dx and dy must be finite and > 0");
+    if (!(c->g > 0) || !std::isfinite(c->g)) return bad("g must be finite and > 0");
+    if (!(c->cfl > 0) || !(c->cfl <= 1)) return bad("cfl must be in (0, 1]");
+    if (!(c->h_dry >= 0) || !std::isfinite(c->h_dry)) return bad("h_dry must be >= 0");
+    if (!(c->kappa >= 0) || !(c->kappa <= 4)) return bad("kappa must be in [0, 4]");
+    if (!(c->eps_max >= 0) || !(c->eps_max <= 0.25)) return bad("eps_max must be in [0, 0.25]");
+    if (!(c->dt_max > 0) || !std::isfinite(c->dt_max)) return bad("dt_max must be finite and > 0");
+    if (std::isnan(c->dt_fixed) || std::isinf(c->dt_fixed)) return bad("dt_fixed must be finite");
+    if (!std::isfinite(c->t0)) return bad("t0 must be finite");
+    if (c->tile_rows < 0 || c->tile_rows > 65536) return bad("tile_rows out of range");
+    for (int k = 0; k < 4; ++k) {
+        if (c->bc[k] < SWE_BC_WALL || c->bc[k] > SWE_BC_INFLOW) return bad("unknown boundary kind");
+    }
+    if (c->hydro_len < 0 || c->hydro_len > swe::kMaxHydro) return bad("hydro_len out of range");
+    if (c->hydro_len > 0) {
+        if (!c->hydro_t || !c->hydro_q) return bad("hydrograph pointers are NULL");
+        for (int k = 0; k < c->hydro_len; ++k) {
+            if (!std::isfinite(c->hydro_t[k]) || !std::isfinite(c->hydro_q[k]))
+                return bad("hydrograph values must be finite");
+            if (k > 0 && !(c->hydro_t[k] > c->hydro_t[k - 1]))
+                return bad("hydrograph times must increase");
+        }
+    }
+    if (!c->z || !c->n || !c->eta || !c->qx || !c->qy) return bad("a field pointer is NULL");
+    return SWE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int swe_abi_version(void) { return SWE_ABI_VERSION; }
+
+void swe_config_init(swe_config* c) {
+    if (!c) return;
+    std::memset(c, 0, sizeof(*c));
+    c->dtype = SWE_F64;
+    c->path = SWE_PATH_FUSED;
+    c->g = 9.81;
+    c->cfl = 0.5;
+    c->h_dry = 1e-3;
+    c->kappa = 0.5;
+    c->eps_max = 0.25;
+    c->dt_max = 1.0;
+    c->dt_fixed = 0.0;
+    c->t0 = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        c->bc[k] = SWE_BC_WALL;
+        c->inflow_lo[k] = 0;
+        c->inflow_hi[k] = INT32_MAX;
+    }
+}
+
+int swe_create(const swe_config* c, swe_handle** out) {
+    if (!out) return fail(nullptr, SWE_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::string why;
+    int rc = validate(c, why);
+    if (rc) return fail(nullptr, rc, why);
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        return fail(nullptr, SWE_EDEVICE, "no HIP device is available");
+    }
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
+    const void* ptrs[5] = {c->z, c->n, c->eta, c->qx, c->qy};
+    for (const void* p : ptrs)
+        if (!is_device_ptr(p, dev))
+            return fail(nullptr, SWE_EDEVICE, "a field pointer is not device memory of the current device");
+
+    swe_handle* h = new (std::nothrow) swe_handle();
+    if (!h) return fail(nullptr, SWE_ENOMEM, "host allocation failed");
+    h->dtype = c->dtype;
+    h->elem = c->dtype == SWE_F32 ? 4 : 8;
+    h->path = c->path;
+    h->stream = (hipStream_t)c->stream;
+    h->device = dev;
+    h->eta = c->eta;
+    h->qx = c->qx;
+    h->qy = c->qy;
+    h->z = c->z;
+    Params& P = h->P;
+    P.nx = c->nx;
+    P.ny = c->ny;
+    P.pitch = c->pitch;
+    for (int k = 0; k < 4; ++k) {
+        P.bc[k] = c->bc[k];
+        P.lo[k] = c->inflow_lo[k];
+        P.hi[k] = c->inflow_hi[k];
+    }
+    P.hydro_len = c->hydro_len;
+    P.dx = c->dx; P.dy = c->dy; P.g = c->g; P.cfl = c->cfl; P.h_dry = c->h_dry;
+    P.kappa = c->kappa; P.eps_max = c->eps_max; P.dt_max = c->dt_max; P.dt_fixed = c->dt_fixed;
+    P.idx = 1.0 / c->dx;
+    P.idy = 1.0 / c->dy;
+    h->H = c->tile_rows > 0 ? c->tile_rows : 128;
+    h->gy = (c->ny + h->H - 1) / h->H;
+    h->nparts = std::max(swe::fused_blocks(c->nx, c->ny, h->H), swe::scan_partials(c->nx, c->ny));
+
+    auto cleanup = [&](int code) {
+        swe_destroy(h);
+        return code;
+    };
+    if ((e = hipMalloc(&h->buf, 4 * field_bytes(h))) != hipSuccess) {
+        h->buf = nullptr;
+        fail(nullptr, SWE_ENOMEM, std::string("hipMalloc of the state buffer failed: ") + hip_text(e));
+        return cleanup(SWE_ENOMEM);
+    }
+    if ((e = hipMalloc((void**)&h->ctl, sizeof(Ctl))) != hipSuccess ||
+        (e = hipMalloc((void**)&h->part, 2 * sizeof(double) * (size_t)h->nparts)) != hipSuccess) {
+        fail(nullptr, SWE_ENOMEM, std::string("hipMalloc failed: ") + hip_text(e));
+        return cleanup(SWE_ENOMEM);
+    }
+    std::vector<double> hy(2 * (size_t)std::max(1, c->hydro_len), 0.0);
+    for (int k = 0; k < c->hydro_len; ++k) {
+        hy[k] = c->hydro_t[k];
+        hy[c->hydro_len + k] = c->hydro_q[k];
+    }
+    if ((e = hipMalloc((void**)&h->hydro, hy.size() * sizeof(double))) != hipSuccess) {
+        fail(nullptr, SWE_ENOMEM, std::string("hipMalloc failed: ") + hip_text(e));
+        return cleanup(SWE_ENOMEM);
+    }
+    e = hipMemcpyAsync(h->hydro, hy.data(), hy.size() * sizeof(double), hipMemcpyHostToDevice,
+                       h->stream);
+    P.hydro_t = h->hydro;
+    P.hydro_q = h->hydro + std::max(0, c->hydro_len);
+    if (e == hipSuccess) e = hipMemsetAsync(h->part, 0, 2 * sizeof(double) * h->nparts, h->stream);
+    if (e == hipSuccess)
+        e = h->dtype == SWE_F32
+                ? swe::launch_manning_m<float>(P, (const float*)c->n, (float*)bufB(h, 3), h->stream)
+                : swe::launch_manning_m<double>(P, (const double*)c->n, (double*)bufB(h, 3),
+                                                h->stream);
+    if (e == hipSuccess) e = swe::launch_init_ctl(h->ctl, c->t0, 0, 0u, 0.0, h->stream);
+    if (e == hipSuccess)
+        e = h->dtype == SWE_F32
+                ? swe::launch_scan<float>(P, h->ctl, INFINITY, (const float*)c->eta,
+                                          (const float*)c->qx, (const float*)c->qy,
+                                          (const float*)c->z, h->part, h->part + h->nparts, 0,
+                                          h->stream)
+                : swe::launch_scan<double>(P, h->ctl, INFINITY, (const double*)c->eta,
+                                           (const double*)c->qx, (const double*)c->qy,
+                                           (const double*)c->z, h->part, h->part + h->nparts, 0,
+                                           h->stream);
+    if (e == hipSuccess && h->path == SWE_PATH_UNFUSED) {
+        int rc2 = ensure_trace(h);
+        if (rc2) {
+            fail(nullptr, rc2, h->err);
+            return cleanup(rc2);
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        hip_fail(nullptr, e, "swe_create");
+        return cleanup(SWE_EDEVICE);
+    }
+    h->step_host = 0;
+    *out = h;
+    return SWE_OK;
+}
+
+void swe_destroy(swe_handle* h) {
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+    if (h->buf) (void)hipFree(h->buf);
+    if (h->ctl) (void)hipFree(h->ctl);
+    if (h->part) (void)hipFree(h->part);
+    if (h->hydro) (void)hipFree(h->hydro);
+    if (h->trace) (void)hipFree(h->trace);
+    delete h;
+}
+
+int swe_run(swe_handle* h, int64_t nsteps, double t_end, swe_stats* out) {
+    if (!h) return fail(nullptr, SWE_EINVAL, "handle is NULL");
+    if (nsteps < 0) return fail(h, SWE_EINVAL, "nsteps must be >= 0");
+    if (std::isnan(t_end)) return fail(h, SWE_EINVAL, "t_end is NaN");
+    const bool unfused = h->path == SWE_PATH_UNFUSED;
+    hipError_t e = swe::launch_begin_call(h->ctl, h->stream);
+    for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) e = enqueue(h, k, t_end, unfused);
+    if (e == hipSuccess) e = enqueue_copy_back(h);
+    if (e != hipSuccess) return hip_fail(h, e, "launching the step kernels");
+    return fill_stats(h, out);
+}
+
+int swe_step(swe_handle* h, double* dt_used) {
+    if (!h) return fail(nullptr, SWE_EINVAL, "handle is NULL");
+    double dt_before = 0.0;
+    if (dt_used) {
+        Ctl c;
+        hipError_t e = hipMemcpyAsync(&c, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "reading the control block");
+        dt_before = c.dt;
+    }
+    hipError_t e = swe::launch_begin_call(h->ctl, h->stream);
+    if (e == hipSuccess) e = enqueue(h, 0, INFINITY, h->path == SWE_PATH_UNFUSED);
+    if (e == hipSuccess) e = enqueue_copy_back(h);
+    if (e != hipSuccess) return hip_fail(h, e, "launching the step kernels");
+    h->step_host += 1;
+    if (dt_used) {
+        int rc = fill_stats(h, nullptr);
+        *dt_used = dt_before;
+        return rc;
+    }
+    return SWE_OK;
+}
+
+int swe_get_stats(swe_handle* h, swe_stats* out) {
+    if (!h) return fail(nullptr, SWE_EINVAL, "handle is NULL");
+    if (!out) return fail(h, SWE_EINVAL, "out is NULL");
+    return fill_stats(h, out);
+}
+
+size_t swe_trace_bytes(const swe_handle* h) {
+    if (!h) return 0;
+    return (size_t)swe::kTraceArrays * padded_elems(h) * h->elem;
+}
+
+int swe_trace_step(swe_handle* h, void* arrays, size_t bytes, double* scalars) {
+    if (!h) return fail(nullptr, SWE_EINVAL, "handle is NULL");
+    if (!arrays || !scalars) return fail(h, SWE_EINVAL, "arrays or scalars is NULL");
+    if (bytes < swe_trace_bytes(h)) return fail(h, SWE_EINVAL, "trace buffer too small");
+    if (!is_device_ptr(arrays, h->device)) return fail(h, SWE_EINVAL, "arrays is not device memory");
+    int rc = ensure_trace(h);
+    if (rc) return rc;
+    Ctl before, after;
+    hipError_t e = hipMemcpyAsync(&before, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = swe::launch_begin_call(h->ctl, h->stream);
+    if (e == hipSuccess) e = enqueue(h, 0, INFINITY, true);
+    if (e == hipSuccess) e = enqueue_copy_back(h);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(arrays, h->trace, swe_trace_bytes(h), hipMemcpyDeviceToDevice, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&after, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "swe_trace_step");
+    h->step_host = after.step;
+    for (int k = 0; k < 16; ++k) scalars[k] = 0.0;
+    scalars[0] = before.qin0;
+    scalars[1] = before.qin1;
+    scalars[2] = before.rx;
+    scalars[3] = before.ry;
+    scalars[4] = after.last_defect_depth;
+    scalars[5] = after.lam_max;
+    scalars[6] = after.dt;
+    scalars[7] = after.volume;
+    scalars[8] = (double)after.last_step_flags;
+    scalars[9] = (before.step & 1) ? -1.0 : 1.0;
+    scalars[10] = after.t;
+    if (after.flags & swe::FLAG_FATAL) return fail(h, SWE_EUNSTABLE, "unstable step");
+    return SWE_OK;
+}
+
+int swe_save(swe_handle* h, swe_checkpoint* ck) {
+    if (!h || !ck) return fail(h, SWE_EINVAL, "handle or checkpoint is NULL");
+    Ctl c;
+    hipError_t e = hipMemcpyAsync(&c, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "swe_save");
+    std::memset(ck, 0, sizeof(*ck));
+    ck->step = c.step;
+    ck->flags = c.flags;
+    ck->t = c.t;
+    ck->dt = c.dt;
+    ck->defect = c.defect;
+    return SWE_OK;
+}
+
+int swe_load(swe_handle* h, const swe_checkpoint* ck) {
+    if (!h || !ck) return fail(h, SWE_EINVAL, "handle or checkpoint is NULL");
+    if (!std::isfinite(ck->t) || ck->step < 0) return fail(h, SWE_EINVAL, "bad checkpoint");
+    hipError_t e = swe::launch_init_ctl(h->ctl, ck->t, ck->step, ck->flags, ck->defect, h->stream);
+    if (e == hipSuccess)
+        e = h->dtype == SWE_F32
+                ? swe::launch_scan<float>(h->P, h->ctl, INFINITY, (const float*)h->eta,
+                                          (const float*)h->qx, (const float*)h->qy,
+                                          (const float*)h->z, h->part, h->part + h->nparts, 0,
+                                          h->stream)
+                : swe::launch_scan<double>(h->P, h->ctl, INFINITY, (const double*)h->eta,
+                                           (const double*)h->qx, (const double*)h->qy,
+                                           (const double*)h->z, h->part, h->part + h->nparts, 0,
+                                           h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "swe_load");
+    h->step_host = ck->step;
+    return SWE_OK;
+}
+
+const char* swe_last_error(const swe_handle* h) {
+    return h ? h->err.c_str() : g_create_err.c_str();
+}
+
+int swe_probe_copy(void* dst, const void* src, size_t bytes, void* stream) {
+    if (!dst || !src || (bytes % 16) || ((uintptr_t)dst % 16) || ((uintptr_t)src % 16))
+        return fail(nullptr, SWE_EINVAL, "swe_probe_copy: pointers must be 16-byte aligned and bytes a multiple of 16");
+    hipError_t e = swe::launch_copy16(dst, src, bytes / 16, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "swe_probe_copy");
+    return SWE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,301 @@
+// swe_common.hpp -- device-side definitions shared by the fused and the
+// unfused kernels of libswe: the control block that keeps t, dt and the
+// diagnostics resident on the GPU, the problem parameters, the per-face and
+// per-cell formulas of the scheme, wave reductions and the finalisation of a
+// time step (the new dt is computed on the device; the paper copied the state
+// to the host every step for this, §3.1, which is what this layout removes).
+//
+// The discrete scheme (our reading; the paper, §1, fixes the predictor-
+// corrector MacCormack method, explicitness and the sixteen cell-independent
+// sub-steps per step, and defers the equations to a thesis that is not
+// available).  Unknowns eta, qx, qy; h = eta - z; wet <=> h > h_dry.
+//   S1  ghost ring of U^n (eta copied; WALL mirrors the normal discharge,
+//       OPEN copies, INFLOW imposes q_in(t^n) inward with zero tangential).
+//   S2  h = eta - z, r = wet ? 1/h : 0, u = qx*r, v = qy*r.
+//   S3  nu_x = 0.25*(|(eta_E - eta_C) - (eta_C - eta_W)| * r_C), nu_y alike.
+//   S4  eps_f = (wet_L && wet_R) ? min(kappa*max(nu_L, nu_R), eps_max) : 0 on
+//       interior faces, 0 on boundary faces;
+//       D = (eps_E*(U_E-U_C) - eps_W*(U_C-U_W)) + (eps_N*(U_N-U_C) - eps_S*(U_C-U_S)).
+//   S5/S6  face fluxes with the donor on the sigma side (sigma = +1 on even
+//       steps): fm = wet_d ? q_d : 0, (fm, fm*u_d, fm*v_d); pressure
+//       P = (g*(0.5*(h+_L + h+_R)))*(eta_R - eta_L) on interior faces that are
+//       not dry banks.  WALL faces carry nothing; OPEN faces carry the flux of
+//       the adjacent cell; INFLOW faces carry q_in inward with momentum
+//       q_in*(q_in*r_adj).
+//   S7  U* = U^n - dt/dx*(dF + P_x on the sigma face) - dt/dy*(dG + P_y).
+//   S8..S11  the same on U* with -sigma and q_in(t^n + dt).
+//   S12 U^c = 0.5*(U^n + (U* - L_{-sigma}(U*))).   S13 U^d = U^c + D.
+//   S14 point-implicit Manning: q /= 1 + dt*m*|q|/h*h^(-4/3) (m = g n^2).
+//   S15 negative depth clipped (volume recorded), dry cells lose discharge.
+//   S16 lam = (|u|+c)/dx + (|v|+c)/dy over wet cells (c = sqrt(g h)),
+//       dt^{n+1} = min(cfl/max lam, dt_max) (or dt_fixed).
+// Every expression keeps one fixed evaluation order and the code is built
+// without floating-point contraction, so FP64 results are reproducible bit
+// for bit by any implementation of the same order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace swe {
+
+constexpr int kWave = 64;
+constexpr int BC_WALL = 0, BC_OPEN = 1, BC_INFLOW = 2;
+constexpr int EDGE_W = 0, EDGE_E = 1, EDGE_S = 2, EDGE_N = 3;
+constexpr unsigned FLAG_NAN = 1u, FLAG_CLIPPED = 2u, FLAG_BADDT = 4u;
+constexpr unsigned FLAG_FATAL = FLAG_NAN | FLAG_BADDT;
+constexpr int kMaxHydro = 4096;
+
+// Device-resident scalars of one handle.  Written only by the finalisation of
+// a step (one wave, after every block of the step has finished its sweep) and
+// read by every block at the start of the next step.
+struct Ctl {
+    double t;            // t^n
+    double dt;           // dt^n: the step the next launch takes
+    double rx, ry;       // dt/dx, dt/dy
+    double qin0, qin1;   // q_in(t^n), q_in(t^n + dt^n)
+    double defect;       // clipped volume since create
+    double volume;       // sum h dx dy of the current state
+    double lam_max;      // lam_max of the current state
+    double dt_min, dt_max_used;  // over the current host call
+    double last_defect_depth;    // sum of clipped depth of the last step
+    long long step;      // n
+    long long bad_step;  // first step that raised a fatal flag, or -1
+    long long call_steps;
+    unsigned flags;      // OR of all flags
+    unsigned step_flags; // flags raised by the step in flight
+    unsigned last_step_flags;
+    unsigned ticket;     // blocks of the step in flight that have finished
+    unsigned long long lam_bits;  // running max of lam (IEEE bits, lam >= 0)
+};
+
+struct Params {
+    int nx, ny;
+    long long pitch;
+    int bc[4], lo[4], hi[4];
+    int hydro_len;
+    double dx, dy, g, cfl, h_dry, kappa, eps_max, dt_max, dt_fixed;
+    double idx, idy;     // 1/dx, 1/dy
+    const double* hydro_t;   // device copies
+    const double* hydro_q;
+};
+
+// Kind of the boundary face number k along an edge (INFLOW outside its band
+// is a wall).
+__host__ __device__ inline int face_kind(const Params& P, int edge, int k) {
+    int kind = P.bc[edge];
+    if (kind == BC_INFLOW && !(k >= P.lo[edge] && k < P.hi[edge])) return BC_WALL;
+    return kind;
+}
+
+// Piecewise-linear hydrograph, constant outside its points.
+__device__ inline double q_inflow(const Params& P, double t) {
+    int L = P.hydro_len;
+    if (L <= 0) return 0.0;
+    if (t <= P.hydro_t[0]) return P.hydro_q[0];
+    if (t >= P.hydro_t[L - 1]) return P.hydro_q[L - 1];
+    int k = 0;
+    while (k + 1 < L && !(t < P.hydro_t[k + 1])) ++k;
+    double w = (t - P.hydro_t[k]) / (P.hydro_t[k + 1] - P.hydro_t[k]);
+    return P.hydro_q[k] + w * (P.hydro_q[k + 1] - P.hydro_q[k]);
+}
+
+__device__ inline double next_dt(const Params& P, double lam) {
+    if (P.dt_fixed > 0.0) return P.dt_fixed;
+    if (lam > 0.0) {
+        double d = P.cfl / lam;
+        return d < P.dt_max ? d : P.dt_max;
+    }
+    return P.dt_max;
+}
+
+// ------------------------------------------------------------ cell formulas
+
+__device__ __forceinline__ float tfabs(float x) { return __builtin_fabsf(x); }
+__device__ __forceinline__ double tfabs(double x) { return __builtin_fabs(x); }
+__device__ __forceinline__ float tsqrt(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double tsqrt(double x) { return __builtin_sqrt(x); }
+__device__ __forceinline__ float tcbrt(float x) { return cbrtf(x); }
+__device__ __forceinline__ double tcbrt(double x) { return cbrt(x); }
+__device__ __forceinline__ bool tfinite(float x) { return __builtin_isfinite(x); }
+__device__ __forceinline__ bool tfinite(double x) { return __builtin_isfinite(x); }
+
+template <typename T> __device__ __forceinline__ T hpos(T h) { return h > T(0) ? h : T(0); }
+template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+template <typename T> __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
+
+// S2: reciprocal depth of a wet cell, 0 for a dry one.
+template <typename T> __device__ __forceinline__ T recip_depth(T h, T hdry) {
+    return h > hdry ? T(1) / h : T(0);
+}
+
+// S3: curvature switch of the water surface at a cell.
+template <typename T> __device__ __forceinline__ T curv_switch(T eW, T eC, T eE, T rC) {
+    return T(0.25) * (tfabs((eE - eC) - (eC - eW)) * rC);
+}
+
+// S4: dissipation coefficient of an interior face.
+template <typename T>
+__device__ __forceinline__ T face_eps(T hL, T hR, T nuL, T nuR, T hdry, T kappa, T emax) {
+    return (hL > hdry && hR > hdry) ? tmin(kappa * tmax(nuL, nuR), emax) : T(0);
+}
+
+// S5/S6: pressure of an interior face between cells L (low) and R (high).
+template <typename T>
+__device__ __forceinline__ T face_pressure(T eL, T hL, T zL, T eR, T hR, T zR, T hdry, T g) {
+    bool bank = (!(hL > hdry) && zL > eR) || (!(hR > hdry) && zR > eL);
+    return bank ? T(0) : (g * (T(0.5) * (hpos(hL) + hpos(hR)))) * (eR - eL);
+}
+
+// Flux a boundary face carries when the adjacent interior cell has the
+// donor fluxes (fm, fa, fb) (fa: momentum along the face normal... see
+// normal_is_x) and reciprocal depth r.  qs is the signed inflow discharge
+// (positive along +x or +y).  For x faces the normal momentum is the second
+// component, for y faces the third.
+template <typename T>
+__device__ __forceinline__ void boundary_flux(int kind, bool normal_is_x, T fm, T f1, T f2, T qs,
+                                              T r, T& Fm, T& F1, T& F2) {
+    if (kind == BC_WALL) {
+        Fm = T(0); F1 = T(0); F2 = T(0);
+    } else if (kind == BC_OPEN) {
+        Fm = fm; F1 = f1; F2 = f2;
+    } else {
+        Fm = qs;
+        if (normal_is_x) {
+            F1 = qs * (qs * r);
+            F2 = qs * (T(0) * r);
+        } else {
+            F1 = qs * (T(0) * r);
+            F2 = qs * (qs * r);
+        }
+    }
+}
+
+// S14: point-implicit Manning friction of a wet cell with reciprocal depth r.
+template <typename T>
+__device__ __forceinline__ void manning(T dt, T m, T r, T& qx, T& qy) {
+    T s = tsqrt(qx * qx + qy * qy) * r;
+    T k = r * tcbrt(r);
+    T phi = T(1) + ((dt * m) * s) * k;
+    T psi = T(1) / phi;
+    qx = qx * psi;
+    qy = qy * psi;
+}
+
+// S16: characteristic speed sum of a wet cell.
+template <typename T>
+__device__ __forceinline__ T cfl_lambda(T h, T r, T qx, T qy, T g, T idx, T idy) {
+    T u = qx * r, v = qy * r;
+    T c = tsqrt(g * h);
+    return (tfabs(u) + c) * idx + (tfabs(v) + c) * idy;
+}
+
+// Running max of lam that lets a NaN through.
+template <typename T> __device__ __forceinline__ T lam_acc(T acc, T lam) {
+    return !(lam <= acc) ? lam : acc;
+}
+
+__device__ __forceinline__ unsigned long long lam_to_bits(float x) {
+    return (unsigned long long)__float_as_uint(x);
+}
+__device__ __forceinline__ unsigned long long lam_to_bits(double x) {
+    return (unsigned long long)__double_as_longlong(x);
+}
+
+// ------------------------------------------------------------- reductions
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = v + __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        unsigned long long o = __shfl_xor(v, off, kWave);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ unsigned wave_or(unsigned v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Publish one block's contribution to a step: max lam (bits), flags and its
+// defect/volume partial sums (slot `blk`).  Called by every lane of the
+// block's first wave with wave-reduced values.
+__device__ __forceinline__ void publish_partial(Ctl* ctl, double* part_def, double* part_vol,
+                                                int blk, unsigned long long lam_bits,
+                                                unsigned flags, double def, double vol) {
+    if (threadIdx.x == 0) {
+        part_def[blk] = def;
+        part_vol[blk] = vol;
+        if (lam_bits) atomicMax(&ctl->lam_bits, lam_bits);
+        if (flags) atomicOr(&ctl->step_flags, flags);
+    }
+}
+
+// Finalise a step (mode 1) or the initial scan (mode 0): one wave sums the
+// nparts partials in a fixed order, decodes lam_max, computes dt^{n+1} and
+// the inflow values of the next step, advances t and the step counter, and
+// clears the accumulators for the next launch.  Must run after every block
+// of the step has published (a kernel boundary or the ticket protocol).
+__device__ inline void finalize_wave(Ctl* ctl, const Params& P, const double* part_def,
+                                     const double* part_vol, int nparts, bool lam_is_f32,
+                                     int mode) {
+    const int lane = threadIdx.x;
+    double sd = 0.0, sv = 0.0;
+    for (int k = lane; k < nparts; k += kWave) {
+        sd = sd + part_def[k];
+        sv = sv + part_vol[k];
+    }
+    sd = wave_sum(sd);
+    sv = wave_sum(sv);
+    if (lane == 0) {
+        unsigned long long bits = __hip_atomic_load(&ctl->lam_bits, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        double lam = lam_is_f32 ? (double)__uint_as_float((unsigned)bits)
+                                : __longlong_as_double((long long)bits);
+        unsigned sf = __hip_atomic_load(&ctl->step_flags, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+        double dtn = next_dt(P, lam);
+        if (!__builtin_isfinite(lam)) sf |= FLAG_NAN;
+        if (!(dtn > 0.0) || !__builtin_isfinite(dtn)) sf |= FLAG_BADDT;
+        const double area = P.dx * P.dy;
+        if (mode == 1) {
+            double dt_used = ctl->dt;
+            ctl->defect = ctl->defect + sd * area;
+            ctl->last_defect_depth = sd;
+            ctl->t = ctl->t + dt_used;
+            ctl->dt_min = dt_used < ctl->dt_min ? dt_used : ctl->dt_min;
+            ctl->dt_max_used = dt_used > ctl->dt_max_used ? dt_used : ctl->dt_max_used;
+            if ((sf & FLAG_FATAL) && ctl->bad_step < 0) ctl->bad_step = ctl->step;
+            ctl->step = ctl->step + 1;
+            ctl->call_steps = ctl->call_steps + 1;
+        }
+        ctl->flags |= sf;
+        ctl->last_step_flags = sf;
+        ctl->volume = sv * area;
+        ctl->lam_max = lam;
+        ctl->dt = dtn;
+        ctl->rx = dtn / P.dx;
+        ctl->ry = dtn / P.dy;
+        ctl->qin0 = q_inflow(P, ctl->t);
+        ctl->qin1 = q_inflow(P, ctl->t + dtn);
+        ctl->lam_bits = 0ull;
+        ctl->step_flags = 0u;
+        ctl->ticket = 0u;
+    }
+}
+
+// Whether the launch for the current step should do nothing: the run already
+// reached t_end, or an earlier step raised a fatal flag.
+__device__ __forceinline__ bool step_is_noop(const Ctl* ctl, double t_end) {
+    return !(ctl->t < t_end) || (ctl->flags & FLAG_FATAL);
+}
+
+}  // namespace swe

@@ -1,0 +1,88 @@
+// swe_internal.hpp -- launch interfaces between the C ABI layer and the
+// kernels of libswe (not part of the public interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include "swe_common.hpp"
+
+namespace swe {
+
+// Arguments of the fused step kernel.
+template <typename T>
+struct FusedArgs {
+    Params P;
+    Ctl* ctl;
+    double t_end;
+    const T* eta;
+    const T* qx;
+    const T* qy;
+    const T* z;
+    const T* m;
+    T* eta1;
+    T* qx1;
+    T* qy1;
+    double* part_def;   // one slot per workgroup
+    double* part_vol;
+    int gy;             // chunks along y
+    int H;              // output rows per chunk
+};
+
+template <typename T>
+hipError_t launch_fused(const FusedArgs<T>& a, int sigma, hipStream_t s);
+int fused_blocks(int nx, int ny, int H);
+
+// Arguments of the unfused path: the trace block holds the 47 padded arrays
+// in trace order; zp/mp are the padded static fields.
+template <typename T>
+struct UnfusedArgs {
+    Params P;
+    Ctl* ctl;
+    double t_end;
+    const T* eta;       // U^n (pitched)
+    const T* qx;
+    const T* qy;
+    const T* z;         // pitched
+    T* eta1;            // U^{n+1} (pitched)
+    T* qx1;
+    T* qy1;
+    T* trace;           // 47 * (nx+2) * (ny+2)
+    const T* zp;        // padded
+    const T* mp;
+    double* part_def;
+    double* part_vol;
+};
+
+constexpr int kTraceArrays = 47;
+
+template <typename T>
+hipError_t launch_unfused_step(const UnfusedArgs<T>& a, int sigma, hipStream_t s);
+int unfused_partials(int nx, int ny);
+
+// Pad the static fields z and m (= g n^2, already computed) into (nx+2) x
+// (ny+2) arrays whose ghost ring copies the adjacent cell.
+template <typename T>
+hipError_t launch_pad_static(const Params& P, const T* z, const T* m, T* zp, T* mp, hipStream_t s);
+
+// m = g n^2 on the pitched layout.
+template <typename T>
+hipError_t launch_manning_m(const Params& P, const T* n, T* m, hipStream_t s);
+
+// Initial scan: lam_max and volume of the state, then dt^0 (mode 0) -- also
+// the S16 sweep of the unfused path (mode 1).
+template <typename T>
+hipError_t launch_scan(const Params& P, Ctl* ctl, double t_end, const T* eta, const T* qx,
+                       const T* qy, const T* z, double* part_def, double* part_vol, int mode,
+                       hipStream_t s);
+int scan_partials(int nx, int ny);
+
+// Reset the per-call statistics (dt_min, dt_max_used, call_steps).
+hipError_t launch_begin_call(Ctl* ctl, hipStream_t s);
+// Set the control block from host values (t, step, flags, defect) and clear
+// the accumulators.
+hipError_t launch_init_ctl(Ctl* ctl, double t, long long step, unsigned flags, double defect,
+                           hipStream_t s);
+
+// Copy `n16` 16-byte words.
+hipError_t launch_copy16(void* dst, const void* src, size_t n16, hipStream_t s);
+
+}  // namespace swe

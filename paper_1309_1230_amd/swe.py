@@ -1,0 +1,288 @@
+"""Thin ctypes binding of libswe.so (include/swe.h).
+
+Every step of the solver runs in the HIP kernels of libswe.so; this module
+only marshals arguments: it passes PyTorch device tensors' pointers and the
+current HIP stream to the C ABI.  There is no CPU fallback: if the library
+is not built, or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswe.so")
+
+SWE_OK, SWE_EINVAL, SWE_ENOMEM, SWE_EDEVICE, SWE_EUNSTABLE, SWE_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+SWE_F32, SWE_F64 = 1, 2
+SWE_BC_WALL, SWE_BC_OPEN, SWE_BC_INFLOW = 0, 1, 2
+SWE_PATH_FUSED, SWE_PATH_UNFUSED = 0, 1
+FLAG_NAN, FLAG_CLIPPED, FLAG_BADDT = 1, 2, 4
+NTRACE = 47
+TRACE_NAMES = (
+    ["S1.eta", "S1.qx", "S1.qy", "S2.h", "S2.r", "S2.u", "S2.v", "S3.nux", "S3.nuy",
+     "S4.Deta", "S4.Dqx", "S4.Dqy", "S5.Fm", "S5.Fx", "S5.Fy", "S5.Px",
+     "S6.Gm", "S6.Gx", "S6.Gy", "S6.Py", "S7.eta", "S7.qx", "S7.qy",
+     "S9.h", "S9.r", "S9.u", "S9.v", "S10.Fm", "S10.Fx", "S10.Fy", "S10.Px",
+     "S11.Gm", "S11.Gx", "S11.Gy", "S11.Py", "S12.eta", "S12.qx", "S12.qy",
+     "S13.eta", "S13.qx", "S13.qy", "S14.eta", "S14.qx", "S14.qy",
+     "S15.eta", "S15.qx", "S15.qy"])
+SCALAR_NAMES = ["qin_n", "qin_n1", "rx", "ry", "defect_depth", "lam_max", "dt_next",
+                "volume", "flags", "sigma", "t_next"]
+
+
+class SweError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libswe error {code}: {msg}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("path", ctypes.c_int32), ("bc", ctypes.c_int32 * 4),
+                ("inflow_lo", ctypes.c_int32 * 4), ("inflow_hi", ctypes.c_int32 * 4),
+                ("hydro_len", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+                ("pitch", ctypes.c_int64)] + [
+                (f, ctypes.c_double) for f in
+                ("dx", "dy", "g", "cfl", "h_dry", "kappa", "eps_max", "dt_max", "dt_fixed", "t0")] + [
+                ("hydro_t", ctypes.POINTER(ctypes.c_double)),
+                ("hydro_q", ctypes.POINTER(ctypes.c_double)),
+                ("z", ctypes.c_void_p), ("n", ctypes.c_void_p), ("eta", ctypes.c_void_p),
+                ("qx", ctypes.c_void_p), ("qy", ctypes.c_void_p), ("stream", ctypes.c_void_p)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("steps", ctypes.c_int64), ("bad_step", ctypes.c_int64),
+                ("flags", ctypes.c_uint32), ("pad_", ctypes.c_uint32)] + [
+                (f, ctypes.c_double) for f in
+                ("t", "dt", "dt_min", "dt_max", "volume", "defect", "lambda_max")]
+
+
+class Checkpoint(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("flags", ctypes.c_uint32), ("pad_", ctypes.c_uint32),
+                ("t", ctypes.c_double), ("dt", ctypes.c_double), ("defect", ctypes.c_double)]
+
+
+@dataclasses.dataclass
+class Stats:
+    step: int
+    steps: int
+    bad_step: int
+    flags: int
+    t: float
+    dt: float
+    dt_min: float
+    dt_max: float
+    volume: float
+    defect: float
+    lambda_max: float
+
+
+#: every function include/swe.h declares
+EXPORTS = ("swe_abi_version", "swe_config_init", "swe_create", "swe_destroy", "swe_step",
+           "swe_run", "swe_get_stats", "swe_trace_step", "swe_trace_bytes", "swe_save",
+           "swe_load", "swe_last_error", "swe_probe_copy")
+
+_lib = None
+
+
+def lib():
+    """Load libswe.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1309_1230_amd._build` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        H = ctypes.c_void_p
+        L.swe_abi_version.restype = ctypes.c_int
+        L.swe_config_init.argtypes = [ctypes.POINTER(Config)]
+        L.swe_config_init.restype = None
+        L.swe_create.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(H)]
+        L.swe_create.restype = ctypes.c_int
+        L.swe_destroy.argtypes = [H]
+        L.swe_destroy.restype = None
+        L.swe_step.argtypes = [H, ctypes.POINTER(ctypes.c_double)]
+        L.swe_step.restype = ctypes.c_int
+        L.swe_run.argtypes = [H, ctypes.c_int64, ctypes.c_double, ctypes.POINTER(_Stats)]
+        L.swe_run.restype = ctypes.c_int
+        L.swe_get_stats.argtypes = [H, ctypes.POINTER(_Stats)]
+        L.swe_get_stats.restype = ctypes.c_int
+        L.swe_trace_step.argtypes = [H, ctypes.c_void_p, ctypes.c_size_t,
+                                     ctypes.POINTER(ctypes.c_double)]
+        L.swe_trace_step.restype = ctypes.c_int
+        L.swe_trace_bytes.argtypes = [H]
+        L.swe_trace_bytes.restype = ctypes.c_size_t
+        L.swe_save.argtypes = [H, ctypes.POINTER(Checkpoint)]
+        L.swe_save.restype = ctypes.c_int
+        L.swe_load.argtypes = [H, ctypes.POINTER(Checkpoint)]
+        L.swe_load.restype = ctypes.c_int
+        L.swe_last_error.argtypes = [H]
+        L.swe_last_error.restype = ctypes.c_char_p
+        L.swe_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                     ctypes.c_void_p]
+        L.swe_probe_copy.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def last_error(handle=None) -> str:
+    return lib().swe_last_error(handle).decode()
+
+
+def default_config() -> Config:
+    c = Config()
+    lib().swe_config_init(ctypes.byref(c))
+    return c
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Solver:
+    """A libswe handle over caller-owned device tensors (eta, qx, qy are
+    advanced in place; z and n are read)."""
+
+    def __init__(self, z, n, eta, qx, qy, *, dx: float, dy: float, g: float = 9.81,
+                 cfl: float = 0.5, h_dry: float = 1e-3, kappa: float = 0.5, eps_max: float = 0.25,
+                 dt_max: float = 1.0, dt_fixed: float = 0.0, t0: float = 0.0,
+                 bc=(SWE_BC_WALL,) * 4, inflow_lo=(0, 0, 0, 0), inflow_hi=None,
+                 hydro_t=(), hydro_q=(), path: str = "fused", tile_rows: int = 0, stream=None):
+        torch = _torch()
+        fields = (z, n, eta, qx, qy)
+        dt0 = eta.dtype
+        if dt0 not in (torch.float32, torch.float64):
+            raise TypeError("fields must be float32 or float64")
+        for f in fields:
+            if f.dtype != dt0 or f.device != eta.device or f.dim() != 2 or not f.is_cuda:
+                raise TypeError("z, n, eta, qx, qy must be 2-D CUDA tensors of one dtype and device")
+            if f.shape != eta.shape or f.stride(1) != 1 or f.stride(0) != eta.stride(0):
+                raise TypeError("fields must share shape and row pitch, unit stride along x")
+        ny, nx = eta.shape
+        self._keep = list(fields)
+        self.nx, self.ny = nx, ny
+        self.dtype = dt0
+        c = default_config()
+        c.nx, c.ny = nx, ny
+        c.dtype = SWE_F32 if dt0 == torch.float32 else SWE_F64
+        c.path = {"fused": SWE_PATH_FUSED, "unfused": SWE_PATH_UNFUSED}[path]
+        c.pitch = eta.stride(0)
+        c.tile_rows = int(tile_rows)
+        if inflow_hi is None:
+            inflow_hi = (ny, ny, nx, nx)
+        for k in range(4):
+            c.bc[k] = int(bc[k])
+            c.inflow_lo[k] = int(inflow_lo[k])
+            c.inflow_hi[k] = int(inflow_hi[k])
+        c.dx, c.dy, c.g, c.cfl, c.h_dry = float(dx), float(dy), float(g), float(cfl), float(h_dry)
+        c.kappa, c.eps_max, c.dt_max = float(kappa), float(eps_max), float(dt_max)
+        c.dt_fixed, c.t0 = float(dt_fixed), float(t0)
+        ht = (ctypes.c_double * max(1, len(hydro_t)))(*[float(v) for v in hydro_t])
+        hq = (ctypes.c_double * max(1, len(hydro_q)))(*[float(v) for v in hydro_q])
+        if len(hydro_t) != len(hydro_q):
+            raise ValueError("hydro_t and hydro_q differ in length")
+        c.hydro_len = len(hydro_t)
+        c.hydro_t = ctypes.cast(ht, ctypes.POINTER(ctypes.c_double))
+        c.hydro_q = ctypes.cast(hq, ctypes.POINTER(ctypes.c_double))
+        c.z, c.n = z.data_ptr(), n.data_ptr()
+        c.eta, c.qx, c.qy = eta.data_ptr(), qx.data_ptr(), qy.data_ptr()
+        with torch.cuda.device(eta.device):
+            c.stream = _stream_ptr(stream)
+            h = ctypes.c_void_p()
+            rc = lib().swe_create(ctypes.byref(c), ctypes.byref(h))
+        if rc != SWE_OK:
+            raise SweError(rc, last_error(None))
+        self._h = h
+        self.eta, self.qx, self.qy, self.z, self.n = eta, qx, qy, z, n
+
+    @classmethod
+    def from_problem(cls, p, dtype=None, device="cuda", path: str = "fused", tile_rows: int = 0,
+                     stream=None):
+        """Upload a workloads.Problem (float64 numpy arrays) and create a solver."""
+        torch = _torch()
+        dtype = dtype or torch.float64
+        t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(device=device, dtype=dtype).contiguous()
+        return cls(t(p.z), t(p.n), t(p.eta), t(p.qx), t(p.qy), dx=p.dx, dy=p.dy, g=p.g, cfl=p.cfl,
+                   h_dry=p.h_dry, kappa=p.kappa, eps_max=p.eps_max, dt_max=p.dt_max,
+                   dt_fixed=p.dt_fixed, bc=p.bc, inflow_lo=p.inflow_lo, inflow_hi=p.inflow_hi,
+                   hydro_t=p.hydro_t, hydro_q=p.hydro_q, path=path, tile_rows=tile_rows,
+                   stream=stream)
+
+    def _check(self, rc):
+        if rc != SWE_OK:
+            raise SweError(rc, last_error(self._h))
+
+    def run(self, nsteps: int, t_end: float = math.inf, check: bool = True) -> Stats:
+        st = _Stats()
+        rc = lib().swe_run(self._h, int(nsteps), float(t_end), ctypes.byref(st))
+        if check:
+            self._check(rc)
+        return self._stats(st)
+
+    def step(self, sync: bool = True) -> Optional[float]:
+        if sync:
+            d = ctypes.c_double()
+            self._check(lib().swe_step(self._h, ctypes.byref(d)))
+            return d.value
+        self._check(lib().swe_step(self._h, None))
+        return None
+
+    def stats(self) -> Stats:
+        st = _Stats()
+        self._check(lib().swe_get_stats(self._h, ctypes.byref(st)))
+        return self._stats(st)
+
+    @staticmethod
+    def _stats(st) -> Stats:
+        return Stats(st.step, st.steps, st.bad_step, st.flags, st.t, st.dt, st.dt_min, st.dt_max,
+                     st.volume, st.defect, st.lambda_max)
+
+    def trace_step(self):
+        """One unfused step exposing every intermediate: (dict name -> (ny+2,
+        nx+2) device tensor, dict name -> scalar)."""
+        torch = _torch()
+        nbytes = lib().swe_trace_bytes(self._h)
+        buf = torch.empty(NTRACE, self.ny + 2, self.nx + 2, dtype=self.dtype, device=self.eta.device)
+        assert buf.numel() * buf.element_size() == nbytes
+        sc = (ctypes.c_double * 16)()
+        self._check(lib().swe_trace_step(self._h, buf.data_ptr(), nbytes, sc))
+        return ({nm: buf[k] for k, nm in enumerate(TRACE_NAMES)},
+                {nm: sc[k] for k, nm in enumerate(SCALAR_NAMES)})
+
+    def save(self) -> Checkpoint:
+        ck = Checkpoint()
+        self._check(lib().swe_save(self._h, ctypes.byref(ck)))
+        return ck
+
+    def load(self, ck: Checkpoint):
+        self._check(lib().swe_load(self._h, ctypes.byref(ck)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().swe_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def probe_copy(dst, src, stream=None):
+    """Device copy through the library's plain copy kernel (bandwidth probe)."""
+    nbytes = src.numel() * src.element_size()
+    rc = lib().swe_probe_copy(dst.data_ptr(), src.data_ptr(), nbytes, _stream_ptr(stream))
+    if rc != SWE_OK:
+        raise SweError(rc, last_error(None))

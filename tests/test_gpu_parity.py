@@ -1,0 +1,299 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Tolerances.  FP64 results are compared with the maximum relative error
+max |gpu - oracle| / max(|oracle|, s), s = 1 (m for eta, m^2/s for q), at
+most 1e-11; the two sides perform the same correctly rounded operations in
+the same order, so they agree to the last bit except where the friction
+step's cube root (the one libm call besides sqrt) differs by an ulp between
+the GPU and host math libraries.  FP32 state is checked on depth against the
+FP64 oracle: maximum relative error 1e-4 with a floor of 10 h_dry on the dam
+break, and relative L1 error 1e-4 on the wet/dry reservoir workload, where a
+front may legitimately move by one cell under FP32 rounding.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1309_1230_amd import swe
+from paper_1309_1230_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def solver(p, dtype="f64", path="fused", tile_rows=0):
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    return swe.Solver.from_problem(p, dtype=dt, path=path, tile_rows=tile_rows)
+
+
+def state(s):
+    return [t.double().cpu().numpy() for t in (s.eta, s.qx, s.qy)]
+
+
+def max_rel(a, b, floor=1.0):
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), floor)))
+
+
+def oracle_state_from(p, eta, qx, qy, t, step):
+    q = p.copy()
+    q.eta, q.qx, q.qy = eta.copy(), qx.copy(), qy.copy()
+    s = O.State(q, t0=t, step0=step)
+    return s
+
+
+# ------------------------------------------------------------ parity ladder
+
+@pytest.mark.parametrize("dtype", ["f64"])
+def test_trace_ladder_against_oracle(dtype):
+    """Every intermediate array of every sub-step, for three consecutive steps
+    of a rough state with wet, thin and dry cells and all boundary kinds."""
+    p = W.random_valid_state(70, 45, seed=21)
+    note(f"trace ladder {p.name} {dtype}")
+    g = solver(p, dtype, path="unfused")
+    o = O.State(p)
+    assert g.stats().dt == o.dt
+    for step in range(3):
+        ta, ts = g.trace_step()
+        oa, os_ = o.trace()
+        for nm in swe.TRACE_NAMES:
+            a = ta[nm].double().cpu().numpy()
+            b = oa[nm]
+            sub = int(nm.split(".")[0][1:])
+            if step == 0 and sub <= 13:
+                assert np.array_equal(a, b), f"step {step} {nm}: max diff {np.abs(a - b).max()}"
+            else:
+                assert max_rel(a, b) <= 1e-13, f"step {step} {nm}: {max_rel(a, b)}"
+        for nm in ("qin_n", "qin_n1", "rx", "ry", "sigma"):
+            assert ts[nm] == os_[nm], nm
+        for nm in ("lam_max", "dt_next", "t_next", "volume", "defect_depth"):
+            assert ts[nm] == pytest.approx(os_[nm], rel=1e-13, abs=1e-13), nm
+        assert int(ts["flags"]) == int(os_["flags"])
+
+
+# -------------------------------------------------------- fused == unfused
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("tile_rows", [7, 16, 128])
+def test_fused_equals_unfused_bitwise(dtype, tile_rows):
+    """Cell order does not change the result (§1): the fused kernel, at any
+    tile height, reproduces the one-kernel-per-sub-step chain bit for bit."""
+    p = W.random_valid_state(130, 77, seed=5)
+    note(f"fused vs unfused {p.name} {dtype} H={tile_rows}")
+    a = solver(p, dtype, path="fused", tile_rows=tile_rows)
+    b = solver(p, dtype, path="unfused")
+    sa = a.run(6)
+    sb = b.run(6)
+    for x, y in zip(state(a), state(b)):
+        assert np.array_equal(x, y)
+    assert sa.dt == sb.dt and sa.t == sb.t and sa.step == sb.step == 6
+    assert sa.volume == pytest.approx(sb.volume, rel=1e-12)
+    assert sa.defect == pytest.approx(sb.defect, rel=1e-12, abs=1e-12)
+
+
+def test_fused_run_to_run_deterministic():
+    p = W.reservoir_release(nx=300, ny=220, dx=60.0, hills=30, seed=1001)
+    note("run-to-run determinism reservoir300x220")
+    outs = []
+    for _ in range(2):
+        s = solver(p, "f64")
+        st = s.run(40)
+        outs.append((state(s), st.volume, st.defect, st.dt))
+    for x, y in zip(outs[0][0], outs[1][0]):
+        assert np.array_equal(x, y)
+    assert outs[0][1:] == outs[1][1:]
+
+
+# ---------------------------------------------------- end-to-end vs oracle
+
+def test_stoker_128_fp64_matches_oracle():
+    p = W.stoker()
+    note("stoker 128x128 f64 200 steps")
+    g = solver(p, "f64")
+    st = g.run(200)
+    o, ost = O.run(p, 200)
+    for x, y in zip(state(g), (o.eta, o.qx, o.qy)):
+        assert max_rel(x, y) <= 1e-11
+    assert st.t == pytest.approx(ost.t, rel=1e-13)
+    assert st.dt == pytest.approx(ost.dt, rel=1e-13)
+    assert st.step == 200 and st.flags == 0
+
+
+def test_stoker_128_fp32_depth_within_1e4():
+    p = W.stoker()
+    note("stoker 128x128 f32 200 steps")
+    g = solver(p, "f32")
+    g.run(200)
+    o, _ = O.run(p, 200)
+    h_gpu = state(g)[0] - p.z
+    h_orc = o.eta - p.z
+    assert max_rel(h_gpu, h_orc, floor=10 * p.h_dry) <= 1e-4
+
+
+@pytest.mark.parametrize("shape", [(257, 190), (121, 61)])
+def test_reservoir_reduced_fp64_matches_oracle(shape):
+    nx, ny = shape
+    p = W.reservoir_release(nx=nx, ny=ny, dx=20480.0 / nx, hills=200, seed=1001)
+    note(f"reservoir {nx}x{ny} f64 200 steps")
+    g = solver(p, "f64")
+    st = g.run(200)
+    o, ost = O.run(p, 200)
+    for x, y in zip(state(g), (o.eta, o.qx, o.qy)):
+        assert max_rel(x, y) <= 1e-11
+    assert st.defect == pytest.approx(ost.defect, rel=1e-9, abs=1e-6)
+    assert st.volume == pytest.approx(ost.volume, rel=1e-12)
+    assert st.t == pytest.approx(ost.t, rel=1e-12)
+
+
+def test_reservoir_reduced_fp32_depth_l1_within_1e4():
+    p = W.reservoir_release(nx=257, ny=190, dx=20480.0 / 257, hills=200, seed=1001)
+    note("reservoir 257x190 f32 200 steps")
+    g = solver(p, "f32")
+    g.run(200)
+    o, _ = O.run(p, 200)
+    h_gpu = state(g)[0] - p.z
+    h_orc = o.eta - p.z
+    assert np.abs(h_gpu - h_orc).sum() / np.abs(h_orc).sum() <= 1e-4
+
+
+def test_inflow_channel_matches_oracle():
+    p = W.inflow_channel(96, 40, seed=3, q_peak=2.0, dry=True, t_peak=10.0, t_end=30.0)
+    p.inflow_lo = (8, 0, 0, 0)
+    p.inflow_hi = (32, 40, 96, 96)
+    note("inflow channel 96x40 f64 150 steps")
+    g = solver(p, "f64")
+    st = g.run(150)
+    o, ost = O.run(p, 150)
+    for x, y in zip(state(g), (o.eta, o.qx, o.qy)):
+        assert max_rel(x, y) <= 1e-11
+    assert st.volume == pytest.approx(ost.volume, rel=1e-12)
+
+
+@pytest.mark.parametrize("shape", [(5, 5), (61, 9), (60, 129), (121, 130), (64, 5)])
+def test_edge_sizes_match_oracle(shape):
+    nx, ny = shape
+    p = W.random_valid_state(nx, ny, seed=nx * 1000 + ny)
+    note(f"edge size {nx}x{ny} f64 20 steps")
+    for path in ("fused", "unfused"):
+        g = solver(p, "f64", path=path, tile_rows=8)
+        g.run(20)
+        o, _ = O.run(p, 20)
+        for x, y in zip(state(g), (o.eta, o.qx, o.qy)):
+            assert max_rel(x, y) <= 1e-11, path
+
+
+# --------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_lake_at_rest_gpu_bitwise(dtype):
+    p = W.lake_at_rest(200, 150, seed=8, dry_banks=True)
+    note(f"lake at rest 200x150 {dtype} 300 steps")
+    g = solver(p, dtype)
+    e0 = g.eta.clone()
+    st = g.run(300)
+    assert torch.equal(g.eta, e0)
+    assert not torch.any(g.qx) and not torch.any(g.qy)
+    assert st.defect == 0.0
+
+
+def test_closed_basin_mass_gpu():
+    p = W.smooth_wet(192, 160, seed=11)
+    note("closed basin 192x160 f64 200 steps")
+    g = solver(p, "f64")
+    v0 = g.stats().volume
+    st = g.run(200)
+    assert st.defect == 0.0
+    assert abs(st.volume - v0) / v0 < 1e-12
+
+
+# ------------------------------------------------------------ ABI behaviour
+
+def test_nan_state_reports_unstable_and_stops():
+    p = W.smooth_wet(64, 48, seed=1)
+    p.eta[10, 20] = np.nan
+    note("NaN state -> SWE_EUNSTABLE")
+    g = solver(p, "f64")
+    with pytest.raises(swe.SweError) as ei:
+        g.run(5)
+    assert ei.value.code == swe.SWE_EUNSTABLE
+    st = g.run(5, check=False)
+    assert st.flags & swe.FLAG_NAN
+    assert st.steps == 0
+
+
+def test_checkpoint_resume_is_bitwise():
+    p = W.reservoir_release(nx=180, ny=150, dx=100.0, hills=40, seed=1001)
+    note("checkpoint/resume 180x150")
+    g = solver(p, "f64")
+    g.run(31)
+    ck = g.save()
+    saved = [t.clone() for t in (g.eta, g.qx, g.qy)]
+    g.run(20)
+    a = [t.clone() for t in (g.eta, g.qx, g.qy)]
+    sa = g.stats()
+    for t, s in zip((g.eta, g.qx, g.qy), saved):
+        t.copy_(s)
+    g.load(ck)
+    g.run(20)
+    sb = g.stats()
+    for x, y in zip(a, (g.eta, g.qx, g.qy)):
+        assert torch.equal(x, y)
+    assert sa.t == sb.t and sa.dt == sb.dt and sa.step == sb.step
+
+
+def test_t_end_stops_like_oracle():
+    p = W.stoker(nx=96, ny=20, dx=1.0, x_dam=48.0)
+    note("t_end stop 96x20")
+    g = solver(p, "f64")
+    st = g.run(10 ** 4, t_end=3.0)
+    o = O.State(p)
+    ost = o.run(10 ** 4, t_end=3.0)
+    assert st.steps == ost.steps and st.t == ost.t and st.t >= 3.0
+    for x, y in zip(state(g), (o.eta, o.qx, o.qy)):
+        assert max_rel(x, y) <= 1e-11
+
+
+def test_step_matches_run():
+    p = W.random_valid_state(90, 70, seed=4)
+    note("swe_step x5 vs swe_run(5)")
+    a = solver(p, "f64")
+    b = solver(p, "f64")
+    for _ in range(5):
+        a.step()
+    b.run(5)
+    for x, y in zip(state(a), state(b)):
+        assert np.array_equal(x, y)
+
+
+# ---------------------------------------------------- full-size workload
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_full_size_reservoir_step_matches_oracle(dtype):
+    """4096 x 4096, dx = 5 m reservoir release in the benchmark's launch
+    configuration: after 30 GPU steps, one more GPU step is compared over the
+    whole grid with one oracle step from the same state."""
+    p = W.reservoir_release()
+    note(f"full-size reservoir 4096x4096 {dtype}: 30 GPU steps, then 1-step parity")
+    g = solver(p, dtype)
+    st = g.run(30)
+    assert st.flags & swe.FLAG_NAN == 0
+    e, a, b = state(g)
+    o = oracle_state_from(p, e, a, b, st.t, st.step)
+    if dtype == "f64":
+        assert o.dt == st.dt
+    g.run(1)
+    o.run(1)
+    ge, ga, gb = state(g)
+    if dtype == "f64":
+        for x, y in zip((ge, ga, gb), (o.eta, o.qx, o.qy)):
+            assert max_rel(x, y) <= 1e-11
+    else:
+        assert max_rel(ge - p.z, o.eta - p.z, floor=10 * p.h_dry) <= 1e-4
