@@ -81,6 +81,8 @@ def lib():
         L.orc_trace.restype = ctypes.c_int
         L.orc_initial_dt.argtypes = [ctypes.POINTER(_Cfg), dp, dp, dp, dp, dp, dp]
         L.orc_initial_dt.restype = ctypes.c_double
+        L.orc_cbrt3.argtypes = [ctypes.c_double]
+        L.orc_cbrt3.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -195,3 +197,8 @@ def run(problem, nsteps: int, t_end: float = math.inf):
     s = State(problem)
     st = s.run(nsteps, t_end)
     return s, st
+
+
+def cbrt3(x: float) -> float:
+    """The friction step's cube root (exponent-thirding guess, two Halley steps)."""
+    return lib().orc_cbrt3(float(x))

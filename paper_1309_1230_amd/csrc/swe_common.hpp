@@ -25,7 +25,8 @@
 //   S7  U* = U^n - dt/dx*(dF + P_x on the sigma face) - dt/dy*(dG + P_y).
 //   S8..S11  the same on U* with -sigma and q_in(t^n + dt).
 //   S12 U^c = 0.5*(U^n + (U* - L_{-sigma}(U*))).   S13 U^d = U^c + D.
-//   S14 point-implicit Manning: q /= 1 + dt*m*|q|/h*h^(-4/3) (m = g n^2).
+//   S14 point-implicit Manning: q /= 1 + dt*m*|q|/h*h^(-4/3) (m = g n^2),
+//       h^(-4/3) = r*cbrt(r) with the reproducible cube root tcbrt.
 //   S15 negative depth clipped (volume recorded), dry cells lose discharge.
 //   S16 lam = (|u|+c)/dx + (|v|+c)/dy over wet cells (c = sqrt(g h)),
 //       dt^{n+1} = min(cfl/max lam, dt_max) (or dt_fixed).
@@ -115,8 +116,35 @@ __device__ __forceinline__ float tfabs(float x) { return __builtin_fabsf(x); }
 __device__ __forceinline__ double tfabs(double x) { return __builtin_fabs(x); }
 __device__ __forceinline__ float tsqrt(float x) { return __builtin_sqrtf(x); }
 __device__ __forceinline__ double tsqrt(double x) { return __builtin_sqrt(x); }
-__device__ __forceinline__ float tcbrt(float x) { return cbrtf(x); }
-__device__ __forceinline__ double tcbrt(double x) { return cbrt(x); }
+// Cube root of x > 0 used by the friction step: the exponent-thirding guess
+// (integer arithmetic on the IEEE-754 bits, Kahan's cube-root note) refined by
+// two Halley steps y <- y*((t + 2x)/(2t + x)), t = y^3.  Every operation is
+// exact or correctly rounded, so the FP64 result is reproducible bit for bit
+// on any IEEE machine (a math library's cbrt is only faithful to about an ulp
+// and differs between libraries).  Relative error < 7e-15 (FP64), < 3e-7
+// (FP32).
+__device__ __forceinline__ double tcbrt(double x) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    b = b / 3ull + 0x2A9F789300000000ull;
+    double y = __longlong_as_double((long long)b);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double t = (y * y) * y;
+        y = y * ((t + (x + x)) / ((t + t) + x));
+    }
+    return y;
+}
+__device__ __forceinline__ float tcbrt(float x) {
+    unsigned b = __float_as_uint(x);
+    b = b / 3u + 0x2A5137A0u;
+    float y = __uint_as_float(b);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float t = (y * y) * y;
+        y = y * ((t + (x + x)) / ((t + t) + x));
+    }
+    return y;
+}
 __device__ __forceinline__ bool tfinite(float x) { return __builtin_isfinite(x); }
 __device__ __forceinline__ bool tfinite(double x) { return __builtin_isfinite(x); }
 

@@ -303,3 +303,16 @@ def test_radial_dam_break_is_transpose_symmetric():
     assert scale > 0.1
     assert np.abs(s.eta - s.eta.T).max() < 1e-12
     assert np.abs(s.qx - s.qy.T).max() < 1e-12 * scale
+
+
+def test_friction_cube_root_accuracy():
+    """The friction step's cube root (a fixed guess-plus-Halley sequence, so
+    that every implementation reproduces it bit for bit) against numpy's cbrt
+    over the range of reciprocal depths a wet cell can have."""
+    rng = np.random.default_rng(12)
+    xs = np.exp(rng.uniform(np.log(1e-6), np.log(1e6), 20000))
+    xs = np.concatenate([xs, [1.0, 8.0, 27.0, 0.125, 1e3, 1e-3, 2.0 ** -20, 2.0 ** 30]])
+    got = np.array([O.cbrt3(x) for x in xs])
+    assert np.max(np.abs(got / np.cbrt(xs) - 1.0)) < 1e-14
+    assert O.cbrt3(8.0) == pytest.approx(2.0, rel=1e-15)
+    assert O.cbrt3(1e3) == pytest.approx(10.0, rel=1e-15)
