@@ -28,6 +28,38 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "cell-updates/s and % HBM peak (fwd)"
+KERNEL_SOURCES = ("paper_1309_1230_amd/csrc/swe_fused.hip", "paper_1309_1230_amd/csrc/swe_common.hpp")
+TRAFFIC_PROFILE = "profiles/fused_step_reservoir4096_traffic.txt"
+
+
+def kernel_source_hash():
+    """SHA-1 of the fused kernel's sources: a traffic figure measured on other
+    sources no longer describes the kernel and is reported as null."""
+    import hashlib
+    h = hashlib.sha1()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(dtype):
+    """HBM bytes per launch of the fused step from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary, or None when it was taken on other kernel
+    sources (or is absent)."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) == 2 and not line.startswith("#"):
+                vals[parts[0]] = parts[1]
+    if vals.get("source_sha1") != kernel_source_hash():
+        return None
+    v = vals.get(f"{dtype}_traffic_bytes_per_launch")
+    return float(v) if v is not None else None
 
 
 def parse():
@@ -42,6 +74,11 @@ def parse():
                     help="oracle steps timed for the CPU baseline (0: skip)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the other-precision and unfused comparison runs")
+    ap.add_argument("--print-source-hash", action="store_true",
+                    help="print the fused kernel's source hash and exit")
+    ap.add_argument("--probe-copy-mb", type=int, default=0,
+                    help="also run the library's plain copy kernel once over this many MiB "
+                         "(calibrates HBM traffic counters)")
     return ap.parse_args()
 
 
@@ -88,6 +125,9 @@ def cpu_baseline(W, p, nsteps):
 
 def main():
     a = parse()
+    if a.print_source_hash:
+        print(kernel_source_hash())
+        return
     if a.gpus != 1:
         print(f"bench.py: --gpus {a.gpus} requested, but this build measures one GPU only "
               "(the row-slab multi-GPU split is a design, not built); run with --gpus 1",
@@ -100,6 +140,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if a.probe_copy_mb > 0:
+        n = a.probe_copy_mb * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        swe.probe_copy(dst, src)
+        torch.cuda.synchronize()
+        del src, dst
     nx = a.nx
     p = W.reservoir_release(nx=nx, ny=nx, dx=20480.0 / nx)
     cells = p.nx * p.ny
@@ -125,12 +173,13 @@ def main():
         "config": {"workload": f"reservoir release {p.nx}x{p.ny}, dx={p.dx:g} m, 200 hills + 1/f "
                                f"noise, surface 25 m behind x=0.2L, n=0.035, open east, "
                                f"{a.steps} adaptive steps",
-                   "nx": p.nx, "ny": p.ny, "path": "fused", "tile_rows": a.tile_rows or 128,
+                   "nx": p.nx, "ny": p.ny, "path": "fused", "tile_rows": a.tile_rows or "auto",
                    "sim_time_s": st.t},
         "hbm_pct": 100.0 * achieved / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_fused_step",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(a.dtype),
+                     "kernel": f"k_fused_step_{a.dtype}",
+                     "bytes_per_launch_algorithmic": bpc * cells,
                      "bytes_per_cell_update": bpc},
         "wall_s": wall,
     }

@@ -213,6 +213,25 @@ bool is_device_ptr(const void* p, int device) {
     return at.type == hipMemoryTypeDevice && at.device == device;
 }
 
+// Rows per fused workgroup: as many chunks per strip as there are resident
+// wave slots on the device, so the whole grid runs in one round of waves (a
+// partial second round would leave most of the GPU idle), but never fewer
+// than 16 rows (the two-row halo at each chunk end costs (H+4)/H).
+int auto_tile_rows(const swe_handle* h, int dev) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
+    const int per_cu = h->dtype == SWE_F32 ? swe::fused_waves_per_cu<float>()
+                                           : swe::fused_waves_per_cu<double>();
+    const long long slots = (long long)cus * per_cu;
+    const int gx = swe::fused_strips(h->P.nx);
+    if (slots <= 0) return 128;
+    long long gy = slots / gx;
+    if (gy < 1) gy = 1;
+    int H = (int)((h->P.ny + gy - 1) / gy);
+    if (H < 16) H = 16;
+    return H;
+}
+
 int validate(const swe_config* c, std::string& why) {
     auto bad = [&](const char* m) {
         why = m;
@@ -322,7 +341,7 @@ int swe_create(const swe_config* c, swe_handle** out) {
     P.kappa = c->kappa; P.eps_max = c->eps_max; P.dt_max = c->dt_max; P.dt_fixed = c->dt_fixed;
     P.idx = 1.0 / c->dx;
     P.idy = 1.0 / c->dy;
-    h->H = c->tile_rows > 0 ? c->tile_rows : 128;
+    h->H = c->tile_rows > 0 ? c->tile_rows : auto_tile_rows(h, dev);
     h->gy = (c->ny + h->H - 1) / h->H;
     h->nparts = std::max(swe::fused_blocks(c->nx, c->ny, h->H), swe::scan_partials(c->nx, c->ny));
 

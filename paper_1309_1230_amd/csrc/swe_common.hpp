@@ -117,16 +117,16 @@ __device__ __forceinline__ double tfabs(double x) { return __builtin_fabs(x); }
 __device__ __forceinline__ float tsqrt(float x) { return __builtin_sqrtf(x); }
 __device__ __forceinline__ double tsqrt(double x) { return __builtin_sqrt(x); }
 // Cube root of x > 0 used by the friction step: the exponent-thirding guess
-// (integer arithmetic on the IEEE-754 bits, Kahan's cube-root note) refined by
+// (integer arithmetic on the IEEE-754 bits: high word w/3 + 0x2A9F7893, low
+// word 0 in FP64; bits/3 + 0x2A5137A0 in FP32; Kahan's cube-root note) refined by
 // two Halley steps y <- y*((t + 2x)/(2t + x)), t = y^3.  Every operation is
 // exact or correctly rounded, so the FP64 result is reproducible bit for bit
 // on any IEEE machine (a math library's cbrt is only faithful to about an ulp
 // and differs between libraries).  Relative error < 7e-15 (FP64), < 3e-7
 // (FP32).
 __device__ __forceinline__ double tcbrt(double x) {
-    unsigned long long b = (unsigned long long)__double_as_longlong(x);
-    b = b / 3ull + 0x2A9F789300000000ull;
-    double y = __longlong_as_double((long long)b);
+    const unsigned w = (unsigned)__double2hiint(x);
+    double y = __hiloint2double((int)(w / 3u + 0x2A9F7893u), 0);
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const double t = (y * y) * y;
@@ -168,11 +168,14 @@ __device__ __forceinline__ T face_eps(T hL, T hR, T nuL, T nuR, T hdry, T kappa,
     return (hL > hdry && hR > hdry) ? tmin(kappa * tmax(nuL, nuR), emax) : T(0);
 }
 
-// S5/S6: pressure of an interior face between cells L (low) and R (high).
+// S5/S6: pressure of an interior face between cells L (low) and R (high),
+// (g*(0.5*(h+_L + h+_R)))*(eta_R - eta_L).  hg = 0.5*g: halving is exact, so
+// hg*S rounds the same real number as g*(0.5*S) and the two forms agree bit
+// for bit (no underflow is possible at these magnitudes).
 template <typename T>
-__device__ __forceinline__ T face_pressure(T eL, T hL, T zL, T eR, T hR, T zR, T hdry, T g) {
+__device__ __forceinline__ T face_pressure(T eL, T hL, T zL, T eR, T hR, T zR, T hdry, T hg) {
     bool bank = (!(hL > hdry) && zL > eR) || (!(hR > hdry) && zR > eL);
-    return bank ? T(0) : (g * (T(0.5) * (hpos(hL) + hpos(hR)))) * (eR - eL);
+    return bank ? T(0) : (hg * (hpos(hL) + hpos(hR))) * (eR - eL);
 }
 
 // Flux a boundary face carries when the adjacent interior cell has the

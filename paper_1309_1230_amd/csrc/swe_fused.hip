@@ -9,8 +9,9 @@
 // MacCormack pair one) and marches up the rows of a chunk of `H` output rows.
 // Each iteration ingests one row of U^n (eta, qx, qy, z); the y neighbours of
 // every sub-step are earlier rows held in the lane's own registers, and the x
-// neighbours are exchanged between adjacent lanes of the wave, so no LDS
-// barrier is ever needed.  The output row trails the ingested row by two:
+// neighbours come from the adjacent lanes through DPP wavefront shifts (one
+// VALU move per 32 bits, no LDS traffic and no barrier).  The output row
+// trails the ingested row R by two:
 //   row R     : S2 PRIM, S3 switch in x, S4 dissipation in x, S5 x fluxes
 //   row R-1   : S3 switch in y, S6 y face R-1/2 -> S7 predictor U*, S9 PRIM*,
 //               S10 x fluxes of U*
@@ -20,9 +21,10 @@
 // read eta, qx, qy, z, m and write eta, qx, qy (8 words).  Boundary faces are
 // evaluated from the face rules directly (no ghost ring in memory): ghost
 // columns/rows read the adjacent cell, and wall, open and inflow faces take
-// their fluxes from the rules.  dt lives on the device: the block that
-// finishes last (ticket counter) reduces the per-block partials in a fixed
-// order and writes dt^{n+1}.
+// their fluxes from the rules; only strips that touch the west or east edge
+// execute that code.  dt lives on the device: the workgroup that finishes
+// last (ticket counter) reduces the per-workgroup partials in a fixed order
+// and writes dt^{n+1}.
 #include "swe_common.hpp"
 #include "swe_internal.hpp"
 
@@ -30,10 +32,27 @@ namespace swe {
 
 constexpr int kOutW = kWave - 4;   // output columns per strip
 
-__device__ __forceinline__ float sh_dn(float x) { return __shfl_down(x, 1, kWave); }
-__device__ __forceinline__ double sh_dn(double x) { return __shfl_down(x, 1, kWave); }
-__device__ __forceinline__ float sh_up(float x) { return __shfl_up(x, 1, kWave); }
-__device__ __forceinline__ double sh_up(double x) { return __shfl_up(x, 1, kWave); }
+// DPP wavefront shifts: lane l receives the value of lane l+1 (from_east) or
+// l-1 (from_west).  The end lanes (63, resp. 0) receive 0; they are halo
+// lanes whose shifted values feed no output column.
+__device__ __forceinline__ int dpp_from_east(int v) {
+    return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true);   // wave_shl:1
+}
+__device__ __forceinline__ int dpp_from_west(int v) {
+    return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true);   // wave_shr:1
+}
+__device__ __forceinline__ float from_east(float x) {
+    return __int_as_float(dpp_from_east(__float_as_int(x)));
+}
+__device__ __forceinline__ float from_west(float x) {
+    return __int_as_float(dpp_from_west(__float_as_int(x)));
+}
+__device__ __forceinline__ double from_east(double x) {
+    return __hiloint2double(dpp_from_east(__double2hiint(x)), dpp_from_east(__double2loint(x)));
+}
+__device__ __forceinline__ double from_west(double x) {
+    return __hiloint2double(dpp_from_west(__double2hiint(x)), dpp_from_west(__double2loint(x)));
+}
 
 // Workgroup id -> tile id so that each XCD (workgroups are dealt round-robin
 // over the 8 XCDs) receives one contiguous run of tiles: vertically adjacent
@@ -49,230 +68,339 @@ struct XDiv { T m, x, y; };     // x part of the flux divergence (pressure inclu
 template <typename T>
 struct YFace { T m, x, y, p; }; // fluxes through one y face
 
+// Per-wave constants of one step.
+template <typename T>
+struct Consts {
+    T rx, ry, dt, qin0, qin1, hdry, hg, g, kap, emax, idx, idy;
+};
+
+// Override the fluxes of the west (i == 0) or east (i == nx-1) boundary face
+// with the face rules; (fm, fx, fy) are the adjacent cell's donor fluxes.
+template <typename T>
+__device__ __forceinline__ void x_boundary(bool at, int kind, T fm, T fx, T fy, T qs, T r, T& Fm,
+                                           T& Fx, T& Fy) {
+    T bm, bx, by;
+    boundary_flux(kind, true, fm, fx, fy, qs, r, bm, bx, by);
+    Fm = at ? bm : Fm;
+    Fx = at ? bx : Fx;
+    Fy = at ? by : Fy;
+}
+
+// x part of the flux divergence of one row (S5 / S10 and the x pressure of
+// S7 / S12), donor direction DIR.  eN/hN/zN are the neighbour on the DIR
+// side (east for DIR > 0, west otherwise), already shifted in.
+template <typename T, int DIR>
+__device__ __forceinline__ XDiv<T> x_divergence(const Consts<T>& c, T e, T q, T h, T r, T u, T v,
+                                                T z, T eN, T hN, T zN, T qin, bool edge, bool atW,
+                                                bool atE, int kW, int kE) {
+    const T fm = h > c.hdry ? q : T(0);
+    const T fx = fm * u, fy = fm * v;
+    T FmE, FxE, FyE, FmW, FxW, FyW, Ps;
+    if (DIR > 0) {
+        FmE = from_east(fm); FxE = from_east(fx); FyE = from_east(fy);
+        FmW = fm; FxW = fx; FyW = fy;
+        Ps = face_pressure(e, h, z, eN, hN, zN, c.hdry, c.hg);
+    } else {
+        FmE = fm; FxE = fx; FyE = fy;
+        FmW = from_west(fm); FxW = from_west(fx); FyW = from_west(fy);
+        Ps = face_pressure(eN, hN, zN, e, h, z, c.hdry, c.hg);
+    }
+    if (edge) {   // uniform: this strip contains the west or the east edge
+        x_boundary(atE, kE, fm, fx, fy, -qin, r, FmE, FxE, FyE);
+        x_boundary(atW, kW, fm, fx, fy, qin, r, FmW, FxW, FyW);
+        Ps = ((DIR > 0 && atE) || (DIR < 0 && atW)) ? T(0) : Ps;
+    }
+    XDiv<T> d;
+    d.m = FmE - FmW;
+    d.x = (FxE - FxW) + Ps;
+    d.y = FyE - FyW;
+    return d;
+}
+
+// Fluxes through the y face j+1/2 between a lower cell S (row j) and an upper
+// cell N (row j+1), donor direction DIR (S6 / S11).  `bnd` is uniform: the
+// face is the south (j == -1) or north (j == ny-1) boundary face.
+template <typename T, int DIR>
+__device__ __forceinline__ YFace<T> y_face(const Consts<T>& c, bool bnd, bool south, int kS,
+                                           int kN, T eS, T qS, T hS, T rS, T uS, T vS, T zS, T eN,
+                                           T qN, T hN, T rN, T uN, T vN, T zN, T qin) {
+    YFace<T> f;
+    if (!bnd) {
+        const T qd = DIR > 0 ? qN : qS, hd = DIR > 0 ? hN : hS;
+        const T ud = DIR > 0 ? uN : uS, vd = DIR > 0 ? vN : vS;
+        const T fm = hd > c.hdry ? qd : T(0);
+        f.m = fm;
+        f.x = fm * ud;
+        f.y = fm * vd;
+        f.p = face_pressure(eS, hS, zS, eN, hN, zN, c.hdry, c.hg);
+    } else {
+        // the adjacent interior cell is N for the south face, S for the north
+        const T qa = south ? qN : qS, ha = south ? hN : hS, ra = south ? rN : rS;
+        const T ua = south ? uN : uS, va = south ? vN : vS;
+        const T fm = ha > c.hdry ? qa : T(0);
+        boundary_flux(south ? kS : kN, false, fm, fm * ua, fm * va, south ? qin : -qin, ra, f.m,
+                      f.x, f.y);
+        f.p = T(0);
+    }
+    return f;
+}
+
+// State of one wave's march up its chunk: per-lane constants, the rows and
+// faces carried from one iteration to the next, the prefetched row and the
+// running partial sums.  Rows are named relative to the ingested row R.
 template <typename T, int SIG>
-__global__ void __launch_bounds__(kWave)
-k_fused_step(FusedArgs<T> A) {
-    Ctl* ctl = A.ctl;
-    if (step_is_noop(ctl, A.t_end)) return;
-    const Params& P = A.P;
-    const T rx = T(ctl->rx), ry = T(ctl->ry), dt = T(ctl->dt);
-    const T qin0 = T(ctl->qin0), qin1 = T(ctl->qin1);
-    const T hdry = T(P.h_dry), g = T(P.g), kap = T(P.kappa), emax = T(P.eps_max);
-    const T idx = T(P.idx), idy = T(P.idy);
-    const int nx = P.nx, ny = P.ny;
-    const long long pitch = P.pitch;
+struct March {
+    Consts<T> c;
+    const Params* P;
+    const T* __restrict__ eta;
+    const T* __restrict__ qx;
+    const T* __restrict__ qy;
+    const T* __restrict__ zb;
+    const T* __restrict__ mm;
+    T* __restrict__ eta1;
+    T* __restrict__ qx1;
+    T* __restrict__ qy1;
+    long long pitch;
+    int nx, ny, i, ic, y0, yEnd, kS, kN;
+    bool colOut, faceE_interior, atW, atE;
 
-    const int lane = threadIdx.x;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int strip = tile / A.gy, chunk = tile - strip * A.gy;
-    const int x0 = strip * kOutW, y0 = chunk * A.H;
-    const int yEnd = min(y0 + A.H, ny);
-    const int i = x0 - 2 + lane;
-    const int ic = min(max(i, 0), nx - 1);
-    const bool colOut = lane >= 2 && lane < 2 + kOutW && i < nx;
-    const bool faceE_interior = i >= 0 && i <= nx - 2;   // face i+1/2 is interior
-    const int kS = face_kind(P, EDGE_S, ic), kN = face_kind(P, EDGE_N, ic);
-
-    const T* __restrict__ eta = A.eta;
-    const T* __restrict__ qx = A.qx;
-    const T* __restrict__ qy = A.qy;
-    const T* __restrict__ zb = A.z;
-    const T* __restrict__ mm = A.m;
-
-    // Kind of the W and E faces of row j (only used by the lanes at i == 0 and
-    // i == nx-1).
-    auto kindW = [&](int j) { return face_kind(P, EDGE_W, min(max(j, 0), ny - 1)); };
-    auto kindE = [&](int j) { return face_kind(P, EDGE_E, min(max(j, 0), ny - 1)); };
-
-    // x part of the flux divergence of one row (S5 / S10 and the x pressure
-    // of S7 / S12), donor direction dir, inflow discharge qin.
-    auto xdiv = [&](int dir, T e, T q_n, T h, T r, T u, T v, T z, T qin, int kW, int kE) {
-        const T fm = h > hdry ? q_n : T(0);
-        const T fx = fm * u, fy = fm * v;
-        T FmE, FxE, FyE, FmW, FxW, FyW, Ps;
-        if (dir > 0) {
-            FmE = sh_dn(fm); FxE = sh_dn(fx); FyE = sh_dn(fy);
-            FmW = fm; FxW = fx; FyW = fy;
-            const T eR = sh_dn(e), hR = sh_dn(h), zR = sh_dn(z);
-            Ps = face_pressure(e, h, z, eR, hR, zR, hdry, g);
-        } else {
-            FmE = fm; FxE = fx; FyE = fy;
-            FmW = sh_up(fm); FxW = sh_up(fx); FyW = sh_up(fy);
-            const T eL = sh_up(e), hL = sh_up(h), zL = sh_up(z);
-            Ps = face_pressure(eL, hL, zL, e, h, z, hdry, g);
-        }
-        if (i == nx - 1) {
-            boundary_flux(kE, true, fm, fx, fy, -qin, r, FmE, FxE, FyE);
-            if (dir > 0) Ps = T(0);
-        }
-        if (i == 0) {
-            boundary_flux(kW, true, fm, fx, fy, qin, r, FmW, FxW, FyW);
-            if (dir < 0) Ps = T(0);
-        }
-        XDiv<T> d;
-        d.m = FmE - FmW;
-        d.x = (FxE - FxW) + Ps;
-        d.y = FyE - FyW;
-        return d;
-    };
-
-    // Fluxes through the y face j+1/2 between a lower cell S (row j) and an
-    // upper cell N (row j+1), donor direction dir (S6 / S11).
-    auto yface = [&](int j, int dir, T eS, T qS, T hS, T rS, T uS, T vS, T zS, T eN, T qN, T hN,
-                     T rN, T uN, T vN, T zN, T qin) {
-        YFace<T> f;
-        if (j == -1 || j == ny - 1) {
-            // boundary face: the adjacent interior cell is N for the south
-            // face and S for the north face
-            const bool south = j == -1;
-            const T qa = south ? qN : qS, ha = south ? hN : hS, ra = south ? rN : rS;
-            const T ua = south ? uN : uS, va = south ? vN : vS;
-            const T fm = ha > hdry ? qa : T(0);
-            boundary_flux(south ? kS : kN, false, fm, fm * ua, fm * va, south ? qin : -qin, ra,
-                          f.m, f.x, f.y);
-            f.p = T(0);
-        } else {
-            const T qd = dir > 0 ? qN : qS, hd = dir > 0 ? hN : hS;
-            const T ud = dir > 0 ? uN : uS, vd = dir > 0 ? vN : vS;
-            const T fm = hd > hdry ? qd : T(0);
-            f.m = fm;
-            f.x = fm * ud;
-            f.y = fm * vd;
-            f.p = face_pressure(eS, hS, zS, eN, hN, zN, hdry, g);
-        }
-        return f;
-    };
-
-    // ---- carried state (rows relative to the ingested row R)
-    T e1 = 0, a1 = 0, b1 = 0, z1 = 0, h1 = 0, r1 = 0, u1 = 0, v1 = 0;  // U^n row R-1
-    T e2 = 0, a2 = 0, b2 = 0, z2 = 0, h2 = 0;                           // U^n row R-2
+    T e1 = 0, a1 = 0, b1 = 0, z1 = 0, h1 = 0, r1 = 0;   // U^n row R-1
+    T e2 = 0, a2 = 0, b2 = 0, z2 = 0, h2 = 0;           // U^n row R-2
     T nuy2 = 0;                      // nu_y(R-2)
     T dx1m = 0, dx1a = 0, dx1b = 0;  // x dissipation of row R-1
     T dx2m = 0, dx2a = 0, dx2b = 0;  // x dissipation of row R-2
     T phm = 0, pha = 0, phb = 0;     // y dissipation flux through face (R-3)+1/2
     XDiv<T> A1 = {0, 0, 0};          // predictor x part of row R-1
     YFace<T> G1 = {0, 0, 0, 0};      // predictor y face (R-2)+1/2
-    T se2 = 0, sa2 = 0, sb2 = 0, sh2 = 0, sr2 = 0, su2 = 0, sv2 = 0;  // U* row R-2
+    T se2 = 0, sa2 = 0, sb2 = 0, sh2 = 0, sr2 = 0;  // U* row R-2
     XDiv<T> B2 = {0, 0, 0};          // corrector x part of row R-2
     YFace<T> H1 = {0, 0, 0, 0};      // corrector y face (R-3)+1/2
+    // Prefetched rows, double-buffered: the iteration that consumes slot S
+    // loads the next row into slot 1-S, so a loaded register is read by the
+    // next iteration directly and no copy (which would have to wait for the
+    // load) sits on the loop's back edge.
+    T pe[2] = {0, 0}, pa[2] = {0, 0}, pb[2] = {0, 0}, pz[2] = {0, 0}, pm[2] = {0, 0};
 
     double vol = 0.0, def = 0.0;
     T lmax = T(0);
     unsigned flags = 0u;
 
-    // software prefetch of the first ingested row
-    auto rowoff = [&](int R) {
+    __device__ __forceinline__ long long rowoff(int R) const {
         return (long long)min(max(R, 0), ny - 1) * pitch + ic;
-    };
-    long long off = rowoff(y0 - 2);
-    T ne = eta[off], na = qx[off], nb = qy[off], nz = zb[off];
-    T nm = T(0);
+    }
 
-    for (int R = y0 - 2; R <= yEnd + 1; ++R) {
-        const T e0 = ne, a0 = na, b0 = nb, z0 = nz;
-        const T m2 = nm;                    // m of row R-2
-        {
-            const long long o = rowoff(R + 1);
-            ne = eta[o]; na = qx[o]; nb = qy[o]; nz = zb[o];
-            nm = mm[rowoff(R - 1)];
+    template <int S>
+    __device__ __forceinline__ void prefetch(int R) {
+        const long long o = rowoff(R);
+        pe[S] = eta[o]; pa[S] = qx[o]; pb[S] = qy[o]; pz[S] = zb[o];
+    }
+
+    // One iteration of the march, ingesting row R from prefetch slot SLOT.
+    // EDGE: the strip holds the west or east edge; BND: a y face of this
+    // iteration may be a boundary face (otherwise 2 <= R <= ny-2), and then
+    // `out` says whether row R-2 is an output row of the chunk (always so
+    // when !BND).
+    template <bool EDGE, bool BND, int SLOT>
+    __device__ __forceinline__ void iter(int R, bool out) {
+        const T e0 = pe[SLOT], a0 = pa[SLOT], b0 = pb[SLOT], z0 = pz[SLOT];
+        const T m2 = pm[SLOT];              // m of row R-2
+        prefetch<1 - SLOT>(R + 1);
+        pm[1 - SLOT] = mm[rowoff(R - 1)];
+        int kW0 = BC_WALL, kE0 = BC_WALL, kW1 = BC_WALL, kE1 = BC_WALL;
+        if (EDGE) {
+            const int Rc = min(max(R, 0), ny - 1), R1c = min(max(R - 1, 0), ny - 1);
+            kW0 = face_kind(*P, EDGE_W, Rc); kE0 = face_kind(*P, EDGE_E, Rc);
+            kW1 = face_kind(*P, EDGE_W, R1c); kE1 = face_kind(*P, EDGE_E, R1c);
         }
+
         // ---- S2 on row R
         const T h0 = e0 - z0;
-        const T r0 = recip_depth(h0, hdry);
+        T r0 = T(0);
+        if (h0 > c.hdry) r0 = T(1) / h0;
         const T u0 = a0 * r0, v0 = b0 * r0;
 
         // ---- S3/S4 in x on row R
-        const T eE = sh_dn(e0), eW = sh_up(e0);
+        const T eE = from_east(e0), eW = from_west(e0);
+        const T hE = from_east(h0);
         const T nux0 = curv_switch(eW, e0, eE, r0);
-        const T nuxE = sh_dn(nux0), hE = sh_dn(h0);
-        const T aE = sh_dn(a0), bE = sh_dn(b0);
-        const T epsE = faceE_interior ? face_eps(h0, hE, nux0, nuxE, hdry, kap, emax) : T(0);
-        const T fxm = epsE * (eE - e0), fxa = epsE * (aE - a0), fxb = epsE * (bE - b0);
-        const T dx0m = fxm - sh_up(fxm), dx0a = fxa - sh_up(fxa), dx0b = fxb - sh_up(fxb);
+        const T nuxE = from_east(nux0);
+        const T epsE = faceE_interior ? face_eps(h0, hE, nux0, nuxE, c.hdry, c.kap, c.emax) : T(0);
+        const T fdm = epsE * (eE - e0);
+        const T fda = epsE * (from_east(a0) - a0);
+        const T fdb = epsE * (from_east(b0) - b0);
+        const T dx0m = fdm - from_west(fdm), dx0a = fda - from_west(fda),
+                dx0b = fdb - from_west(fdb);
 
         // ---- S5 (+ x pressure of S7) on row R
-        const XDiv<T> A0 = xdiv(SIG, e0, a0, h0, r0, u0, v0, z0, qin0, kindW(R), kindE(R));
+        XDiv<T> A0;
+        if (SIG > 0)
+            A0 = x_divergence<T, 1>(c, e0, a0, h0, r0, u0, v0, z0, eE, hE, from_east(z0), c.qin0,
+                                    EDGE, atW, atE, kW0, kE0);
+        else
+            A0 = x_divergence<T, -1>(c, e0, a0, h0, r0, u0, v0, z0, eW, from_west(h0),
+                                     from_west(z0), c.qin0, EDGE, atW, atE, kW0, kE0);
 
         // ---- S3 in y at row R-1, S4 in y through face (R-2)+1/2
         const T nuy1 = curv_switch(e2, e1, e0, r1);
-        const int jf = R - 2;   // face between rows R-2 and R-1
-        const T epsN = (jf >= 0 && jf <= ny - 2) ? face_eps(h2, h1, nuy2, nuy1, hdry, kap, emax)
-                                                 : T(0);
+        const bool fInt = !BND || (R - 2 >= 0 && R - 2 <= ny - 2);
+        const T epsN = fInt ? face_eps(h2, h1, nuy2, nuy1, c.hdry, c.kap, c.emax) : T(0);
         const T pnm = epsN * (e1 - e2), pna = epsN * (a1 - a2), pnb = epsN * (b1 - b2);
-        const T Dm = dx2m + (pnm - phm), Da = dx2a + (pna - pha), Db = dx2b + (pnb - phb);
 
         // ---- S6 through face (R-1)+1/2, S7 predictor of row R-1
-        const YFace<T> G0 = yface(R - 1, SIG, e1, b1, h1, r1, u1, v1, z1, e0, b0, h0, r0, u0, v0,
-                                  z0, qin0);
+        const bool bndG = BND && ((R - 1 == -1) || (R - 1 == ny - 1));
+        const YFace<T> G0 = y_face<T, SIG>(c, bndG, R - 1 == -1, kS, kN, e1, b1, h1, r1,
+                                           a1 * r1, b1 * r1, z1, e0, b0, h0, r0, u0, v0, z0,
+                                           c.qin0);
         const T pys = SIG > 0 ? G0.p : G1.p;
-        const T se1 = (e1 - rx * A1.m) - ry * (G0.m - G1.m);
-        const T sa1 = (a1 - rx * A1.x) - ry * (G0.x - G1.x);
-        const T sb1 = (b1 - rx * A1.y) - ry * ((G0.y - G1.y) + pys);
+        const T se1 = (e1 - c.rx * A1.m) - c.ry * (G0.m - G1.m);
+        const T sa1 = (a1 - c.rx * A1.x) - c.ry * (G0.x - G1.x);
+        const T sb1 = (b1 - c.rx * A1.y) - c.ry * ((G0.y - G1.y) + pys);
 
         // ---- S9 on U*(R-1), S10 on U*(R-1)
         const T sh1 = se1 - z1;
-        const T sr1 = recip_depth(sh1, hdry);
+        T sr1 = T(0);
+        if (sh1 > c.hdry) sr1 = T(1) / sh1;
         const T su1 = sa1 * sr1, sv1 = sb1 * sr1;
-        const XDiv<T> B1 = xdiv(-SIG, se1, sa1, sh1, sr1, su1, sv1, z1, qin1, kindW(R - 1),
-                                kindE(R - 1));
+        XDiv<T> B1;
+        if (SIG > 0)   // corrector donor direction -1: neighbour on the west
+            B1 = x_divergence<T, -1>(c, se1, sa1, sh1, sr1, su1, sv1, z1, from_west(se1),
+                                     from_west(sh1), from_west(z1), c.qin1, EDGE, atW, atE, kW1,
+                                     kE1);
+        else
+            B1 = x_divergence<T, 1>(c, se1, sa1, sh1, sr1, su1, sv1, z1, from_east(se1),
+                                    from_east(sh1), from_east(z1), c.qin1, EDGE, atW, atE, kW1,
+                                    kE1);
 
-        // ---- S11 through face (R-2)+1/2, S12 corrector of row R-2
-        const YFace<T> H0 = yface(R - 2, -SIG, se2, sb2, sh2, sr2, su2, sv2, z2, se1, sb1, sh1,
-                                  sr1, su1, sv1, z1, qin1);
-        const T pcs = -SIG > 0 ? H0.p : H1.p;
-        const T ce = T(0.5) * (e2 + ((se2 - rx * B2.m) - ry * (H0.m - H1.m)));
-        const T ca = T(0.5) * (a2 + ((sa2 - rx * B2.x) - ry * (H0.x - H1.x)));
-        const T cb = T(0.5) * (b2 + ((sb2 - rx * B2.y) - ry * ((H0.y - H1.y) + pcs)));
+        // ---- S11 through face (R-2)+1/2
+        const bool bndH = BND && ((R - 2 == -1) || (R - 2 == ny - 1));
+        const YFace<T> H0 = y_face<T, -SIG>(c, bndH, R - 2 == -1, kS, kN, se2, sb2, sh2, sr2,
+                                            sa2 * sr2, sb2 * sr2, z2, se1, sb1, sh1, sr1, su1, sv1,
+                                            z1, c.qin1);
 
-        // ---- S13 .. S16 on row R-2
-        const int jo = R - 2;
-        if (jo >= y0 && jo < yEnd && colOut) {
+        if (!BND || out) {
+            // ---- S4 total, S12 corrector, S13 .. S16 on row R-2
+            const T Dm = dx2m + (pnm - phm), Da = dx2a + (pna - pha), Db = dx2b + (pnb - phb);
+            const T pcs = -SIG > 0 ? H0.p : H1.p;
+            const T ce = T(0.5) * (e2 + ((se2 - c.rx * B2.m) - c.ry * (H0.m - H1.m)));
+            const T ca = T(0.5) * (a2 + ((sa2 - c.rx * B2.x) - c.ry * (H0.x - H1.x)));
+            const T cb = T(0.5) * (b2 + ((sb2 - c.rx * B2.y) - c.ry * ((H0.y - H1.y) + pcs)));
             T e = ce + Dm, a = ca + Da, b = cb + Db;
             T h = e - z2;
-            T r = T(0);
-            if (h > hdry) {
-                r = T(1) / h;
-                manning(dt, m2, r, a, b);
-            }
-            if (h < T(0)) {
-                def = def + (0.0 - (double)h);
-                e = z2;
-                flags |= FLAG_CLIPPED;
-            }
-            h = e - z2;
-            if (!(h > hdry)) {
+            T lam = T(0);
+            if (h > c.hdry) {
+                const T r = T(1) / h;
+                manning(c.dt, m2, r, a, b);
+                // wet stays wet through S15 (h is unchanged), so S16 uses r
+                lam = cfl_lambda(h, r, a, b, c.g, c.idx, c.idy);
+            } else {
+                if (h < T(0)) {
+                    def = def + (colOut ? 0.0 - (double)h : 0.0);
+                    e = z2;
+                    flags |= colOut ? FLAG_CLIPPED : 0u;
+                    h = e - z2;
+                }
                 a = T(0);
                 b = T(0);
-            } else {
-                lmax = lam_acc(lmax, cfl_lambda(h, r, a, b, g, idx, idy));
             }
-            if (!tfinite(e) || !tfinite(a) || !tfinite(b)) flags |= FLAG_NAN;
-            vol = vol + (double)h;
-            const long long so = (long long)jo * pitch + i;
-            A.eta1[so] = e;
-            A.qx1[so] = a;
-            A.qy1[so] = b;
+            if (colOut) {
+                lmax = lam_acc(lmax, lam);
+                if (!tfinite(e) || !tfinite(a) || !tfinite(b)) flags |= FLAG_NAN;
+                vol = vol + (double)h;
+                const long long so = (long long)(R - 2) * pitch + i;
+                eta1[so] = e;
+                qx1[so] = a;
+                qy1[so] = b;
+            }
         }
 
         // ---- rotate the carried rows
         e2 = e1; a2 = a1; b2 = b1; z2 = z1; h2 = h1;
-        e1 = e0; a1 = a0; b1 = b0; z1 = z0; h1 = h0; r1 = r0; u1 = u0; v1 = v0;
+        e1 = e0; a1 = a0; b1 = b0; z1 = z0; h1 = h0; r1 = r0;
         nuy2 = nuy1;
         dx2m = dx1m; dx2a = dx1a; dx2b = dx1b;
         dx1m = dx0m; dx1a = dx0a; dx1b = dx0b;
         phm = pnm; pha = pna; phb = pnb;
         A1 = A0;
         G1 = G0;
-        se2 = se1; sa2 = sa1; sb2 = sb1; sh2 = sh1; sr2 = sr1; su2 = su1; sv2 = sv1;
+        se2 = se1; sa2 = sa1; sb2 = sb1; sh2 = sh1; sr2 = sr1;
         B2 = B1;
         H1 = H0;
     }
 
-    // ---- block partials, then the last block finalises the step
-    vol = wave_sum(vol);
-    def = wave_sum(def);
-    const unsigned long long lb = wave_max_u64(lam_to_bits(lmax));
-    flags = wave_or(flags);
+    template <bool EDGE>
+    __device__ __forceinline__ void run() {
+        prefetch<0>(y0 - 2);
+        // rows y0-2 .. y0+1 only fill the pipeline: no output row yet; the
+        // iteration at row R reads slot (R - y0) mod 2
+        for (int R = y0 - 2; R < y0 + 2; R += 2) {
+            iter<EDGE, true, 0>(R, false);
+            iter<EDGE, true, 1>(R + 1, false);
+        }
+        int R = y0 + 2;
+        const int lim = min(yEnd + 1, ny - 2);   // rows whose faces are all interior
+        for (; R + 1 <= lim; R += 2) {
+            iter<EDGE, false, 0>(R, true);
+            iter<EDGE, false, 1>(R + 1, true);
+        }
+        for (; R <= yEnd + 1; R += 2) {
+            iter<EDGE, true, 0>(R, true);
+            if (R + 1 <= yEnd + 1) iter<EDGE, true, 1>(R + 1, true);
+        }
+    }
+};
+
+template <typename T, int SIG>
+__device__ __forceinline__ void fused_step(FusedArgs<T>& A) {
+    Ctl* ctl = A.ctl;
+    if (step_is_noop(ctl, A.t_end)) return;
+    const Params& P = A.P;
+    March<T, SIG> M;
+    M.c.rx = T(ctl->rx); M.c.ry = T(ctl->ry); M.c.dt = T(ctl->dt);
+    M.c.qin0 = T(ctl->qin0); M.c.qin1 = T(ctl->qin1);
+    M.c.hdry = T(P.h_dry); M.c.g = T(P.g); M.c.hg = T(0.5 * P.g);
+    M.c.kap = T(P.kappa); M.c.emax = T(P.eps_max);
+    M.c.idx = T(P.idx); M.c.idy = T(P.idy);
+    M.P = &A.P;
+    M.eta = A.eta; M.qx = A.qx; M.qy = A.qy; M.zb = A.z; M.mm = A.m;
+    M.eta1 = A.eta1; M.qx1 = A.qx1; M.qy1 = A.qy1;
+    M.nx = P.nx;
+    M.ny = P.ny;
+    M.pitch = P.pitch;
+
+    const int lane = threadIdx.x;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int pos = tile / A.gy, chunk = tile - pos * A.gy;
+    // strips enumerated by residue class mod 8: each XCD's contiguous run of
+    // tiles covers strips spread over the whole domain
+    const int gx = (P.nx + kOutW - 1) / kOutW;
+    int strip = pos, base = 0;
+    for (int r = 0; r < 8; ++r) {
+        const int n_r = gx > r ? (gx - r + 7) / 8 : 0;
+        if (pos < base + n_r) { strip = r + 8 * (pos - base); break; }
+        base += n_r;
+    }
+    const int x0 = strip * kOutW;
+    M.y0 = chunk * A.H;
+    M.yEnd = min(M.y0 + A.H, P.ny);
+    M.i = x0 - 2 + lane;
+    M.ic = min(max(M.i, 0), P.nx - 1);
+    M.colOut = lane >= 2 && lane < 2 + kOutW && M.i < P.nx;
+    M.faceE_interior = M.i >= 0 && M.i <= P.nx - 2;   // face i+1/2 is interior
+    M.atW = M.i == 0;
+    M.atE = M.i == P.nx - 1;
+    M.kS = face_kind(P, EDGE_S, M.ic);
+    M.kN = face_kind(P, EDGE_N, M.ic);
+    const bool edge = x0 - 2 <= 0 || x0 + kWave - 2 >= P.nx;  // uniform
+    if (edge)
+        M.template run<true>();
+    else
+        M.template run<false>();
+
+    // ---- workgroup partials, then the last workgroup finalises the step
+    const double vol = wave_sum(M.vol);
+    const double def = wave_sum(M.def);
+    const unsigned long long lb = wave_max_u64(lam_to_bits(M.lmax));
+    const unsigned flags = wave_or(M.flags);
     publish_partial(ctl, A.part_def, A.part_vol, tile, lb, flags, def, vol);
     __threadfence();
     unsigned ticket = 0;
@@ -284,14 +412,36 @@ k_fused_step(FusedArgs<T> A) {
     }
 }
 
+// The two precisions get their own entry points so that each can be given
+// the register budget of its best occupancy: FP64 holds about twice the live
+// state and runs at 2 waves per SIMD (256 VGPRs), FP32 at 3 (168 VGPRs).
+template <int SIG>
+__global__ void __launch_bounds__(kWave, 2) k_fused_step_f64(FusedArgs<double> A) {
+    fused_step<double, SIG>(A);
+}
+template <int SIG>
+__global__ void __launch_bounds__(kWave, 3) k_fused_step_f32(FusedArgs<float> A) {
+    fused_step<float, SIG>(A);
+}
+
+template <typename T, int SIG>
+constexpr auto fused_kernel() {
+    if constexpr (sizeof(T) == 8)
+        return &k_fused_step_f64<SIG>;
+    else
+        return &k_fused_step_f32<SIG>;
+}
+
 template <typename T>
 hipError_t launch_fused(const FusedArgs<T>& a, int sigma, hipStream_t s) {
     const int gx = (a.P.nx + kOutW - 1) / kOutW;
     const int nblk = gx * a.gy;
+    const auto kp = fused_kernel<T, 1>();
+    const auto km = fused_kernel<T, -1>();
     if (sigma > 0)
-        hipLaunchKernelGGL((k_fused_step<T, 1>), dim3(nblk), dim3(kWave), 0, s, a);
+        hipLaunchKernelGGL(kp, dim3(nblk), dim3(kWave), 0, s, a);
     else
-        hipLaunchKernelGGL((k_fused_step<T, -1>), dim3(nblk), dim3(kWave), 0, s, a);
+        hipLaunchKernelGGL(km, dim3(nblk), dim3(kWave), 0, s, a);
     return hipGetLastError();
 }
 
@@ -301,7 +451,20 @@ int fused_blocks(int nx, int ny, int H) {
     return gx * gy;
 }
 
+int fused_strips(int nx) { return (nx + kOutW - 1) / kOutW; }
+
+template <typename T>
+int fused_waves_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fused_kernel<T, 1>(), kWave,
+                                                     0) != hipSuccess)
+        return 0;
+    return nb;
+}
+
 template hipError_t launch_fused<float>(const FusedArgs<float>&, int, hipStream_t);
 template hipError_t launch_fused<double>(const FusedArgs<double>&, int, hipStream_t);
+template int fused_waves_per_cu<float>();
+template int fused_waves_per_cu<double>();
 
 }  // namespace swe

@@ -30,6 +30,10 @@ struct FusedArgs {
 template <typename T>
 hipError_t launch_fused(const FusedArgs<T>& a, int sigma, hipStream_t s);
 int fused_blocks(int nx, int ny, int H);
+int fused_strips(int nx);
+// Resident fused workgroups (one wave each) per compute unit, or 0.
+template <typename T>
+int fused_waves_per_cu();
 
 // Arguments of the unfused path: the trace block holds the 47 padded arrays
 // in trace order; zp/mp are the padded static fields.

@@ -180,7 +180,7 @@ __global__ void k_s4(UnfusedArgs<T> a) {
 template <typename T>
 __device__ __forceinline__ void face(int kind, int dir, bool ghost_is_R, long long L, long long R,
                                      const T* E, const T* QN, const T* H, const T* U, const T* V,
-                                     const T* Z, T hdry, T g, T out[4]) {
+                                     const T* Z, T hdry, T hg, T out[4]) {
     if (kind == BC_WALL) {
         out[0] = out[1] = out[2] = out[3] = T(0);
         return;
@@ -197,7 +197,7 @@ __device__ __forceinline__ void face(int kind, int dir, bool ghost_is_R, long lo
     out[0] = fm;
     out[1] = fm * U[dn];
     out[2] = fm * V[dn];
-    out[3] = kind < 0 ? face_pressure(E[L], H[L], Z[L], E[R], H[R], Z[R], hdry, g) : T(0);
+    out[3] = kind < 0 ? face_pressure(E[L], H[L], Z[L], E[R], H[R], Z[R], hdry, hg) : T(0);
 }
 
 // S5 / S10: x faces i = -1 .. nx-1 of rows 0 .. ny-1.
@@ -212,7 +212,7 @@ __global__ void k_xflux(UnfusedArgs<T> a, int dir, int src, int prim, int dst) {
     T o[4];
     face(kind, dir, i == d.nx - 1, d.at(i, j), d.at(i + 1, j), arr(a.trace, d, src),
          arr(a.trace, d, src + 1), arr(a.trace, d, prim), arr(a.trace, d, prim + 2),
-         arr(a.trace, d, prim + 3), a.zp, T(a.P.h_dry), T(a.P.g), o);
+         arr(a.trace, d, prim + 3), a.zp, T(a.P.h_dry), T(0.5 * a.P.g), o);
     const long long s = d.at(i, j);
     for (int v = 0; v < 4; ++v) arr(a.trace, d, dst + v)[s] = o[v];
 }
@@ -229,7 +229,7 @@ __global__ void k_yflux(UnfusedArgs<T> a, int dir, int src, int prim, int dst) {
     T o[4];
     face(kind, dir, j == d.ny - 1, d.at(i, j), d.at(i, j + 1), arr(a.trace, d, src),
          arr(a.trace, d, src + 2), arr(a.trace, d, prim), arr(a.trace, d, prim + 2),
-         arr(a.trace, d, prim + 3), a.zp, T(a.P.h_dry), T(a.P.g), o);
+         arr(a.trace, d, prim + 3), a.zp, T(a.P.h_dry), T(0.5 * a.P.g), o);
     const long long s = d.at(i, j);
     for (int v = 0; v < 4; ++v) arr(a.trace, d, dst + v)[s] = o[v];
 }
