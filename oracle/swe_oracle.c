@@ -83,8 +83,9 @@
  *       min(cfl/lam_max, dt_max) if lam_max > 0, else dt_max.
  *       t^{n+1} = t^n + dt^n.  dt^0 is S16 applied to U^0.
  * cbrt3(x), x > 0 normal: the exponent-thirding first guess (integer
- * arithmetic on the IEEE-754 bit pattern b of x: b/3 + 0x2A9F789300000000, as
- * in Kahan's cube-root note) followed by two steps of Halley's method for
+ * arithmetic on the high 32 bits w of the IEEE-754 pattern of x: the guess
+ * has high word w/3 + 0x2A9F7893 and low word 0, as in Kahan's cube-root
+ * note) followed by two steps of Halley's method for
  * y^3 = x: t = (y*y)*y, y = y*((t + (x + x))/((t + t) + x)).  The guess is
  * within 3.3% and each Halley step triples the digits, leaving a relative
  * error below 7e-15.
@@ -164,7 +165,8 @@ static inline double pos(double h) { return h > 0.0 ? h : 0.0; }
 static double cbrt3(double x) {
     uint64_t b;
     memcpy(&b, &x, sizeof b);
-    b = b / 3u + 0x2A9F789300000000ull;
+    uint32_t w = (uint32_t)(b >> 32);
+    b = (uint64_t)(w / 3u + 0x2A9F7893u) << 32;
     double y;
     memcpy(&y, &b, sizeof y);
     for (int k = 0; k < 2; ++k) {
