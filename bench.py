@@ -110,8 +110,13 @@ def timed_run(torch, swe, W, p, dtype, steps, warmup, tile_rows, path="fused"):
     return st, ms, wall
 
 
+def progress(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def cpu_baseline(W, p, nsteps):
     from oracle import oracle as O
+    progress(f"CPU oracle baseline: {nsteps} timed steps of {p.nx}x{p.ny}")
     s = O.State(p)
     s.run(1)                       # untimed: first touch of the work arrays
     st = s.run(nsteps)
@@ -151,7 +156,9 @@ def main():
     nx = a.nx
     p = W.reservoir_release(nx=nx, ny=nx, dx=20480.0 / nx)
     cells = p.nx * p.ny
+    progress(f"workload ready; timing {a.steps} {a.dtype} steps")
     st, ms, wall = timed_run(torch, swe, W, p, a.dtype, a.steps, a.warmup, a.tile_rows)
+    progress(f"{a.dtype}: {ms / a.steps * 1e3:.1f} us/step")
     assert st.steps == a.steps, st
     value = cells * a.steps / (ms / 1e3)
     ms_step = ms / a.steps
