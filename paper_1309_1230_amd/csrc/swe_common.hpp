@@ -114,7 +114,13 @@ __device__ inline double next_dt(const Params& P, double lam) {
 
 __device__ __forceinline__ float tfabs(float x) { return __builtin_fabsf(x); }
 __device__ __forceinline__ double tfabs(double x) { return __builtin_fabs(x); }
-__device__ __forceinline__ float tsqrt(float x) { return __builtin_sqrtf(x); }
+// Reciprocal and square root.  FP64: correctly rounded, so the FP64 path is
+// reproducible bit for bit by any IEEE implementation of the same expression
+// order.  FP32: the single hardware instructions (1 ulp); the FP32 state is
+// held to a tolerance against the FP64 oracle, not to bit equality.
+__device__ __forceinline__ double trcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float trcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float tsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double tsqrt(double x) { return __builtin_sqrt(x); }
 // Cube root of x > 0 used by the friction step: the exponent-thirding guess
 // (integer arithmetic on the IEEE-754 bits: high word w/3 + 0x2A9F7893, low
@@ -122,8 +128,8 @@ __device__ __forceinline__ double tsqrt(double x) { return __builtin_sqrt(x); }
 // two Halley steps y <- y*((t + 2x)/(2t + x)), t = y^3.  Every operation is
 // exact or correctly rounded, so the FP64 result is reproducible bit for bit
 // on any IEEE machine (a math library's cbrt is only faithful to about an ulp
-// and differs between libraries).  Relative error < 7e-15 (FP64), < 3e-7
-// (FP32).
+// and differs between libraries).  Relative error < 7e-15 (FP64).  The FP32
+// version divides through the hardware reciprocal: a few ulp.
 __device__ __forceinline__ double tcbrt(double x) {
     const unsigned w = (unsigned)__double2hiint(x);
     double y = __hiloint2double((int)(w / 3u + 0x2A9F7893u), 0);
@@ -141,7 +147,7 @@ __device__ __forceinline__ float tcbrt(float x) {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const float t = (y * y) * y;
-        y = y * ((t + (x + x)) / ((t + t) + x));
+        y = y * ((t + (x + x)) * trcp((t + t) + x));
     }
     return y;
 }
@@ -154,7 +160,7 @@ template <typename T> __device__ __forceinline__ T tmin(T a, T b) { return a < b
 
 // S2: reciprocal depth of a wet cell, 0 for a dry one.
 template <typename T> __device__ __forceinline__ T recip_depth(T h, T hdry) {
-    return h > hdry ? T(1) / h : T(0);
+    return h > hdry ? trcp(h) : T(0);
 }
 
 // S3: curvature switch of the water surface at a cell.
@@ -208,7 +214,7 @@ __device__ __forceinline__ void manning(T dt, T m, T r, T& qx, T& qy) {
     T s = tsqrt(qx * qx + qy * qy) * r;
     T k = r * tcbrt(r);
     T phi = T(1) + ((dt * m) * s) * k;
-    T psi = T(1) / phi;
+    T psi = trcp(phi);
     qx = qx * psi;
     qy = qy * psi;
 }

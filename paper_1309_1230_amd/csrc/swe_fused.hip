@@ -164,15 +164,17 @@ struct March {
     int nx, ny, i, ic, y0, yEnd, kS, kN;
     bool colOut, faceE_interior, atW, atE;
 
-    T e1 = 0, a1 = 0, b1 = 0, z1 = 0, h1 = 0, r1 = 0;   // U^n row R-1
-    T e2 = 0, a2 = 0, b2 = 0, z2 = 0, h2 = 0;           // U^n row R-2
+    // Depths are not carried: h = eta - z is recomputed from the carried
+    // eta and z (the same operands, so the same bits) to save registers.
+    T e1 = 0, a1 = 0, b1 = 0, z1 = 0, r1 = 0;   // U^n row R-1
+    T e2 = 0, a2 = 0, b2 = 0, z2 = 0;           // U^n row R-2
     T nuy2 = 0;                      // nu_y(R-2)
     T dx1m = 0, dx1a = 0, dx1b = 0;  // x dissipation of row R-1
     T dx2m = 0, dx2a = 0, dx2b = 0;  // x dissipation of row R-2
     T phm = 0, pha = 0, phb = 0;     // y dissipation flux through face (R-3)+1/2
     XDiv<T> A1 = {0, 0, 0};          // predictor x part of row R-1
     YFace<T> G1 = {0, 0, 0, 0};      // predictor y face (R-2)+1/2
-    T se2 = 0, sa2 = 0, sb2 = 0, sh2 = 0, sr2 = 0;  // U* row R-2
+    T se2 = 0, sa2 = 0, sb2 = 0, sr2 = 0;  // U* row R-2
     XDiv<T> B2 = {0, 0, 0};          // corrector x part of row R-2
     YFace<T> H1 = {0, 0, 0, 0};      // corrector y face (R-3)+1/2
     // Prefetched rows, double-buffered: the iteration that consumes slot S
@@ -216,7 +218,7 @@ struct March {
         // ---- S2 on row R
         const T h0 = e0 - z0;
         T r0 = T(0);
-        if (h0 > c.hdry) r0 = T(1) / h0;
+        if (h0 > c.hdry) r0 = trcp(h0);
         const T u0 = a0 * r0, v0 = b0 * r0;
 
         // ---- S3/S4 in x on row R
@@ -243,6 +245,7 @@ struct March {
         // ---- S3 in y at row R-1, S4 in y through face (R-2)+1/2
         const T nuy1 = curv_switch(e2, e1, e0, r1);
         const bool fInt = !BND || (R - 2 >= 0 && R - 2 <= ny - 2);
+        const T h1 = e1 - z1, h2 = e2 - z2;
         const T epsN = fInt ? face_eps(h2, h1, nuy2, nuy1, c.hdry, c.kap, c.emax) : T(0);
         const T pnm = epsN * (e1 - e2), pna = epsN * (a1 - a2), pnb = epsN * (b1 - b2);
 
@@ -259,7 +262,7 @@ struct March {
         // ---- S9 on U*(R-1), S10 on U*(R-1)
         const T sh1 = se1 - z1;
         T sr1 = T(0);
-        if (sh1 > c.hdry) sr1 = T(1) / sh1;
+        if (sh1 > c.hdry) sr1 = trcp(sh1);
         const T su1 = sa1 * sr1, sv1 = sb1 * sr1;
         XDiv<T> B1;
         if (SIG > 0)   // corrector donor direction -1: neighbour on the west
@@ -273,6 +276,7 @@ struct March {
 
         // ---- S11 through face (R-2)+1/2
         const bool bndH = BND && ((R - 2 == -1) || (R - 2 == ny - 1));
+        const T sh2 = se2 - z2;
         const YFace<T> H0 = y_face<T, -SIG>(c, bndH, R - 2 == -1, kS, kN, se2, sb2, sh2, sr2,
                                             sa2 * sr2, sb2 * sr2, z2, se1, sb1, sh1, sr1, su1, sv1,
                                             z1, c.qin1);
@@ -288,7 +292,7 @@ struct March {
             T h = e - z2;
             T lam = T(0);
             if (h > c.hdry) {
-                const T r = T(1) / h;
+                const T r = trcp(h);
                 manning(c.dt, m2, r, a, b);
                 // wet stays wet through S15 (h is unchanged), so S16 uses r
                 lam = cfl_lambda(h, r, a, b, c.g, c.idx, c.idy);
@@ -314,15 +318,15 @@ struct March {
         }
 
         // ---- rotate the carried rows
-        e2 = e1; a2 = a1; b2 = b1; z2 = z1; h2 = h1;
-        e1 = e0; a1 = a0; b1 = b0; z1 = z0; h1 = h0; r1 = r0;
+        e2 = e1; a2 = a1; b2 = b1; z2 = z1;
+        e1 = e0; a1 = a0; b1 = b0; z1 = z0; r1 = r0;
         nuy2 = nuy1;
         dx2m = dx1m; dx2a = dx1a; dx2b = dx1b;
         dx1m = dx0m; dx1a = dx0a; dx1b = dx0b;
         phm = pnm; pha = pna; phb = pnb;
         A1 = A0;
         G1 = G0;
-        se2 = se1; sa2 = sa1; sb2 = sb1; sh2 = sh1; sr2 = sr1;
+        se2 = se1; sa2 = sa1; sb2 = sb1; sr2 = sr1;
         B2 = B1;
         H1 = H0;
     }

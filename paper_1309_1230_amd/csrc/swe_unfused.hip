@@ -289,7 +289,7 @@ __global__ void k_s14(UnfusedArgs<T> a) {
     const T e = arr(a.trace, d, T_UD)[C];
     T qx = arr(a.trace, d, T_UD + 1)[C], qy = arr(a.trace, d, T_UD + 2)[C];
     const T h = e - a.zp[C];
-    if (h > T(a.P.h_dry)) manning(T(a.ctl->dt), a.mp[C], T(1) / h, qx, qy);
+    if (h > T(a.P.h_dry)) manning(T(a.ctl->dt), a.mp[C], trcp(h), qx, qy);
     arr(a.trace, d, T_UF)[C] = e;
     arr(a.trace, d, T_UF + 1)[C] = qx;
     arr(a.trace, d, T_UF + 2)[C] = qy;
@@ -356,7 +356,7 @@ __global__ void k_scan(Params P, Ctl* ctl, double t_end, const T* eta, const T* 
             const long long o = (long long)j * P.pitch + i;
             const T h = eta[o] - z[o];
             vol = vol + (double)h;
-            if (h > hdry) lmax = lam_acc(lmax, cfl_lambda(h, T(1) / h, qx[o], qy[o], g, idx, idy));
+            if (h > hdry) lmax = lam_acc(lmax, cfl_lambda(h, trcp(h), qx[o], qy[o], g, idx, idy));
         }
     }
     vol = wave_sum(vol);
