@@ -1,4 +1,4 @@
-"""Python front-end of the serial FP64 CPU oracle (swe_oracle.c).
+"""Python front-end of the serial FP64 CPU oracle (swe_oracle.cpp).
 
 TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
 baseline call this module; the GPU library never does.  It takes problems
@@ -16,7 +16,7 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "swe_oracle.c")
+SRC = os.path.join(HERE, "swe_oracle.cpp")
 LIB = os.path.join(HERE, "liboracle.so")
 
 FLAG_NAN, FLAG_CLIPPED, FLAG_BADDT = 1, 2, 4
@@ -35,11 +35,11 @@ SCALAR_NAMES = ["qin_n", "qin_n1", "rx", "ry", "defect_depth", "lam_max", "dt_ne
 
 
 def build(force: bool = False) -> str:
-    """Compile swe_oracle.c with gcc (no FMA contraction, no fast-math)."""
+    """Compile swe_oracle.cpp with g++ (no FMA contraction, no fast-math)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
-                               "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-o", tmp, SRC])
         os.replace(tmp, LIB)
     return LIB
 
@@ -83,6 +83,15 @@ def lib():
         L.orc_initial_dt.restype = ctypes.c_double
         L.orc_cbrt3.argtypes = [ctypes.c_double]
         L.orc_cbrt3.restype = ctypes.c_double
+        L.orc_run_record.argtypes = L.orc_run.argtypes + [dp]
+        L.orc_run_record.restype = ctypes.c_int
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        loss_args = [ctypes.POINTER(_Cfg), dp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_int64,
+                     ctypes.c_int64, dp, ctypes.c_int32, i64p, ctypes.c_int32, dp]
+        L.orc_loss_tangent.argtypes = loss_args + [dp, dp, dp, dp]
+        L.orc_loss_tangent.restype = ctypes.c_int
+        L.orc_loss_gradient.argtypes = loss_args + [dp, dp, dp]
+        L.orc_loss_gradient.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -202,3 +211,92 @@ def run(problem, nsteps: int, t_end: float = math.inf):
 def cbrt3(x: float) -> float:
     """The friction step's cube root (exponent-thirding guess, two Halley steps)."""
     return lib().orc_cbrt3(float(x))
+
+
+# ------------------------------------------------------------ derivatives
+
+def run_record(problem, nsteps: int):
+    """Adaptive forward run from the problem's state: (State, dts), dts[n] the
+    time step dt^n each step used (the sequence the loss holds fixed)."""
+    s = State(problem)
+    keep = []
+    c = _cfg(problem, keep)
+    t = ctypes.c_double(s.t)
+    n = ctypes.c_int64(s.step)
+    dt = ctypes.c_double(s.dt)
+    st = _Stats()
+    dts = np.zeros(max(int(nsteps), 1))
+    rc = lib().orc_run_record(ctypes.byref(c), _ptr(s.eta), _ptr(s.qx), _ptr(s.qy),
+                              _ptr(problem.z), _ptr(problem.n), ctypes.byref(t), ctypes.byref(n),
+                              ctypes.byref(dt), int(nsteps), math.inf, ctypes.byref(st),
+                              _ptr(dts))
+    if rc != 0 or st.steps != nsteps:
+        raise ValueError("oracle forward run failed")
+    s.t, s.step, s.dt = t.value, n.value, dt.value
+    return s, dts[:nsteps]
+
+
+@dataclasses.dataclass
+class Gauges:
+    """Gauge-misfit loss: cells (flattened j*nx + i), observed depths
+    hobs[k, g] after steps (k+1)*every, and the fixed time steps dts."""
+    cells: np.ndarray
+    every: int
+    hobs: np.ndarray
+    dts: np.ndarray
+
+
+def _loss_args(problem, G: Gauges, keep, eta0=None, qx0=None, qy0=None, z=None, nman=None):
+    c = _cfg(problem, keep)
+    eta0 = problem.eta if eta0 is None else eta0
+    qx0 = problem.qx if qx0 is None else qx0
+    qy0 = problem.qy if qy0 is None else qy0
+    z = problem.z if z is None else z
+    nman = problem.n if nman is None else nman
+    cells = np.ascontiguousarray(G.cells, dtype=np.int64)
+    hobs = np.ascontiguousarray(G.hobs, dtype=np.float64)
+    dts = np.ascontiguousarray(G.dts, dtype=np.float64)
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (eta0, qx0, qy0, z, nman)]
+    keep += [cells, hobs, dts] + arrs
+    return [ctypes.byref(c)] + [_ptr(a) for a in arrs] + [
+        0.0, 0, len(dts), _ptr(dts), len(cells),
+        cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(G.every), _ptr(hobs)]
+
+
+def loss(problem, G: Gauges, **fields) -> float:
+    """The gauge-misfit loss (fields: optional eta0, qx0, qy0, z, nman)."""
+    keep = []
+    J = ctypes.c_double()
+    rc = lib().orc_loss_tangent(*_loss_args(problem, G, keep, **fields), None, None,
+                                ctypes.byref(J), None)
+    if rc:
+        raise ValueError("oracle rejected the loss arguments")
+    return J.value
+
+
+def loss_tangent(problem, G: Gauges, dn=None, dz=None, **fields):
+    """(J, dJ): the loss and its derivative along (dn, dz), forward mode."""
+    keep = []
+    J, dJ = ctypes.c_double(), ctypes.c_double()
+    dn = None if dn is None else np.ascontiguousarray(dn, dtype=np.float64)
+    dz = None if dz is None else np.ascontiguousarray(dz, dtype=np.float64)
+    keep += [dn, dz]
+    rc = lib().orc_loss_tangent(*_loss_args(problem, G, keep, **fields),
+                                None if dn is None else _ptr(dn), None if dz is None else _ptr(dz),
+                                ctypes.byref(J), ctypes.byref(dJ))
+    if rc:
+        raise ValueError("oracle rejected the loss arguments")
+    return J.value, dJ.value
+
+
+def loss_gradient(problem, G: Gauges, **fields):
+    """(J, dJ/dn, dJ/dz): the loss and its gradient, reverse mode."""
+    keep = []
+    J = ctypes.c_double()
+    gn = np.zeros((problem.ny, problem.nx))
+    gz = np.zeros((problem.ny, problem.nx))
+    rc = lib().orc_loss_gradient(*_loss_args(problem, G, keep, **fields), ctypes.byref(J),
+                                 _ptr(gn), _ptr(gz))
+    if rc:
+        raise ValueError("oracle rejected the loss arguments")
+    return J.value, gn, gz

@@ -1,0 +1,120 @@
+"""Pins of the oracle's derivatives of the gauge-misfit loss (CPU only).
+
+The loss J(n, z) runs a fixed number of steps with the time steps of a
+forward run held fixed and sums squared depth misfits at gauge cells every
+few steps.  The oracle computes its directional derivative by forward mode
+and its gradient by reverse mode, both over the same generic step.  They are
+pinned here against things outside themselves:
+  - central finite differences of J, which converge to the derivative with
+    O(eps^2) error on a smooth, everywhere-wet flow (no branch changes);
+  - the lake at rest, whose state does not move when the bed or the friction
+    changes under still water: dJ/dn is exactly zero and dJ/dz is the direct
+    term -2 sum (h - h_obs) at the gauges;
+  - the transposition identity <grad J, v> = dJ(v) between the two modes,
+    including every unit direction of a small grid, on states with dry
+    cells, banks and every boundary kind.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1309_1230_amd import workloads as W
+
+
+def gauges_for(p, nsteps, every, ncell, seed, noise=0.01, cells=None):
+    """Fixed time steps of a forward run and synthetic observations: the
+    depths of that run at random gauge cells plus seeded noise."""
+    rng = np.random.default_rng(seed)
+    _, dts = O.run_record(p, nsteps)
+    if cells is None:
+        cells = rng.choice(p.nx * p.ny, ncell, replace=False)
+    hobs = np.zeros((nsteps // every, len(cells)))
+    st = O.State(p)
+    for k in range(nsteps // every):
+        st.run(every)
+        hobs[k] = (st.eta - p.z).ravel()[cells] + rng.normal(0.0, noise, len(cells))
+    return O.Gauges(cells=np.asarray(cells), every=every, hobs=hobs, dts=dts)
+
+
+def test_tangent_matches_central_differences():
+    p = W.smooth_wet(24, 18, seed=5)
+    G = gauges_for(p, 30, 5, 10, seed=1)
+    rng = np.random.default_rng(2)
+    for _ in range(3):
+        dn = rng.normal(size=p.n.shape) * 1e-3
+        dz = rng.normal(size=p.z.shape) * 1e-2
+        _, dJ = O.loss_tangent(p, G, dn=dn, dz=dz)
+        eps = 1e-4
+        fd = (O.loss(p, G, nman=p.n + eps * dn, z=p.z + eps * dz)
+              - O.loss(p, G, nman=p.n - eps * dn, z=p.z - eps * dz)) / (2 * eps)
+        assert abs(fd - dJ) <= 1e-6 * abs(dJ), (fd, dJ)
+
+
+def test_finite_differences_converge_at_second_order():
+    """The difference between the central quotient and the tangent shrinks
+    like eps^2 (until rounding takes over): the tangent is the derivative,
+    not merely close to it."""
+    p = W.smooth_wet(20, 16, seed=7)
+    G = gauges_for(p, 20, 4, 8, seed=3)
+    rng = np.random.default_rng(4)
+    dn = rng.normal(size=p.n.shape) * 1e-3
+    dz = rng.normal(size=p.z.shape) * 1e-2
+    _, dJ = O.loss_tangent(p, G, dn=dn, dz=dz)
+    errs = []
+    for eps in (1.6, 0.8, 0.4):
+        fd = (O.loss(p, G, nman=p.n + eps * dn, z=p.z + eps * dz)
+              - O.loss(p, G, nman=p.n - eps * dn, z=p.z - eps * dz)) / (2 * eps)
+        errs.append(abs(fd - dJ))
+    assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0, errs
+
+
+def test_lake_at_rest_gradient_closed_form():
+    p = W.lake_at_rest(30, 24, seed=8, dry_banks=True)
+    h0 = (p.eta - p.z).ravel()
+    wet = np.flatnonzero(h0 > 10 * p.h_dry)
+    rng = np.random.default_rng(5)
+    cells = rng.choice(wet, 12, replace=False)
+    G = gauges_for(p, 24, 6, 12, seed=6, noise=0.05, cells=cells)
+    J, gn, gz = O.loss_gradient(p, G)
+    assert np.all(gn == 0.0)
+    expect = np.zeros(p.nx * p.ny)
+    for k in range(G.hobs.shape[0]):
+        np.add.at(expect, cells, -2.0 * (h0[cells] - G.hobs[k]))
+    np.testing.assert_allclose(gz.ravel(), expect, rtol=1e-13, atol=1e-15)
+    assert J == pytest.approx(((h0[cells][None, :] - G.hobs) ** 2).sum(), rel=1e-13)
+
+
+@pytest.mark.parametrize("make", [
+    lambda: W.smooth_wet(20, 14, seed=9),
+    lambda: W.random_valid_state(22, 17, seed=21),
+    lambda: W.inflow_channel(26, 12, seed=3, q_peak=2.0, dry=True, t_peak=2.0, t_end=6.0),
+])
+def test_reverse_gradient_is_the_transposed_tangent(make):
+    p = make()
+    if p.name.startswith("inflow"):
+        p.inflow_lo = (2, 0, 0, 0)
+        p.inflow_hi = (10, 12, 26, 26)
+    G = gauges_for(p, 16, 4, 9, seed=11)
+    J, gn, gz = O.loss_gradient(p, G)
+    rng = np.random.default_rng(12)
+    for _ in range(3):
+        dn = rng.normal(size=p.n.shape) * 1e-3
+        dz = rng.normal(size=p.z.shape) * 1e-2
+        J2, dJ = O.loss_tangent(p, G, dn=dn, dz=dz)
+        assert J2 == J
+        dot = float((gn * dn).sum() + (gz * dz).sum())
+        assert abs(dot - dJ) <= 1e-12 * max(abs(dJ), np.abs(gn).sum() * 1e-3 + np.abs(gz).sum() * 1e-2)
+
+
+def test_full_gradient_equals_unit_tangents_on_a_small_grid():
+    p = W.random_valid_state(9, 7, seed=2)
+    G = gauges_for(p, 10, 2, 6, seed=13)
+    J, gn, gz = O.loss_gradient(p, G)
+    scale = max(np.abs(gn).max(), np.abs(gz).max())
+    for k in range(p.nx * p.ny):
+        e = np.zeros(p.nx * p.ny)
+        e[k] = 1.0
+        _, dn_k = O.loss_tangent(p, G, dn=e.reshape(p.n.shape))
+        _, dz_k = O.loss_tangent(p, G, dz=e.reshape(p.z.shape))
+        assert abs(gn.ravel()[k] - dn_k) <= 1e-12 * scale
+        assert abs(gz.ravel()[k] - dz_k) <= 1e-12 * scale
