@@ -190,6 +190,36 @@ int swe_load(swe_handle* h, const swe_checkpoint* ck);
  * when h is NULL.  Never NULL; valid until the next call on that handle. */
 const char* swe_last_error(const swe_handle* h);
 
+/* Gauges of the misfit loss of swe_grad. */
+typedef struct swe_gauges {
+    int32_t ngauge;          /* number of gauge cells (>= 0) */
+    int32_t obs_every;       /* observe after steps obs_every, 2*obs_every, ... (>= 1) */
+    const int64_t* cells;    /* host, ngauge distinct cells j*nx + i */
+    const double* hobs;      /* device, FP64, [floor(nsteps/obs_every)][ngauge]
+                                observed depths, row k after step (k+1)*obs_every */
+} swe_gauges;
+
+/* Discrete adjoint (NEXT growth path: calibration of the friction and bed
+ * fields).  Runs nsteps time steps from the current state, exactly as
+ * swe_run(nsteps) would (the handle ends advanced by nsteps steps), and
+ * returns the gauge-misfit loss
+ *   J = sum_k sum_g ((eta - z)(cell_g, after step k*obs_every) - hobs[k-1][g])^2
+ * together with its gradient with respect to the Manning field n and the bed
+ * z of the handle, for the sequence of time steps dt^n the run took held
+ * fixed (dt is not differentiated).  The gradient is the exact derivative of
+ * the discrete step (S1..S15 in reverse, branches as taken in the forward
+ * run; max/min follow the argument they return, |x| and sqrt have
+ * derivative 0 at 0).  Memory: states every ckpt_every steps are kept, and
+ * each segment of ckpt_every steps is recomputed once during the reverse
+ * sweep (about 2 + 1/ckpt_every forward passes in all).  dJ_dn and dJ_dz
+ * (device, FP64, caller-owned, the handle's pitch) receive the gradients;
+ * *loss (host) receives J.  FP64 handles only.  Synchronises.  Errors:
+ * SWE_EINVAL (arguments, gauge cells out of range or repeated, FP32 handle),
+ * SWE_ENOMEM, SWE_EDEVICE, SWE_EUNSTABLE (the forward run raised a fatal
+ * flag). */
+int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_every,
+             double* loss, void* dJ_dn, void* dJ_dz);
+
 /* Plain device-to-device copy kernel of `bytes` bytes (multiple of 16, both
  * pointers 16-byte aligned) on `stream`: the bandwidth probe the HBM traffic
  * counters are calibrated against.  Asynchronous.  SWE_EINVAL on misuse. */

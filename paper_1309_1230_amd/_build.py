@@ -19,7 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libswe.so")
-SOURCES = ["swe_api.hip", "swe_fused.hip", "swe_unfused.hip"]
+SOURCES = ["swe_api.hip", "swe_fused.hip", "swe_unfused.hip", "swe_adjoint.hip"]
 ARCH = os.environ.get("SWE_OFFLOAD_ARCH", "gfx950")
 
 

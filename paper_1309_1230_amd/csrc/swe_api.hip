@@ -30,6 +30,7 @@ struct swe_handle {
     void* qx = nullptr;
     void* qy = nullptr;
     const void* z = nullptr;
+    const void* n = nullptr;   // caller's Manning field (for the adjoint's dJ/dn)
     void* buf = nullptr;       // library: state buffer B (3 fields) + m
     Ctl* ctl = nullptr;
     double* part = nullptr;    // 2 * nparts
@@ -327,6 +328,7 @@ int swe_create(const swe_config* c, swe_handle** out) {
     h->qx = c->qx;
     h->qy = c->qy;
     h->z = c->z;
+    h->n = c->n;
     Params& P = h->P;
     P.nx = c->nx;
     P.ny = c->ny;
@@ -531,6 +533,225 @@ int swe_load(swe_handle* h, const swe_checkpoint* ck) {
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "swe_load");
     h->step_host = ck->step;
+    return SWE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t alloc(size_t bytes) { return hipMalloc(&p, bytes ? bytes : 16); }
+    double* d() const { return (double*)p; }
+};
+
+__global__ void k_log_ctl(const Ctl* ctl, double* dt_out, double* t_out) {
+    if (threadIdx.x == 0) {
+        *dt_out = ctl->dt;
+        *t_out = ctl->t;
+    }
+}
+
+// Elements of a pitched field that belong to it (the last row ends at nx).
+size_t state_elems(const swe_handle* h) {
+    return (size_t)(h->P.ny - 1) * (size_t)h->P.pitch + (size_t)h->P.nx;
+}
+
+hipError_t copy_state(swe_handle* h, double* const dst[3], const double* const src[3]) {
+    hipError_t e = hipSuccess;
+    for (int f = 0; f < 3 && e == hipSuccess; ++f)
+        e = hipMemcpyAsync(dst[f], src[f], state_elems(h) * sizeof(double),
+                           hipMemcpyDeviceToDevice, h->stream);
+    return e;
+}
+
+// Control block for step n of a replay: t^n and n set, dt^n (and dt/dx,
+// dt/dy, the inflow values) recomputed from the state U^n by sub-step 16,
+// exactly as at the start of a run.
+hipError_t set_replay_ctl(swe_handle* h, Ctl* ctl, double t, long long step,
+                          double* const U[3]) {
+    hipError_t e = swe::launch_init_ctl(ctl, t, step, 0u, 0.0, h->stream);
+    if (e == hipSuccess)
+        e = swe::launch_scan<double>(h->P, ctl, INFINITY, U[0], U[1], U[2], (const double*)h->z,
+                                     h->part, h->part + h->nparts, 0, h->stream);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_every,
+             double* loss, void* dJ_dn, void* dJ_dz) {
+    if (!h) return fail(nullptr, SWE_EINVAL, "handle is NULL");
+    if (h->dtype != SWE_F64) return fail(h, SWE_EINVAL, "swe_grad needs an FP64 handle");
+    if (nsteps < 0 || !g || !loss || !dJ_dn || !dJ_dz || ckpt_every < 1)
+        return fail(h, SWE_EINVAL, "swe_grad: bad arguments");
+    if (g->ngauge < 0 || g->obs_every < 1) return fail(h, SWE_EINVAL, "swe_grad: bad gauges");
+    const int64_t nobs = nsteps / g->obs_every;
+    const int ng = g->ngauge;
+    if (ng > 0 && (!g->cells || (nobs > 0 && !g->hobs)))
+        return fail(h, SWE_EINVAL, "swe_grad: gauge cells or observations missing");
+    {
+        std::vector<int64_t> cs(g->cells, g->cells + ng);
+        std::sort(cs.begin(), cs.end());
+        const int64_t ncell = (int64_t)h->P.nx * h->P.ny;
+        for (int k = 0; k < ng; ++k)
+            if (cs[k] < 0 || cs[k] >= ncell || (k > 0 && cs[k] == cs[k - 1]))
+                return fail(h, SWE_EINVAL, "swe_grad: gauge cells must be distinct and inside the grid");
+    }
+    if (!is_device_ptr(dJ_dn, h->device) || !is_device_ptr(dJ_dz, h->device) ||
+        (ng > 0 && nobs > 0 && !is_device_ptr(g->hobs, h->device)))
+        return fail(h, SWE_EINVAL, "swe_grad: gradients and observations must be device memory");
+    int rc = ensure_trace(h);
+    if (rc) return rc;
+    rc = fill_stats(h, nullptr);
+    if (rc) return rc;
+    Ctl c0;
+    hipError_t e = hipMemcpyAsync(&c0, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "swe_grad: reading the control block");
+    const long long step0 = c0.step;
+    const size_t fe = (size_t)h->P.ny * (size_t)h->P.pitch;   // elements of a field slot
+    const size_t Npad = padded_elems(h);
+    const int64_t C = std::max<int64_t>(1, std::min<int64_t>(ckpt_every, std::max<int64_t>(nsteps, 1)));
+    const int64_t nseg = (nsteps + C - 1) / C;
+    DevBuf ck, seg, scratch, work, logs, mis, dcells, actl;
+    if ((e = ck.alloc((size_t)nseg * 3 * fe * sizeof(double))) != hipSuccess ||
+        (e = seg.alloc((size_t)C * 3 * fe * sizeof(double))) != hipSuccess ||
+        (e = scratch.alloc(3 * fe * sizeof(double))) != hipSuccess ||
+        (e = work.alloc((size_t)swe::adjoint_work_arrays() * Npad * sizeof(double))) != hipSuccess ||
+        (e = logs.alloc(2 * (size_t)std::max<int64_t>(nsteps, 1) * sizeof(double))) != hipSuccess ||
+        (e = mis.alloc((size_t)std::max<int64_t>(nobs * ng, 1) * sizeof(double))) != hipSuccess ||
+        (e = dcells.alloc((size_t)std::max(ng, 1) * sizeof(long long))) != hipSuccess ||
+        (e = actl.alloc(sizeof(Ctl))) != hipSuccess)
+        return fail(h, SWE_ENOMEM, std::string("swe_grad: hipMalloc failed: ") + hip_text(e));
+    if (ng > 0)
+        e = hipMemcpyAsync(dcells.p, g->cells, (size_t)ng * sizeof(long long),
+                           hipMemcpyHostToDevice, h->stream);
+    double* dtlog = logs.d();
+    double* tlog = logs.d() + std::max<int64_t>(nsteps, 1);
+    auto slot = [&](double* base, int64_t m, double* U[3]) {
+        for (int f = 0; f < 3; ++f) U[f] = base + ((size_t)m * 3 + f) * fe;
+    };
+    // ---- forward: the run itself, with checkpoints, time steps and misfits
+    if (e == hipSuccess) e = swe::launch_begin_call(h->ctl, h->stream);
+    for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) {
+        double* cur[3];
+        for (int f = 0; f < 3; ++f) cur[f] = (double*)((k & 1) ? bufB(h, f) : bufA(h, f));
+        if (k % C == 0) {
+            double* dst[3];
+            slot(ck.d(), k / C, dst);
+            e = copy_state(h, dst, cur);
+        }
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_log_ctl, dim3(1), dim3(64), 0, h->stream, h->ctl, dtlog + k,
+                               tlog + k);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = enqueue(h, k, INFINITY, false);
+        if (e == hipSuccess && ng > 0 && (k + 1) % g->obs_every == 0) {
+            const int64_t row = (k + 1) / g->obs_every - 1;
+            const double* nxt = (const double*)((k & 1) ? bufA(h, 0) : bufB(h, 0));
+            e = swe::launch_misfit(h->P, nxt, (const double*)h->z, (const long long*)dcells.p, ng,
+                                   g->hobs + row * ng, mis.d() + row * ng, h->stream);
+        }
+    }
+    if (e == hipSuccess) e = enqueue_copy_back(h);
+    if (e != hipSuccess) return hip_fail(h, e, "swe_grad: forward run");
+    rc = fill_stats(h, nullptr);
+    if (rc) return rc;
+    std::vector<double> hdt((size_t)std::max<int64_t>(nsteps, 1)), ht(hdt.size()),
+        hm((size_t)std::max<int64_t>(nobs * ng, 1));
+    e = hipMemcpyAsync(hdt.data(), dtlog, hdt.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ht.data(), tlog, ht.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hm.data(), mis.p, hm.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "swe_grad: reading the forward logs");
+    double J = 0.0;
+    for (int64_t k = 0; k < nobs * ng; ++k) J = J + hm[(size_t)k];
+    // ---- reverse sweep, segment by segment
+    e = hipMemsetAsync(work.p, 0, (size_t)swe::adjoint_work_arrays() * Npad * sizeof(double), h->stream);
+    swe::AdjointArgs aa;
+    aa.P = h->P;
+    aa.trace = (const double*)h->trace;
+    aa.zp = aa.trace + (size_t)swe::kTraceArrays * Npad;
+    aa.mp = aa.zp + Npad;
+    aa.nman = (const double*)h->n;
+    aa.work = work.d();
+    Ctl* rc_ctl = (Ctl*)actl.p;
+    for (int64_t sg = nseg - 1; sg >= 0 && e == hipSuccess; --sg) {
+        const int64_t s0 = sg * C, s1 = std::min(s0 + C, nsteps);
+        double *U0[3], *CK[3];
+        slot(seg.d(), 0, U0);
+        slot(ck.d(), sg, CK);
+        e = copy_state(h, U0, CK);
+        for (int64_t k = s0; k + 1 < s1 && e == hipSuccess; ++k) {
+            double *Uk[3], *Un[3];
+            slot(seg.d(), k - s0, Uk);
+            slot(seg.d(), k + 1 - s0, Un);
+            e = set_replay_ctl(h, rc_ctl, ht[(size_t)k], step0 + k, Uk);
+            if (e != hipSuccess) break;
+            swe::FusedArgs<double> fa;
+            fa.P = h->P;
+            fa.ctl = rc_ctl;
+            fa.t_end = INFINITY;
+            fa.eta = Uk[0]; fa.qx = Uk[1]; fa.qy = Uk[2];
+            fa.z = (const double*)h->z;
+            fa.m = (const double*)bufB(h, 3);
+            fa.eta1 = Un[0]; fa.qx1 = Un[1]; fa.qy1 = Un[2];
+            fa.part_def = h->part;
+            fa.part_vol = h->part + h->nparts;
+            fa.gy = h->gy;
+            fa.H = h->H;
+            e = swe::launch_fused<double>(fa, ((step0 + k) & 1) ? -1 : 1, h->stream);
+        }
+        for (int64_t k = s1 - 1; k >= s0 && e == hipSuccess; --k) {
+            double *Uk[3], *Sc[3];
+            slot(seg.d(), k - s0, Uk);
+            slot(scratch.d(), 0, Sc);
+            e = set_replay_ctl(h, rc_ctl, ht[(size_t)k], step0 + k, Uk);
+            if (e != hipSuccess) break;
+            swe::UnfusedArgs<double> ua;
+            ua.P = h->P;
+            ua.ctl = rc_ctl;
+            ua.t_end = INFINITY;
+            ua.eta = Uk[0]; ua.qx = Uk[1]; ua.qy = Uk[2];
+            ua.z = (const double*)h->z;
+            ua.eta1 = Sc[0]; ua.qx1 = Sc[1]; ua.qy1 = Sc[2];
+            ua.trace = (double*)h->trace;
+            ua.zp = aa.zp;
+            ua.mp = aa.mp;
+            ua.part_def = h->part;
+            ua.part_vol = h->part + h->nparts;
+            const int sigma = ((step0 + k) & 1) ? -1 : 1;
+            e = swe::launch_unfused_step<double>(ua, sigma, h->stream);
+            if (e != hipSuccess) break;
+            aa.dt = hdt[(size_t)k];
+            aa.rx = aa.dt / h->P.dx;
+            aa.ry = aa.dt / h->P.dy;
+            aa.sigma = sigma;
+            const bool obs = ng > 0 && (k + 1) % g->obs_every == 0;
+            const double* hrow = obs ? g->hobs + ((k + 1) / g->obs_every - 1) * ng : nullptr;
+            e = swe::launch_adjoint_step(aa, (const long long*)dcells.p, ng, hrow, h->stream);
+        }
+    }
+    if (e == hipSuccess)
+        e = swe::launch_unpad(h->P, work.d() + (size_t)swe::kAdjGradN * Npad, (double*)dJ_dn, h->stream);
+    if (e == hipSuccess)
+        e = swe::launch_unpad(h->P, work.d() + (size_t)swe::kAdjGradZ * Npad, (double*)dJ_dz, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "swe_grad: reverse sweep");
+    *loss = J;
     return SWE_OK;
 }
 

@@ -86,6 +86,33 @@ hipError_t launch_begin_call(Ctl* ctl, hipStream_t s);
 hipError_t launch_init_ctl(Ctl* ctl, double t, long long step, unsigned flags, double defect,
                            hipStream_t s);
 
+// Arguments of the adjoint of one step (FP64): the step's forward
+// intermediates in the unfused trace layout, the padded static fields, and
+// the adjoint work arrays (adjoint_work_arrays() padded arrays; lambda in
+// slots 15..17 on entry and exit, dJ/dn and dJ/dz accumulators in 18, 19).
+struct AdjointArgs {
+    Params P;
+    const double* trace;
+    const double* zp;
+    const double* mp;
+    const double* nman;   // Manning field (pitched)
+    double* work;
+    double dt, rx, ry;
+    int sigma;
+};
+
+int adjoint_work_arrays();
+constexpr int kAdjLambda = 15, kAdjGradN = 18, kAdjGradZ = 19;
+// Adjoint of one step; adds the gauge terms first when hobs is not NULL.
+hipError_t launch_adjoint_step(const AdjointArgs& a, const long long* cells, int ngauge,
+                               const double* hobs, hipStream_t s);
+// out[g] = ((eta - z)(cell g) - hobs[g])^2 on a pitched state.
+hipError_t launch_misfit(const Params& P, const double* eta, const double* z,
+                         const long long* cells, int ngauge, const double* hobs, double* out,
+                         hipStream_t s);
+// Interior of a padded array into a pitched one.
+hipError_t launch_unpad(const Params& P, const double* src, double* dst, hipStream_t s);
+
 // Copy `n16` 16-byte words.
 hipError_t launch_copy16(void* dst, const void* src, size_t n16, hipStream_t s);
 

@@ -81,10 +81,15 @@ class Stats:
     lambda_max: float
 
 
+class Gauges(ctypes.Structure):
+    _fields_ = [("ngauge", ctypes.c_int32), ("obs_every", ctypes.c_int32),
+                ("cells", ctypes.POINTER(ctypes.c_int64)), ("hobs", ctypes.c_void_p)]
+
+
 #: every function include/swe.h declares
 EXPORTS = ("swe_abi_version", "swe_config_init", "swe_create", "swe_destroy", "swe_step",
            "swe_run", "swe_get_stats", "swe_trace_step", "swe_trace_bytes", "swe_save",
-           "swe_load", "swe_last_error", "swe_probe_copy")
+           "swe_load", "swe_last_error", "swe_probe_copy", "swe_grad")
 
 _lib = None
 
@@ -125,6 +130,9 @@ def lib():
         L.swe_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                      ctypes.c_void_p]
         L.swe_probe_copy.restype = ctypes.c_int
+        L.swe_grad.argtypes = [H, ctypes.c_int64, ctypes.POINTER(Gauges), ctypes.c_int32,
+                               ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_void_p]
+        L.swe_grad.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -260,6 +268,36 @@ class Solver:
         return ({nm: buf[k] for k, nm in enumerate(TRACE_NAMES)},
                 {nm: sc[k] for k, nm in enumerate(SCALAR_NAMES)})
 
+    def grad(self, nsteps: int, cells, obs_every: int, hobs, ckpt_every: int = 45):
+        """Discrete adjoint: run nsteps steps (the state advances, as with
+        run) and return (J, dJ/dn, dJ/dz) of the gauge-misfit loss, the time
+        steps of the run held fixed.  cells: distinct flattened cells j*nx+i;
+        hobs: (nsteps // obs_every, len(cells)) float64 device tensor of
+        observed depths.  FP64 solvers only."""
+        torch = _torch()
+        import numpy as np
+        cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int64).ravel())
+        ng = len(cells)
+        nobs = int(nsteps) // int(obs_every)
+        if hobs is None:
+            hobs = torch.zeros(max(nobs, 1), max(ng, 1), dtype=torch.float64, device=self.eta.device)
+        if hobs.dtype != torch.float64 or not hobs.is_cuda:
+            raise TypeError("hobs must be a float64 CUDA tensor")
+        hobs = hobs.contiguous()
+        if nobs > 0 and ng > 0 and tuple(hobs.shape) != (nobs, ng):
+            raise ValueError(f"hobs must have shape ({nobs}, {ng})")
+        g = Gauges()
+        g.ngauge = ng
+        g.obs_every = int(obs_every)
+        g.cells = cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if ng else None
+        g.hobs = hobs.data_ptr()
+        gn = torch.zeros_like(self.eta, dtype=torch.float64)
+        gz = torch.zeros_like(self.eta, dtype=torch.float64)
+        J = ctypes.c_double()
+        self._check(lib().swe_grad(self._h, int(nsteps), ctypes.byref(g), int(ckpt_every),
+                                   ctypes.byref(J), gn.data_ptr(), gz.data_ptr()))
+        return J.value, gn, gz
+
     def save(self) -> Checkpoint:
         ck = Checkpoint()
         self._check(lib().swe_save(self._h, ctypes.byref(ck)))
@@ -286,3 +324,48 @@ def probe_copy(dst, src, stream=None):
     rc = lib().swe_probe_copy(dst.data_ptr(), src.data_ptr(), nbytes, _stream_ptr(stream))
     if rc != SWE_OK:
         raise SweError(rc, last_error(None))
+
+
+def _make_loss_function():
+    torch = _torch()
+
+    class SweLoss(torch.autograd.Function):
+        """Gauge-misfit loss of a run as a differentiable function of the
+        Manning field n and the bed z (FP64 CUDA tensors).  forward runs the
+        library's discrete adjoint once and keeps the gradient; backward
+        scales it.  The time steps of the run are held fixed.
+
+            J = SweLoss.apply(n, z, eta0, qx0, qy0, solver_kwargs, nsteps,
+                              cells, obs_every, hobs, ckpt_every)
+        """
+
+        @staticmethod
+        def forward(ctx, n, z, eta0, qx0, qy0, solver_kwargs, nsteps, cells, obs_every, hobs,
+                    ckpt_every=45):
+            s = Solver(z.detach().contiguous(), n.detach().contiguous(), eta0.detach().clone(),
+                       qx0.detach().clone(), qy0.detach().clone(), **solver_kwargs)
+            try:
+                J, gn, gz = s.grad(nsteps, cells, obs_every, hobs, ckpt_every)
+            finally:
+                s.close()
+            ctx.save_for_backward(gn, gz)
+            return torch.tensor(J, dtype=torch.float64, device=n.device)
+
+        @staticmethod
+        def backward(ctx, gout):
+            gn, gz = ctx.saved_tensors
+            return (gout * gn, gout * gz) + (None,) * 9
+
+    return SweLoss
+
+
+_SweLoss = None
+
+
+def SweLoss():
+    """The torch.autograd.Function of the gauge-misfit loss (created on first
+    use so that importing this module does not import torch)."""
+    global _SweLoss
+    if _SweLoss is None:
+        _SweLoss = _make_loss_function()
+    return _SweLoss

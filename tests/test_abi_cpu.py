@@ -103,3 +103,9 @@ def test_create_without_device_reports_edevice():
     rc = swe.lib().swe_create(ctypes.byref(c), ctypes.byref(h))
     assert rc == swe.SWE_EDEVICE
     assert "device" in swe.last_error(None).lower()
+
+
+def test_grad_rejects_null_handle():
+    import ctypes
+    J = ctypes.c_double()
+    assert swe.lib().swe_grad(None, 1, None, 1, ctypes.byref(J), None, None) == swe.SWE_EINVAL

@@ -1,0 +1,142 @@
+"""GPU discrete adjoint (swe_grad) against the oracle's reverse-mode gradient.
+
+The loss is the gauge-misfit sum over observation steps with the time steps
+of the run held fixed.  The FP64 forward run is bit-identical to the
+oracle's, so both differentiate the same discrete trajectory; they differ
+only in the rounding of the derivative arithmetic, accumulated over the
+steps.  Tolerance: 1e-9 of the gradient's largest entry (the CPU pins show
+the two oracle modes agree to 1e-12 and finite differences to 1e-9).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import oracle as O
+from paper_1309_1230_amd import swe
+from paper_1309_1230_amd import workloads as W
+
+
+def note(msg):
+    print(f"[gpu-adjoint] {msg}", flush=True)
+
+
+def gauges_for(p, nsteps, every, ncell, seed, noise=0.01, cells=None):
+    rng = np.random.default_rng(seed)
+    _, dts = O.run_record(p, nsteps)
+    if cells is None:
+        cells = rng.choice(p.nx * p.ny, ncell, replace=False)
+    hobs = np.zeros((nsteps // every, len(cells)))
+    st = O.State(p)
+    for k in range(nsteps // every):
+        st.run(every)
+        hobs[k] = (st.eta - p.z).ravel()[cells] + rng.normal(0.0, noise, len(cells))
+    return O.Gauges(cells=np.asarray(cells), every=every, hobs=hobs, dts=dts)
+
+
+def gpu_grad(p, G, nsteps, ckpt):
+    s = swe.Solver.from_problem(p, dtype=torch.float64)
+    hobs = torch.as_tensor(G.hobs, dtype=torch.float64, device="cuda")
+    J, gn, gz = s.grad(nsteps, G.cells, G.every, hobs, ckpt)
+    out = (J, gn.cpu().numpy(), gz.cpu().numpy(), s)
+    return out
+
+
+def prep(name):
+    if name == "smooth":
+        return W.smooth_wet(48, 36, seed=9)
+    if name == "random":
+        return W.random_valid_state(45, 33, seed=21)
+    p = W.inflow_channel(40, 18, seed=3, q_peak=2.0, dry=True, t_peak=2.0, t_end=6.0)
+    p.inflow_lo = (3, 0, 0, 0)
+    p.inflow_hi = (14, 18, 40, 40)
+    return p
+
+
+@pytest.mark.parametrize("name", ["smooth", "random", "inflow"])
+def test_gradient_matches_oracle(name):
+    p = prep(name)
+    nsteps, every = 24, 4
+    G = gauges_for(p, nsteps, every, 15, seed=5)
+    note(f"{name} {p.nx}x{p.ny}: {nsteps} steps, adjoint vs oracle")
+    J, gn, gz, s = gpu_grad(p, G, nsteps, 7)
+    Jo, gno, gzo = O.loss_gradient(p, G)
+    assert J == pytest.approx(Jo, rel=1e-13)
+    scale_n = np.abs(gno).max()
+    scale_z = np.abs(gzo).max()
+    assert scale_n > 0 and scale_z > 0
+    en = np.abs(gn - gno).max() / scale_n
+    ez = np.abs(gz - gzo).max() / scale_z
+    note(f"max err / max |grad|: n {en:.2e}, z {ez:.2e}")
+    assert en <= 1e-9 and ez <= 1e-9
+
+
+def test_checkpoint_spacing_does_not_change_the_gradient():
+    p = prep("random")
+    G = gauges_for(p, 20, 5, 10, seed=6)
+    note("checkpoint spacing 1, 6, 20")
+    outs = [gpu_grad(p, G, 20, c) for c in (1, 6, 20)]
+    for o in outs[1:]:
+        assert o[0] == outs[0][0]
+        assert np.array_equal(o[1], outs[0][1]) and np.array_equal(o[2], outs[0][2])
+
+
+def test_state_after_grad_equals_run():
+    p = prep("smooth")
+    G = gauges_for(p, 12, 3, 6, seed=7)
+    note("state after swe_grad vs swe_run")
+    _, _, _, s = gpu_grad(p, G, 12, 5)
+    r = swe.Solver.from_problem(p, dtype=torch.float64)
+    r.run(12)
+    for a, b in ((s.eta, r.eta), (s.qx, r.qx), (s.qy, r.qy)):
+        assert torch.equal(a, b)
+    assert s.stats().step == r.stats().step == 12
+
+
+def test_lake_at_rest_closed_form_on_gpu():
+    p = W.lake_at_rest(40, 30, seed=8, dry_banks=True)
+    h0 = (p.eta - p.z).ravel()
+    wet = np.flatnonzero(h0 > 10 * p.h_dry)
+    cells = np.random.default_rng(5).choice(wet, 12, replace=False)
+    G = gauges_for(p, 24, 6, 12, seed=6, noise=0.05, cells=cells)
+    note("lake at rest closed-form gradient")
+    J, gn, gz, _ = gpu_grad(p, G, 24, 8)
+    assert np.all(gn == 0.0)
+    expect = np.zeros(p.nx * p.ny)
+    for k in range(G.hobs.shape[0]):
+        np.add.at(expect, cells, -2.0 * (h0[cells] - G.hobs[k]))
+    np.testing.assert_allclose(gz.ravel(), expect, rtol=1e-13, atol=1e-15)
+
+
+def test_autograd_function_matches_solver_grad():
+    p = prep("smooth")
+    G = gauges_for(p, 12, 4, 8, seed=8)
+    note("SweLoss autograd")
+    t = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()
+    n = t(p.n).requires_grad_(True)
+    z = t(p.z).requires_grad_(True)
+    kw = dict(dx=p.dx, dy=p.dy, g=p.g, cfl=p.cfl, h_dry=p.h_dry, kappa=p.kappa,
+              eps_max=p.eps_max, dt_max=p.dt_max, dt_fixed=p.dt_fixed, bc=p.bc,
+              inflow_lo=p.inflow_lo, inflow_hi=p.inflow_hi, hydro_t=p.hydro_t, hydro_q=p.hydro_q)
+    hobs = t(G.hobs)
+    J = swe.SweLoss().apply(n, z, t(p.eta), t(p.qx), t(p.qy), kw, 12, G.cells, G.every, hobs, 5)
+    (3.0 * J).backward()
+    Jr, gn, gz, _ = gpu_grad(p, G, 12, 5)
+    assert float(J.detach()) == Jr
+    assert torch.equal(n.grad, 3.0 * torch.as_tensor(gn, device="cuda"))
+    assert torch.equal(z.grad, 3.0 * torch.as_tensor(gz, device="cuda"))
+
+
+def test_grad_rejects_fp32_and_repeated_gauges():
+    p = prep("smooth")
+    note("swe_grad argument errors")
+    s32 = swe.Solver.from_problem(p, dtype=torch.float32)
+    hobs = torch.zeros(2, 2, dtype=torch.float64, device="cuda")
+    with pytest.raises(swe.SweError) as ei:
+        s32.grad(4, [1, 2], 2, hobs)
+    assert ei.value.code == swe.SWE_EINVAL
+    s64 = swe.Solver.from_problem(p, dtype=torch.float64)
+    with pytest.raises(swe.SweError) as ei:
+        s64.grad(4, [3, 3], 2, hobs)
+    assert ei.value.code == swe.SWE_EINVAL
