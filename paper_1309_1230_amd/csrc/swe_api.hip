@@ -572,18 +572,6 @@ hipError_t copy_state(swe_handle* h, double* const dst[3], const double* const s
     return e;
 }
 
-// Control block for step n of a replay: t^n and n set, dt^n (and dt/dx,
-// dt/dy, the inflow values) recomputed from the state U^n by sub-step 16,
-// exactly as at the start of a run.
-hipError_t set_replay_ctl(swe_handle* h, Ctl* ctl, double t, long long step,
-                          double* const U[3]) {
-    hipError_t e = swe::launch_init_ctl(ctl, t, step, 0u, 0.0, h->stream);
-    if (e == hipSuccess)
-        e = swe::launch_scan<double>(h->P, ctl, INFINITY, U[0], U[1], U[2], (const double*)h->z,
-                                     h->part, h->part + h->nparts, 0, h->stream);
-    return e;
-}
-
 }  // namespace
 
 extern "C" {
@@ -695,12 +683,13 @@ int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_ev
         slot(seg.d(), 0, U0);
         slot(ck.d(), sg, CK);
         e = copy_state(h, U0, CK);
+        // the fused kernel's own finalisation carries dt from step to step
+        if (s1 - s0 > 1) e = swe::launch_replay_ctl(h->P, rc_ctl, ht[(size_t)s0], step0 + s0,
+                                                    hdt[(size_t)s0], h->stream);
         for (int64_t k = s0; k + 1 < s1 && e == hipSuccess; ++k) {
             double *Uk[3], *Un[3];
             slot(seg.d(), k - s0, Uk);
             slot(seg.d(), k + 1 - s0, Un);
-            e = set_replay_ctl(h, rc_ctl, ht[(size_t)k], step0 + k, Uk);
-            if (e != hipSuccess) break;
             swe::FusedArgs<double> fa;
             fa.P = h->P;
             fa.ctl = rc_ctl;
@@ -719,7 +708,8 @@ int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_ev
             double *Uk[3], *Sc[3];
             slot(seg.d(), k - s0, Uk);
             slot(scratch.d(), 0, Sc);
-            e = set_replay_ctl(h, rc_ctl, ht[(size_t)k], step0 + k, Uk);
+            e = swe::launch_replay_ctl(h->P, rc_ctl, ht[(size_t)k], step0 + k, hdt[(size_t)k],
+                                       h->stream);
             if (e != hipSuccess) break;
             swe::UnfusedArgs<double> ua;
             ua.P = h->P;
@@ -734,7 +724,7 @@ int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_ev
             ua.part_def = h->part;
             ua.part_vol = h->part + h->nparts;
             const int sigma = ((step0 + k) & 1) ? -1 : 1;
-            e = swe::launch_unfused_step<double>(ua, sigma, h->stream);
+            e = swe::launch_unfused_step<double>(ua, sigma, h->stream, false);
             if (e != hipSuccess) break;
             aa.dt = hdt[(size_t)k];
             aa.rx = aa.dt / h->P.dx;

@@ -59,7 +59,9 @@ struct UnfusedArgs {
 constexpr int kTraceArrays = 47;
 
 template <typename T>
-hipError_t launch_unfused_step(const UnfusedArgs<T>& a, int sigma, hipStream_t s);
+// s16 = false leaves out S16 (the CFL scan and the dt finalisation): a replay
+// of a step whose dt is already known.
+hipError_t launch_unfused_step(const UnfusedArgs<T>& a, int sigma, hipStream_t s, bool s16 = true);
 int unfused_partials(int nx, int ny);
 
 // Pad the static fields z and m (= g n^2, already computed) into (nx+2) x
@@ -81,6 +83,10 @@ int scan_partials(int nx, int ny);
 
 // Reset the per-call statistics (dt_min, dt_max_used, call_steps).
 hipError_t launch_begin_call(Ctl* ctl, hipStream_t s);
+// Control block of a replayed step n whose dt^n is known: t, n, dt, dt/dx,
+// dt/dy and the inflow values set as the finalisation of step n-1 sets them.
+hipError_t launch_replay_ctl(const Params& P, Ctl* ctl, double t, long long step, double dt,
+                             hipStream_t s);
 // Set the control block from host values (t, step, flags, defect) and clear
 // the accumulators.
 hipError_t launch_init_ctl(Ctl* ctl, double t, long long step, unsigned flags, double defect,

@@ -384,6 +384,26 @@ __global__ void k_begin_call(Ctl* ctl) {
     }
 }
 
+// Control block of a replayed step n with a known dt^n: the values the
+// finalisation of step n-1 would have left (dt/dx and dt/dy as dt / dx, dt /
+// dy; the inflow at t^n and t^n + dt^n), flags and accumulators cleared.
+__global__ void k_replay_ctl(Params P, Ctl* ctl, double t, long long step, double dt) {
+    if (threadIdx.x == 0) {
+        ctl->t = t;
+        ctl->dt = dt;
+        ctl->rx = dt / P.dx;
+        ctl->ry = dt / P.dy;
+        ctl->qin0 = q_inflow(P, t);
+        ctl->qin1 = q_inflow(P, t + dt);
+        ctl->step = step;
+        ctl->flags = 0u;
+        ctl->step_flags = 0u;
+        ctl->ticket = 0u;
+        ctl->lam_bits = 0ull;
+        ctl->bad_step = -1;
+    }
+}
+
 __global__ void k_init_ctl(Ctl* ctl, double t, long long step, unsigned flags, double defect) {
     if (threadIdx.x == 0) {
         ctl->t = t;
@@ -440,7 +460,7 @@ inline dim3 grid2(int w, int h) { return dim3((w + kBX - 1) / kBX, (h + kBY - 1)
 }  // namespace
 
 template <typename T>
-hipError_t launch_unfused_step(const UnfusedArgs<T>& a, int sigma, hipStream_t s) {
+hipError_t launch_unfused_step(const UnfusedArgs<T>& a, int sigma, hipStream_t s, bool s16) {
     const int nx = a.P.nx, ny = a.P.ny;
     const dim3 b2(kBX, kBY);
     const long long N = (long long)(nx + 2) * (ny + 2);
@@ -468,6 +488,7 @@ hipError_t launch_unfused_step(const UnfusedArgs<T>& a, int sigma, hipStream_t s
     hipLaunchKernelGGL(k_s14<T>, grid2(nx, ny), b2, 0, s, a);                         // S14
     const dim3 gr((nx + kWave - 1) / kWave, (ny + kRB - 1) / kRB);
     hipLaunchKernelGGL(k_s15<T>, gr, dim3(kWave), 0, s, a);                           // S15
+    if (!s16) return hipGetLastError();
     hipLaunchKernelGGL(k_scan<T>, gr, dim3(kWave), 0, s, a.P, a.ctl, a.t_end,
                        (const T*)a.eta1, (const T*)a.qx1, (const T*)a.qy1, a.z, a.part_def,
                        a.part_vol, 1);                                                // S16
@@ -514,6 +535,12 @@ hipError_t launch_begin_call(Ctl* ctl, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_replay_ctl(const Params& P, Ctl* ctl, double t, long long step, double dt,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_replay_ctl, dim3(1), dim3(kWave), 0, s, P, ctl, t, step, dt);
+    return hipGetLastError();
+}
+
 hipError_t launch_init_ctl(Ctl* ctl, double t, long long step, unsigned flags, double defect,
                            hipStream_t s) {
     hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(kWave), 0, s, ctl, t, step, flags, defect);
@@ -530,7 +557,7 @@ hipError_t launch_copy16(void* dst, const void* src, size_t n16, hipStream_t s) 
 }
 
 #define SWE_INST(T)                                                                            \
-    template hipError_t launch_unfused_step<T>(const UnfusedArgs<T>&, int, hipStream_t);        \
+    template hipError_t launch_unfused_step<T>(const UnfusedArgs<T>&, int, hipStream_t, bool);        \
     template hipError_t launch_scan<T>(const Params&, Ctl*, double, const T*, const T*,         \
                                        const T*, const T*, double*, double*, int, hipStream_t); \
     template hipError_t launch_pad_static<T>(const Params&, const T*, const T*, T*, T*,         \

@@ -237,6 +237,63 @@ def inflow_channel(nx: int, ny: int, seed: int, q_peak: float = 2.0, dry: bool =
                    hydro_t=(0.0, t_peak, t_end), hydro_q=(0.0, q_peak, 0.0), name="inflow")
 
 
+def gaussian_random_field(nx: int, ny: int, dx: float, corr: float,
+                          rng: np.random.Generator) -> np.ndarray:
+    """Smooth stationary random field: white noise filtered by a Gaussian
+    kernel of standard deviation `corr` metres (spectral multiplication),
+    rescaled to [0, 1]."""
+    kx = np.fft.rfftfreq(nx, d=dx)
+    ky = np.fft.fftfreq(ny, d=dx)
+    k2 = kx[None, :] ** 2 + ky[:, None] ** 2
+    filt = np.exp(-2.0 * (np.pi * corr) ** 2 * k2)
+    f = np.fft.irfft2(np.fft.rfft2(rng.standard_normal((ny, nx))) * filt, s=(ny, nx))
+    f -= f.min()
+    m = f.max()
+    return f / m if m > 0 else f
+
+
+@dataclasses.dataclass
+class Calibration:
+    """A friction-calibration case: the problem at the first-guess Manning
+    field, the true field the observations come from, the gauge cells and
+    observation stride, and the run length."""
+    problem: Problem
+    n_true: np.ndarray
+    cells: np.ndarray
+    obs_every: int
+    nsteps: int
+
+
+def calibration(nx: int = 1024, ny: int = 1024, dx: float = 2.0, seed: int = 1003,
+                nsteps: int = 2000, ngauge: int = 64, obs_every: int = 10, depth: float = 1.5,
+                slope: float = 1e-3, n_guess: float = 0.05, n_range=(0.02, 0.08),
+                corr: float = 100.0, hill_height=(0.0, 1.0), dt_fixed: float = 0.0) -> Calibration:
+    """Manning-field calibration: 1024 x 1024, dx = 2 m by default.  Bed: a
+    plane sloping down along x at `slope` plus Gaussian hills up to 1 m.  True
+    Manning field: a Gaussian random field with 100 m correlation length
+    mapped to [0.02, 0.08].  Initial state: depth 1.5 m everywhere with the
+    uniform-flow discharge q = h^(5/3) sqrt(slope) / n_guess along x; the
+    west edge feeds that discharge in, the east edge is open, north and south
+    are walls; everything stays wet.  64 distinct gauge cells, observed every
+    10 steps of a 2000-step run.  The problem carries the first guess
+    n = 0.05 everywhere (where the gradient is evaluated)."""
+    rng = np.random.default_rng(seed)
+    L = nx * dx
+    xc = (np.arange(nx) + 0.5) * dx
+    z = np.broadcast_to((slope * (L - xc))[None, :], (ny, nx)).copy()
+    z += gaussian_hills(nx, ny, dx, dx, rng, 40, hill_height, (0.02 * L, 0.1 * L))
+    n_true = n_range[0] + (n_range[1] - n_range[0]) * gaussian_random_field(nx, ny, dx, corr, rng)
+    q = depth ** (5.0 / 3.0) * math.sqrt(slope) / n_guess
+    eta = z + depth
+    cells = rng.choice(nx * ny, ngauge, replace=False)
+    p = Problem(nx=nx, ny=ny, dx=dx, dy=dx, z=z, n=np.full((ny, nx), n_guess), eta=eta,
+                qx=np.full((ny, nx), q), qy=np.zeros((ny, nx)), dt_fixed=dt_fixed,
+                bc=(INFLOW, OPEN, WALL, WALL), hydro_t=(0.0,), hydro_q=(q,),
+                name=f"calibration{nx}x{ny}")
+    return Calibration(problem=p, n_true=n_true, cells=np.sort(cells), obs_every=obs_every,
+                       nsteps=nsteps)
+
+
 def random_valid_state(nx: int, ny: int, seed: int, dry_fraction: float = 0.2,
                        dx: float = 1.0) -> Problem:
     """Rough random state with wet, thin and dry cells, banks and every
