@@ -10,8 +10,9 @@ the state already resident in HBM.
 
 Prints one JSON line: cell-updates/s, the roofline of the fused step kernel
 (algorithmic bytes 64 B/cell-update in FP64, 32 B in FP32, over the kernel's
-average duration from HIP events on its stream, against 8 TB/s HBM) and the
-CPU oracle timed on a bounded sample of the same workload.
+average duration from HIP events on its stream, against 8 TB/s HBM), the
+adjoint/forward cost ratio on the 1024 x 1024 Manning calibration workload,
+and the CPU oracle timed on a bounded sample of the reservoir workload.
 
     python bench.py [--steps K] [--warmup W] [--dtype f64|f32]
 """
@@ -76,6 +77,13 @@ def parse():
                     help="skip the other-precision and unfused comparison runs")
     ap.add_argument("--print-source-hash", action="store_true",
                     help="print the fused kernel's source hash and exit")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint/forward cost ratio on the calibration workload")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the adjoint measurement (for profiling)")
+    ap.add_argument("--adj-nx", type=int, default=1024)
+    ap.add_argument("--adj-steps", type=int, default=2000)
+    ap.add_argument("--adj-ckpt", type=int, default=45)
     ap.add_argument("--probe-copy-mb", type=int, default=0,
                     help="also run the library's plain copy kernel once over this many MiB "
                          "(calibrates HBM traffic counters)")
@@ -114,6 +122,51 @@ def progress(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
+def adjoint_ratio(torch, swe, W, nx, nsteps, ckpt):
+    """Cost of the discrete adjoint against the forward run on the Manning
+    calibration workload: synthetic gauge observations from the true field,
+    then (a) the forward run at the first guess, timed, and (b) swe_grad of
+    the misfit loss over the same run (forward with checkpoints, segment
+    recompute, reverse sweep), timed on a fresh solver."""
+    c = W.calibration(nx=nx, ny=nx, nsteps=nsteps)
+    p = c.problem
+    progress(f"adjoint: {p.nx}x{p.ny} calibration, {nsteps} steps, checkpoint every {ckpt}")
+    truth = p.copy()
+    truth.n = c.n_true
+    s = swe.Solver.from_problem(truth, dtype=torch.float64)
+    cells = torch.as_tensor(c.cells, device="cuda")
+    zc = s.z.reshape(-1)[cells]
+    obs = []
+    for _ in range(nsteps // c.obs_every):
+        s.run(c.obs_every)
+        obs.append(s.eta.reshape(-1)[cells] - zc)
+    hobs = torch.stack(obs).contiguous()
+    s.close()
+    w = swe.Solver.from_problem(p, dtype=torch.float64)
+    w.run(20)
+    w.close()
+    f = swe.Solver.from_problem(p, dtype=torch.float64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f.run(nsteps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    f.close()
+    g = swe.Solver.from_problem(p, dtype=torch.float64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, gn, gz = g.grad(nsteps, c.cells, c.obs_every, hobs, ckpt)
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    g.close()
+    progress(f"adjoint: forward {t_fwd * 1e3:.1f} ms, swe_grad {t_grad * 1e3:.1f} ms")
+    return {"workload": f"Manning calibration {p.nx}x{p.ny}, dx={p.dx:g} m, FP64, {nsteps} steps, "
+                        f"{len(c.cells)} gauges every {c.obs_every} steps, checkpoint every {ckpt}",
+            "metric": "adjoint/fwd cost ratio", "value": t_grad / t_fwd,
+            "higher_is_better": False, "fwd_ms": t_fwd * 1e3, "grad_ms": t_grad * 1e3,
+            "loss": J, "max_abs_dJ_dn": float(gn.abs().max()), "max_abs_dJ_dz": float(gz.abs().max())}
+
+
 def cpu_baseline(W, p, nsteps):
     from oracle import oracle as O
     progress(f"CPU oracle baseline: {nsteps} timed steps of {p.nx}x{p.ny}")
@@ -123,7 +176,7 @@ def cpu_baseline(W, p, nsteps):
     cells = p.nx * p.ny * st.steps
     return {"value": cells / st.loop_seconds, "unit": "cell-updates/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"serial C FP64 oracle, {p.nx}x{p.ny} reservoir release, steps 1..{nsteps} "
+            "sample": f"serial FP64 oracle (C++), {p.nx}x{p.ny} reservoir release, steps 1..{nsteps} "
                       f"after one untimed step, {st.loop_seconds:.1f} s of step loop on "
                       f"{platform.processor() or platform.machine()}"}
 
@@ -153,6 +206,10 @@ def main():
         swe.probe_copy(dst, src)
         torch.cuda.synchronize()
         del src, dst
+    if a.adjoint_only:
+        out = adjoint_ratio(torch, swe, W, a.adj_nx, a.adj_steps, a.adj_ckpt)
+        print(json.dumps({"adjoint": out}), flush=True)
+        return
     nx = a.nx
     p = W.reservoir_release(nx=nx, ny=nx, dx=20480.0 / nx)
     cells = p.nx * p.ny
@@ -200,6 +257,8 @@ def main():
         st3, ms3, _ = timed_run(torch, swe, W, p, a.dtype, nu, 2, a.tile_rows, path="unfused")
         out["variants"]["unfused_" + a.dtype] = {"value": cells * nu / (ms3 / 1e3),
                                                  "ms_per_step": ms3 / nu, "steps": nu}
+    if not a.no_adjoint:
+        out["adjoint"] = adjoint_ratio(torch, swe, W, a.adj_nx, a.adj_steps, a.adj_ckpt)
     if a.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(W, p, a.cpu_steps)
     print(json.dumps(out), flush=True)
