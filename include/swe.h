@@ -220,6 +220,41 @@ typedef struct swe_gauges {
 int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_every,
              double* loss, void* dJ_dn, void* dJ_dz);
 
+/* Ensemble (NEXT growth path: many independent scenarios per launch).
+ * `count` scenarios, each a full swe_config (its own grid size, bed, Manning
+ * field, state arrays, boundary kinds, hydrograph and CFL-adaptive dt; all of
+ * one dtype, path FUSED, t0 = 0).  Every time step of all scenarios is ONE
+ * launch of the fused step kernel over the concatenated tile lists
+ * (workgroup -> (scenario, tile) by a prefix-sum lookup); each scenario's dt
+ * is finalised by the last of its own workgroups, so scenarios keep separate
+ * time steps and stop independently (t_end, fatal flags).  The ensemble owns
+ * one non-blocking stream (cfg->stream is ignored) and the scenarios' scratch.
+ * tile_rows > 0 fixes the tile height for every scenario; 0 lets the
+ * library's autotuner time the candidate heights 16, 32, 64 and 128 on the
+ * ensemble itself (a few steps each, state restored afterwards) and keep the
+ * fastest (cached per set of grid sizes for the life of the process).
+ * Errors: as swe_create, plus SWE_EINVAL for mixed dtypes, an unfused path or
+ * t0 != 0. */
+typedef struct swe_ensemble swe_ensemble;
+int swe_ensemble_create(const swe_config* cfgs, int32_t count, int32_t tile_rows,
+                        swe_ensemble** out);
+void swe_ensemble_destroy(swe_ensemble* e);
+/* nsteps steps of every scenario (stopping each at t_end or a fatal flag),
+ * asynchronous; the final states are in the callers' arrays once the stream
+ * reaches the end. */
+int swe_ensemble_run(swe_ensemble* e, int64_t nsteps, double t_end);
+/* Capture one swe_ensemble_run(nsteps, +inf) (nsteps even, so that every
+ * replay starts on an even step) into a HIP graph; swe_ensemble_replay
+ * launches it once (asynchronous).  The graph holds kernel nodes only. */
+int swe_ensemble_capture(swe_ensemble* e, int64_t nsteps);
+int swe_ensemble_replay(swe_ensemble* e);
+/* Synchronise and fill out[0 .. count) (may be NULL: synchronise only).
+ * SWE_EUNSTABLE if any scenario raised a fatal flag. */
+int swe_ensemble_stats(swe_ensemble* e, swe_stats* out);
+/* Tile height in use (after autotuning). */
+int32_t swe_ensemble_tile_rows(const swe_ensemble* e);
+const char* swe_ensemble_last_error(const swe_ensemble* e);
+
 /* Plain device-to-device copy kernel of `bytes` bytes (multiple of 16, both
  * pointers 16-byte aligned) on `stream`: the bandwidth probe the HBM traffic
  * counters are calibrated against.  Asynchronous.  SWE_EINVAL on misuse. */

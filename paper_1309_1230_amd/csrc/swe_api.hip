@@ -12,6 +12,8 @@
 #include <string>
 #include <vector>
 
+#include <map>
+#include <string>
 #include "swe.h"
 #include "swe_internal.hpp"
 
@@ -743,6 +745,342 @@ int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_ev
     if (e != hipSuccess) return hip_fail(h, e, "swe_grad: reverse sweep");
     *loss = J;
     return SWE_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ ensemble
+
+struct swe_ensemble {
+    std::vector<swe_handle*> h;
+    int dtype = SWE_F64;
+    hipStream_t stream = nullptr;
+    int H = 0;
+    double args_t_end = -1.0;   // t_end the device argument arrays were built for
+    void* args[2] = {nullptr, nullptr};   // FusedArgs per scenario: even (A->B), odd (B->A)
+    int* first = nullptr;                 // count + 1 prefix sums of workgroups
+    int total = 0;
+    int64_t step_host = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t graph_steps = 0;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_ens_err = "no error";
+
+int efail(swe_ensemble* e, int code, const std::string& msg) {
+    if (e)
+        e->err = msg;
+    else
+        g_ens_err = msg;
+    return code;
+}
+
+template <typename T>
+swe::FusedArgs<T> fused_args_of(swe_handle* h, int parity, double t_end) {
+    swe::FusedArgs<T> a;
+    a.P = h->P;
+    a.ctl = h->ctl;
+    a.t_end = t_end;
+    const int s = parity & 1;
+    a.eta = (const T*)(s ? bufB(h, 0) : bufA(h, 0));
+    a.qx = (const T*)(s ? bufB(h, 1) : bufA(h, 1));
+    a.qy = (const T*)(s ? bufB(h, 2) : bufA(h, 2));
+    a.z = (const T*)h->z;
+    a.m = (const T*)bufB(h, 3);
+    a.eta1 = (T*)(s ? bufA(h, 0) : bufB(h, 0));
+    a.qx1 = (T*)(s ? bufA(h, 1) : bufB(h, 1));
+    a.qy1 = (T*)(s ? bufA(h, 2) : bufB(h, 2));
+    a.part_def = h->part;
+    a.part_vol = h->part + h->nparts;
+    a.gy = h->gy;
+    a.H = h->H;
+    return a;
+}
+
+template <typename T>
+hipError_t upload_args(swe_ensemble* e, double t_end) {
+    const size_t n = e->h.size();
+    for (int parity = 0; parity < 2; ++parity) {
+        std::vector<swe::FusedArgs<T>> v(n);
+        for (size_t k = 0; k < n; ++k) v[k] = fused_args_of<T>(e->h[k], parity, t_end);
+        hipError_t err = hipMemcpy(e->args[parity], v.data(), n * sizeof(swe::FusedArgs<T>),
+                                   hipMemcpyHostToDevice);
+        if (err != hipSuccess) return err;
+    }
+    e->args_t_end = t_end;
+    return hipSuccess;
+}
+
+hipError_t ens_upload(swe_ensemble* e, double t_end) {
+    return e->dtype == SWE_F32 ? upload_args<float>(e, t_end) : upload_args<double>(e, t_end);
+}
+
+// Give every scenario tile height H and rebuild the workgroup table.
+hipError_t ens_set_tile_rows(swe_ensemble* e, int H) {
+    std::vector<int> first(e->h.size() + 1, 0);
+    for (size_t k = 0; k < e->h.size(); ++k) {
+        swe_handle* h = e->h[k];
+        h->H = H;
+        h->gy = (h->P.ny + H - 1) / H;
+        first[k + 1] = first[k] + swe::fused_blocks(h->P.nx, h->P.ny, H);
+    }
+    e->H = H;
+    e->total = first.back();
+    hipError_t err = hipMemcpy(e->first, first.data(), first.size() * sizeof(int),
+                               hipMemcpyHostToDevice);
+    if (err == hipSuccess) err = ens_upload(e, e->args_t_end < 0.0 ? INFINITY : e->args_t_end);
+    return err;
+}
+
+hipError_t ens_enqueue(swe_ensemble* e, int64_t nsteps) {
+    hipError_t err = hipSuccess;
+    for (swe_handle* h : e->h)
+        if (err == hipSuccess) err = swe::launch_begin_call(h->ctl, e->stream);
+    const int count = (int)e->h.size();
+    for (int64_t k = 0; k < nsteps && err == hipSuccess; ++k) {
+        const int sigma = ((e->step_host + k) & 1) ? -1 : 1;
+        err = e->dtype == SWE_F32
+                  ? swe::launch_ensemble<float>((const swe::FusedArgs<float>*)e->args[k & 1],
+                                                e->first, count, e->total, sigma, e->stream)
+                  : swe::launch_ensemble<double>((const swe::FusedArgs<double>*)e->args[k & 1],
+                                                 e->first, count, e->total, sigma, e->stream);
+    }
+    for (swe_handle* h : e->h)
+        if (err == hipSuccess) err = enqueue_copy_back(h);
+    return err;
+}
+
+// Restore every scenario to its saved initial state (t = 0, step 0).
+hipError_t ens_restore(swe_ensemble* e, const std::vector<void*>& saved) {
+    hipError_t err = hipSuccess;
+    for (size_t k = 0; k < e->h.size() && err == hipSuccess; ++k) {
+        swe_handle* h = e->h[k];
+        const size_t n = state_elems(h) * h->elem;
+        for (int f = 0; f < 3 && err == hipSuccess; ++f)
+            err = hipMemcpyAsync(bufA(h, f), (char*)saved[k] + f * n, n, hipMemcpyDeviceToDevice,
+                                 e->stream);
+        if (err == hipSuccess) err = swe::launch_init_ctl(h->ctl, 0.0, 0, 0u, 0.0, e->stream);
+        if (err == hipSuccess)
+            err = h->dtype == SWE_F32
+                      ? swe::launch_scan<float>(h->P, h->ctl, INFINITY, (const float*)h->eta,
+                                                (const float*)h->qx, (const float*)h->qy,
+                                                (const float*)h->z, h->part, h->part + h->nparts,
+                                                0, e->stream)
+                      : swe::launch_scan<double>(h->P, h->ctl, INFINITY, (const double*)h->eta,
+                                                 (const double*)h->qx, (const double*)h->qy,
+                                                 (const double*)h->z, h->part,
+                                                 h->part + h->nparts, 0, e->stream);
+    }
+    e->step_host = 0;
+    return err;
+}
+
+// Time a few steps of the ensemble at each candidate tile height on the
+// ensemble itself, keep the fastest, restore the initial states.
+int ens_autotune(swe_ensemble* e) {
+    static std::map<std::string, int> cache;
+    std::string key = std::to_string(e->dtype);
+    for (swe_handle* h : e->h) key += "," + std::to_string(h->P.nx) + "x" + std::to_string(h->P.ny);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+        hipError_t err = ens_set_tile_rows(e, it->second);
+        return err == hipSuccess ? SWE_OK : efail(e, SWE_EDEVICE, hip_text(err));
+    }
+    std::vector<void*> saved(e->h.size(), nullptr);
+    auto release = [&]() {
+        for (void* p : saved)
+            if (p) (void)hipFree(p);
+    };
+    hipError_t err = hipSuccess;
+    for (size_t k = 0; k < e->h.size() && err == hipSuccess; ++k) {
+        swe_handle* h = e->h[k];
+        const size_t n = state_elems(h) * h->elem;
+        err = hipMalloc(&saved[k], 3 * n);
+        for (int f = 0; f < 3 && err == hipSuccess; ++f)
+            err = hipMemcpyAsync((char*)saved[k] + f * n, bufA(h, f), n, hipMemcpyDeviceToDevice,
+                                 e->stream);
+    }
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (err == hipSuccess) err = hipEventCreate(&ev0);
+    if (err == hipSuccess) err = hipEventCreate(&ev1);
+    int best = 0;
+    float best_ms = 0.0f;
+    for (int H : {16, 32, 64, 128}) {
+        if (err != hipSuccess) break;
+        err = ens_set_tile_rows(e, H);
+        if (err == hipSuccess) err = ens_enqueue(e, 2);
+        if (err == hipSuccess) err = hipEventRecord(ev0, e->stream);
+        e->step_host += 2;
+        if (err == hipSuccess) err = ens_enqueue(e, 6);
+        if (err == hipSuccess) err = hipEventRecord(ev1, e->stream);
+        if (err == hipSuccess) err = hipEventSynchronize(ev1);
+        float ms = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, ev0, ev1);
+        if (err == hipSuccess && (best == 0 || ms < best_ms)) {
+            best = H;
+            best_ms = ms;
+        }
+        if (err == hipSuccess) err = ens_restore(e, saved);
+    }
+    if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    release();
+    if (err == hipSuccess) err = ens_set_tile_rows(e, best);
+    if (err != hipSuccess) return efail(e, SWE_EDEVICE, std::string("autotuning: ") + hip_text(err));
+    cache[key] = best;
+    return SWE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void swe_ensemble_destroy(swe_ensemble* e) {
+    if (!e) return;
+    if (e->stream) (void)hipStreamSynchronize(e->stream);
+    if (e->exec) (void)hipGraphExecDestroy(e->exec);
+    if (e->graph) (void)hipGraphDestroy(e->graph);
+    for (swe_handle* h : e->h) swe_destroy(h);
+    if (e->args[0]) (void)hipFree(e->args[0]);
+    if (e->args[1]) (void)hipFree(e->args[1]);
+    if (e->first) (void)hipFree(e->first);
+    if (e->stream) (void)hipStreamDestroy(e->stream);
+    delete e;
+}
+
+int swe_ensemble_create(const swe_config* cfgs, int32_t count, int32_t tile_rows,
+                        swe_ensemble** out) {
+    if (!out) return efail(nullptr, SWE_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!cfgs || count < 1) return efail(nullptr, SWE_EINVAL, "need at least one scenario");
+    if (tile_rows < 0) return efail(nullptr, SWE_EINVAL, "tile_rows must be >= 0");
+    for (int k = 0; k < count; ++k) {
+        if (cfgs[k].dtype != cfgs[0].dtype) return efail(nullptr, SWE_EINVAL, "scenarios mix dtypes");
+        if (cfgs[k].path != SWE_PATH_FUSED) return efail(nullptr, SWE_EINVAL, "ensembles use the fused path");
+        if (cfgs[k].t0 != 0.0) return efail(nullptr, SWE_EINVAL, "ensemble scenarios start at t0 = 0");
+    }
+    swe_ensemble* e = new swe_ensemble;
+    e->dtype = cfgs[0].dtype;
+    hipError_t err = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking);
+    if (err != hipSuccess) {
+        e->stream = nullptr;
+        swe_ensemble_destroy(e);
+        return efail(nullptr, SWE_EDEVICE, std::string("hipStreamCreate: ") + hip_text(err));
+    }
+    for (int k = 0; k < count; ++k) {
+        swe_config c = cfgs[k];
+        c.stream = e->stream;
+        c.tile_rows = tile_rows > 0 ? tile_rows : 16;   // scratch sized for the smallest height
+        swe_handle* h = nullptr;
+        const int rc = swe_create(&c, &h);
+        if (rc != SWE_OK) {
+            const std::string msg = std::string("scenario ") + std::to_string(k) + ": " +
+                                    swe_last_error(nullptr);
+            swe_ensemble_destroy(e);
+            return efail(nullptr, rc, msg);
+        }
+        e->h.push_back(h);
+    }
+    const size_t asz = e->dtype == SWE_F32 ? sizeof(swe::FusedArgs<float>) : sizeof(swe::FusedArgs<double>);
+    if ((err = hipMalloc(&e->args[0], asz * count)) != hipSuccess ||
+        (err = hipMalloc(&e->args[1], asz * count)) != hipSuccess ||
+        (err = hipMalloc((void**)&e->first, sizeof(int) * (count + 1))) != hipSuccess) {
+        swe_ensemble_destroy(e);
+        return efail(nullptr, SWE_ENOMEM, std::string("hipMalloc: ") + hip_text(err));
+    }
+    e->args_t_end = INFINITY;
+    if (tile_rows > 0) {
+        err = ens_set_tile_rows(e, tile_rows);
+        if (err != hipSuccess) {
+            swe_ensemble_destroy(e);
+            return efail(nullptr, SWE_EDEVICE, hip_text(err));
+        }
+    } else {
+        const int rc = ens_autotune(e);
+        if (rc != SWE_OK) {
+            const std::string msg = e->err;
+            swe_ensemble_destroy(e);
+            return efail(nullptr, rc, msg);
+        }
+    }
+    *out = e;
+    return SWE_OK;
+}
+
+int swe_ensemble_run(swe_ensemble* e, int64_t nsteps, double t_end) {
+    if (!e) return efail(nullptr, SWE_EINVAL, "ensemble is NULL");
+    if (nsteps < 0 || std::isnan(t_end)) return efail(e, SWE_EINVAL, "bad nsteps or t_end");
+    hipError_t err = hipSuccess;
+    if (t_end != e->args_t_end) {
+        err = hipStreamSynchronize(e->stream);
+        if (err == hipSuccess) err = ens_upload(e, t_end);
+    }
+    if (err == hipSuccess) err = ens_enqueue(e, nsteps);
+    if (err != hipSuccess) return efail(e, SWE_EDEVICE, std::string("swe_ensemble_run: ") + hip_text(err));
+    e->step_host += nsteps;
+    return SWE_OK;
+}
+
+int swe_ensemble_capture(swe_ensemble* e, int64_t nsteps) {
+    if (!e) return efail(nullptr, SWE_EINVAL, "ensemble is NULL");
+    if (nsteps < 0 || (nsteps & 1)) return efail(e, SWE_EINVAL, "capture needs an even step count");
+    if (e->step_host & 1) return efail(e, SWE_EINVAL, "capture must start on an even step");
+    hipError_t err = hipStreamSynchronize(e->stream);
+    if (err == hipSuccess && e->args_t_end != INFINITY) err = ens_upload(e, INFINITY);
+    if (e->exec) {
+        (void)hipGraphExecDestroy(e->exec);
+        e->exec = nullptr;
+    }
+    if (e->graph) {
+        (void)hipGraphDestroy(e->graph);
+        e->graph = nullptr;
+    }
+    if (err == hipSuccess) err = hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal);
+    if (err == hipSuccess) {
+        const hipError_t enq = ens_enqueue(e, nsteps);
+        err = hipStreamEndCapture(e->stream, &e->graph);
+        if (enq != hipSuccess) err = enq;
+    }
+    if (err == hipSuccess) err = hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0);
+    if (err != hipSuccess) return efail(e, SWE_EDEVICE, std::string("graph capture: ") + hip_text(err));
+    e->graph_steps = nsteps;
+    return SWE_OK;
+}
+
+int swe_ensemble_replay(swe_ensemble* e) {
+    if (!e) return efail(nullptr, SWE_EINVAL, "ensemble is NULL");
+    if (!e->exec) return efail(e, SWE_EINVAL, "nothing captured");
+    if (e->step_host & 1) return efail(e, SWE_EINVAL, "replay must start on an even step");
+    hipError_t err = hipGraphLaunch(e->exec, e->stream);
+    if (err != hipSuccess) return efail(e, SWE_EDEVICE, std::string("hipGraphLaunch: ") + hip_text(err));
+    e->step_host += e->graph_steps;
+    return SWE_OK;
+}
+
+int swe_ensemble_stats(swe_ensemble* e, swe_stats* out) {
+    if (!e) return efail(nullptr, SWE_EINVAL, "ensemble is NULL");
+    hipError_t err = hipStreamSynchronize(e->stream);
+    if (err != hipSuccess) return efail(e, SWE_EDEVICE, hip_text(err));
+    int worst = SWE_OK;
+    for (size_t k = 0; k < e->h.size(); ++k) {
+        const int rc = fill_stats(e->h[k], out ? out + k : nullptr);
+        if (rc != SWE_OK) {
+            worst = rc;
+            e->err = "scenario " + std::to_string(k) + ": " + e->h[k]->err;
+        }
+    }
+    return worst;
+}
+
+int32_t swe_ensemble_tile_rows(const swe_ensemble* e) { return e ? e->H : 0; }
+
+const char* swe_ensemble_last_error(const swe_ensemble* e) {
+    return e ? e->err.c_str() : g_ens_err.c_str();
 }
 
 const char* swe_last_error(const swe_handle* h) {

@@ -353,8 +353,12 @@ struct March {
     }
 };
 
+// One workgroup's share of a fused step: tile `blk` of the nblk tiles of the
+// grid described by A (in the single-grid launch blk = blockIdx.x and nblk =
+// gridDim.x; in an ensemble launch, the workgroup's tile within its
+// scenario).  The last of the nblk workgroups to finish finalises the step.
 template <typename T, int SIG>
-__device__ __forceinline__ void fused_step(FusedArgs<T>& A) {
+__device__ __forceinline__ void fused_step(const FusedArgs<T>& A, int blk, int nblk) {
     Ctl* ctl = A.ctl;
     if (step_is_noop(ctl, A.t_end)) return;
     const Params& P = A.P;
@@ -372,7 +376,7 @@ __device__ __forceinline__ void fused_step(FusedArgs<T>& A) {
     M.pitch = P.pitch;
 
     const int lane = threadIdx.x;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int tile = xcd_tile(blk, nblk);
     const int pos = tile / A.gy, chunk = tile - pos * A.gy;
     // strips enumerated by residue class mod 8: each XCD's contiguous run of
     // tiles covers strips spread over the whole domain
@@ -410,9 +414,9 @@ __device__ __forceinline__ void fused_step(FusedArgs<T>& A) {
     unsigned ticket = 0;
     if (lane == 0) ticket = atomicAdd(&ctl->ticket, 1u);
     ticket = __shfl(ticket, 0, kWave);
-    if (ticket == gridDim.x - 1) {
+    if (ticket == (unsigned)nblk - 1) {
         __threadfence();
-        finalize_wave(ctl, P, A.part_def, A.part_vol, gridDim.x, sizeof(T) == 4, 1);
+        finalize_wave(ctl, P, A.part_def, A.part_vol, nblk, sizeof(T) == 4, 1);
     }
 }
 
@@ -421,11 +425,59 @@ __device__ __forceinline__ void fused_step(FusedArgs<T>& A) {
 // state and runs at 2 waves per SIMD (256 VGPRs), FP32 at 3 (168 VGPRs).
 template <int SIG>
 __global__ void __launch_bounds__(kWave, 2) k_fused_step_f64(FusedArgs<double> A) {
-    fused_step<double, SIG>(A);
+    fused_step<double, SIG>(A, blockIdx.x, gridDim.x);
 }
 template <int SIG>
 __global__ void __launch_bounds__(kWave, 3) k_fused_step_f32(FusedArgs<float> A) {
-    fused_step<float, SIG>(A);
+    fused_step<float, SIG>(A, blockIdx.x, gridDim.x);
+}
+
+// Ensemble launch: the workgroups of every scenario in one grid.  Scenario s
+// owns workgroups first[s] .. first[s+1]-1 (first[count] = total); its
+// arguments are args[s].  A workgroup finds its scenario by binary search.
+template <typename T>
+__device__ __forceinline__ void ensemble_locate(const int* first, int count, int& s, int& blk,
+                                                int& nblk) {
+    const int b = blockIdx.x;
+    int lo = 0, hi = count;   // first[lo] <= b < first[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (first[mid] <= b) lo = mid; else hi = mid;
+    }
+    s = lo;
+    blk = b - first[lo];
+    nblk = first[lo + 1] - first[lo];
+}
+
+template <int SIG>
+__global__ void __launch_bounds__(kWave, 2)
+k_ensemble_step_f64(const FusedArgs<double>* args, const int* first, int count) {
+    int sc, blk, nblk;
+    ensemble_locate<double>(first, count, sc, blk, nblk);
+    fused_step<double, SIG>(args[sc], blk, nblk);
+}
+template <int SIG>
+__global__ void __launch_bounds__(kWave, 3)
+k_ensemble_step_f32(const FusedArgs<float>* args, const int* first, int count) {
+    int sc, blk, nblk;
+    ensemble_locate<float>(first, count, sc, blk, nblk);
+    fused_step<float, SIG>(args[sc], blk, nblk);
+}
+
+template <typename T>
+hipError_t launch_ensemble(const FusedArgs<T>* args, const int* first, int count, int total,
+                           int sigma, hipStream_t s) {
+    if (total <= 0) return hipSuccess;
+    if constexpr (sizeof(T) == 8) {
+        const auto kp = &k_ensemble_step_f64<1>;
+        const auto km = &k_ensemble_step_f64<-1>;
+        hipLaunchKernelGGL(sigma > 0 ? kp : km, dim3(total), dim3(kWave), 0, s, args, first, count);
+    } else {
+        const auto kp = &k_ensemble_step_f32<1>;
+        const auto km = &k_ensemble_step_f32<-1>;
+        hipLaunchKernelGGL(sigma > 0 ? kp : km, dim3(total), dim3(kWave), 0, s, args, first, count);
+    }
+    return hipGetLastError();
 }
 
 template <typename T, int SIG>
@@ -466,6 +518,10 @@ int fused_waves_per_cu() {
     return nb;
 }
 
+template hipError_t launch_ensemble<float>(const FusedArgs<float>*, const int*, int, int, int,
+                                           hipStream_t);
+template hipError_t launch_ensemble<double>(const FusedArgs<double>*, const int*, int, int, int,
+                                            hipStream_t);
 template hipError_t launch_fused<float>(const FusedArgs<float>&, int, hipStream_t);
 template hipError_t launch_fused<double>(const FusedArgs<double>&, int, hipStream_t);
 template int fused_waves_per_cu<float>();

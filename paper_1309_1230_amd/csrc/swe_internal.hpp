@@ -29,6 +29,11 @@ struct FusedArgs {
 
 template <typename T>
 hipError_t launch_fused(const FusedArgs<T>& a, int sigma, hipStream_t s);
+// One fused step of every scenario of an ensemble in one launch: scenario s
+// owns workgroups first[s] .. first[s+1]-1 of `total` (args, first: device).
+template <typename T>
+hipError_t launch_ensemble(const FusedArgs<T>* args, const int* first, int count, int total,
+                           int sigma, hipStream_t s);
 int fused_blocks(int nx, int ny, int H);
 int fused_strips(int nx);
 // Resident fused workgroups (one wave each) per compute unit, or 0.

@@ -89,7 +89,10 @@ class Gauges(ctypes.Structure):
 #: every function include/swe.h declares
 EXPORTS = ("swe_abi_version", "swe_config_init", "swe_create", "swe_destroy", "swe_step",
            "swe_run", "swe_get_stats", "swe_trace_step", "swe_trace_bytes", "swe_save",
-           "swe_load", "swe_last_error", "swe_probe_copy", "swe_grad")
+           "swe_load", "swe_last_error", "swe_probe_copy", "swe_grad", "swe_ensemble_create",
+           "swe_ensemble_destroy", "swe_ensemble_run", "swe_ensemble_capture",
+           "swe_ensemble_replay", "swe_ensemble_stats", "swe_ensemble_tile_rows",
+           "swe_ensemble_last_error")
 
 _lib = None
 
@@ -133,6 +136,24 @@ def lib():
         L.swe_grad.argtypes = [H, ctypes.c_int64, ctypes.POINTER(Gauges), ctypes.c_int32,
                                ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_void_p]
         L.swe_grad.restype = ctypes.c_int
+        E = ctypes.c_void_p
+        L.swe_ensemble_create.argtypes = [ctypes.POINTER(Config), ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(E)]
+        L.swe_ensemble_create.restype = ctypes.c_int
+        L.swe_ensemble_destroy.argtypes = [E]
+        L.swe_ensemble_destroy.restype = None
+        L.swe_ensemble_run.argtypes = [E, ctypes.c_int64, ctypes.c_double]
+        L.swe_ensemble_run.restype = ctypes.c_int
+        L.swe_ensemble_capture.argtypes = [E, ctypes.c_int64]
+        L.swe_ensemble_capture.restype = ctypes.c_int
+        L.swe_ensemble_replay.argtypes = [E]
+        L.swe_ensemble_replay.restype = ctypes.c_int
+        L.swe_ensemble_stats.argtypes = [E, ctypes.POINTER(_Stats)]
+        L.swe_ensemble_stats.restype = ctypes.c_int
+        L.swe_ensemble_tile_rows.argtypes = [E]
+        L.swe_ensemble_tile_rows.restype = ctypes.c_int32
+        L.swe_ensemble_last_error.argtypes = [E]
+        L.swe_ensemble_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -158,53 +179,69 @@ def _stream_ptr(stream) -> Optional[int]:
     return s.cuda_stream
 
 
+def _make_config(z, n, eta, qx, qy, *, dx: float, dy: float, g: float = 9.81,
+                 cfl: float = 0.5, h_dry: float = 1e-3, kappa: float = 0.5, eps_max: float = 0.25,
+                 dt_max: float = 1.0, dt_fixed: float = 0.0, t0: float = 0.0,
+                 bc=(SWE_BC_WALL,) * 4, inflow_lo=(0, 0, 0, 0), inflow_hi=None,
+                 hydro_t=(), hydro_q=(), path: str = "fused", tile_rows: int = 0):
+    """Validate five field tensors and build a swe_config for them; returns
+    (config, objects the config points into)."""
+    torch = _torch()
+    fields = (z, n, eta, qx, qy)
+    dt0 = eta.dtype
+    if dt0 not in (torch.float32, torch.float64):
+        raise TypeError("fields must be float32 or float64")
+    for f in fields:
+        if f.dtype != dt0 or f.device != eta.device or f.dim() != 2 or not f.is_cuda:
+            raise TypeError("z, n, eta, qx, qy must be 2-D CUDA tensors of one dtype and device")
+        if f.shape != eta.shape or f.stride(1) != 1 or f.stride(0) != eta.stride(0):
+            raise TypeError("fields must share shape and row pitch, unit stride along x")
+    ny, nx = eta.shape
+    c = default_config()
+    c.nx, c.ny = nx, ny
+    c.dtype = SWE_F32 if dt0 == torch.float32 else SWE_F64
+    c.path = {"fused": SWE_PATH_FUSED, "unfused": SWE_PATH_UNFUSED}[path]
+    c.pitch = eta.stride(0)
+    c.tile_rows = int(tile_rows)
+    if inflow_hi is None:
+        inflow_hi = (ny, ny, nx, nx)
+    for k in range(4):
+        c.bc[k] = int(bc[k])
+        c.inflow_lo[k] = int(inflow_lo[k])
+        c.inflow_hi[k] = int(inflow_hi[k])
+    c.dx, c.dy, c.g, c.cfl, c.h_dry = float(dx), float(dy), float(g), float(cfl), float(h_dry)
+    c.kappa, c.eps_max, c.dt_max = float(kappa), float(eps_max), float(dt_max)
+    c.dt_fixed, c.t0 = float(dt_fixed), float(t0)
+    if len(hydro_t) != len(hydro_q):
+        raise ValueError("hydro_t and hydro_q differ in length")
+    ht = (ctypes.c_double * max(1, len(hydro_t)))(*[float(v) for v in hydro_t])
+    hq = (ctypes.c_double * max(1, len(hydro_q)))(*[float(v) for v in hydro_q])
+    c.hydro_len = len(hydro_t)
+    c.hydro_t = ctypes.cast(ht, ctypes.POINTER(ctypes.c_double))
+    c.hydro_q = ctypes.cast(hq, ctypes.POINTER(ctypes.c_double))
+    c.z, c.n = z.data_ptr(), n.data_ptr()
+    c.eta, c.qx, c.qy = eta.data_ptr(), qx.data_ptr(), qy.data_ptr()
+    return c, [ht, hq] + list(fields)
+
+
+def _problem_kwargs(p):
+    return dict(dx=p.dx, dy=p.dy, g=p.g, cfl=p.cfl, h_dry=p.h_dry, kappa=p.kappa,
+                eps_max=p.eps_max, dt_max=p.dt_max, dt_fixed=p.dt_fixed, bc=p.bc,
+                inflow_lo=p.inflow_lo, inflow_hi=p.inflow_hi, hydro_t=p.hydro_t,
+                hydro_q=p.hydro_q)
+
+
 class Solver:
     """A libswe handle over caller-owned device tensors (eta, qx, qy are
     advanced in place; z and n are read)."""
 
-    def __init__(self, z, n, eta, qx, qy, *, dx: float, dy: float, g: float = 9.81,
-                 cfl: float = 0.5, h_dry: float = 1e-3, kappa: float = 0.5, eps_max: float = 0.25,
-                 dt_max: float = 1.0, dt_fixed: float = 0.0, t0: float = 0.0,
-                 bc=(SWE_BC_WALL,) * 4, inflow_lo=(0, 0, 0, 0), inflow_hi=None,
-                 hydro_t=(), hydro_q=(), path: str = "fused", tile_rows: int = 0, stream=None):
+    def __init__(self, z, n, eta, qx, qy, *, path: str = "fused", tile_rows: int = 0,
+                 stream=None, **kw):
         torch = _torch()
-        fields = (z, n, eta, qx, qy)
-        dt0 = eta.dtype
-        if dt0 not in (torch.float32, torch.float64):
-            raise TypeError("fields must be float32 or float64")
-        for f in fields:
-            if f.dtype != dt0 or f.device != eta.device or f.dim() != 2 or not f.is_cuda:
-                raise TypeError("z, n, eta, qx, qy must be 2-D CUDA tensors of one dtype and device")
-            if f.shape != eta.shape or f.stride(1) != 1 or f.stride(0) != eta.stride(0):
-                raise TypeError("fields must share shape and row pitch, unit stride along x")
-        ny, nx = eta.shape
-        self._keep = list(fields)
-        self.nx, self.ny = nx, ny
-        self.dtype = dt0
-        c = default_config()
-        c.nx, c.ny = nx, ny
-        c.dtype = SWE_F32 if dt0 == torch.float32 else SWE_F64
-        c.path = {"fused": SWE_PATH_FUSED, "unfused": SWE_PATH_UNFUSED}[path]
-        c.pitch = eta.stride(0)
-        c.tile_rows = int(tile_rows)
-        if inflow_hi is None:
-            inflow_hi = (ny, ny, nx, nx)
-        for k in range(4):
-            c.bc[k] = int(bc[k])
-            c.inflow_lo[k] = int(inflow_lo[k])
-            c.inflow_hi[k] = int(inflow_hi[k])
-        c.dx, c.dy, c.g, c.cfl, c.h_dry = float(dx), float(dy), float(g), float(cfl), float(h_dry)
-        c.kappa, c.eps_max, c.dt_max = float(kappa), float(eps_max), float(dt_max)
-        c.dt_fixed, c.t0 = float(dt_fixed), float(t0)
-        ht = (ctypes.c_double * max(1, len(hydro_t)))(*[float(v) for v in hydro_t])
-        hq = (ctypes.c_double * max(1, len(hydro_q)))(*[float(v) for v in hydro_q])
-        if len(hydro_t) != len(hydro_q):
-            raise ValueError("hydro_t and hydro_q differ in length")
-        c.hydro_len = len(hydro_t)
-        c.hydro_t = ctypes.cast(ht, ctypes.POINTER(ctypes.c_double))
-        c.hydro_q = ctypes.cast(hq, ctypes.POINTER(ctypes.c_double))
-        c.z, c.n = z.data_ptr(), n.data_ptr()
-        c.eta, c.qx, c.qy = eta.data_ptr(), qx.data_ptr(), qy.data_ptr()
+        c, keep = _make_config(z, n, eta, qx, qy, path=path, tile_rows=tile_rows, **kw)
+        self._keep = keep
+        self.ny, self.nx = eta.shape
+        self.dtype = eta.dtype
         with torch.cuda.device(eta.device):
             c.stream = _stream_ptr(stream)
             h = ctypes.c_void_p()
@@ -221,11 +258,8 @@ class Solver:
         torch = _torch()
         dtype = dtype or torch.float64
         t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(device=device, dtype=dtype).contiguous()
-        return cls(t(p.z), t(p.n), t(p.eta), t(p.qx), t(p.qy), dx=p.dx, dy=p.dy, g=p.g, cfl=p.cfl,
-                   h_dry=p.h_dry, kappa=p.kappa, eps_max=p.eps_max, dt_max=p.dt_max,
-                   dt_fixed=p.dt_fixed, bc=p.bc, inflow_lo=p.inflow_lo, inflow_hi=p.inflow_hi,
-                   hydro_t=p.hydro_t, hydro_q=p.hydro_q, path=path, tile_rows=tile_rows,
-                   stream=stream)
+        return cls(t(p.z), t(p.n), t(p.eta), t(p.qx), t(p.qy), path=path, tile_rows=tile_rows,
+                   stream=stream, **_problem_kwargs(p))
 
     def _check(self, rc):
         if rc != SWE_OK:
@@ -369,3 +403,75 @@ def SweLoss():
     if _SweLoss is None:
         _SweLoss = _make_loss_function()
     return _SweLoss
+
+
+class Ensemble:
+    """Many independent scenarios advanced together: one fused-kernel launch
+    per time step for all of them (each keeps its own grid, fields,
+    boundaries and CFL-adaptive dt).  Fields are caller-owned CUDA tensors,
+    advanced in place; the ensemble runs on its own stream."""
+
+    def __init__(self, scenarios, tile_rows: int = 0):
+        """scenarios: list of (z, n, eta, qx, qy, kwargs) with the kwargs of
+        Solver (dx, dy, bc, hydrograph, ...)."""
+        cfgs = (Config * len(scenarios))()
+        self._keep = []
+        self.fields = []
+        for k, (z, n, eta, qx, qy, kw) in enumerate(scenarios):
+            c, keep = _make_config(z, n, eta, qx, qy, **kw)
+            cfgs[k] = c
+            self._keep += keep
+            self.fields.append((eta, qx, qy))
+        self.count = len(scenarios)
+        h = ctypes.c_void_p()
+        rc = lib().swe_ensemble_create(cfgs, self.count, int(tile_rows), ctypes.byref(h))
+        if rc != SWE_OK:
+            raise SweError(rc, (lib().swe_ensemble_last_error(None) or b"").decode())
+        self._e = h
+
+    @classmethod
+    def from_problems(cls, problems, dtype=None, device="cuda", tile_rows: int = 0):
+        torch = _torch()
+        dtype = dtype or torch.float32
+        t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(device=device, dtype=dtype).contiguous()
+        return cls([(t(p.z), t(p.n), t(p.eta), t(p.qx), t(p.qy), _problem_kwargs(p))
+                    for p in problems], tile_rows=tile_rows)
+
+    def _check(self, rc):
+        if rc != SWE_OK:
+            raise SweError(rc, (lib().swe_ensemble_last_error(self._e) or b"").decode())
+
+    @property
+    def tile_rows(self) -> int:
+        return int(lib().swe_ensemble_tile_rows(self._e))
+
+    def run(self, nsteps: int, t_end: float = math.inf):
+        """Enqueue nsteps steps of every scenario (asynchronous)."""
+        self._check(lib().swe_ensemble_run(self._e, int(nsteps), float(t_end)))
+
+    def capture(self, nsteps: int):
+        """Capture an nsteps run (nsteps even) into a HIP graph."""
+        self._check(lib().swe_ensemble_capture(self._e, int(nsteps)))
+
+    def replay(self):
+        """Launch the captured graph once (asynchronous)."""
+        self._check(lib().swe_ensemble_replay(self._e))
+
+    def stats(self, check: bool = True):
+        """Synchronise; per-scenario Stats."""
+        st = (_Stats * self.count)()
+        rc = lib().swe_ensemble_stats(self._e, st)
+        if check:
+            self._check(rc)
+        return [Solver._stats(x) for x in st]
+
+    def close(self):
+        if getattr(self, "_e", None):
+            lib().swe_ensemble_destroy(self._e)
+            self._e = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

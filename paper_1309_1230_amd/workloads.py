@@ -294,6 +294,39 @@ def calibration(nx: int = 1024, ny: int = 1024, dx: float = 2.0, seed: int = 100
                        nsteps=nsteps)
 
 
+def flood_scenario(index: int, nx: int, ny: int, dx: float = 2.0, seed_base: int = 100000,
+                   hills: int = 20, slope: float = 1e-3) -> Problem:
+    """One scenario of the flood ensemble: initially dry ground (a plane
+    sloping down along x plus `hills` Gaussian hills of height U(0, 5) m and
+    width U(0.05, 0.2) of the shorter side), a uniform Manning field
+    n ~ U(0.02, 0.06), a triangular inflow hydrograph on the whole west edge
+    (0 at t = 0, peak Q ~ U(0.5, 5) m^2/s at 20 s, 0 again at 60 s), open
+    east edge, walls north and south.  Seeded by seed_base + index."""
+    rng = np.random.default_rng(seed_base + index)
+    Lx, Ly = nx * dx, ny * dx
+    xc = (np.arange(nx) + 0.5) * dx
+    z = np.broadcast_to((slope * (Lx - xc))[None, :], (ny, nx)).copy()
+    side = min(Lx, Ly)
+    z += gaussian_hills(nx, ny, dx, dx, rng, hills, (0.0, 5.0), (0.05 * side, 0.2 * side))
+    n = np.full((ny, nx), rng.uniform(0.02, 0.06))
+    qp = rng.uniform(0.5, 5.0)
+    return Problem(nx=nx, ny=ny, dx=dx, dy=dx, z=z, n=n, eta=z.copy(), qx=np.zeros((ny, nx)),
+                   qy=np.zeros((ny, nx)), bc=(INFLOW, OPEN, WALL, WALL),
+                   hydro_t=(0.0, 20.0, 60.0), hydro_q=(0.0, qp, 0.0),
+                   name=f"flood{index}_{nx}x{ny}")
+
+
+def flood_ensemble(count: int = 256, seed: int = 1002, nx_range=(64, 1024), ny_range=(64, 512),
+                   dx: float = 2.0) -> list:
+    """The flood ensemble: `count` scenarios whose grid sizes are drawn from
+    `seed` uniformly in nx_range x ny_range (integers, non-square allowed),
+    each built by flood_scenario."""
+    rng = np.random.default_rng(seed)
+    nxs = rng.integers(nx_range[0], nx_range[1] + 1, count)
+    nys = rng.integers(ny_range[0], ny_range[1] + 1, count)
+    return [flood_scenario(k, int(nxs[k]), int(nys[k]), dx=dx) for k in range(count)]
+
+
 def random_valid_state(nx: int, ny: int, seed: int, dry_fraction: float = 0.2,
                        dx: float = 1.0) -> Problem:
     """Rough random state with wet, thin and dry cells, banks and every
