@@ -12,7 +12,9 @@ Prints one JSON line: cell-updates/s, the roofline of the fused step kernel
 (algorithmic bytes 64 B/cell-update in FP64, 32 B in FP32, over the kernel's
 average duration from HIP events on its stream, against 8 TB/s HBM), the
 adjoint/forward cost ratio on the 1024 x 1024 Manning calibration workload,
-and the CPU oracle timed on a bounded sample of the reservoir workload.
+the flood-ensemble throughput (256 scenarios in one launch per step, graph
+replay) against one-grid-at-a-time runs, and the CPU oracle timed on a
+bounded sample of the reservoir workload.
 
     python bench.py [--steps K] [--warmup W] [--dtype f64|f32]
 """
@@ -84,6 +86,12 @@ def parse():
     ap.add_argument("--adj-nx", type=int, default=1024)
     ap.add_argument("--adj-steps", type=int, default=2000)
     ap.add_argument("--adj-ckpt", type=int, default=45)
+    ap.add_argument("--no-ensemble", action="store_true",
+                    help="skip the flood-ensemble throughput measurement")
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="run only the ensemble measurement (for profiling)")
+    ap.add_argument("--ens-count", type=int, default=256)
+    ap.add_argument("--ens-steps", type=int, default=500)
     ap.add_argument("--probe-copy-mb", type=int, default=0,
                     help="also run the library's plain copy kernel once over this many MiB "
                          "(calibrates HBM traffic counters)")
@@ -167,6 +175,46 @@ def adjoint_ratio(torch, swe, W, nx, nsteps, ckpt):
             "loss": J, "max_abs_dJ_dn": float(gn.abs().max()), "max_abs_dJ_dz": float(gz.abs().max())}
 
 
+def ensemble_throughput(torch, swe, W, count, nsteps):
+    """Flood ensemble: `count` scenarios (FP32) advanced together, one
+    fused launch per step for all of them, the nsteps-step run captured in a
+    HIP graph and replayed; against the same scenarios run one grid at a time
+    through the single-grid library, one after another."""
+    probs = W.flood_ensemble(count=count)
+    cells = sum(p.nx * p.ny for p in probs)
+    progress(f"ensemble: {count} scenarios, {cells / 1e6:.1f} M cells, {nsteps} steps")
+    e = swe.Ensemble.from_problems(probs, dtype=torch.float32, tile_rows=0)
+    H = e.tile_rows
+    e.capture(nsteps)
+    e.close()
+    e = swe.Ensemble.from_problems(probs, dtype=torch.float32, tile_rows=H)
+    e.capture(nsteps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e.replay()
+    st = e.stats()
+    t_ens = time.perf_counter() - t0
+    steps = sum(x.step for x in st)
+    e.close()
+    solvers = [swe.Solver.from_problem(p, dtype=torch.float32) for p in probs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in solvers:
+        s.run(nsteps)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    for s in solvers:
+        s.close()
+    cu = sum(p.nx * p.ny for p in probs) * nsteps
+    progress(f"ensemble: graph replay {t_ens * 1e3:.1f} ms, one grid at a time {t_seq * 1e3:.1f} ms")
+    return {"workload": f"flood ensemble: {count} scenarios, grids 64..1024 x 64..512 (seeded), "
+                        f"{cells} cells, FP32, {nsteps}-step run captured in a HIP graph",
+            "metric": "ensemble cells/s", "value": cu / t_ens, "unit": "cell-updates/s",
+            "sequential_value": cu / t_seq, "speedup_vs_sequential": t_seq / t_ens,
+            "tile_rows": H, "ms": t_ens * 1e3, "sequential_ms": t_seq * 1e3,
+            "steps_taken": steps}
+
+
 def cpu_baseline(W, p, nsteps):
     from oracle import oracle as O
     progress(f"CPU oracle baseline: {nsteps} timed steps of {p.nx}x{p.ny}")
@@ -206,6 +254,10 @@ def main():
         swe.probe_copy(dst, src)
         torch.cuda.synchronize()
         del src, dst
+    if a.ensemble_only:
+        out = ensemble_throughput(torch, swe, W, a.ens_count, a.ens_steps)
+        print(json.dumps({"ensemble": out}), flush=True)
+        return
     if a.adjoint_only:
         out = adjoint_ratio(torch, swe, W, a.adj_nx, a.adj_steps, a.adj_ckpt)
         print(json.dumps({"adjoint": out}), flush=True)
@@ -259,6 +311,8 @@ def main():
                                                  "ms_per_step": ms3 / nu, "steps": nu}
     if not a.no_adjoint:
         out["adjoint"] = adjoint_ratio(torch, swe, W, a.adj_nx, a.adj_steps, a.adj_ckpt)
+    if not a.no_ensemble:
+        out["ensemble"] = ensemble_throughput(torch, swe, W, a.ens_count, a.ens_steps)
     if a.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(W, p, a.cpu_steps)
     print(json.dumps(out), flush=True)
