@@ -11,8 +11,9 @@ the state already resident in HBM.
 Prints one JSON line: cell-updates/s, the roofline of the fused step kernel
 (algorithmic bytes 64 B/cell-update in FP64, 32 B in FP32, over the kernel's
 average duration from HIP events on its stream, against 8 TB/s HBM), the
-adjoint/forward cost ratio on the 1024 x 1024 Manning calibration workload,
-the flood-ensemble throughput (256 scenarios in one launch per step, graph
+the same run with the dry-tile skip (dense-equivalent and active cell-update
+rates), the adjoint/forward cost ratio on the 1024 x 1024 Manning calibration
+workload, the flood-ensemble throughput (256 scenarios in one launch per step, graph
 replay) against one-grid-at-a-time runs, and the CPU oracle timed on a
 bounded sample of the reservoir workload.
 
@@ -92,6 +93,10 @@ def parse():
                     help="run only the ensemble measurement (for profiling)")
     ap.add_argument("--ens-count", type=int, default=256)
     ap.add_argument("--ens-steps", type=int, default=500)
+    ap.add_argument("--no-dry-skip", action="store_true",
+                    help="skip the dry-tile-skip measurement of the reservoir workload")
+    ap.add_argument("--dry-only", action="store_true",
+                    help="run only the dense and dry-skip reservoir runs (for profiling)")
     ap.add_argument("--probe-copy-mb", type=int, default=0,
                     help="also run the library's plain copy kernel once over this many MiB "
                          "(calibrates HBM traffic counters)")
@@ -103,14 +108,15 @@ def bytes_per_cell(dtype):
     return 8 * (8 if dtype == "f64" else 4)
 
 
-def timed_run(torch, swe, W, p, dtype, steps, warmup, tile_rows, path="fused"):
+def timed_run(torch, swe, W, p, dtype, steps, warmup, tile_rows, path="fused", dry_skip=False):
     tdt = torch.float64 if dtype == "f64" else torch.float32
     if warmup > 0:
-        w = swe.Solver.from_problem(p, dtype=tdt, path=path, tile_rows=tile_rows)
+        w = swe.Solver.from_problem(p, dtype=tdt, path=path, tile_rows=tile_rows,
+                                    dry_skip=dry_skip)
         w.run(warmup)
         w.close()
         del w
-    s = swe.Solver.from_problem(p, dtype=tdt, path=path, tile_rows=tile_rows)
+    s = swe.Solver.from_problem(p, dtype=tdt, path=path, tile_rows=tile_rows, dry_skip=dry_skip)
     stream = torch.cuda.current_stream()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -215,6 +221,24 @@ def ensemble_throughput(torch, swe, W, count, nsteps):
             "steps_taken": steps}
 
 
+def dry_skip_run(torch, swe, W, p, dtype, steps, warmup, tile_rows, dense_st, dense_ms):
+    """The reservoir workload again with the dry-tile skip on.  Dense-
+    equivalent throughput counts every cell of every step; active throughput
+    counts only the cell updates the kernel computed."""
+    progress(f"dry skip: timing {steps} {dtype} steps")
+    st, ms, _ = timed_run(torch, swe, W, p, dtype, steps, warmup, tile_rows, dry_skip=True)
+    total = p.nx * p.ny * steps
+    same = all(getattr(st, f) == getattr(dense_st, f)
+               for f in ("t", "dt", "volume", "defect", "lambda_max", "dt_min", "dt_max"))
+    progress(f"dry skip {dtype}: {ms / steps * 1e3:.1f} us/step, skipped "
+             f"{st.cells_skipped / total:.3f} of the cell updates, stats equal: {same}")
+    return {"dtype": dtype, "ms_per_step": ms / steps,
+            "dense_equivalent_value": total / (ms / 1e3),
+            "active_value": (total - st.cells_skipped) / (ms / 1e3),
+            "unit": "cell-updates/s", "skipped_fraction": st.cells_skipped / total,
+            "speedup_vs_dense": dense_ms / ms, "stats_equal_to_dense": same}
+
+
 def cpu_baseline(W, p, nsteps):
     from oracle import oracle as O
     progress(f"CPU oracle baseline: {nsteps} timed steps of {p.nx}x{p.ny}")
@@ -299,6 +323,11 @@ def main():
                      "bytes_per_cell_update": bpc},
         "wall_s": wall,
     }
+    if a.dry_only:
+        out["dry_skip"] = dry_skip_run(torch, swe, W, p, a.dtype, a.steps, a.warmup, a.tile_rows,
+                                       st, ms)
+        print(json.dumps(out), flush=True)
+        return
     if not a.no_variants:
         other = "f32" if a.dtype == "f64" else "f64"
         st2, ms2, _ = timed_run(torch, swe, W, p, other, a.steps, a.warmup, a.tile_rows)
@@ -309,6 +338,12 @@ def main():
         st3, ms3, _ = timed_run(torch, swe, W, p, a.dtype, nu, 2, a.tile_rows, path="unfused")
         out["variants"]["unfused_" + a.dtype] = {"value": cells * nu / (ms3 / 1e3),
                                                  "ms_per_step": ms3 / nu, "steps": nu}
+    if not a.no_dry_skip:
+        out["dry_skip"] = dry_skip_run(torch, swe, W, p, a.dtype, a.steps, a.warmup, a.tile_rows,
+                                       st, ms)
+        if not a.no_variants:
+            out["dry_skip_" + other] = dry_skip_run(torch, swe, W, p, other, a.steps, a.warmup,
+                                                    a.tile_rows, st2, ms2)
     if not a.no_adjoint:
         out["adjoint"] = adjoint_ratio(torch, swe, W, a.adj_nx, a.adj_steps, a.adj_ckpt)
     if not a.no_ensemble:

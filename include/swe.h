@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define SWE_ABI_VERSION 1
+#define SWE_ABI_VERSION 2
 
 typedef enum swe_status {
     SWE_OK = 0,
@@ -98,6 +98,16 @@ typedef struct swe_config {
     void* qx;                /* device, in/out: unit discharge along x (m^2/s) */
     void* qy;                /* device, in/out: unit discharge along y (m^2/s) */
     void* stream;            /* hipStream_t, or NULL */
+    int32_t dry_skip;        /* 1: dry-tile skip (FUSED only), 0: every tile computed.
+                              * A tile of the fused kernel whose cells, and the cells
+                              * of its eight neighbour tiles, were all dry (h <= h_dry,
+                              * zero discharge) after the previous step and that lies
+                              * at least two cells from every edge is left out: the
+                              * step provably maps it to itself, so results are bit
+                              * for bit those of the dense step.  Flags are rebuilt
+                              * from a dense first step at the start of every call
+                              * (swe_run, swe_step, ensemble run or replay), so the
+                              * caller may change the state between calls. */
 } swe_config;
 
 /* Progress and diagnostics of a handle. */
@@ -113,6 +123,7 @@ typedef struct swe_stats {
     double volume;           /* sum of (eta - z) dx dy over the state (m^3) */
     double defect;           /* clipped volume added since create (m^3) */
     double lambda_max;       /* max over wet cells of (|u|+c)/dx + (|v|+c)/dy */
+    int64_t cells_skipped;   /* cell updates of the call left out by the dry-tile skip */
 } swe_stats;
 
 /* Scalars needed to resume a run bitwise: the caller saves its own eta, qx,

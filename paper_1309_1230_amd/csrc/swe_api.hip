@@ -39,6 +39,8 @@ struct swe_handle {
     int nparts = 0;
     double* hydro = nullptr;   // device copy of (t, q)
     void* trace = nullptr;     // unfused scratch: 47 padded arrays + zp + mp
+    unsigned* dry = nullptr;   // dry-tile skip flags (2 * nparts words), or NULL
+    void* fpart = nullptr;     // fused path: tile and group records, group tickets
     long long step_host = 0;
     std::string err;
 };
@@ -139,11 +141,18 @@ hipError_t enqueue_step(swe_handle* h, int64_t k, double t_end, bool unfused) {
     a.z = (const T*)h->z;
     a.m = (const T*)bufB(h, 3);
     a.eta1 = dst[0]; a.qx1 = dst[1]; a.qy1 = dst[2];
-    a.part_def = h->part;
-    a.part_vol = h->part + h->nparts;
+    swe::fused_part_layout(a, h->fpart, h->nparts);
     a.gy = h->gy;
     a.H = h->H;
+    a.dry = h->dry;
     return swe::launch_fused<T>(a, sigma, h->stream);
+}
+
+// Start of a host call: per-call statistics reset and, with the dry-tile
+// skip on, every tile flag cleared (the caller may have changed the state
+// since the last call, so the first step of a call computes every tile).
+hipError_t begin_call(swe_handle* h, hipStream_t s) {
+    return swe::launch_begin_call(h->ctl, s, h->dry, 2 * h->nparts);
 }
 
 hipError_t enqueue(swe_handle* h, int64_t k, double t_end, bool unfused) {
@@ -197,6 +206,7 @@ int fill_stats(swe_handle* h, swe_stats* out) {
         out->volume = c.volume;
         out->defect = c.defect;
         out->lambda_max = c.lam_max;
+        out->cells_skipped = (int64_t)c.skipped;
     }
     if (c.flags & swe::FLAG_FATAL) {
         char buf[160];
@@ -219,19 +229,22 @@ bool is_device_ptr(const void* p, int device) {
 // Rows per fused workgroup: as many chunks per strip as there are resident
 // wave slots on the device, so the whole grid runs in one round of waves (a
 // partial second round would leave most of the GPU idle), but never fewer
-// than 16 rows (the two-row halo at each chunk end costs (H+4)/H).
-int auto_tile_rows(const swe_handle* h, int dev) {
+// than 16 rows (the two-row halo at each chunk end costs (H+4)/H).  With
+// the dry-tile skip at most 32 rows: smaller tiles follow the wet/dry front
+// more closely, and the skipped ones free their wave slot at once.
+int auto_tile_rows(const swe_handle* h, int dev, bool dry_skip) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
     const int per_cu = h->dtype == SWE_F32 ? swe::fused_waves_per_cu<float>()
                                            : swe::fused_waves_per_cu<double>();
     const long long slots = (long long)cus * per_cu;
     const int gx = swe::fused_strips(h->P.nx);
-    if (slots <= 0) return 128;
+    if (slots <= 0) return dry_skip ? 32 : 128;
     long long gy = slots / gx;
     if (gy < 1) gy = 1;
     int H = (int)((h->P.ny + gy - 1) / gy);
     if (H < 16) H = 16;
+    if (dry_skip && H > 32) H = 32;
     return H;
 }
 
@@ -257,6 +270,8 @@ int validate(const swe_config* c, std::string& why) {
     if (std::isnan(c->dt_fixed) || std::isinf(c->dt_fixed)) return bad("dt_fixed must be finite");
     if (!std::isfinite(c->t0)) return bad("t0 must be finite");
     if (c->tile_rows < 0 || c->tile_rows > 65536) return bad("tile_rows out of range");
+    if (c->dry_skip != 0 && c->dry_skip != 1) return bad("dry_skip must be 0 or 1");
+    if (c->dry_skip && c->path != SWE_PATH_FUSED) return bad("dry_skip needs the fused path");
     for (int k = 0; k < 4; ++k) {
         if (c->bc[k] < SWE_BC_WALL || c->bc[k] > SWE_BC_INFLOW) return bad("unknown boundary kind");
     }
@@ -345,7 +360,7 @@ int swe_create(const swe_config* c, swe_handle** out) {
     P.kappa = c->kappa; P.eps_max = c->eps_max; P.dt_max = c->dt_max; P.dt_fixed = c->dt_fixed;
     P.idx = 1.0 / c->dx;
     P.idy = 1.0 / c->dy;
-    h->H = c->tile_rows > 0 ? c->tile_rows : auto_tile_rows(h, dev);
+    h->H = c->tile_rows > 0 ? c->tile_rows : auto_tile_rows(h, dev, c->dry_skip != 0);
     h->gy = (c->ny + h->H - 1) / h->H;
     h->nparts = std::max(swe::fused_blocks(c->nx, c->ny, h->H), swe::scan_partials(c->nx, c->ny));
 
@@ -376,6 +391,19 @@ int swe_create(const swe_config* c, swe_handle** out) {
                        h->stream);
     P.hydro_t = h->hydro;
     P.hydro_q = h->hydro + std::max(0, c->hydro_len);
+    if (c->dry_skip) {
+        if ((e = hipMalloc((void**)&h->dry, 2 * sizeof(unsigned) * (size_t)h->nparts)) != hipSuccess) {
+            h->dry = nullptr;
+            fail(nullptr, SWE_ENOMEM, std::string("hipMalloc failed: ") + hip_text(e));
+            return cleanup(SWE_ENOMEM);
+        }
+    }
+    if ((e = hipMalloc(&h->fpart, swe::fused_part_bytes(h->nparts))) != hipSuccess) {
+        h->fpart = nullptr;
+        fail(nullptr, SWE_ENOMEM, std::string("hipMalloc failed: ") + hip_text(e));
+        return cleanup(SWE_ENOMEM);
+    }
+    e = hipMemsetAsync(h->fpart, 0, swe::fused_part_bytes(h->nparts), h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->part, 0, 2 * sizeof(double) * h->nparts, h->stream);
     if (e == hipSuccess)
         e = h->dtype == SWE_F32
@@ -419,6 +447,8 @@ void swe_destroy(swe_handle* h) {
     if (h->part) (void)hipFree(h->part);
     if (h->hydro) (void)hipFree(h->hydro);
     if (h->trace) (void)hipFree(h->trace);
+    if (h->dry) (void)hipFree(h->dry);
+    if (h->fpart) (void)hipFree(h->fpart);
     delete h;
 }
 
@@ -427,7 +457,7 @@ int swe_run(swe_handle* h, int64_t nsteps, double t_end, swe_stats* out) {
     if (nsteps < 0) return fail(h, SWE_EINVAL, "nsteps must be >= 0");
     if (std::isnan(t_end)) return fail(h, SWE_EINVAL, "t_end is NaN");
     const bool unfused = h->path == SWE_PATH_UNFUSED;
-    hipError_t e = swe::launch_begin_call(h->ctl, h->stream);
+    hipError_t e = begin_call(h, h->stream);
     for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) e = enqueue(h, k, t_end, unfused);
     if (e == hipSuccess) e = enqueue_copy_back(h);
     if (e != hipSuccess) return hip_fail(h, e, "launching the step kernels");
@@ -444,7 +474,7 @@ int swe_step(swe_handle* h, double* dt_used) {
         if (e != hipSuccess) return hip_fail(h, e, "reading the control block");
         dt_before = c.dt;
     }
-    hipError_t e = swe::launch_begin_call(h->ctl, h->stream);
+    hipError_t e = begin_call(h, h->stream);
     if (e == hipSuccess) e = enqueue(h, 0, INFINITY, h->path == SWE_PATH_UNFUSED);
     if (e == hipSuccess) e = enqueue_copy_back(h);
     if (e != hipSuccess) return hip_fail(h, e, "launching the step kernels");
@@ -478,7 +508,7 @@ int swe_trace_step(swe_handle* h, void* arrays, size_t bytes, double* scalars) {
     Ctl before, after;
     hipError_t e = hipMemcpyAsync(&before, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e == hipSuccess) e = swe::launch_begin_call(h->ctl, h->stream);
+    if (e == hipSuccess) e = begin_call(h, h->stream);
     if (e == hipSuccess) e = enqueue(h, 0, INFINITY, true);
     if (e == hipSuccess) e = enqueue_copy_back(h);
     if (e == hipSuccess)
@@ -632,7 +662,7 @@ int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_ev
         for (int f = 0; f < 3; ++f) U[f] = base + ((size_t)m * 3 + f) * fe;
     };
     // ---- forward: the run itself, with checkpoints, time steps and misfits
-    if (e == hipSuccess) e = swe::launch_begin_call(h->ctl, h->stream);
+    if (e == hipSuccess) e = begin_call(h, h->stream);
     for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) {
         double* cur[3];
         for (int f = 0; f < 3; ++f) cur[f] = (double*)((k & 1) ? bufB(h, f) : bufA(h, f));
@@ -700,8 +730,7 @@ int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_ev
             fa.z = (const double*)h->z;
             fa.m = (const double*)bufB(h, 3);
             fa.eta1 = Un[0]; fa.qx1 = Un[1]; fa.qy1 = Un[2];
-            fa.part_def = h->part;
-            fa.part_vol = h->part + h->nparts;
+            swe::fused_part_layout(fa, h->fpart, h->nparts);
             fa.gy = h->gy;
             fa.H = h->H;
             e = swe::launch_fused<double>(fa, ((step0 + k) & 1) ? -1 : 1, h->stream);
@@ -794,10 +823,10 @@ swe::FusedArgs<T> fused_args_of(swe_handle* h, int parity, double t_end) {
     a.eta1 = (T*)(s ? bufA(h, 0) : bufB(h, 0));
     a.qx1 = (T*)(s ? bufA(h, 1) : bufB(h, 1));
     a.qy1 = (T*)(s ? bufA(h, 2) : bufB(h, 2));
-    a.part_def = h->part;
-    a.part_vol = h->part + h->nparts;
+    swe::fused_part_layout(a, h->fpart, h->nparts);
     a.gy = h->gy;
     a.H = h->H;
+    a.dry = h->dry;
     return a;
 }
 
@@ -839,15 +868,17 @@ hipError_t ens_set_tile_rows(swe_ensemble* e, int H) {
 hipError_t ens_enqueue(swe_ensemble* e, int64_t nsteps) {
     hipError_t err = hipSuccess;
     for (swe_handle* h : e->h)
-        if (err == hipSuccess) err = swe::launch_begin_call(h->ctl, e->stream);
+        if (err == hipSuccess) err = begin_call(h, e->stream);
     const int count = (int)e->h.size();
+    bool dry = false;
+    for (swe_handle* h : e->h) dry = dry || h->dry != nullptr;
     for (int64_t k = 0; k < nsteps && err == hipSuccess; ++k) {
         const int sigma = ((e->step_host + k) & 1) ? -1 : 1;
         err = e->dtype == SWE_F32
                   ? swe::launch_ensemble<float>((const swe::FusedArgs<float>*)e->args[k & 1],
-                                                e->first, count, e->total, sigma, e->stream)
+                                                e->first, count, e->total, sigma, dry, e->stream)
                   : swe::launch_ensemble<double>((const swe::FusedArgs<double>*)e->args[k & 1],
-                                                 e->first, count, e->total, sigma, e->stream);
+                                                 e->first, count, e->total, sigma, dry, e->stream);
     }
     for (swe_handle* h : e->h)
         if (err == hipSuccess) err = enqueue_copy_back(h);

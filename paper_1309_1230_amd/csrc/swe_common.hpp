@@ -68,6 +68,7 @@ struct Ctl {
     unsigned last_step_flags;
     unsigned ticket;     // blocks of the step in flight that have finished
     unsigned long long lam_bits;  // running max of lam (IEEE bits, lam >= 0)
+    unsigned long long skipped;   // cell updates the dry-tile skip left out, this call
 };
 
 struct Params {
@@ -262,25 +263,49 @@ __device__ __forceinline__ unsigned wave_or(unsigned v) {
     return v;
 }
 
-// Publish one block's contribution to a step: max lam (bits), flags and its
-// defect/volume partial sums (slot `blk`).  Called by every lane of the
-// block's first wave with wave-reduced values.
-__device__ __forceinline__ void publish_partial(Ctl* ctl, double* part_def, double* part_vol,
-                                                int blk, unsigned long long lam_bits,
-                                                unsigned flags, double def, double vol) {
-    if (threadIdx.x == 0) {
-        part_def[blk] = def;
-        part_vol[blk] = vol;
-        if (lam_bits) atomicMax(&ctl->lam_bits, lam_bits);
-        if (flags) atomicOr(&ctl->step_flags, flags);
+// Finalise a step (mode 1) or the initial scan (mode 0) from its reduced
+// partials: defect and volume sums sd, sv (depth units), lam_max, and the
+// flags the step raised.  Computes dt^{n+1} and the inflow values of the
+// next step, advances t and the step counter, and clears the accumulators
+// for the next launch.  One lane.
+__device__ inline void finalize_scalars(Ctl* ctl, const Params& P, double sd, double sv,
+                                        double lam, unsigned sf, int mode) {
+    double dtn = next_dt(P, lam);
+    if (!__builtin_isfinite(lam)) sf |= FLAG_NAN;
+    if (!(dtn > 0.0) || !__builtin_isfinite(dtn)) sf |= FLAG_BADDT;
+    const double area = P.dx * P.dy;
+    if (mode == 1) {
+        double dt_used = ctl->dt;
+        ctl->defect = ctl->defect + sd * area;
+        ctl->last_defect_depth = sd;
+        ctl->t = ctl->t + dt_used;
+        ctl->dt_min = dt_used < ctl->dt_min ? dt_used : ctl->dt_min;
+        ctl->dt_max_used = dt_used > ctl->dt_max_used ? dt_used : ctl->dt_max_used;
+        if ((sf & FLAG_FATAL) && ctl->bad_step < 0) ctl->bad_step = ctl->step;
+        ctl->step = ctl->step + 1;
+        ctl->call_steps = ctl->call_steps + 1;
     }
+    ctl->flags |= sf;
+    ctl->last_step_flags = sf;
+    ctl->volume = sv * area;
+    ctl->lam_max = lam;
+    ctl->dt = dtn;
+    ctl->rx = dtn / P.dx;
+    ctl->ry = dtn / P.dy;
+    ctl->qin0 = q_inflow(P, ctl->t);
+    ctl->qin1 = q_inflow(P, ctl->t + dtn);
+    ctl->lam_bits = 0ull;
+    ctl->step_flags = 0u;
+    ctl->ticket = 0u;
 }
 
-// Finalise a step (mode 1) or the initial scan (mode 0): one wave sums the
-// nparts partials in a fixed order, decodes lam_max, computes dt^{n+1} and
-// the inflow values of the next step, advances t and the step counter, and
-// clears the accumulators for the next launch.  Must run after every block
-// of the step has published (a kernel boundary or the ticket protocol).
+__device__ __forceinline__ double lam_from_bits(unsigned long long bits, bool lam_is_f32) {
+    return lam_is_f32 ? (double)__uint_as_float((unsigned)bits) : __longlong_as_double((long long)bits);
+}
+
+// Finalisation after a kernel boundary (unfused path, initial scan): one wave
+// sums the nparts partials in a fixed order; lam_max and the flags come from
+// the control block's accumulators.
 __device__ inline void finalize_wave(Ctl* ctl, const Params& P, const double* part_def,
                                      const double* part_vol, int nparts, bool lam_is_f32,
                                      int mode) {
@@ -295,39 +320,25 @@ __device__ inline void finalize_wave(Ctl* ctl, const Params& P, const double* pa
     if (lane == 0) {
         unsigned long long bits = __hip_atomic_load(&ctl->lam_bits, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
-        double lam = lam_is_f32 ? (double)__uint_as_float((unsigned)bits)
-                                : __longlong_as_double((long long)bits);
         unsigned sf = __hip_atomic_load(&ctl->step_flags, __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT);
-        double dtn = next_dt(P, lam);
-        if (!__builtin_isfinite(lam)) sf |= FLAG_NAN;
-        if (!(dtn > 0.0) || !__builtin_isfinite(dtn)) sf |= FLAG_BADDT;
-        const double area = P.dx * P.dy;
-        if (mode == 1) {
-            double dt_used = ctl->dt;
-            ctl->defect = ctl->defect + sd * area;
-            ctl->last_defect_depth = sd;
-            ctl->t = ctl->t + dt_used;
-            ctl->dt_min = dt_used < ctl->dt_min ? dt_used : ctl->dt_min;
-            ctl->dt_max_used = dt_used > ctl->dt_max_used ? dt_used : ctl->dt_max_used;
-            if ((sf & FLAG_FATAL) && ctl->bad_step < 0) ctl->bad_step = ctl->step;
-            ctl->step = ctl->step + 1;
-            ctl->call_steps = ctl->call_steps + 1;
-        }
-        ctl->flags |= sf;
-        ctl->last_step_flags = sf;
-        ctl->volume = sv * area;
-        ctl->lam_max = lam;
-        ctl->dt = dtn;
-        ctl->rx = dtn / P.dx;
-        ctl->ry = dtn / P.dy;
-        ctl->qin0 = q_inflow(P, ctl->t);
-        ctl->qin1 = q_inflow(P, ctl->t + dtn);
-        ctl->lam_bits = 0ull;
-        ctl->step_flags = 0u;
-        ctl->ticket = 0u;
+        finalize_scalars(ctl, P, sd, sv, lam_from_bits(bits, lam_is_f32), sf, mode);
     }
 }
+
+// Partial results of one workgroup of the fused step (and, reduced, of a
+// group of kGroup workgroups): defect and volume sums, max lam (IEEE bits of
+// the kernel's precision, lam >= 0), flags, and the cell updates the
+// dry-tile skip left out.  32 bytes, so a wave reads 64 of them in one
+// coalesced sweep.  Records are written and read with agent-scope atomic
+// accesses, which are coherent across the XCDs' separate L2 caches without
+// a whole-cache write-back or invalidation.
+struct TilePart {
+    double def, vol;
+    unsigned long long lam;
+    unsigned long long fs;   // flags | skipped << 32
+};
+constexpr int kGroup = kWave;
 
 // Whether the launch for the current step should do nothing: the run already
 // reached t_end, or an earlier step raised a fatal flag.

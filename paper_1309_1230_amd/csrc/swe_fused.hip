@@ -22,9 +22,11 @@
 // evaluated from the face rules directly (no ghost ring in memory): ghost
 // columns/rows read the adjacent cell, and wall, open and inflow faces take
 // their fluxes from the rules; only strips that touch the west or east edge
-// execute that code.  dt lives on the device: the workgroup that finishes
-// last (ticket counter) reduces the per-workgroup partials in a fixed order
-// and writes dt^{n+1}.
+// execute that code.  dt lives on the device: per-workgroup records are
+// reduced through a two-level ticket (groups of 64 tiles, then the groups)
+// in a fixed order, and the last workgroup writes dt^{n+1}; no device-wide
+// fence is taken, since on gfx950 such a fence writes back and invalidates
+// the whole L2 of the XCD.
 #include "swe_common.hpp"
 #include "swe_internal.hpp"
 
@@ -53,6 +55,24 @@ __device__ __forceinline__ double from_east(double x) {
 __device__ __forceinline__ double from_west(double x) {
     return __hiloint2double(dpp_from_west(__double2hiint(x)), dpp_from_west(__double2loint(x)));
 }
+
+__device__ __forceinline__ bool is_neg_zero(float x) { return __float_as_uint(x) == 0x80000000u; }
+__device__ __forceinline__ bool is_neg_zero(double x) {
+    return (unsigned long long)__double_as_longlong(x) == 0x8000000000000000ull;
+}
+
+// Dry-tile skip.  A cell whose neighbourhood of radius two is dry, finite,
+// without discharge and away from the domain edge maps to itself under the
+// step: every donor flux is zero (dry donor), the dissipation coefficient of
+// every face vanishes (dry sides), so U* has the cell's eta and the corrector
+// returns 0.5*(eta + eta) = eta; a pressure term can make the momentum of U*
+// non-zero but the dry-cell rule of S15 clears it again.  The dissipation sum
+// is a signed zero, which leaves eta unchanged unless eta is -0 itself, so a
+// cell with eta = -0 does not count as dry here.  Tile flag words, one per
+// tile and step parity:
+constexpr unsigned kDryStill = 1u;    // after the step every output cell is dry
+                                      // (h <= h_dry), finite and not eta = -0
+constexpr unsigned kDrySkipped = 2u;  // the step skipped the tile
 
 // Workgroup id -> tile id so that each XCD (workgroups are dealt round-robin
 // over the 8 XCDs) receives one contiguous run of tiles: vertically adjacent
@@ -148,7 +168,7 @@ __device__ __forceinline__ YFace<T> y_face(const Consts<T>& c, bool bnd, bool so
 // State of one wave's march up its chunk: per-lane constants, the rows and
 // faces carried from one iteration to the next, the prefetched row and the
 // running partial sums.  Rows are named relative to the ingested row R.
-template <typename T, int SIG>
+template <typename T, int SIG, bool DRY>
 struct March {
     Consts<T> c;
     const Params* P;
@@ -186,6 +206,7 @@ struct March {
     double vol = 0.0, def = 0.0;
     T lmax = T(0);
     unsigned flags = 0u;
+    bool dirty = false;   // an output cell is wet, not finite, or has eta = -0 (DRY only)
 
     __device__ __forceinline__ long long rowoff(int R) const {
         return (long long)min(max(R, 0), ny - 1) * pitch + ic;
@@ -310,6 +331,7 @@ struct March {
                 lmax = lam_acc(lmax, lam);
                 if (!tfinite(e) || !tfinite(a) || !tfinite(b)) flags |= FLAG_NAN;
                 vol = vol + (double)h;
+                if (DRY) dirty = dirty || !(h <= c.hdry) || !tfinite(e) || is_neg_zero(e);
                 const long long so = (long long)(R - 2) * pitch + i;
                 eta1[so] = e;
                 qx1[so] = a;
@@ -353,16 +375,128 @@ struct March {
     }
 };
 
+// Agent-scope relaxed loads and stores: coherent across the XCDs (their L2
+// caches are not), with no cache-wide write-back or invalidation, unlike a
+// device-scope fence.
+__device__ __forceinline__ void st_agent(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(unsigned* p, unsigned v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_agent(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_agent(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until every memory access this wave issued has completed (s_waitcnt
+// vmcnt(0)): the record stores are then at the coherence point, before the
+// ticket increment that announces them.
+__device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+__device__ __forceinline__ void put_record(TilePart* r, double def, double vol,
+                                           unsigned long long lam, unsigned long long fs) {
+    st_agent(&r->def, def);
+    st_agent(&r->vol, vol);
+    st_agent(&r->lam, lam);
+    st_agent(&r->fs, fs);
+}
+
+// End of a workgroup's share of a step: a two-level ticket.  The last
+// workgroup to finish in each group of kGroup consecutive tiles reduces the
+// group's records (one coalesced read, fixed order) into a group record; the
+// last group to finish reduces the group records and finalises the step.
+// The order of every sum is fixed by the tile numbering, never by the order
+// in which workgroups finish, so results are reproducible; and no address
+// takes more than kGroup (or number-of-groups) atomics per step.  The
+// records travel through agent-scope accesses and the stores are complete
+// before each ticket increment, so no device-wide fence is needed (the
+// output fields are read only by the next launch).
+template <typename T>
+__device__ __forceinline__ void finish_step(const FusedArgs<T>& A, int tile, int nblk,
+                                            bool lam_is_f32) {
+    const int lane = threadIdx.x;
+    const int g = tile / kGroup;
+    const int gsize = min(kGroup, nblk - g * kGroup);
+    wait_stores();
+    unsigned t = 0;
+    if (lane == 0) t = atomicAdd(&A.gticket[g], 1u);
+    t = __shfl(t, 0, kWave);
+    if (t != (unsigned)gsize - 1) return;
+    double def = 0.0, vol = 0.0;
+    unsigned long long lam = 0ull, fs = 0ull;
+    if (lane < gsize) {
+        const TilePart* r = A.tpart + g * kGroup + lane;
+        def = ld_agent(&r->def);
+        vol = ld_agent(&r->vol);
+        lam = ld_agent(&r->lam);
+        fs = ld_agent(&r->fs);
+    }
+    const double gdef = wave_sum(def);
+    const double gvol = wave_sum(vol);
+    const unsigned long long glam = wave_max_u64(lam);
+    const unsigned gflags = wave_or((unsigned)fs);
+    unsigned gskip = (unsigned)(fs >> 32);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) gskip += __shfl_xor(gskip, off, kWave);
+    const int ngroups = (nblk + kGroup - 1) / kGroup;
+    if (lane == 0) {
+        put_record(A.gpart + g, gdef, gvol, glam,
+                   (unsigned long long)gflags | ((unsigned long long)gskip << 32));
+        st_agent(&A.gticket[g], 0u);   // every member has counted: ready for the next step
+    }
+    wait_stores();
+    Ctl* ctl = A.ctl;
+    unsigned t2 = 0;
+    if (lane == 0) t2 = atomicAdd(&ctl->ticket, 1u);
+    t2 = __shfl(t2, 0, kWave);
+    if (t2 != (unsigned)ngroups - 1) return;
+    double sd = 0.0, sv = 0.0;
+    unsigned long long lm = 0ull, sk = 0ull;
+    unsigned fl = 0u;
+    for (int k = lane; k < ngroups; k += kWave) {
+        const TilePart* q = A.gpart + k;
+        sd = sd + ld_agent(&q->def);
+        sv = sv + ld_agent(&q->vol);
+        const unsigned long long ql = ld_agent(&q->lam), qf = ld_agent(&q->fs);
+        lm = ql > lm ? ql : lm;
+        fl |= (unsigned)qf;
+        sk += qf >> 32;
+    }
+    sd = wave_sum(sd);
+    sv = wave_sum(sv);
+    lm = wave_max_u64(lm);
+    fl = wave_or(fl);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) sk += __shfl_xor(sk, off, kWave);
+    if (lane == 0) {
+        ctl->skipped = ctl->skipped + sk;
+        finalize_scalars(ctl, A.P, sd, sv, lam_from_bits(lm, lam_is_f32), fl, 1);
+    }
+}
+
 // One workgroup's share of a fused step: tile `blk` of the nblk tiles of the
 // grid described by A (in the single-grid launch blk = blockIdx.x and nblk =
 // gridDim.x; in an ensemble launch, the workgroup's tile within its
 // scenario).  The last of the nblk workgroups to finish finalises the step.
-template <typename T, int SIG>
+// DRY: the dry-tile skip is compiled in and used when A.dry is not NULL.  A
+// tile skips the step when it and its eight neighbour tiles were flagged
+// kDryStill by the previous step and no cell within two of its output cells
+// is a boundary cell or beyond; it then writes the record a computed step
+// would (zero defect, no wave speed, no flags; the volume in the record is
+// still its unchanged volume) and refreshes the output buffer only if the
+// previous step computed it (after a skip both buffers already hold the
+// tile's state).
+template <typename T, int SIG, bool DRY>
 __device__ __forceinline__ void fused_step(const FusedArgs<T>& A, int blk, int nblk) {
     Ctl* ctl = A.ctl;
     if (step_is_noop(ctl, A.t_end)) return;
     const Params& P = A.P;
-    March<T, SIG> M;
+    March<T, SIG, DRY> M;
     M.c.rx = T(ctl->rx); M.c.ry = T(ctl->ry); M.c.dt = T(ctl->dt);
     M.c.qin0 = T(ctl->qin0); M.c.qin1 = T(ctl->qin1);
     M.c.hdry = T(P.h_dry); M.c.g = T(P.g); M.c.hg = T(0.5 * P.g);
@@ -399,37 +533,75 @@ __device__ __forceinline__ void fused_step(const FusedArgs<T>& A, int blk, int n
     M.kS = face_kind(P, EDGE_S, M.ic);
     M.kN = face_kind(P, EDGE_N, M.ic);
     const bool edge = x0 - 2 <= 0 || x0 + kWave - 2 >= P.nx;  // uniform
-    if (edge)
-        M.template run<true>();
-    else
-        M.template run<false>();
 
-    // ---- workgroup partials, then the last workgroup finalises the step
-    const double vol = wave_sum(M.vol);
-    const double def = wave_sum(M.def);
-    const unsigned long long lb = wave_max_u64(lam_to_bits(M.lmax));
-    const unsigned flags = wave_or(M.flags);
-    publish_partial(ctl, A.part_def, A.part_vol, tile, lb, flags, def, vol);
-    __threadfence();
-    unsigned ticket = 0;
-    if (lane == 0) ticket = atomicAdd(&ctl->ticket, 1u);
-    ticket = __shfl(ticket, 0, kWave);
-    if (ticket == (unsigned)nblk - 1) {
-        __threadfence();
-        finalize_wave(ctl, P, A.part_def, A.part_vol, nblk, sizeof(T) == 4, 1);
+    bool skip = false;
+    unsigned* dcur = nullptr;
+    int gi = 0;
+    if (DRY && A.dry) {
+        const int ntile = gx * A.gy;
+        gi = strip * A.gy + chunk;
+        const int par = (int)(ctl->step & 1);
+        const unsigned* dprev = A.dry + par * ntile;
+        dcur = A.dry + (1 - par) * ntile;
+        // output columns x0 .. x0+59 and rows y0 .. yEnd-1 at least two
+        // cells from every edge, and the radius-two halo inside the eight
+        // neighbour tiles (H >= 2)
+        const bool inner = !edge && strip >= 1 && strip + 1 < gx && chunk >= 1 &&
+                           chunk + 1 < A.gy && A.H >= 2 && M.y0 >= 2 && M.yEnd + 2 <= P.ny;
+        if (inner) {
+            unsigned f = kDryStill;
+            if (lane < 9) f = dprev[(strip + lane % 3 - 1) * A.gy + (chunk + lane / 3 - 1)];
+            skip = __ballot(!(f & kDryStill)) == 0ull;
+        }
+        if (skip) {
+            if (!(dprev[gi] & kDrySkipped) && M.colOut) {
+                for (int r = M.y0; r < M.yEnd; ++r) {
+                    const long long o = (long long)r * P.pitch + M.i;
+                    A.eta1[o] = A.eta[o];
+                    A.qx1[o] = T(0);
+                    A.qy1[o] = T(0);
+                }
+            }
+            if (lane == 0) {
+                dcur[gi] = kDryStill | kDrySkipped;
+                // the volume of the record is the tile's unchanged volume
+                TilePart* rec = A.tpart + tile;
+                st_agent(&rec->def, 0.0);
+                st_agent(&rec->lam, 0ull);
+                st_agent(&rec->fs, (unsigned long long)((M.yEnd - M.y0) * kOutW) << 32);
+            }
+        }
     }
+
+    if (!skip) {
+        if (edge)
+            M.template run<true>();
+        else
+            M.template run<false>();
+        // ---- the workgroup's record (lane 0's reduction order is the fixed one)
+        const double vol = wave_sum(M.vol);
+        const double def = wave_sum(M.def);
+        const unsigned long long lb = wave_max_u64(lam_to_bits(M.lmax));
+        const unsigned flags = wave_or(M.flags);
+        if (lane == 0) put_record(A.tpart + tile, def, vol, lb, flags);
+        if (DRY && dcur) {
+            const bool still = __ballot(M.dirty) == 0ull;
+            if (lane == 0) dcur[gi] = still ? kDryStill : 0u;
+        }
+    }
+    finish_step(A, tile, nblk, sizeof(T) == 4);
 }
 
 // The two precisions get their own entry points so that each can be given
 // the register budget of its best occupancy: FP64 holds about twice the live
 // state and runs at 2 waves per SIMD (256 VGPRs), FP32 at 3 (168 VGPRs).
-template <int SIG>
+template <int SIG, bool DRY>
 __global__ void __launch_bounds__(kWave, 2) k_fused_step_f64(FusedArgs<double> A) {
-    fused_step<double, SIG>(A, blockIdx.x, gridDim.x);
+    fused_step<double, SIG, DRY>(A, blockIdx.x, gridDim.x);
 }
-template <int SIG>
+template <int SIG, bool DRY>
 __global__ void __launch_bounds__(kWave, 3) k_fused_step_f32(FusedArgs<float> A) {
-    fused_step<float, SIG>(A, blockIdx.x, gridDim.x);
+    fused_step<float, SIG, DRY>(A, blockIdx.x, gridDim.x);
 }
 
 // Ensemble launch: the workgroups of every scenario in one grid.  Scenario s
@@ -449,55 +621,55 @@ __device__ __forceinline__ void ensemble_locate(const int* first, int count, int
     nblk = first[lo + 1] - first[lo];
 }
 
-template <int SIG>
+template <int SIG, bool DRY>
 __global__ void __launch_bounds__(kWave, 2)
 k_ensemble_step_f64(const FusedArgs<double>* args, const int* first, int count) {
     int sc, blk, nblk;
     ensemble_locate<double>(first, count, sc, blk, nblk);
-    fused_step<double, SIG>(args[sc], blk, nblk);
+    fused_step<double, SIG, DRY>(args[sc], blk, nblk);
 }
-template <int SIG>
+template <int SIG, bool DRY>
 __global__ void __launch_bounds__(kWave, 3)
 k_ensemble_step_f32(const FusedArgs<float>* args, const int* first, int count) {
     int sc, blk, nblk;
     ensemble_locate<float>(first, count, sc, blk, nblk);
-    fused_step<float, SIG>(args[sc], blk, nblk);
+    fused_step<float, SIG, DRY>(args[sc], blk, nblk);
+}
+
+template <typename T, int SIG, bool DRY>
+constexpr auto ensemble_kernel() {
+    if constexpr (sizeof(T) == 8)
+        return &k_ensemble_step_f64<SIG, DRY>;
+    else
+        return &k_ensemble_step_f32<SIG, DRY>;
 }
 
 template <typename T>
 hipError_t launch_ensemble(const FusedArgs<T>* args, const int* first, int count, int total,
-                           int sigma, hipStream_t s) {
+                           int sigma, bool dry, hipStream_t s) {
     if (total <= 0) return hipSuccess;
-    if constexpr (sizeof(T) == 8) {
-        const auto kp = &k_ensemble_step_f64<1>;
-        const auto km = &k_ensemble_step_f64<-1>;
-        hipLaunchKernelGGL(sigma > 0 ? kp : km, dim3(total), dim3(kWave), 0, s, args, first, count);
-    } else {
-        const auto kp = &k_ensemble_step_f32<1>;
-        const auto km = &k_ensemble_step_f32<-1>;
-        hipLaunchKernelGGL(sigma > 0 ? kp : km, dim3(total), dim3(kWave), 0, s, args, first, count);
-    }
+    const auto k = sigma > 0 ? (dry ? ensemble_kernel<T, 1, true>() : ensemble_kernel<T, 1, false>())
+                             : (dry ? ensemble_kernel<T, -1, true>() : ensemble_kernel<T, -1, false>());
+    hipLaunchKernelGGL(k, dim3(total), dim3(kWave), 0, s, args, first, count);
     return hipGetLastError();
 }
 
-template <typename T, int SIG>
+template <typename T, int SIG, bool DRY>
 constexpr auto fused_kernel() {
     if constexpr (sizeof(T) == 8)
-        return &k_fused_step_f64<SIG>;
+        return &k_fused_step_f64<SIG, DRY>;
     else
-        return &k_fused_step_f32<SIG>;
+        return &k_fused_step_f32<SIG, DRY>;
 }
 
 template <typename T>
 hipError_t launch_fused(const FusedArgs<T>& a, int sigma, hipStream_t s) {
     const int gx = (a.P.nx + kOutW - 1) / kOutW;
     const int nblk = gx * a.gy;
-    const auto kp = fused_kernel<T, 1>();
-    const auto km = fused_kernel<T, -1>();
-    if (sigma > 0)
-        hipLaunchKernelGGL(kp, dim3(nblk), dim3(kWave), 0, s, a);
-    else
-        hipLaunchKernelGGL(km, dim3(nblk), dim3(kWave), 0, s, a);
+    const bool dry = a.dry != nullptr;
+    const auto k = sigma > 0 ? (dry ? fused_kernel<T, 1, true>() : fused_kernel<T, 1, false>())
+                             : (dry ? fused_kernel<T, -1, true>() : fused_kernel<T, -1, false>());
+    hipLaunchKernelGGL(k, dim3(nblk), dim3(kWave), 0, s, a);
     return hipGetLastError();
 }
 
@@ -509,21 +681,36 @@ int fused_blocks(int nx, int ny, int H) {
 
 int fused_strips(int nx) { return (nx + kOutW - 1) / kOutW; }
 
+size_t fused_part_bytes(int ntiles) {
+    const size_t ng = (size_t)(ntiles + kGroup - 1) / kGroup;
+    return ((size_t)ntiles + ng) * sizeof(TilePart) + ng * sizeof(unsigned);
+}
+
+template <typename T>
+void fused_part_layout(FusedArgs<T>& a, void* buf, int ntiles) {
+    const size_t ng = (size_t)(ntiles + kGroup - 1) / kGroup;
+    a.tpart = (TilePart*)buf;
+    a.gpart = a.tpart + ntiles;
+    a.gticket = (unsigned*)(a.gpart + ng);
+}
+
 template <typename T>
 int fused_waves_per_cu() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fused_kernel<T, 1>(), kWave,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fused_kernel<T, 1, false>(), kWave,
                                                      0) != hipSuccess)
         return 0;
     return nb;
 }
 
 template hipError_t launch_ensemble<float>(const FusedArgs<float>*, const int*, int, int, int,
-                                           hipStream_t);
+                                           bool, hipStream_t);
 template hipError_t launch_ensemble<double>(const FusedArgs<double>*, const int*, int, int, int,
-                                            hipStream_t);
+                                            bool, hipStream_t);
 template hipError_t launch_fused<float>(const FusedArgs<float>&, int, hipStream_t);
 template hipError_t launch_fused<double>(const FusedArgs<double>&, int, hipStream_t);
+template void fused_part_layout<float>(FusedArgs<float>&, void*, int);
+template void fused_part_layout<double>(FusedArgs<double>&, void*, int);
 template int fused_waves_per_cu<float>();
 template int fused_waves_per_cu<double>();
 

@@ -21,20 +21,32 @@ struct FusedArgs {
     T* eta1;
     T* qx1;
     T* qy1;
-    double* part_def;   // one slot per workgroup
-    double* part_vol;
+    TilePart* tpart;    // one record per tile (tile index)
+    TilePart* gpart;    // one record per group of kGroup tiles
+    unsigned* gticket;  // per group: members finished this step (0 between steps)
     int gy;             // chunks along y
     int H;              // output rows per chunk
+    // Dry-tile skip: NULL (off), or two flag words per tile (one set per step
+    // parity, tile index strip * gy + chunk), cleared at the start of every
+    // host call.
+    unsigned* dry = nullptr;
 };
 
 template <typename T>
 hipError_t launch_fused(const FusedArgs<T>& a, int sigma, hipStream_t s);
 // One fused step of every scenario of an ensemble in one launch: scenario s
 // owns workgroups first[s] .. first[s+1]-1 of `total` (args, first: device).
+// dry: some scenario has the dry-tile skip on (its args carry the flags).
 template <typename T>
 hipError_t launch_ensemble(const FusedArgs<T>* args, const int* first, int count, int total,
-                           int sigma, hipStream_t s);
+                           int sigma, bool dry, hipStream_t s);
 int fused_blocks(int nx, int ny, int H);
+// Bytes of the fused path's partial-result buffer for up to `ntiles` tiles
+// (tile records, group records, group tickets; zero it before first use).
+size_t fused_part_bytes(int ntiles);
+// Carve that buffer into the three arrays of FusedArgs.
+template <typename T>
+void fused_part_layout(FusedArgs<T>& a, void* buf, int ntiles);
 int fused_strips(int nx);
 // Resident fused workgroups (one wave each) per compute unit, or 0.
 template <typename T>
@@ -86,8 +98,9 @@ hipError_t launch_scan(const Params& P, Ctl* ctl, double t_end, const T* eta, co
                        hipStream_t s);
 int scan_partials(int nx, int ny);
 
-// Reset the per-call statistics (dt_min, dt_max_used, call_steps).
-hipError_t launch_begin_call(Ctl* ctl, hipStream_t s);
+// Reset the per-call statistics (dt_min, dt_max_used, call_steps, skipped
+// cells) and, when `dry` is not NULL, clear its `ndry` flag words.
+hipError_t launch_begin_call(Ctl* ctl, hipStream_t s, unsigned* dry = nullptr, int ndry = 0);
 // Control block of a replayed step n whose dt^n is known: t, n, dt, dt/dx,
 // dt/dy and the inflow values set as the finalisation of step n-1 sets them.
 hipError_t launch_replay_ctl(const Params& P, Ctl* ctl, double t, long long step, double dt,

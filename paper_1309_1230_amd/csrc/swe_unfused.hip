@@ -9,6 +9,8 @@
 // (nx+2) x (ny+2) arrays with a one-cell ghost ring, in the order the trace
 // interface exposes them; faces between cells k and k+1 are stored in the slot
 // of cell k.
+#include <algorithm>
+
 #include "swe_common.hpp"
 #include "swe_internal.hpp"
 
@@ -376,12 +378,16 @@ __global__ void k_finalize(Params P, Ctl* ctl, double t_end, const double* part_
     finalize_wave(ctl, P, part_def, part_vol, nparts, sizeof(T) == 4, mode);
 }
 
-__global__ void k_begin_call(Ctl* ctl) {
-    if (threadIdx.x == 0) {
+__global__ void k_begin_call(Ctl* ctl, unsigned* dry, int ndry) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->dt_min = __builtin_inf();
         ctl->dt_max_used = 0.0;
         ctl->call_steps = 0;
+        ctl->skipped = 0ull;
     }
+    if (dry)
+        for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < ndry; k += gridDim.x * blockDim.x)
+            dry[k] = 0u;
 }
 
 // Control block of a replayed step n with a known dt^n: the values the
@@ -424,6 +430,7 @@ __global__ void k_init_ctl(Ctl* ctl, double t, long long step, unsigned flags, d
         ctl->last_step_flags = 0u;
         ctl->ticket = 0u;
         ctl->lam_bits = 0ull;
+        ctl->skipped = 0ull;
     }
 }
 
@@ -530,8 +537,9 @@ hipError_t launch_manning_m(const Params& P, const T* n, T* m, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_begin_call(Ctl* ctl, hipStream_t s) {
-    hipLaunchKernelGGL(k_begin_call, dim3(1), dim3(kWave), 0, s, ctl);
+hipError_t launch_begin_call(Ctl* ctl, hipStream_t s, unsigned* dry, int ndry) {
+    const int blocks = dry ? std::min(256, std::max(1, (ndry + 255) / 256)) : 1;
+    hipLaunchKernelGGL(k_begin_call, dim3(blocks), dim3(256), 0, s, ctl, dry, dry ? ndry : 0);
     return hipGetLastError();
 }
 

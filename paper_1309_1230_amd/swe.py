@@ -51,14 +51,16 @@ class Config(ctypes.Structure):
                 ("hydro_t", ctypes.POINTER(ctypes.c_double)),
                 ("hydro_q", ctypes.POINTER(ctypes.c_double)),
                 ("z", ctypes.c_void_p), ("n", ctypes.c_void_p), ("eta", ctypes.c_void_p),
-                ("qx", ctypes.c_void_p), ("qy", ctypes.c_void_p), ("stream", ctypes.c_void_p)]
+                ("qx", ctypes.c_void_p), ("qy", ctypes.c_void_p), ("stream", ctypes.c_void_p),
+                ("dry_skip", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("steps", ctypes.c_int64), ("bad_step", ctypes.c_int64),
                 ("flags", ctypes.c_uint32), ("pad_", ctypes.c_uint32)] + [
                 (f, ctypes.c_double) for f in
-                ("t", "dt", "dt_min", "dt_max", "volume", "defect", "lambda_max")]
+                ("t", "dt", "dt_min", "dt_max", "volume", "defect", "lambda_max")] + [
+                ("cells_skipped", ctypes.c_int64)]
 
 
 class Checkpoint(ctypes.Structure):
@@ -79,6 +81,7 @@ class Stats:
     volume: float
     defect: float
     lambda_max: float
+    cells_skipped: int = 0
 
 
 class Gauges(ctypes.Structure):
@@ -183,7 +186,8 @@ def _make_config(z, n, eta, qx, qy, *, dx: float, dy: float, g: float = 9.81,
                  cfl: float = 0.5, h_dry: float = 1e-3, kappa: float = 0.5, eps_max: float = 0.25,
                  dt_max: float = 1.0, dt_fixed: float = 0.0, t0: float = 0.0,
                  bc=(SWE_BC_WALL,) * 4, inflow_lo=(0, 0, 0, 0), inflow_hi=None,
-                 hydro_t=(), hydro_q=(), path: str = "fused", tile_rows: int = 0):
+                 hydro_t=(), hydro_q=(), path: str = "fused", tile_rows: int = 0,
+                 dry_skip: bool = False):
     """Validate five field tensors and build a swe_config for them; returns
     (config, objects the config points into)."""
     torch = _torch()
@@ -203,6 +207,7 @@ def _make_config(z, n, eta, qx, qy, *, dx: float, dy: float, g: float = 9.81,
     c.path = {"fused": SWE_PATH_FUSED, "unfused": SWE_PATH_UNFUSED}[path]
     c.pitch = eta.stride(0)
     c.tile_rows = int(tile_rows)
+    c.dry_skip = 1 if dry_skip else 0
     if inflow_hi is None:
         inflow_hi = (ny, ny, nx, nx)
     for k in range(4):
@@ -253,13 +258,13 @@ class Solver:
 
     @classmethod
     def from_problem(cls, p, dtype=None, device="cuda", path: str = "fused", tile_rows: int = 0,
-                     stream=None):
+                     stream=None, dry_skip: bool = False):
         """Upload a workloads.Problem (float64 numpy arrays) and create a solver."""
         torch = _torch()
         dtype = dtype or torch.float64
         t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(device=device, dtype=dtype).contiguous()
         return cls(t(p.z), t(p.n), t(p.eta), t(p.qx), t(p.qy), path=path, tile_rows=tile_rows,
-                   stream=stream, **_problem_kwargs(p))
+                   stream=stream, dry_skip=dry_skip, **_problem_kwargs(p))
 
     def _check(self, rc):
         if rc != SWE_OK:
@@ -288,7 +293,7 @@ class Solver:
     @staticmethod
     def _stats(st) -> Stats:
         return Stats(st.step, st.steps, st.bad_step, st.flags, st.t, st.dt, st.dt_min, st.dt_max,
-                     st.volume, st.defect, st.lambda_max)
+                     st.volume, st.defect, st.lambda_max, st.cells_skipped)
 
     def trace_step(self):
         """One unfused step exposing every intermediate: (dict name -> (ny+2,
@@ -430,12 +435,14 @@ class Ensemble:
         self._e = h
 
     @classmethod
-    def from_problems(cls, problems, dtype=None, device="cuda", tile_rows: int = 0):
+    def from_problems(cls, problems, dtype=None, device="cuda", tile_rows: int = 0,
+                      dry_skip: bool = False):
         torch = _torch()
         dtype = dtype or torch.float32
         t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(device=device, dtype=dtype).contiguous()
-        return cls([(t(p.z), t(p.n), t(p.eta), t(p.qx), t(p.qy), _problem_kwargs(p))
-                    for p in problems], tile_rows=tile_rows)
+        return cls([(t(p.z), t(p.n), t(p.eta), t(p.qx), t(p.qy),
+                     dict(_problem_kwargs(p), dry_skip=dry_skip)) for p in problems],
+                   tile_rows=tile_rows)
 
     def _check(self, rc):
         if rc != SWE_OK:

@@ -29,11 +29,12 @@ def test_library_exports_every_declared_function():
 
 
 def test_abi_version_and_defaults():
-    assert swe.lib().swe_abi_version() == 1
+    assert swe.lib().swe_abi_version() == 2
     c = swe.default_config()
     assert c.g == 9.81 and c.cfl == 0.5 and c.h_dry == 1e-3 and c.kappa == 0.5
     assert c.eps_max == 0.25 and c.dtype == swe.SWE_F64 and c.path == swe.SWE_PATH_FUSED
     assert list(c.bc) == [0, 0, 0, 0]
+    assert c.dry_skip == 0
 
 
 def _valid_config():
@@ -58,6 +59,8 @@ def _valid_config():
     (lambda c: c.bc.__setitem__(2, 9), "boundary"),
     (lambda c: setattr(c, "eta", None), "NULL"),
     (lambda c: setattr(c, "hydro_len", 3), "hydrograph"),
+    (lambda c: setattr(c, "dry_skip", 2), "dry_skip"),
+    (lambda c: (setattr(c, "dry_skip", 1), setattr(c, "path", swe.SWE_PATH_UNFUSED)), "dry_skip"),
 ])
 def test_create_rejects_bad_arguments(mutate, why):
     c = _valid_config()
