@@ -97,6 +97,13 @@ def parse():
                     help="skip the dry-tile-skip measurement of the reservoir workload")
     ap.add_argument("--dry-only", action="store_true",
                     help="run only the dense and dry-skip reservoir runs (for profiling)")
+    ap.add_argument("--combined", action="store_true",
+                    help="run only the large combined run: FP32 forward and FP64 adjoint of the "
+                         "channel flood (8192 x 8192 by default; several minutes)")
+    ap.add_argument("--comb-nx", type=int, default=8192)
+    ap.add_argument("--comb-steps", type=int, default=5000)
+    ap.add_argument("--comb-ckpt", type=int, default=0, help="0: round(sqrt(steps))")
+    ap.add_argument("--comb-obs-every", type=int, default=50)
     ap.add_argument("--probe-copy-mb", type=int, default=0,
                     help="also run the library's plain copy kernel once over this many MiB "
                          "(calibrates HBM traffic counters)")
@@ -239,6 +246,73 @@ def dry_skip_run(torch, swe, W, p, dtype, steps, warmup, tile_rows, dense_st, de
             "speedup_vs_dense": dense_ms / ms, "stats_equal_to_dense": same}
 
 
+def combined_run(torch, swe, W, nx, nsteps, ckpt, obs_every):
+    """The large combined run: the channel flood at nx x nx, FP32 forward
+    state, FP64 adjoint of the gauge-misfit loss with respect to Manning n
+    (each step linearised at its FP32 state), checkpoint spacing ckpt.
+    Observations come from an FP32 run with the true Manning field."""
+    import dataclasses
+    ckpt = ckpt or max(1, int(round(math.sqrt(nsteps))))
+    c = W.channel_flood(nx=nx, ny=nx, nsteps=nsteps, obs_every=obs_every)
+    p = c.problem
+    cells = p.nx * p.ny
+    progress(f"combined: channel flood {nx}x{nx}, {nsteps} steps, checkpoint every {ckpt}")
+    nobs = nsteps // obs_every
+    gc = torch.as_tensor(c.cells, device="cuda")
+    hobs = torch.empty(nobs, len(c.cells), dtype=torch.float64, device="cuda")
+    s = swe.Solver.from_problem(dataclasses.replace(p, n=c.n_true), dtype=torch.float32)
+    for k in range(nobs):
+        s.run(obs_every)
+        hobs[k] = s.eta.reshape(-1)[gc].double() - s.z.reshape(-1)[gc].double()
+        if (k + 1) % 20 == 0:
+            progress(f"combined: observation run, step {(k + 1) * obs_every}")
+    s.close()
+    del s
+    progress("combined: timing the FP32 forward run")
+    st, ms_fwd, _ = timed_run(torch, swe, W, p, "f32", nsteps, 0, 0)
+    f = swe.Solver.from_problem(p, dtype=torch.float32)
+    free0, total = torch.cuda.mem_get_info()
+    fe = p.ny * p.nx
+    npad = (p.nx + 2) * (p.ny + 2)
+    nseg = (nsteps + ckpt - 1) // ckpt
+    planned = (nseg + ckpt) * 3 * fe * 4 + 9 * fe * 8 + (49 + 20) * npad * 8
+    progress(f"combined: swe_grad, planned scratch {planned / 1e9:.1f} GB of "
+             f"{free0 / 1e9:.1f} GB free")
+    os.environ["SWE_VERBOSE"] = "1"   # the library reports each reverse segment on stderr
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, gn, gz = f.grad(nsteps, c.cells, obs_every, hobs, ckpt)
+    torch.cuda.synchronize()
+    grad_s = time.perf_counter() - t0
+    os.environ.pop("SWE_VERBOSE", None)
+    h = (f.eta - f.z).double()
+    wet = float((h > p.h_dry).double().mean())
+    finite = bool(torch.isfinite(gn).all()) and bool(torch.isfinite(gz).all())
+    fin = lambda v: v if math.isfinite(v) else None
+    out = {"workload": f"channel flood {nx}x{nx}, dx={p.dx:g} m, fractal terrain (5 m, 1/|k|^1.8) "
+                       f"+ diagonal plane (1e-3) + parabolic channel 3 m x 40 m along x=y flowing "
+                       f"0.5 m below its banks, inflow 10 m^2/s (30 s ramp) on the W and S faces "
+                       f"of its deeper part, open N and E, land initially dry, {nsteps} steps",
+           "forward_dtype": "f32", "adjoint_dtype": "f64", "steps": nsteps, "sim_time_s": st.t,
+           "checkpoint_every": ckpt, "forward_ms": ms_fwd,
+           "forward_cell_updates_per_s": cells * nsteps / (ms_fwd / 1e3),
+           "grad_ms": grad_s * 1e3, "adjoint_fwd_ratio": grad_s * 1e3 / ms_fwd,
+           "loss": fin(J), "gradient_finite": finite,
+           "max_abs_dJ_dn": fin(float(gn.abs().max())),
+           "max_abs_dJ_dz": fin(float(gz.abs().max())),
+           "gradient_note": "the discrete adjoint grows exponentially through the wet/dry "
+                            "fronts of this flood (the FP64 oracle shows the same growth on a "
+                            "128x128 version), so the gradient is a diagnostic here; time and "
+                            "memory are the measurement",
+           "planned_scratch_bytes": planned, "device_free_bytes_before": free0,
+           "device_total_bytes": total, "wet_fraction_end": wet,
+           "gauges": len(c.cells), "obs_every": obs_every}
+    f.close()
+    progress(f"combined: forward {ms_fwd:.0f} ms, swe_grad {grad_s * 1e3:.0f} ms, "
+             f"ratio {out['adjoint_fwd_ratio']:.1f}, wet fraction {wet:.4f}")
+    return out
+
+
 def cpu_baseline(W, p, nsteps):
     from oracle import oracle as O
     progress(f"CPU oracle baseline: {nsteps} timed steps of {p.nx}x{p.ny}")
@@ -278,6 +352,10 @@ def main():
         swe.probe_copy(dst, src)
         torch.cuda.synchronize()
         del src, dst
+    if a.combined:
+        out = combined_run(torch, swe, W, a.comb_nx, a.comb_steps, a.comb_ckpt, a.comb_obs_every)
+        print(json.dumps({"combined": out}), flush=True)
+        return
     if a.ensemble_only:
         out = ensemble_throughput(torch, swe, W, a.ens_count, a.ens_steps)
         print(json.dumps({"ensemble": out}), flush=True)

@@ -224,10 +224,15 @@ typedef struct swe_gauges {
  * each segment of ckpt_every steps is recomputed once during the reverse
  * sweep (about 2 + 1/ckpt_every forward passes in all).  dJ_dn and dJ_dz
  * (device, FP64, caller-owned, the handle's pitch) receive the gradients;
- * *loss (host) receives J.  FP64 handles only.  Synchronises.  Errors:
- * SWE_EINVAL (arguments, gauge cells out of range or repeated, FP32 handle),
- * SWE_ENOMEM, SWE_EDEVICE, SWE_EUNSTABLE (the forward run raised a fatal
- * flag). */
+ * *loss (host) receives J.  FP32 handles: the forward run, its checkpoints
+ * and the recomputed segments are FP32 (the state trajectory is that of
+ * swe_run), and the reverse sweep is FP64, each step linearised at its FP32
+ * state promoted to FP64 (with FP64 copies of z, n and m = g n^2); misfits
+ * are formed in FP64 from the promoted depths.  Memory then holds FP32
+ * checkpoints and segment states plus an FP64 replay scratch of 49 padded
+ * arrays.  Synchronises.  Errors: SWE_EINVAL (arguments, gauge cells out of
+ * range or repeated), SWE_ENOMEM, SWE_EDEVICE, SWE_EUNSTABLE (the forward
+ * run raised a fatal flag). */
 int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_every,
              double* loss, void* dJ_dn, void* dJ_dz);
 

@@ -519,14 +519,21 @@ __global__ void k_adj_f(AdjointArgs a) {
 
 // Gauge misfits of the forward pass: m[g] = ((eta - z) - h_obs)^2 at the
 // gauge cells of a pitched state.
-__global__ void k_misfit(Params P, const double* eta, const double* z, const long long* cells,
-                         int ngauge, const double* hobs, double* out) {
+template <typename T>
+__global__ void k_misfit(Params P, const T* eta, const T* z, const long long* cells, int ngauge,
+                         const double* hobs, double* out) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ngauge) return;
     const long long c = cells[g];
     const long long o = (c / P.nx) * P.pitch + (c % P.nx);
-    const double dd = (eta[o] - z[o]) - hobs[g];
+    const double dd = ((double)eta[o] - (double)z[o]) - hobs[g];
     out[g] = dd * dd;
+}
+
+__global__ void k_promote(const float* src, double* dst, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
+        dst[k] = (double)src[k];
 }
 
 // Copy the interior of a padded accumulator to a pitched field.
@@ -558,12 +565,26 @@ hipError_t launch_adjoint_step(const AdjointArgs& a, const long long* cells, int
     return hipGetLastError();
 }
 
-hipError_t launch_misfit(const Params& P, const double* eta, const double* z,
-                         const long long* cells, int ngauge, const double* hobs, double* out,
-                         hipStream_t s) {
+template <typename T>
+hipError_t launch_misfit(const Params& P, const T* eta, const T* z, const long long* cells,
+                         int ngauge, const double* hobs, double* out, hipStream_t s) {
     if (ngauge <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_misfit, dim3((ngauge + 255) / 256), dim3(256), 0, s, P, eta, z, cells,
+    hipLaunchKernelGGL(k_misfit<T>, dim3((ngauge + 255) / 256), dim3(256), 0, s, P, eta, z, cells,
                        ngauge, hobs, out);
+    return hipGetLastError();
+}
+template hipError_t launch_misfit<float>(const Params&, const float*, const float*,
+                                         const long long*, int, const double*, double*,
+                                         hipStream_t);
+template hipError_t launch_misfit<double>(const Params&, const double*, const double*,
+                                          const long long*, int, const double*, double*,
+                                          hipStream_t);
+
+hipError_t launch_promote(const float* src, double* dst, size_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_promote, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n);
     return hipGetLastError();
 }
 

@@ -7,13 +7,13 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
 
-#include <map>
-#include <string>
 #include "swe.h"
 #include "swe_internal.hpp"
 
@@ -596,42 +596,31 @@ size_t state_elems(const swe_handle* h) {
     return (size_t)(h->P.ny - 1) * (size_t)h->P.pitch + (size_t)h->P.nx;
 }
 
-hipError_t copy_state(swe_handle* h, double* const dst[3], const double* const src[3]) {
+template <typename T>
+hipError_t copy_state(swe_handle* h, T* const dst[3], const T* const src[3]) {
     hipError_t e = hipSuccess;
     for (int f = 0; f < 3 && e == hipSuccess; ++f)
-        e = hipMemcpyAsync(dst[f], src[f], state_elems(h) * sizeof(double),
-                           hipMemcpyDeviceToDevice, h->stream);
+        e = hipMemcpyAsync(dst[f], src[f], state_elems(h) * sizeof(T), hipMemcpyDeviceToDevice,
+                           h->stream);
     return e;
 }
 
-}  // namespace
-
-extern "C" {
-
-int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_every,
-             double* loss, void* dJ_dn, void* dJ_dz) {
-    if (!h) return fail(nullptr, SWE_EINVAL, "handle is NULL");
-    if (h->dtype != SWE_F64) return fail(h, SWE_EINVAL, "swe_grad needs an FP64 handle");
-    if (nsteps < 0 || !g || !loss || !dJ_dn || !dJ_dz || ckpt_every < 1)
-        return fail(h, SWE_EINVAL, "swe_grad: bad arguments");
-    if (g->ngauge < 0 || g->obs_every < 1) return fail(h, SWE_EINVAL, "swe_grad: bad gauges");
+// The discrete adjoint of nsteps steps of handle h, whose state has type T.
+// The forward run, its checkpoints and the recomputed segments are in T; the
+// reverse sweep is in FP64.  For T = float each step is linearised at its
+// FP32 state promoted to FP64: the FP64 replay and adjoint of that step use
+// the FP32 run's time step and FP64 copies of z, n and m = g n^2.
+template <typename T>
+int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_every,
+              double* loss, void* dJ_dn, void* dJ_dz) {
+    constexpr bool mixed = sizeof(T) == 4;
     const int64_t nobs = nsteps / g->obs_every;
     const int ng = g->ngauge;
-    if (ng > 0 && (!g->cells || (nobs > 0 && !g->hobs)))
-        return fail(h, SWE_EINVAL, "swe_grad: gauge cells or observations missing");
-    {
-        std::vector<int64_t> cs(g->cells, g->cells + ng);
-        std::sort(cs.begin(), cs.end());
-        const int64_t ncell = (int64_t)h->P.nx * h->P.ny;
-        for (int k = 0; k < ng; ++k)
-            if (cs[k] < 0 || cs[k] >= ncell || (k > 0 && cs[k] == cs[k - 1]))
-                return fail(h, SWE_EINVAL, "swe_grad: gauge cells must be distinct and inside the grid");
+    int rc = SWE_OK;
+    if (!mixed) {
+        rc = ensure_trace(h);
+        if (rc) return rc;
     }
-    if (!is_device_ptr(dJ_dn, h->device) || !is_device_ptr(dJ_dz, h->device) ||
-        (ng > 0 && nobs > 0 && !is_device_ptr(g->hobs, h->device)))
-        return fail(h, SWE_EINVAL, "swe_grad: gradients and observations must be device memory");
-    int rc = ensure_trace(h);
-    if (rc) return rc;
     rc = fill_stats(h, nullptr);
     if (rc) return rc;
     Ctl c0;
@@ -643,9 +632,9 @@ int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_ev
     const size_t Npad = padded_elems(h);
     const int64_t C = std::max<int64_t>(1, std::min<int64_t>(ckpt_every, std::max<int64_t>(nsteps, 1)));
     const int64_t nseg = (nsteps + C - 1) / C;
-    DevBuf ck, seg, scratch, work, logs, mis, dcells, actl;
-    if ((e = ck.alloc((size_t)nseg * 3 * fe * sizeof(double))) != hipSuccess ||
-        (e = seg.alloc((size_t)C * 3 * fe * sizeof(double))) != hipSuccess ||
+    DevBuf ck, seg, scratch, work, logs, mis, dcells, actl, prom, stat64, trace64;
+    if ((e = ck.alloc((size_t)nseg * 3 * fe * sizeof(T))) != hipSuccess ||
+        (e = seg.alloc((size_t)C * 3 * fe * sizeof(T))) != hipSuccess ||
         (e = scratch.alloc(3 * fe * sizeof(double))) != hipSuccess ||
         (e = work.alloc((size_t)swe::adjoint_work_arrays() * Npad * sizeof(double))) != hipSuccess ||
         (e = logs.alloc(2 * (size_t)std::max<int64_t>(nsteps, 1) * sizeof(double))) != hipSuccess ||
@@ -653,23 +642,50 @@ int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_ev
         (e = dcells.alloc((size_t)std::max(ng, 1) * sizeof(long long))) != hipSuccess ||
         (e = actl.alloc(sizeof(Ctl))) != hipSuccess)
         return fail(h, SWE_ENOMEM, std::string("swe_grad: hipMalloc failed: ") + hip_text(e));
-    if (ng > 0)
+    // FP64 views the reverse sweep works on
+    const double* z64 = (const double*)h->z;
+    const double* n64 = (const double*)h->n;
+    double* tr64 = (double*)h->trace;
+    if (mixed) {
+        if ((e = prom.alloc(3 * fe * sizeof(double))) != hipSuccess ||
+            (e = stat64.alloc(3 * fe * sizeof(double))) != hipSuccess ||
+            (e = trace64.alloc((size_t)(swe::kTraceArrays + 2) * Npad * sizeof(double))) != hipSuccess)
+            return fail(h, SWE_ENOMEM, std::string("swe_grad: hipMalloc failed: ") + hip_text(e));
+        double* zz = stat64.d();
+        double* nn = stat64.d() + fe;
+        double* mm = stat64.d() + 2 * fe;
+        const size_t ne = state_elems(h);
+        e = swe::launch_promote((const float*)h->z, zz, ne, h->stream);
+        if (e == hipSuccess) e = swe::launch_promote((const float*)h->n, nn, ne, h->stream);
+        if (e == hipSuccess) e = swe::launch_manning_m<double>(h->P, nn, mm, h->stream);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(trace64.p, 0, (size_t)(swe::kTraceArrays + 2) * Npad * sizeof(double),
+                               h->stream);
+        tr64 = trace64.d();
+        if (e == hipSuccess)
+            e = swe::launch_pad_static<double>(h->P, zz, mm, tr64 + (size_t)swe::kTraceArrays * Npad,
+                                               tr64 + (size_t)(swe::kTraceArrays + 1) * Npad,
+                                               h->stream);
+        z64 = zz;
+        n64 = nn;
+    }
+    if (e == hipSuccess && ng > 0)
         e = hipMemcpyAsync(dcells.p, g->cells, (size_t)ng * sizeof(long long),
                            hipMemcpyHostToDevice, h->stream);
     double* dtlog = logs.d();
     double* tlog = logs.d() + std::max<int64_t>(nsteps, 1);
-    auto slot = [&](double* base, int64_t m, double* U[3]) {
-        for (int f = 0; f < 3; ++f) U[f] = base + ((size_t)m * 3 + f) * fe;
+    auto slot = [&](void* base, int64_t m, T* U[3]) {
+        for (int f = 0; f < 3; ++f) U[f] = (T*)base + ((size_t)m * 3 + f) * fe;
     };
     // ---- forward: the run itself, with checkpoints, time steps and misfits
     if (e == hipSuccess) e = begin_call(h, h->stream);
     for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) {
-        double* cur[3];
-        for (int f = 0; f < 3; ++f) cur[f] = (double*)((k & 1) ? bufB(h, f) : bufA(h, f));
+        T* cur[3];
+        for (int f = 0; f < 3; ++f) cur[f] = (T*)((k & 1) ? bufB(h, f) : bufA(h, f));
         if (k % C == 0) {
-            double* dst[3];
-            slot(ck.d(), k / C, dst);
-            e = copy_state(h, dst, cur);
+            T* dst[3];
+            slot(ck.p, k / C, dst);
+            e = copy_state<T>(h, dst, cur);
         }
         if (e == hipSuccess) {
             hipLaunchKernelGGL(k_log_ctl, dim3(1), dim3(64), 0, h->stream, h->ctl, dtlog + k,
@@ -679,9 +695,9 @@ int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_ev
         if (e == hipSuccess) e = enqueue(h, k, INFINITY, false);
         if (e == hipSuccess && ng > 0 && (k + 1) % g->obs_every == 0) {
             const int64_t row = (k + 1) / g->obs_every - 1;
-            const double* nxt = (const double*)((k & 1) ? bufA(h, 0) : bufB(h, 0));
-            e = swe::launch_misfit(h->P, nxt, (const double*)h->z, (const long long*)dcells.p, ng,
-                                   g->hobs + row * ng, mis.d() + row * ng, h->stream);
+            const T* nxt = (const T*)((k & 1) ? bufA(h, 0) : bufB(h, 0));
+            e = swe::launch_misfit<T>(h->P, nxt, (const T*)h->z, (const long long*)dcells.p, ng,
+                                      g->hobs + row * ng, mis.d() + row * ng, h->stream);
         }
     }
     if (e == hipSuccess) e = enqueue_copy_back(h);
@@ -703,53 +719,77 @@ int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_ev
     e = hipMemsetAsync(work.p, 0, (size_t)swe::adjoint_work_arrays() * Npad * sizeof(double), h->stream);
     swe::AdjointArgs aa;
     aa.P = h->P;
-    aa.trace = (const double*)h->trace;
+    aa.trace = tr64;
     aa.zp = aa.trace + (size_t)swe::kTraceArrays * Npad;
     aa.mp = aa.zp + Npad;
-    aa.nman = (const double*)h->n;
+    aa.nman = n64;
     aa.work = work.d();
     Ctl* rc_ctl = (Ctl*)actl.p;
+    // SWE_VERBOSE=1 in the environment: a line on stderr after the forward run
+    // and after each reverse segment (each waits for the device)
+    const char* verbose_env = std::getenv("SWE_VERBOSE");
+    const bool verbose = verbose_env && verbose_env[0] == '1';
+    if (verbose)
+        std::fprintf(stderr, "swe_grad: forward run of %lld steps done, %lld reverse segments\n",
+                     (long long)nsteps, (long long)nseg);
     for (int64_t sg = nseg - 1; sg >= 0 && e == hipSuccess; --sg) {
+        if (verbose && sg < nseg - 1) {
+            e = hipStreamSynchronize(h->stream);
+            std::fprintf(stderr, "swe_grad: reverse segment %lld of %lld done\n",
+                         (long long)(nseg - 1 - sg), (long long)nseg);
+            if (e != hipSuccess) break;
+        }
         const int64_t s0 = sg * C, s1 = std::min(s0 + C, nsteps);
-        double *U0[3], *CK[3];
-        slot(seg.d(), 0, U0);
-        slot(ck.d(), sg, CK);
-        e = copy_state(h, U0, CK);
+        T *U0[3], *CK[3];
+        slot(seg.p, 0, U0);
+        slot(ck.p, sg, CK);
+        e = copy_state<T>(h, U0, CK);
         // the fused kernel's own finalisation carries dt from step to step
-        if (s1 - s0 > 1) e = swe::launch_replay_ctl(h->P, rc_ctl, ht[(size_t)s0], step0 + s0,
-                                                    hdt[(size_t)s0], h->stream);
+        if (e == hipSuccess && s1 - s0 > 1)
+            e = swe::launch_replay_ctl(h->P, rc_ctl, ht[(size_t)s0], step0 + s0, hdt[(size_t)s0],
+                                       h->stream);
         for (int64_t k = s0; k + 1 < s1 && e == hipSuccess; ++k) {
-            double *Uk[3], *Un[3];
-            slot(seg.d(), k - s0, Uk);
-            slot(seg.d(), k + 1 - s0, Un);
-            swe::FusedArgs<double> fa;
+            T *Uk[3], *Un[3];
+            slot(seg.p, k - s0, Uk);
+            slot(seg.p, k + 1 - s0, Un);
+            swe::FusedArgs<T> fa;
             fa.P = h->P;
             fa.ctl = rc_ctl;
             fa.t_end = INFINITY;
             fa.eta = Uk[0]; fa.qx = Uk[1]; fa.qy = Uk[2];
-            fa.z = (const double*)h->z;
-            fa.m = (const double*)bufB(h, 3);
+            fa.z = (const T*)h->z;
+            fa.m = (const T*)bufB(h, 3);
             fa.eta1 = Un[0]; fa.qx1 = Un[1]; fa.qy1 = Un[2];
             swe::fused_part_layout(fa, h->fpart, h->nparts);
             fa.gy = h->gy;
             fa.H = h->H;
-            e = swe::launch_fused<double>(fa, ((step0 + k) & 1) ? -1 : 1, h->stream);
+            e = swe::launch_fused<T>(fa, ((step0 + k) & 1) ? -1 : 1, h->stream);
         }
         for (int64_t k = s1 - 1; k >= s0 && e == hipSuccess; --k) {
-            double *Uk[3], *Sc[3];
-            slot(seg.d(), k - s0, Uk);
-            slot(scratch.d(), 0, Sc);
-            e = swe::launch_replay_ctl(h->P, rc_ctl, ht[(size_t)k], step0 + k, hdt[(size_t)k],
-                                       h->stream);
+            T* Uk[3];
+            slot(seg.p, k - s0, Uk);
+            const double* U64[3] = {(const double*)Uk[0], (const double*)Uk[1],
+                                    (const double*)Uk[2]};
+            if (mixed) {
+                for (int f = 0; f < 3 && e == hipSuccess; ++f) {
+                    double* d = prom.d() + (size_t)f * fe;
+                    e = swe::launch_promote((const float*)Uk[f], d, state_elems(h), h->stream);
+                    U64[f] = d;
+                }
+            }
+            if (e == hipSuccess)
+                e = swe::launch_replay_ctl(h->P, rc_ctl, ht[(size_t)k], step0 + k, hdt[(size_t)k],
+                                           h->stream);
             if (e != hipSuccess) break;
+            double* Sc = scratch.d();
             swe::UnfusedArgs<double> ua;
             ua.P = h->P;
             ua.ctl = rc_ctl;
             ua.t_end = INFINITY;
-            ua.eta = Uk[0]; ua.qx = Uk[1]; ua.qy = Uk[2];
-            ua.z = (const double*)h->z;
-            ua.eta1 = Sc[0]; ua.qx1 = Sc[1]; ua.qy1 = Sc[2];
-            ua.trace = (double*)h->trace;
+            ua.eta = U64[0]; ua.qx = U64[1]; ua.qy = U64[2];
+            ua.z = z64;
+            ua.eta1 = Sc; ua.qx1 = Sc + fe; ua.qy1 = Sc + 2 * fe;
+            ua.trace = tr64;
             ua.zp = aa.zp;
             ua.mp = aa.mp;
             ua.part_def = h->part;
@@ -774,6 +814,35 @@ int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_ev
     if (e != hipSuccess) return hip_fail(h, e, "swe_grad: reverse sweep");
     *loss = J;
     return SWE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_every,
+             double* loss, void* dJ_dn, void* dJ_dz) {
+    if (!h) return fail(nullptr, SWE_EINVAL, "handle is NULL");
+    if (nsteps < 0 || !g || !loss || !dJ_dn || !dJ_dz || ckpt_every < 1)
+        return fail(h, SWE_EINVAL, "swe_grad: bad arguments");
+    if (g->ngauge < 0 || g->obs_every < 1) return fail(h, SWE_EINVAL, "swe_grad: bad gauges");
+    const int64_t nobs = nsteps / g->obs_every;
+    const int ng = g->ngauge;
+    if (ng > 0 && (!g->cells || (nobs > 0 && !g->hobs)))
+        return fail(h, SWE_EINVAL, "swe_grad: gauge cells or observations missing");
+    {
+        std::vector<int64_t> cs(g->cells, g->cells + ng);
+        std::sort(cs.begin(), cs.end());
+        const int64_t ncell = (int64_t)h->P.nx * h->P.ny;
+        for (int k = 0; k < ng; ++k)
+            if (cs[k] < 0 || cs[k] >= ncell || (k > 0 && cs[k] == cs[k - 1]))
+                return fail(h, SWE_EINVAL, "swe_grad: gauge cells must be distinct and inside the grid");
+    }
+    if (!is_device_ptr(dJ_dn, h->device) || !is_device_ptr(dJ_dz, h->device) ||
+        (ng > 0 && nobs > 0 && !is_device_ptr(g->hobs, h->device)))
+        return fail(h, SWE_EINVAL, "swe_grad: gradients and observations must be device memory");
+    return h->dtype == SWE_F32 ? grad_impl<float>(h, nsteps, g, ckpt_every, loss, dJ_dn, dJ_dz)
+                               : grad_impl<double>(h, nsteps, g, ckpt_every, loss, dJ_dn, dJ_dz);
 }
 
 }  // extern "C"

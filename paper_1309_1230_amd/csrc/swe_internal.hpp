@@ -130,10 +130,13 @@ constexpr int kAdjLambda = 15, kAdjGradN = 18, kAdjGradZ = 19;
 // Adjoint of one step; adds the gauge terms first when hobs is not NULL.
 hipError_t launch_adjoint_step(const AdjointArgs& a, const long long* cells, int ngauge,
                                const double* hobs, hipStream_t s);
-// out[g] = ((eta - z)(cell g) - hobs[g])^2 on a pitched state.
-hipError_t launch_misfit(const Params& P, const double* eta, const double* z,
-                         const long long* cells, int ngauge, const double* hobs, double* out,
-                         hipStream_t s);
+// out[g] = ((eta - z)(cell g) - hobs[g])^2 on a pitched state, in FP64 (an FP32
+// state is promoted before the difference).
+template <typename T>
+hipError_t launch_misfit(const Params& P, const T* eta, const T* z, const long long* cells,
+                         int ngauge, const double* hobs, double* out, hipStream_t s);
+// dst[k] = (double)src[k], k < n.
+hipError_t launch_promote(const float* src, double* dst, size_t n, hipStream_t s);
 // Interior of a padded array into a pitched one.
 hipError_t launch_unpad(const Params& P, const double* src, double* dst, hipStream_t s);
 

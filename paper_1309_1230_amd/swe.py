@@ -312,7 +312,9 @@ class Solver:
         run) and return (J, dJ/dn, dJ/dz) of the gauge-misfit loss, the time
         steps of the run held fixed.  cells: distinct flattened cells j*nx+i;
         hobs: (nsteps // obs_every, len(cells)) float64 device tensor of
-        observed depths.  FP64 solvers only."""
+        observed depths.  FP32 solvers run the forward in FP32 and the reverse
+        sweep in FP64, linearised at the promoted FP32 states; the gradients
+        are float64 either way."""
         torch = _torch()
         import numpy as np
         cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int64).ravel())

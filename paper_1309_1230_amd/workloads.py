@@ -117,14 +117,16 @@ def gaussian_hills(nx: int, ny: int, dx: float, dy: float, rng: np.random.Genera
     return (gy * a[None, :]) @ gx
 
 
-def fractal_noise(nx: int, ny: int, rng: np.random.Generator, amplitude: float) -> np.ndarray:
-    """1/f noise by spectral synthesis: amplitude proportional to 1/|k|, random
-    phases, zero mean, scaled so that max |noise| = amplitude."""
+def fractal_noise(nx: int, ny: int, rng: np.random.Generator, amplitude: float,
+                  exponent: float = 1.0) -> np.ndarray:
+    """Fractal noise by spectral synthesis: amplitude proportional to
+    1/|k|^exponent (1: 1/f noise), random phases, zero mean, scaled so that
+    max |noise| = amplitude."""
     kx = np.fft.rfftfreq(nx)
     ky = np.fft.fftfreq(ny)
     kk = np.sqrt(kx[None, :] ** 2 + ky[:, None] ** 2)
     kk[0, 0] = np.inf
-    spec = (1.0 / kk) * np.exp(2j * np.pi * rng.uniform(0.0, 1.0, kk.shape))
+    spec = (1.0 / kk ** exponent) * np.exp(2j * np.pi * rng.uniform(0.0, 1.0, kk.shape))
     spec[0, 0] = 0.0
     f = np.fft.irfft2(spec, s=(ny, nx))
     f -= f.mean()
@@ -290,6 +292,62 @@ def calibration(nx: int = 1024, ny: int = 1024, dx: float = 2.0, seed: int = 100
                 qx=np.full((ny, nx), q), qy=np.zeros((ny, nx)), dt_fixed=dt_fixed,
                 bc=(INFLOW, OPEN, WALL, WALL), hydro_t=(0.0,), hydro_q=(q,),
                 name=f"calibration{nx}x{ny}")
+    return Calibration(problem=p, n_true=n_true, cells=np.sort(cells), obs_every=obs_every,
+                       nsteps=nsteps)
+
+
+def channel_flood(nx: int = 8192, ny: int = 8192, dx: float = 1.0, seed: int = 1005,
+                  nsteps: int = 5000, ngauge: int = 64, obs_every: int = 50,
+                  noise_amp: float = 5.0, noise_exponent: float = 1.8, slope: float = 1e-3,
+                  depth: float = 3.0, width: float = 40.0, freeboard: float = 0.5,
+                  q_in: float = 10.0, ramp: float = 30.0, dt_max: float = 0.1,
+                  n_guess: float = 0.035, n_range=(0.02, 0.08),
+                  corr: float = 100.0) -> Calibration:
+    """The large combined run: 8192 x 8192, dx = 1 m by default.  Bed:
+    fractal noise of amplitude 5 m (amplitude spectrum 1/|k|^1.8, a terrain-
+    like Hurst exponent of 0.8) plus a plane descending along the diagonal
+    from the south-west corner at `slope`, with a channel 40 m wide carved
+    along x = y: inside it the bed is the lower of the terrain and a parabolic
+    cross-section 3 m below the plane on the axis.  The channel starts
+    flowing 0.5 m below its banks at the uniform-flow discharge of the first
+    guess n along the axis; all land outside it is dry.  Inflow 10 m^2/s
+    through the west and south boundary faces of the channel's deeper part
+    (starting depth >= 1 m), ramped up linearly over the first 30 s,
+    overtops the channel and floods the land; north and east open;
+    dt_max = 0.1 s.  True Manning field: a Gaussian
+    random field with 100 m correlation length mapped to [0.02, 0.08]; the
+    problem carries the first guess n = 0.035.  64 gauges on the channel
+    axis, the first 400 m from the corner, observed every 50 steps of a
+    5000-step run."""
+    rng = np.random.default_rng(seed)
+    xc = (np.arange(nx) + 0.5) * dx
+    yc = (np.arange(ny) + 0.5) * dx
+    plane = slope * ((nx * dx - xc)[None, :] + (ny * dx - yc)[:, None]) / math.sqrt(2.0)
+    z = fractal_noise(nx, ny, rng, noise_amp, noise_exponent) + plane
+    dist = np.abs(xc[None, :] - yc[:, None]) / math.sqrt(2.0)
+    inside = dist < 0.5 * width
+    # carved bed: parabolic cross-section `depth` below the plane on the axis
+    bed = plane - depth * (1.0 - (2.0 * dist / width) ** 2)
+    z = np.where(inside, np.minimum(z, bed), z)
+    n_true = n_range[0] + (n_range[1] - n_range[0]) * gaussian_random_field(nx, ny, dx, corr, rng)
+    # inflow faces: those of the channel band where the starting depth is at
+    # least 1 m (the parabolic section's inner part; the shallow bank cells
+    # would turn 10 m^2/s into a thin, very fast jet)
+    inner = 0.5 * width * math.sqrt(max(0.0, 1.0 - (freeboard + 1.0) / depth))
+    band_w = int(np.count_nonzero(np.abs(0.5 * dx - yc) / math.sqrt(2.0) < inner))
+    band_s = int(np.count_nonzero(np.abs(xc - 0.5 * dx) / math.sqrt(2.0) < inner))
+    diag = np.unique(np.linspace(8, min(nx, ny, int(400 / dx)) - 1, ngauge).astype(np.int64))
+    cells = diag * nx + diag
+    # the channel flows bank-full less the freeboard at uniform-flow discharge
+    # along the axis; the land around it is dry
+    eta = np.where(inside, np.maximum(z, plane - freeboard), z)
+    h = eta - z
+    q = np.where(h > 0.0, h ** (5.0 / 3.0) * math.sqrt(slope) / n_guess, 0.0) / math.sqrt(2.0)
+    p = Problem(nx=nx, ny=ny, dx=dx, dy=dx, z=z, n=np.full((ny, nx), n_guess), eta=eta,
+                qx=q.copy(), qy=q, dt_max=dt_max,
+                bc=(INFLOW, OPEN, INFLOW, OPEN), inflow_lo=(0, 0, 0, 0),
+                inflow_hi=(band_w, ny, band_s, nx), hydro_t=(0.0, ramp), hydro_q=(0.0, q_in),
+                name=f"channel{nx}x{ny}")
     return Calibration(problem=p, n_true=n_true, cells=np.sort(cells), obs_every=obs_every,
                        nsteps=nsteps)
 
