@@ -1,12 +1,16 @@
 // swe_adjoint.hip -- discrete adjoint of one time step (FP64).
 //
-// Reverse mode through S15 .. S1 of one step, given the forward
-// intermediates of that step as the unfused path records them (the 47
-// padded arrays of the parity ladder, plus the padded bed zp and m = g n^2).
-// The adjoint lam^{n+1} of U^{n+1} (plus the gauge misfit terms of the loss
-// when step n+1 is observed) becomes lam^n, the adjoint of U^n, and the
-// step's contributions to dJ/dn and dJ/dz are added to the accumulators.
-// dt^n is held fixed (not differentiated).
+// Reverse mode through S15 .. S1 of one step.  The step's forward data are
+// U^n, U* (after S7) and U^d (after S13, before friction), pitched like the
+// state, which the tracing fused step writes; everything else the reverse
+// sweep needs (the ghost rings of S1 and S8, the primitives of S2 and S9, the
+// switches of S3, the friction of S14 and the dry fix of S15) is recomputed
+// here from them with the forward step's own expressions, so each value is
+// bit for bit the one the forward step used.  The adjoint lam^{n+1} of
+// U^{n+1} (plus the gauge misfit terms of the loss when step n+1 is
+// observed) becomes lam^n, the adjoint of U^n, and the step's contributions
+// to dJ/dn and dJ/dz are added to the accumulators.  dt^n is held fixed (not
+// differentiated).
 //
 // Every kernel gathers: a thread owns one cell (or one padded cell) and
 // recomputes what it needs from the faces and neighbours that reach it, so
@@ -25,12 +29,8 @@ namespace {
 
 constexpr int kBX = 64, kBY = 4;
 
-enum {
-    T_UN = 0, T_H = 3, T_R = 4, T_U = 5, T_V = 6, T_NUX = 7, T_NUY = 8, T_D = 9, T_F = 12,
-    T_G = 16, T_US = 20, T_HS = 23, T_RS = 24, T_USU = 25, T_USV = 26, T_FS = 27, T_GS = 31,
-    T_UC = 35, T_UD = 38, T_UF = 41, T_UNEW = 44
-};
-
+// The adjoint's own arrays are padded with a one-cell ring: element (i, j),
+// i in [-1, nx], j in [-1, ny], at (j+1)*(nx+2) + (i+1).
 struct Pad {
     int nx, ny, P2;
     long long N;
@@ -51,9 +51,6 @@ __device__ __forceinline__ Pad pad_of(const Params& P) {
     return d;
 }
 
-__device__ __forceinline__ const double* tr(const AdjointArgs& a, const Pad& d, int k) {
-    return a.trace + (long long)k * d.N;
-}
 __device__ __forceinline__ double* wk(const AdjointArgs& a, const Pad& d, int k) {
     return a.work + (long long)k * d.N;
 }
@@ -63,6 +60,50 @@ __device__ __forceinline__ double* wk(const AdjointArgs& a, const Pad& d, int k)
 // dJ/dn and dJ/dz accumulators.
 enum { W_AB = 0, W_AD = 3, W_AUS = 6, W_AUN = 9, W_ANX = 12, W_ANY = 13, W_AZP = 14,
        W_LAM = 15, W_GN = 18, W_GZ = 19 };
+
+__device__ __forceinline__ long long pitched(const Params& P, int i, int j) {
+    return (long long)j * P.pitch + i;
+}
+
+// eta of U^n or U* at padded cell (i, j): a ghost copies the adjacent cell.
+__device__ __forceinline__ double eta_at(const Params& P, const double* E, int i, int j) {
+    return E[pitched(P, min(max(i, 0), P.nx - 1), min(max(j, 0), P.ny - 1))];
+}
+
+// A state (U^n with q_in(t^n), or U* with q_in(t^n + dt)) at padded cell
+// (i, j), not a corner: the interior value or the ghost ring rule (S1, S8),
+// with its primitives (S2, S9).
+struct Cell { double e, qx, qy, h, r, u, v; };
+
+__device__ __forceinline__ Cell cell_at(const AdjointArgs& a, const Pad& d,
+                                        const double* const* U, double qin, int i, int j) {
+    const Params& P = a.P;
+    const long long s = pitched(P, min(max(i, 0), P.nx - 1), min(max(j, 0), P.ny - 1));
+    Cell c;
+    c.e = U[0][s];
+    c.qx = U[1][s];
+    c.qy = U[2][s];
+    if (i < 0 || i >= P.nx)
+        ghost(face_kind(P, i < 0 ? EDGE_W : EDGE_E, j), true, i < 0 ? qin : -qin, c.e, c.qx,
+              c.qy, c.e, c.qx, c.qy);
+    else if (j < 0 || j >= P.ny)
+        ghost(face_kind(P, j < 0 ? EDGE_S : EDGE_N, i), false, j < 0 ? qin : -qin, c.e, c.qx,
+              c.qy, c.e, c.qx, c.qy);
+    c.h = c.e - a.zp[d.at(i, j)];
+    c.r = recip_depth(c.h, a.P.h_dry);
+    c.u = c.qx * c.r;
+    c.v = c.qy * c.r;
+    return c;
+}
+
+// S3: switch of U^n at interior cell (i, j) along x (xdir) or y.
+__device__ __forceinline__ double nu_at(const AdjointArgs& a, int i, int j, bool xdir, double eC,
+                                        double rC) {
+    const double* E = a.un[0];
+    const double eM = xdir ? eta_at(a.P, E, i - 1, j) : eta_at(a.P, E, i, j - 1);
+    const double eP = xdir ? eta_at(a.P, E, i + 1, j) : eta_at(a.P, E, i, j + 1);
+    return curv_switch(eM, eC, eP, rC);
+}
 
 // Reverse of the friction cube root y = cbrt3(x): returns x-bar given y-bar.
 __device__ double cbrt3_adjoint(double x, double ybar) {
@@ -98,6 +139,7 @@ __device__ double cbrt3_adjoint(double x, double ybar) {
 
 // Loss terms of an observed step: lambda_eta += 2 d and dJ/dz -= 2 d at
 // each gauge, d = (eta^{n+1} - z) - h_obs.  Gauge cells are distinct.
+// eta^{n+1} is the dry fix of eta^d (friction leaves eta unchanged).
 __global__ void k_adj_seed(AdjointArgs a, const long long* cells, int ngauge, const double* hobs) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= ngauge) return;
@@ -105,7 +147,9 @@ __global__ void k_adj_seed(AdjointArgs a, const long long* cells, int ngauge, co
     const long long c = cells[g];
     const int i = (int)(c % a.P.nx), j = (int)(c / a.P.nx);
     const long long C = d.at(i, j);
-    const double dd = (tr(a, d, T_UNEW)[C] - a.zp[C]) - hobs[g];
+    const double zp = a.zp[C], ef = a.ud[0][pitched(a.P, i, j)];
+    const double en = ef - zp < 0.0 ? zp : ef;
+    const double dd = (en - zp) - hobs[g];
     wk(a, d, W_LAM)[C] += dd + dd;
     wk(a, d, W_GZ)[C] += 0.0 - (dd + dd);
 }
@@ -115,12 +159,13 @@ __global__ void k_adj_a(AdjointArgs a) {
     const Pad d = pad_of(a.P);
     const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y;
     if (i >= d.nx || j >= d.ny) return;
-    const long long C = d.at(i, j);
+    const long long C = d.at(i, j), o = pitched(a.P, i, j);
     const double hdry = a.P.h_dry, zp = a.zp[C];
     const double* LAM = wk(a, d, W_LAM);
     const double le = LAM[C], lx = LAM[d.N + C], ly = LAM[2 * d.N + C];
-    // S15 dry fix
-    const double ef = tr(a, d, T_UF)[C];
+    // S15 dry fix (S14 leaves eta as U^d's)
+    const double ed = a.ud[0][o], qx = a.ud[1][o], qy = a.ud[2][o];
+    const double ef = ed;
     const bool clip = ef - zp < 0.0;
     const double en = clip ? zp : ef;
     const bool dry = !(en - zp > hdry);
@@ -128,7 +173,6 @@ __global__ void k_adj_a(AdjointArgs a) {
     const double efb = clip ? 0.0 : le;
     const double qxfb = dry ? 0.0 : lx, qyfb = dry ? 0.0 : ly;
     // S14 friction
-    const double ed = tr(a, d, T_UD)[C], qx = tr(a, d, T_UD + 1)[C], qy = tr(a, d, T_UD + 2)[C];
     const double h = ed - zp;
     double edb = efb, qxdb = qxfb, qydb = qyfb;
     if (h > hdry) {
@@ -162,7 +206,7 @@ __global__ void k_adj_a(AdjointArgs a) {
         edb += hb;
         azp -= hb;
         // m = g n^2 at this cell
-        const double n = a.nman[(long long)j * a.P.pitch + i];
+        const double n = a.nman[o];
         const double mg = mb * a.P.g;
         wk(a, d, W_GN)[C] += mg * n + mg * n;
     }
@@ -199,30 +243,27 @@ __device__ __forceinline__ FaceBar face_bar(const double* A0, const double* A1, 
 }
 
 // Contributions of one face's flux adjoint to the adjoints of the cell
-// `me` (one of L, R): eta-bar, qx-bar, qy-bar, u-bar, v-bar, h-bar.
+// `me` (L or R of the face): eta-bar, qx-bar, qy-bar, u-bar, v-bar, h-bar.
 struct CellBar { double e, qx, qy, u, v, h; };
 
 __device__ __forceinline__ void face_flux_adjoint(const FaceBar& fb, int kind, int dir,
-                                                  bool ghost_is_R, long long L, long long R,
-                                                  bool me_is_L, bool xface, const double* E,
-                                                  const double* QN, const double* H,
-                                                  const double* U, const double* V,
-                                                  const double* Z, double hdry, double hg,
+                                                  bool ghost_is_R, bool me_is_L, bool xface,
+                                                  const Cell& L, const Cell& R, double zL,
+                                                  double zR, double hdry, double hg,
                                                   CellBar& cb) {
     if (kind == BC_WALL) return;
-    long long dn;
-    bool pass;
+    bool dnR, pass;
     if (kind == BC_INFLOW) {
-        dn = ghost_is_R ? R : L;
+        dnR = ghost_is_R;
         pass = true;
     } else {
-        dn = dir > 0 ? R : L;
-        pass = H[dn] > hdry;
+        dnR = dir > 0;
+        pass = (dnR ? R.h : L.h) > hdry;
     }
-    const long long me = me_is_L ? L : R;
-    if (dn == me) {
-        const double fm = pass ? QN[dn] : 0.0;
-        const double fmb = (fb.m + fb.x * U[dn]) + fb.y * V[dn];
+    if (dnR != me_is_L) {   // the donor cell is `me`
+        const Cell& D = dnR ? R : L;
+        const double fm = pass ? (xface ? D.qx : D.qy) : 0.0;
+        const double fmb = (fb.m + fb.x * D.u) + fb.y * D.v;
         cb.u += fb.x * fm;
         cb.v += fb.y * fm;
         if (pass) {
@@ -233,20 +274,19 @@ __device__ __forceinline__ void face_flux_adjoint(const FaceBar& fb, int kind, i
         }
     }
     if (kind >= 0) return;   // boundary faces carry no pressure
-    const bool wetL = H[L] > hdry, wetR = H[R] > hdry;
-    const bool bank = (!wetL && Z[L] > E[R]) || (!wetR && Z[R] > E[L]);
+    const bool wetL = L.h > hdry, wetR = R.h > hdry;
+    const bool bank = (!wetL && zL > R.e) || (!wetR && zR > L.e);
     if (bank) return;
-    const double hL = H[L], hR = H[R];
-    const double A = hg * (hpos(hL) + hpos(hR));
-    const double del = E[R] - E[L];
+    const double A = hg * (hpos(L.h) + hpos(R.h));
+    const double del = R.e - L.e;
     const double Ab = fb.p * del, delb = fb.p * A;
     const double Sb = Ab * hg;
     if (me_is_L) {
         cb.e -= delb;
-        cb.h += hL > 0.0 ? Sb : 0.0;
+        cb.h += L.h > 0.0 ? Sb : 0.0;
     } else {
         cb.e += delb;
-        cb.h += hR > 0.0 ? Sb : 0.0;
+        cb.h += R.h > 0.0 ? Sb : 0.0;
     }
 }
 
@@ -258,27 +298,29 @@ __device__ __forceinline__ int yface_kind(const Params& P, int i, int fj) {
 }
 
 // Sum over the (up to) four faces of padded cell (i, j) of the flux
-// adjoints, for the fluxes of the state at trace slots (src, prim) with
+// adjoints, for the fluxes of state U (with inflow qin) whose cell `me` is,
 // donor direction dir, whose update's adjoint is A (three arrays).
-__device__ CellBar gather_faces(const AdjointArgs& a, const Pad& d, int i, int j, int src,
-                                int prim, int dir, const double* A0, const double* A1,
-                                const double* A2, double rx, double ry) {
+__device__ CellBar gather_faces(const AdjointArgs& a, const Pad& d, int i, int j, const Cell& me,
+                                const double* const* U, double qin, int dir, const double* A0,
+                                const double* A1, const double* A2, double rx, double ry) {
     CellBar cb = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const double hdry = a.P.h_dry, hg = 0.5 * a.P.g;
-    const double* E = tr(a, d, src);
-    const double* QX = tr(a, d, src + 1);
-    const double* QY = tr(a, d, src + 2);
-    const double* H = tr(a, d, prim);
-    const double* U = tr(a, d, prim + 2);
-    const double* V = tr(a, d, prim + 3);
+    const double zme = a.zp[d.at(i, j)];
     if (j >= 0 && j < d.ny) {    // x faces: rows 0 .. ny-1, slots -1 .. nx-1
         for (int side = 0; side < 2; ++side) {
             const int fi = side == 0 ? i : i - 1;    // me is L of face fi when side == 0
             if (fi < -1 || fi > d.nx - 1) continue;
             const int kind = xface_kind(a.P, fi, j);
             const FaceBar fb = face_bar(A0, A1, A2, d, fi, j, fi + 1, j, rx, dir, true);
-            face_flux_adjoint(fb, kind, dir, fi == d.nx - 1, d.at(fi, j), d.at(fi + 1, j),
-                              side == 0, true, E, QX, H, U, V, a.zp, hdry, hg, cb);
+            const int io = side == 0 ? i + 1 : i - 1;
+            const Cell other = cell_at(a, d, U, qin, io, j);
+            const double zo = a.zp[d.at(io, j)];
+            if (side == 0)
+                face_flux_adjoint(fb, kind, dir, fi == d.nx - 1, true, true, me, other, zme, zo,
+                                  hdry, hg, cb);
+            else
+                face_flux_adjoint(fb, kind, dir, fi == d.nx - 1, false, true, other, me, zo, zme,
+                                  hdry, hg, cb);
         }
     }
     if (i >= 0 && i < d.nx) {    // y faces: columns 0 .. nx-1, slots -1 .. ny-1
@@ -287,8 +329,15 @@ __device__ CellBar gather_faces(const AdjointArgs& a, const Pad& d, int i, int j
             if (fj < -1 || fj > d.ny - 1) continue;
             const int kind = yface_kind(a.P, i, fj);
             const FaceBar fb = face_bar(A0, A1, A2, d, i, fj, i, fj + 1, ry, dir, false);
-            face_flux_adjoint(fb, kind, dir, fj == d.ny - 1, d.at(i, fj), d.at(i, fj + 1),
-                              side == 0, false, E, QY, H, U, V, a.zp, hdry, hg, cb);
+            const int jo = side == 0 ? j + 1 : j - 1;
+            const Cell other = cell_at(a, d, U, qin, i, jo);
+            const double zo = a.zp[d.at(i, jo)];
+            if (side == 0)
+                face_flux_adjoint(fb, kind, dir, fj == d.ny - 1, true, false, me, other, zme, zo,
+                                  hdry, hg, cb);
+            else
+                face_flux_adjoint(fb, kind, dir, fj == d.ny - 1, false, false, other, me, zo, zme,
+                                  hdry, hg, cb);
         }
     }
     return cb;
@@ -309,19 +358,20 @@ __global__ void k_adj_c(AdjointArgs a) {
     if (!padded_cell(d, blockIdx.x * kBX + threadIdx.x, blockIdx.y * kBY + threadIdx.y, i, j))
         return;
     const long long C = d.at(i, j);
+    const double qin1 = a.ctl->qin1;
     const double* AB = wk(a, d, W_AB);
-    const CellBar cb = gather_faces(a, d, i, j, T_US, T_HS, -a.sigma, AB, AB + d.N, AB + 2 * d.N,
-                                    a.rx, a.ry);
+    const Cell me = cell_at(a, d, a.us, qin1, i, j);
+    const CellBar cb = gather_faces(a, d, i, j, me, a.us, qin1, -a.sigma, AB, AB + d.N,
+                                    AB + 2 * d.N, a.rx, a.ry);
     const bool in = d.interior(i, j);
     double eb = cb.e + (in ? AB[C] : 0.0);
     double qxb = cb.qx + (in ? AB[d.N + C] : 0.0);
     double qyb = cb.qy + (in ? AB[2 * d.N + C] : 0.0);
     // S9: h = eta - zp, r = wet ? 1/h : 0, u = qx r, v = qy r
-    const double h = tr(a, d, T_HS)[C], r = tr(a, d, T_RS)[C];
-    const double qx = tr(a, d, T_US + 1)[C], qy = tr(a, d, T_US + 2)[C];
+    const double h = me.h, r = me.r;
     qxb += cb.u * r;
     qyb += cb.v * r;
-    const double rb = cb.u * qx + cb.v * qy;
+    const double rb = cb.u * me.qx + cb.v * me.qy;
     const double hb = cb.h + (h > a.P.h_dry ? -(rb * r) / h : 0.0);
     eb += hb;
     double* AUS = wk(a, d, W_AUS);
@@ -371,13 +421,12 @@ __global__ void k_adj_d(AdjointArgs a) {
 
 // Face coefficient of S4 between cells L and R and the derivative of it
 // with respect to nu: which of the two it follows (0: L, 1: R, -1: none).
-__device__ __forceinline__ double eps_and_arg(const double* H, const double* NU, long long L,
-                                              long long R, double hdry, double kap, double emax,
-                                              int& arg) {
+__device__ __forceinline__ double eps_and_arg(double hL, double hR, double nuL, double nuR,
+                                              double hdry, double kap, double emax, int& arg) {
     arg = -1;
-    if (!(H[L] > hdry && H[R] > hdry)) return 0.0;
-    const bool takeL = NU[L] > NU[R];
-    const double t = kap * (takeL ? NU[L] : NU[R]);
+    if (!(hL > hdry && hR > hdry)) return 0.0;
+    const bool takeL = nuL > nuR;
+    const double t = kap * (takeL ? nuL : nuR);
     if (t < emax) {
         arg = takeL ? 0 : 1;
         return t;
@@ -393,10 +442,11 @@ __global__ void k_adj_e1(AdjointArgs a) {
     if (i >= d.nx || j >= d.ny) return;
     const long long C = d.at(i, j);
     const double hdry = a.P.h_dry, kap = a.P.kappa, emax = a.P.eps_max;
-    const double* H = tr(a, d, T_H);
-    const double* Q = tr(a, d, T_UN);
+    const double qin0 = a.ctl->qin0;
     const double* AD = wk(a, d, W_AD);
     const double* AB = wk(a, d, W_AB);
+    const Cell me = cell_at(a, d, a.un, qin0, i, j);
+    const double nuMe[2] = {nu_at(a, i, j, true, me.e, me.r), nu_at(a, i, j, false, me.e, me.r)};
     double un[3] = {AB[C], AB[d.N + C], AB[2 * d.N + C]};
     double nub[2] = {0.0, 0.0};
     for (int f = 0; f < 4; ++f) {
@@ -405,16 +455,20 @@ __global__ void k_adj_e1(AdjointArgs a) {
         const int nj = xf ? j : (f == 2 ? j + 1 : j - 1);
         if (ni < 0 || ni >= d.nx || nj < 0 || nj >= d.ny) continue;   // boundary face: eps = 0
         const long long nb = d.at(ni, nj);
+        const Cell on = cell_at(a, d, a.un, qin0, ni, nj);
+        const double nuOn = nu_at(a, ni, nj, xf, on.e, on.r);
         const bool meL = f == 0 || f == 2;
         const long long L = meL ? C : nb, R = meL ? nb : C;
-        const double* NU = tr(a, d, xf ? T_NUX : T_NUY);
+        const Cell& cL = meL ? me : on;
+        const Cell& cR = meL ? on : me;
+        const double nuL = meL ? nuMe[xf ? 0 : 1] : nuOn, nuR = meL ? nuOn : nuMe[xf ? 0 : 1];
         int arg;
-        const double eps = eps_and_arg(H, NU, L, R, hdry, kap, emax, arg);
+        const double eps = eps_and_arg(cL.h, cR.h, nuL, nuR, hdry, kap, emax, arg);
+        const double qL[3] = {cL.e, cL.qx, cL.qy}, qR[3] = {cR.e, cR.qx, cR.qy};
         double epsb = 0.0;
         for (int k = 0; k < 3; ++k) {
-            const double* q = Q + (long long)k * d.N;
             const double* ad = AD + (long long)k * d.N;
-            epsb += (ad[L] - ad[R]) * (q[R] - q[L]);
+            epsb += (ad[L] - ad[R]) * (qR[k] - qL[k]);
             un[k] += eps * (ad[nb] - ad[C]);
         }
         if (arg == (meL ? 0 : 1)) nub[xf ? 0 : 1] += epsb * kap;
@@ -429,13 +483,12 @@ __global__ void k_adj_e1(AdjointArgs a) {
 
 // d-bar of the curvature switch at interior cell X (x or y direction), and
 // its |d| for the r-bar term.
-__device__ __forceinline__ double switch_dbar(const double* E, const double* R, const double* NUB,
-                                              long long Xm, long long X, long long Xp,
-                                              double& absd_t) {
-    const double dd = (E[Xp] - E[X]) - (E[X] - E[Xm]);
-    const double t = 0.25 * NUB[X];
+__device__ __forceinline__ double switch_dbar(double eXm, double eX, double eXp, double rX,
+                                              double nubX, double& absd_t) {
+    const double dd = (eXp - eX) - (eX - eXm);
+    const double t = 0.25 * nubX;
     absd_t = t * __builtin_fabs(dd);
-    const double absb = t * R[X];
+    const double absb = t * rX;
     return dd > 0.0 ? absb : (dd < 0.0 ? -absb : 0.0);
 }
 
@@ -447,8 +500,10 @@ __global__ void k_adj_e2(AdjointArgs a) {
         return;
     const long long C = d.at(i, j);
     const bool in = d.interior(i, j);
+    const double qin0 = a.ctl->qin0;
     const double* AUS = wk(a, d, W_AUS);
-    const CellBar cb = gather_faces(a, d, i, j, T_UN, T_H, a.sigma, AUS, AUS + d.N,
+    const Cell me = cell_at(a, d, a.un, qin0, i, j);
+    const CellBar cb = gather_faces(a, d, i, j, me, a.un, qin0, a.sigma, AUS, AUS + d.N,
                                     AUS + 2 * d.N, a.rx, a.ry);
     double* AUN = wk(a, d, W_AUN);
     double eb = cb.e, qxb = cb.qx, qyb = cb.qy;
@@ -458,19 +513,19 @@ __global__ void k_adj_e2(AdjointArgs a) {
         qyb += AUN[2 * d.N + C] + AUS[2 * d.N + C];
     }
     // S3: nu = 0.25*(|d| r) at interior cells X; d reaches X-1, X, X+1
-    const double* E = tr(a, d, T_UN);
-    const double* R = tr(a, d, T_R);
-    double rb = cb.u * tr(a, d, T_UN + 1)[C] + cb.v * tr(a, d, T_UN + 2)[C];
+    const double* E = a.un[0];
+    double rb = cb.u * me.qx + cb.v * me.qy;
     for (int dirn = 0; dirn < 2; ++dirn) {
         const double* NUB = wk(a, d, dirn == 0 ? W_ANX : W_ANY);
         for (int o = -1; o <= 1; ++o) {
             const int xi = dirn == 0 ? i + o : i, xj = dirn == 0 ? j : j + o;
             if (!d.interior(xi, xj)) continue;
-            const long long X = d.at(xi, xj);
-            const long long Xm = dirn == 0 ? d.at(xi - 1, xj) : d.at(xi, xj - 1);
-            const long long Xp = dirn == 0 ? d.at(xi + 1, xj) : d.at(xi, xj + 1);
+            const double eX = E[pitched(a.P, xi, xj)];
+            const double eXm = dirn == 0 ? eta_at(a.P, E, xi - 1, xj) : eta_at(a.P, E, xi, xj - 1);
+            const double eXp = dirn == 0 ? eta_at(a.P, E, xi + 1, xj) : eta_at(a.P, E, xi, xj + 1);
+            const double rX = recip_depth(eX - a.zp[d.at(xi, xj)], a.P.h_dry);
             double absd_t;
-            const double db = switch_dbar(E, R, NUB, Xm, X, Xp, absd_t);
+            const double db = switch_dbar(eXm, eX, eXp, rX, NUB[d.at(xi, xj)], absd_t);
             if (o == 0) {
                 eb += -db - db;
                 rb += absd_t;
@@ -480,7 +535,7 @@ __global__ void k_adj_e2(AdjointArgs a) {
         }
     }
     // S2: h = eta - zp, r = wet ? 1/h : 0, u = qx r, v = qy r
-    const double h = tr(a, d, T_H)[C], r = R[C];
+    const double h = me.h, r = me.r;
     qxb += cb.u * r;
     qyb += cb.v * r;
     const double hb = cb.h + (h > a.P.h_dry ? -(rb * r) / h : 0.0);

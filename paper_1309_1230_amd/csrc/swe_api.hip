@@ -616,12 +616,7 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
     constexpr bool mixed = sizeof(T) == 4;
     const int64_t nobs = nsteps / g->obs_every;
     const int ng = g->ngauge;
-    int rc = SWE_OK;
-    if (!mixed) {
-        rc = ensure_trace(h);
-        if (rc) return rc;
-    }
-    rc = fill_stats(h, nullptr);
+    int rc = fill_stats(h, nullptr);
     if (rc) return rc;
     Ctl c0;
     hipError_t e = hipMemcpyAsync(&c0, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream);
@@ -632,7 +627,7 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
     const size_t Npad = padded_elems(h);
     const int64_t C = std::max<int64_t>(1, std::min<int64_t>(ckpt_every, std::max<int64_t>(nsteps, 1)));
     const int64_t nseg = (nsteps + C - 1) / C;
-    DevBuf ck, seg, scratch, work, logs, mis, dcells, actl, prom, stat64, trace64;
+    DevBuf ck, seg, scratch, work, logs, mis, dcells, actl, prom, stat64, fwd, padst;
     if ((e = ck.alloc((size_t)nseg * 3 * fe * sizeof(T))) != hipSuccess ||
         (e = seg.alloc((size_t)C * 3 * fe * sizeof(T))) != hipSuccess ||
         (e = scratch.alloc(3 * fe * sizeof(double))) != hipSuccess ||
@@ -640,16 +635,17 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
         (e = logs.alloc(2 * (size_t)std::max<int64_t>(nsteps, 1) * sizeof(double))) != hipSuccess ||
         (e = mis.alloc((size_t)std::max<int64_t>(nobs * ng, 1) * sizeof(double))) != hipSuccess ||
         (e = dcells.alloc((size_t)std::max(ng, 1) * sizeof(long long))) != hipSuccess ||
-        (e = actl.alloc(sizeof(Ctl))) != hipSuccess)
+        (e = actl.alloc(2 * sizeof(Ctl))) != hipSuccess ||
+        (e = fwd.alloc(6 * fe * sizeof(double))) != hipSuccess ||
+        (e = padst.alloc(2 * Npad * sizeof(double))) != hipSuccess)
         return fail(h, SWE_ENOMEM, std::string("swe_grad: hipMalloc failed: ") + hip_text(e));
     // FP64 views the reverse sweep works on
     const double* z64 = (const double*)h->z;
     const double* n64 = (const double*)h->n;
-    double* tr64 = (double*)h->trace;
+    const double* m64 = (const double*)bufB(h, 3);
     if (mixed) {
         if ((e = prom.alloc(3 * fe * sizeof(double))) != hipSuccess ||
-            (e = stat64.alloc(3 * fe * sizeof(double))) != hipSuccess ||
-            (e = trace64.alloc((size_t)(swe::kTraceArrays + 2) * Npad * sizeof(double))) != hipSuccess)
+            (e = stat64.alloc(3 * fe * sizeof(double))) != hipSuccess)
             return fail(h, SWE_ENOMEM, std::string("swe_grad: hipMalloc failed: ") + hip_text(e));
         double* zz = stat64.d();
         double* nn = stat64.d() + fe;
@@ -658,17 +654,12 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
         e = swe::launch_promote((const float*)h->z, zz, ne, h->stream);
         if (e == hipSuccess) e = swe::launch_promote((const float*)h->n, nn, ne, h->stream);
         if (e == hipSuccess) e = swe::launch_manning_m<double>(h->P, nn, mm, h->stream);
-        if (e == hipSuccess)
-            e = hipMemsetAsync(trace64.p, 0, (size_t)(swe::kTraceArrays + 2) * Npad * sizeof(double),
-                               h->stream);
-        tr64 = trace64.d();
-        if (e == hipSuccess)
-            e = swe::launch_pad_static<double>(h->P, zz, mm, tr64 + (size_t)swe::kTraceArrays * Npad,
-                                               tr64 + (size_t)(swe::kTraceArrays + 1) * Npad,
-                                               h->stream);
         z64 = zz;
         n64 = nn;
+        m64 = mm;
     }
+    if (e == hipSuccess)
+        e = swe::launch_pad_static<double>(h->P, z64, m64, padst.d(), padst.d() + Npad, h->stream);
     if (e == hipSuccess && ng > 0)
         e = hipMemcpyAsync(dcells.p, g->cells, (size_t)ng * sizeof(long long),
                            hipMemcpyHostToDevice, h->stream);
@@ -717,14 +708,21 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
     for (int64_t k = 0; k < nobs * ng; ++k) J = J + hm[(size_t)k];
     // ---- reverse sweep, segment by segment
     e = hipMemsetAsync(work.p, 0, (size_t)swe::adjoint_work_arrays() * Npad * sizeof(double), h->stream);
+    Ctl* rc_ctl = (Ctl*)actl.p;
+    Ctl* adj_ctl = rc_ctl + 1;   // the step's control block for the adjoint kernels
+    double* US = fwd.d();
+    double* UD = fwd.d() + 3 * fe;
     swe::AdjointArgs aa;
     aa.P = h->P;
-    aa.trace = tr64;
-    aa.zp = aa.trace + (size_t)swe::kTraceArrays * Npad;
-    aa.mp = aa.zp + Npad;
+    aa.ctl = adj_ctl;
+    for (int f = 0; f < 3; ++f) {
+        aa.us[f] = US + (size_t)f * fe;
+        aa.ud[f] = UD + (size_t)f * fe;
+    }
+    aa.zp = padst.d();
+    aa.mp = padst.d() + Npad;
     aa.nman = n64;
     aa.work = work.d();
-    Ctl* rc_ctl = (Ctl*)actl.p;
     // SWE_VERBOSE=1 in the environment: a line on stderr after the forward run
     // and after each reverse segment (each waits for the device)
     const char* verbose_env = std::getenv("SWE_VERBOSE");
@@ -777,25 +775,33 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
                     U64[f] = d;
                 }
             }
+            // the step once more in FP64 with its known dt, writing U* and U^d
             if (e == hipSuccess)
                 e = swe::launch_replay_ctl(h->P, rc_ctl, ht[(size_t)k], step0 + k, hdt[(size_t)k],
                                            h->stream);
+            if (e == hipSuccess)
+                e = swe::launch_replay_ctl(h->P, adj_ctl, ht[(size_t)k], step0 + k,
+                                           hdt[(size_t)k], h->stream);
             if (e != hipSuccess) break;
             double* Sc = scratch.d();
-            swe::UnfusedArgs<double> ua;
-            ua.P = h->P;
-            ua.ctl = rc_ctl;
-            ua.t_end = INFINITY;
-            ua.eta = U64[0]; ua.qx = U64[1]; ua.qy = U64[2];
-            ua.z = z64;
-            ua.eta1 = Sc; ua.qx1 = Sc + fe; ua.qy1 = Sc + 2 * fe;
-            ua.trace = tr64;
-            ua.zp = aa.zp;
-            ua.mp = aa.mp;
-            ua.part_def = h->part;
-            ua.part_vol = h->part + h->nparts;
+            swe::FusedArgs<double> ta;
+            ta.P = h->P;
+            ta.ctl = rc_ctl;
+            ta.t_end = INFINITY;
+            ta.eta = U64[0]; ta.qx = U64[1]; ta.qy = U64[2];
+            ta.z = z64;
+            ta.m = m64;
+            ta.eta1 = Sc; ta.qx1 = Sc + fe; ta.qy1 = Sc + 2 * fe;
+            swe::fused_part_layout(ta, h->fpart, h->nparts);
+            ta.gy = h->gy;
+            ta.H = h->H;
+            for (int f = 0; f < 3; ++f) {
+                ta.tus[f] = US + (size_t)f * fe;
+                ta.tud[f] = UD + (size_t)f * fe;
+                aa.un[f] = U64[f];
+            }
             const int sigma = ((step0 + k) & 1) ? -1 : 1;
-            e = swe::launch_unfused_step<double>(ua, sigma, h->stream, false);
+            e = swe::launch_fused_trace(ta, sigma, h->stream);
             if (e != hipSuccess) break;
             aa.dt = hdt[(size_t)k];
             aa.rx = aa.dt / h->P.dx;

@@ -209,6 +209,24 @@ __device__ __forceinline__ void boundary_flux(int kind, bool normal_is_x, T fm, 
     }
 }
 
+// S1 / S8: ghost value of a W/E (normal = qx) or S/N (normal = qy) edge
+// cell (e, qx, qy: the adjacent interior cell; inward: the signed inflow).
+template <typename T>
+__device__ __forceinline__ void ghost(int kind, bool normal_is_x, T inward, T e, T qx, T qy,
+                                      T& ge, T& gqx, T& gqy) {
+    ge = e;
+    if (kind == BC_OPEN) {
+        gqx = qx;
+        gqy = qy;
+    } else if (kind == BC_INFLOW) {
+        gqx = normal_is_x ? inward : T(0);
+        gqy = normal_is_x ? T(0) : inward;
+    } else {
+        gqx = normal_is_x ? -qx : qx;
+        gqy = normal_is_x ? qy : -qy;
+    }
+}
+
 // S14: point-implicit Manning friction of a wet cell with reciprocal depth r.
 template <typename T>
 __device__ __forceinline__ void manning(T dt, T m, T r, T& qx, T& qy) {

@@ -168,7 +168,7 @@ __device__ __forceinline__ YFace<T> y_face(const Consts<T>& c, bool bnd, bool so
 // State of one wave's march up its chunk: per-lane constants, the rows and
 // faces carried from one iteration to the next, the prefetched row and the
 // running partial sums.  Rows are named relative to the ingested row R.
-template <typename T, int SIG, bool DRY>
+template <typename T, int SIG, bool DRY, bool TRACE = false>
 struct March {
     Consts<T> c;
     const Params* P;
@@ -180,6 +180,9 @@ struct March {
     T* __restrict__ eta1;
     T* __restrict__ qx1;
     T* __restrict__ qy1;
+    // TRACE: U* (S7) and U^d (S13, before friction) of the output cells
+    T* tus[3];
+    T* tud[3];
     long long pitch;
     int nx, ny, i, ic, y0, yEnd, kS, kN;
     bool colOut, faceE_interior, atW, atE;
@@ -285,6 +288,12 @@ struct March {
         T sr1 = T(0);
         if (sh1 > c.hdry) sr1 = trcp(sh1);
         const T su1 = sa1 * sr1, sv1 = sb1 * sr1;
+        if (TRACE && colOut && R - 1 >= y0 && R - 1 < yEnd) {
+            const long long so = (long long)(R - 1) * pitch + i;
+            tus[0][so] = se1;
+            tus[1][so] = sa1;
+            tus[2][so] = sb1;
+        }
         XDiv<T> B1;
         if (SIG > 0)   // corrector donor direction -1: neighbour on the west
             B1 = x_divergence<T, -1>(c, se1, sa1, sh1, sr1, su1, sv1, z1, from_west(se1),
@@ -310,6 +319,12 @@ struct March {
             const T ca = T(0.5) * (a2 + ((sa2 - c.rx * B2.x) - c.ry * (H0.x - H1.x)));
             const T cb = T(0.5) * (b2 + ((sb2 - c.rx * B2.y) - c.ry * ((H0.y - H1.y) + pcs)));
             T e = ce + Dm, a = ca + Da, b = cb + Db;
+            if (TRACE && colOut) {
+                const long long so = (long long)(R - 2) * pitch + i;
+                tud[0][so] = e;
+                tud[1][so] = a;
+                tud[2][so] = b;
+            }
             T h = e - z2;
             T lam = T(0);
             if (h > c.hdry) {
@@ -491,12 +506,17 @@ __device__ __forceinline__ void finish_step(const FusedArgs<T>& A, int tile, int
 // still its unchanged volume) and refreshes the output buffer only if the
 // previous step computed it (after a skip both buffers already hold the
 // tile's state).
-template <typename T, int SIG, bool DRY>
+template <typename T, int SIG, bool DRY, bool TRACE = false>
 __device__ __forceinline__ void fused_step(const FusedArgs<T>& A, int blk, int nblk) {
     Ctl* ctl = A.ctl;
     if (step_is_noop(ctl, A.t_end)) return;
     const Params& P = A.P;
-    March<T, SIG, DRY> M;
+    March<T, SIG, DRY, TRACE> M;
+    if (TRACE)
+        for (int f = 0; f < 3; ++f) {
+            M.tus[f] = A.tus[f];
+            M.tud[f] = A.tud[f];
+        }
     M.c.rx = T(ctl->rx); M.c.ry = T(ctl->ry); M.c.dt = T(ctl->dt);
     M.c.qin0 = T(ctl->qin0); M.c.qin1 = T(ctl->qin1);
     M.c.hdry = T(P.h_dry); M.c.g = T(P.g); M.c.hg = T(0.5 * P.g);
@@ -603,6 +623,11 @@ template <int SIG, bool DRY>
 __global__ void __launch_bounds__(kWave, 3) k_fused_step_f32(FusedArgs<float> A) {
     fused_step<float, SIG, DRY>(A, blockIdx.x, gridDim.x);
 }
+// The FP64 step that also writes U* and U^d (the forward data of the adjoint).
+template <int SIG>
+__global__ void __launch_bounds__(kWave, 2) k_fused_trace_f64(FusedArgs<double> A) {
+    fused_step<double, SIG, false, true>(A, blockIdx.x, gridDim.x);
+}
 
 // Ensemble launch: the workgroups of every scenario in one grid.  Scenario s
 // owns workgroups first[s] .. first[s+1]-1 (first[count] = total); its
@@ -670,6 +695,16 @@ hipError_t launch_fused(const FusedArgs<T>& a, int sigma, hipStream_t s) {
     const auto k = sigma > 0 ? (dry ? fused_kernel<T, 1, true>() : fused_kernel<T, 1, false>())
                              : (dry ? fused_kernel<T, -1, true>() : fused_kernel<T, -1, false>());
     hipLaunchKernelGGL(k, dim3(nblk), dim3(kWave), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_trace(const FusedArgs<double>& a, int sigma, hipStream_t s) {
+    const int gx = (a.P.nx + kOutW - 1) / kOutW;
+    const int nblk = gx * a.gy;
+    if (sigma > 0)
+        hipLaunchKernelGGL(k_fused_trace_f64<1>, dim3(nblk), dim3(kWave), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_fused_trace_f64<-1>, dim3(nblk), dim3(kWave), 0, s, a);
     return hipGetLastError();
 }
 

@@ -30,10 +30,16 @@ struct FusedArgs {
     // parity, tile index strip * gy + chunk), cleared at the start of every
     // host call.
     unsigned* dry = nullptr;
+    // launch_fused_trace only: U* and U^d of every cell (pitched, 3 fields each)
+    T* tus[3] = {nullptr, nullptr, nullptr};
+    T* tud[3] = {nullptr, nullptr, nullptr};
 };
 
 template <typename T>
 hipError_t launch_fused(const FusedArgs<T>& a, int sigma, hipStream_t s);
+// The FP64 fused step that also writes U* (after S7) and U^d (after S13,
+// before friction) of every cell to a.tus and a.tud.
+hipError_t launch_fused_trace(const FusedArgs<double>& a, int sigma, hipStream_t s);
 // One fused step of every scenario of an ensemble in one launch: scenario s
 // owns workgroups first[s] .. first[s+1]-1 of `total` (args, first: device).
 // dry: some scenario has the dry-tile skip on (its args carry the flags).
@@ -110,16 +116,20 @@ hipError_t launch_replay_ctl(const Params& P, Ctl* ctl, double t, long long step
 hipError_t launch_init_ctl(Ctl* ctl, double t, long long step, unsigned flags, double defect,
                            hipStream_t s);
 
-// Arguments of the adjoint of one step (FP64): the step's forward
-// intermediates in the unfused trace layout, the padded static fields, and
-// the adjoint work arrays (adjoint_work_arrays() padded arrays; lambda in
-// slots 15..17 on entry and exit, dJ/dn and dJ/dz accumulators in 18, 19).
+// Arguments of the adjoint of one step (FP64): the step's forward data U^n,
+// U* and U^d (pitched, as launch_fused_trace writes them), the control block
+// holding the step's inflow values, the padded static fields, and the
+// adjoint work arrays (adjoint_work_arrays() padded arrays; lambda in slots
+// 15..17 on entry and exit, dJ/dn and dJ/dz accumulators in 18, 19).
 struct AdjointArgs {
     Params P;
-    const double* trace;
-    const double* zp;
+    const Ctl* ctl;          // q_in(t^n) and q_in(t^n + dt) of the step
+    const double* un[3];
+    const double* us[3];
+    const double* ud[3];
+    const double* zp;        // padded bed and m = g n^2 (ghosts copy the edge cell)
     const double* mp;
-    const double* nman;   // Manning field (pitched)
+    const double* nman;      // Manning field (pitched)
     double* work;
     double dt, rx, ry;
     int sigma;

@@ -49,23 +49,6 @@ __device__ __forceinline__ T* arr(T* trace, const Pad& d, int k) {
     return trace + (long long)k * d.N;
 }
 
-// Ghost value of a W/E (normal = qx) or S/N (normal = qy) edge cell.
-template <typename T>
-__device__ __forceinline__ void ghost(int kind, bool normal_is_x, T inward, T e, T qx, T qy,
-                                      T& ge, T& gqx, T& gqy) {
-    ge = e;
-    if (kind == BC_OPEN) {
-        gqx = qx;
-        gqy = qy;
-    } else if (kind == BC_INFLOW) {
-        gqx = normal_is_x ? inward : T(0);
-        gqy = normal_is_x ? T(0) : inward;
-    } else {
-        gqx = normal_is_x ? -qx : qx;
-        gqy = normal_is_x ? qy : -qy;
-    }
-}
-
 // S1: copy U^n into the padded arrays and build its ghost ring.
 template <typename T>
 __global__ void k_s1(UnfusedArgs<T> a) {
