@@ -222,7 +222,11 @@ typedef struct swe_gauges {
  * run; max/min follow the argument they return, |x| and sqrt have
  * derivative 0 at 0).  Memory: states every ckpt_every steps are kept, and
  * each segment of ckpt_every steps is recomputed once during the reverse
- * sweep (about 2 + 1/ckpt_every forward passes in all).  dJ_dn and dJ_dz
+ * sweep (about 2 + 1/ckpt_every forward passes in all); FP64 handles also
+ * keep U* and U^d of each step of the segment being reversed (6 fields per
+ * step) when that fits in a third of the free device memory, else each
+ * step is replayed once more (SWE_GRAD_KEEP=0 in the environment forces the
+ * replay; the gradient is the same bit for bit).  dJ_dn and dJ_dz
  * (device, FP64, caller-owned, the handle's pitch) receive the gradients;
  * *loss (host) receives J.  FP32 handles: the forward run, its checkpoints
  * and the recomputed segments are FP32 (the state trajectory is that of

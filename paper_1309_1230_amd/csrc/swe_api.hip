@@ -639,6 +639,20 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
         (e = fwd.alloc(6 * fe * sizeof(double))) != hipSuccess ||
         (e = padst.alloc(2 * Npad * sizeof(double))) != hipSuccess)
         return fail(h, SWE_ENOMEM, std::string("swe_grad: hipMalloc failed: ") + hip_text(e));
+    // FP64 handles keep U* and U^d of every step of a segment when that fits
+    // in a third of the free device memory: the segment's recompute then runs
+    // the tracing step, and the reverse sweep replays nothing
+    // (SWE_GRAD_KEEP=0 in the environment forces the per-step replay)
+    DevBuf segtr;
+    bool keep = false;
+    const char* keep_env = std::getenv("SWE_GRAD_KEEP");
+    if (!mixed && !(keep_env && keep_env[0] == '0')) {
+        size_t freeb = 0, totalb = 0;
+        const size_t need = (size_t)C * 6 * fe * sizeof(double);
+        if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && need <= freeb / 3)
+            keep = segtr.alloc(need) == hipSuccess;
+        (void)hipGetLastError();
+    }
     // FP64 views the reverse sweep works on
     const double* z64 = (const double*)h->z;
     const double* n64 = (const double*)h->n;
@@ -743,13 +757,18 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
         slot(ck.p, sg, CK);
         e = copy_state<T>(h, U0, CK);
         // the fused kernel's own finalisation carries dt from step to step
-        if (e == hipSuccess && s1 - s0 > 1)
+        if (e == hipSuccess && (keep || s1 - s0 > 1))
             e = swe::launch_replay_ctl(h->P, rc_ctl, ht[(size_t)s0], step0 + s0, hdt[(size_t)s0],
                                        h->stream);
-        for (int64_t k = s0; k + 1 < s1 && e == hipSuccess; ++k) {
+        const int64_t srec = keep ? s1 : s1 - 1;   // steps recomputed
+        for (int64_t k = s0; k < srec && e == hipSuccess; ++k) {
             T *Uk[3], *Un[3];
             slot(seg.p, k - s0, Uk);
-            slot(seg.p, k + 1 - s0, Un);
+            if (k + 1 < s1) {
+                slot(seg.p, k + 1 - s0, Un);
+            } else {
+                for (int f = 0; f < 3; ++f) Un[f] = (T*)scratch.p + (size_t)f * fe;
+            }
             swe::FusedArgs<T> fa;
             fa.P = h->P;
             fa.ctl = rc_ctl;
@@ -761,7 +780,19 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
             swe::fused_part_layout(fa, h->fpart, h->nparts);
             fa.gy = h->gy;
             fa.H = h->H;
-            e = swe::launch_fused<T>(fa, ((step0 + k) & 1) ? -1 : 1, h->stream);
+            const int sig = ((step0 + k) & 1) ? -1 : 1;
+            if constexpr (!mixed) {
+                if (keep) {
+                    double* tk = segtr.d() + (size_t)(k - s0) * 6 * fe;
+                    for (int f = 0; f < 3; ++f) {
+                        fa.tus[f] = tk + (size_t)f * fe;
+                        fa.tud[f] = tk + (size_t)(3 + f) * fe;
+                    }
+                    e = swe::launch_fused_trace(fa, sig, h->stream);
+                    continue;
+                }
+            }
+            e = swe::launch_fused<T>(fa, sig, h->stream);
         }
         for (int64_t k = s1 - 1; k >= s0 && e == hipSuccess; --k) {
             T* Uk[3];
@@ -775,34 +806,46 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
                     U64[f] = d;
                 }
             }
-            // the step once more in FP64 with its known dt, writing U* and U^d
-            if (e == hipSuccess)
-                e = swe::launch_replay_ctl(h->P, rc_ctl, ht[(size_t)k], step0 + k, hdt[(size_t)k],
-                                           h->stream);
             if (e == hipSuccess)
                 e = swe::launch_replay_ctl(h->P, adj_ctl, ht[(size_t)k], step0 + k,
                                            hdt[(size_t)k], h->stream);
             if (e != hipSuccess) break;
-            double* Sc = scratch.d();
-            swe::FusedArgs<double> ta;
-            ta.P = h->P;
-            ta.ctl = rc_ctl;
-            ta.t_end = INFINITY;
-            ta.eta = U64[0]; ta.qx = U64[1]; ta.qy = U64[2];
-            ta.z = z64;
-            ta.m = m64;
-            ta.eta1 = Sc; ta.qx1 = Sc + fe; ta.qy1 = Sc + 2 * fe;
-            swe::fused_part_layout(ta, h->fpart, h->nparts);
-            ta.gy = h->gy;
-            ta.H = h->H;
-            for (int f = 0; f < 3; ++f) {
-                ta.tus[f] = US + (size_t)f * fe;
-                ta.tud[f] = UD + (size_t)f * fe;
-                aa.un[f] = U64[f];
-            }
             const int sigma = ((step0 + k) & 1) ? -1 : 1;
-            e = swe::launch_fused_trace(ta, sigma, h->stream);
-            if (e != hipSuccess) break;
+            const double* US_k = US;
+            const double* UD_k = UD;
+            if (keep) {
+                // U* and U^d were kept by the segment's recompute
+                US_k = segtr.d() + (size_t)(k - s0) * 6 * fe;
+                UD_k = US_k + 3 * fe;
+            } else {
+                // the step once more in FP64 with its known dt, writing U* and U^d
+                e = swe::launch_replay_ctl(h->P, rc_ctl, ht[(size_t)k], step0 + k,
+                                           hdt[(size_t)k], h->stream);
+                if (e != hipSuccess) break;
+                double* Sc = scratch.d();
+                swe::FusedArgs<double> ta;
+                ta.P = h->P;
+                ta.ctl = rc_ctl;
+                ta.t_end = INFINITY;
+                ta.eta = U64[0]; ta.qx = U64[1]; ta.qy = U64[2];
+                ta.z = z64;
+                ta.m = m64;
+                ta.eta1 = Sc; ta.qx1 = Sc + fe; ta.qy1 = Sc + 2 * fe;
+                swe::fused_part_layout(ta, h->fpart, h->nparts);
+                ta.gy = h->gy;
+                ta.H = h->H;
+                for (int f = 0; f < 3; ++f) {
+                    ta.tus[f] = US + (size_t)f * fe;
+                    ta.tud[f] = UD + (size_t)f * fe;
+                }
+                e = swe::launch_fused_trace(ta, sigma, h->stream);
+                if (e != hipSuccess) break;
+            }
+            for (int f = 0; f < 3; ++f) {
+                aa.un[f] = U64[f];
+                aa.us[f] = US_k + (size_t)f * fe;
+                aa.ud[f] = UD_k + (size_t)f * fe;
+            }
             aa.dt = hdt[(size_t)k];
             aa.rx = aa.dt / h->P.dx;
             aa.ry = aa.dt / h->P.dy;

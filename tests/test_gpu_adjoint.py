@@ -82,6 +82,17 @@ def test_checkpoint_spacing_does_not_change_the_gradient():
         assert np.array_equal(o[1], outs[0][1]) and np.array_equal(o[2], outs[0][2])
 
 
+def test_kept_traces_and_replay_give_the_same_gradient(monkeypatch):
+    p = prep("inflow")
+    G = gauges_for(p, 20, 4, 10, seed=9)
+    note("segment traces kept vs replayed per step")
+    a = gpu_grad(p, G, 20, 6)
+    monkeypatch.setenv("SWE_GRAD_KEEP", "0")
+    b = gpu_grad(p, G, 20, 6)
+    assert a[0] == b[0]
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
 def test_state_after_grad_equals_run():
     p = prep("smooth")
     G = gauges_for(p, 12, 3, 6, seed=7)
