@@ -275,7 +275,9 @@ def combined_run(torch, swe, W, nx, nsteps, ckpt, obs_every):
     fe = p.ny * p.nx
     npad = (p.nx + 2) * (p.ny + 2)
     nseg = (nsteps + ckpt - 1) // ckpt
-    planned = (nseg + ckpt) * 3 * fe * 4 + 9 * fe * 8 + (49 + 20) * npad * 8
+    # FP32 checkpoints and segment states; FP64: replay output, promoted state,
+    # z/n/m, U* and U^d (15 pitched fields), padded z and m, 20 adjoint arrays
+    planned = (nseg + ckpt) * 3 * fe * 4 + 15 * fe * 8 + (2 + 20) * npad * 8
     progress(f"combined: swe_grad, planned scratch {planned / 1e9:.1f} GB of "
              f"{free0 / 1e9:.1f} GB free")
     os.environ["SWE_VERBOSE"] = "1"   # the library reports each reverse segment on stderr
