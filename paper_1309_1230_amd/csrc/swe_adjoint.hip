@@ -27,7 +27,7 @@ namespace swe {
 
 namespace {
 
-constexpr int kBX = 64, kBY = 4;
+constexpr int kBX = 128, kBY = 2;   // 2D blocks of the adjoint sweeps (measured best of 32..256 x 1..16)
 
 // The adjoint's own arrays are padded with a one-cell ring: element (i, j),
 // i in [-1, nx], j in [-1, ny], at (j+1)*(nx+2) + (i+1).
@@ -137,37 +137,105 @@ __device__ double cbrt3_adjoint(double x, double ybar) {
     return xbar;
 }
 
-// Loss terms of an observed step: lambda_eta += 2 d and dJ/dz -= 2 d at
-// each gauge, d = (eta^{n+1} - z) - h_obs.  Gauge cells are distinct.
-// eta^{n+1} is the dry fix of eta^d (friction leaves eta unchanged).
-__global__ void k_adj_seed(AdjointArgs a, const long long* cells, int ngauge, const double* hobs) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ngauge) return;
-    const Pad d = pad_of(a.P);
-    const long long c = cells[g];
-    const int i = (int)(c % a.P.nx), j = (int)(c / a.P.nx);
-    const long long C = d.at(i, j);
-    const double zp = a.zp[C], ef = a.ud[0][pitched(a.P, i, j)];
-    const double en = ef - zp < 0.0 ? zp : ef;
-    const double dd = (en - zp) - hobs[g];
-    wk(a, d, W_LAM)[C] += dd + dd;
-    wk(a, d, W_GZ)[C] += 0.0 - (dd + dd);
+// Fold the adjoint of a ghost cell into its interior neighbour C (the ghost
+// ring copies eta, and copies, mirrors or replaces the discharges).
+__device__ __forceinline__ void fold_ghost(double* A, const Pad& d, long long C, long long g,
+                                           int kind, bool normal_is_x) {
+    A[C] += A[g];
+    if (kind == BC_OPEN) {
+        A[d.N + C] += A[d.N + g];
+        A[2 * d.N + C] += A[2 * d.N + g];
+    } else if (kind == BC_WALL) {
+        if (normal_is_x) {
+            A[d.N + C] -= A[d.N + g];
+            A[2 * d.N + C] += A[2 * d.N + g];
+        } else {
+            A[d.N + C] += A[d.N + g];
+            A[2 * d.N + C] -= A[2 * d.N + g];
+        }
+    }
+    // an inflow ghost's discharges are imposed: no adjoint flows back
 }
 
-// S15, S14, S13 and the U^n share of S12, per interior cell.
-__global__ void k_adj_a(AdjointArgs a) {
+__device__ __forceinline__ void fold_ring(const AdjointArgs& a, double* A, const Pad& d, int i,
+                                          int j) {
+    const long long C = d.at(i, j);
+    if (i == 0) fold_ghost(A, d, C, d.at(-1, j), face_kind(a.P, EDGE_W, j), true);
+    if (i == d.nx - 1) fold_ghost(A, d, C, d.at(d.nx, j), face_kind(a.P, EDGE_E, j), true);
+    if (j == 0) fold_ghost(A, d, C, d.at(i, -1), face_kind(a.P, EDGE_S, i), false);
+    if (j == d.ny - 1) fold_ghost(A, d, C, d.at(i, d.ny), face_kind(a.P, EDGE_N, i), false);
+}
+
+// The same fold into a copy: a[0..2] start as A at cell (i, j) and receive
+// its ghost cells' contributions in the order of fold_ring.
+__device__ __forceinline__ void fold_ghost_into(const double* A, const Pad& d, long long g,
+                                                int kind, bool normal_is_x, double* a) {
+    a[0] += A[g];
+    if (kind == BC_OPEN) {
+        a[1] += A[d.N + g];
+        a[2] += A[2 * d.N + g];
+    } else if (kind == BC_WALL) {
+        if (normal_is_x) {
+            a[1] -= A[d.N + g];
+            a[2] += A[2 * d.N + g];
+        } else {
+            a[1] += A[d.N + g];
+            a[2] -= A[2 * d.N + g];
+        }
+    }
+}
+
+__device__ __forceinline__ void fold_ring_into(const AdjointArgs& a, const double* A, const Pad& d,
+                                               int i, int j, double* v) {
+    if (i == 0) fold_ghost_into(A, d, d.at(-1, j), face_kind(a.P, EDGE_W, j), true, v);
+    if (i == d.nx - 1) fold_ghost_into(A, d, d.at(d.nx, j), face_kind(a.P, EDGE_E, j), true, v);
+    if (j == 0) fold_ghost_into(A, d, d.at(i, -1), face_kind(a.P, EDGE_S, i), false, v);
+    if (j == d.ny - 1) fold_ghost_into(A, d, d.at(i, d.ny), face_kind(a.P, EDGE_N, i), false, v);
+}
+
+// S1 of the step reversed before this one (its ghost ring of U^n folded into
+// lambda, the bed's padded adjoint into dJ/dz), the loss terms of this step
+// when it is observed (lambda_eta += 2 d, dJ/dz -= 2 d at each gauge,
+// d = (eta^{n+1} - z) - h_obs, eta^{n+1} being the dry fix of eta^d since
+// friction leaves eta unchanged), then S15, S14, S13 and the U^n share of
+// S12, per interior cell.  gmap: gauge index of each cell (j*nx + i), or -1;
+// hobs: this step's observations, or NULL.
+__global__ void k_adj_fa(AdjointArgs a, const int* gmap, const double* hobs) {
     const Pad d = pad_of(a.P);
     const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y;
     if (i >= d.nx || j >= d.ny) return;
     const long long C = d.at(i, j), o = pitched(a.P, i, j);
     const double hdry = a.P.h_dry, zp = a.zp[C];
-    const double* LAM = wk(a, d, W_LAM);
-    const double le = LAM[C], lx = LAM[d.N + C], ly = LAM[2 * d.N + C];
-    // S15 dry fix (S14 leaves eta as U^d's)
+    // previous step's S1: lambda = AUN with the ghost ring folded in
+    const double* AUN = wk(a, d, W_AUN);
+    double lam[3] = {AUN[C], AUN[d.N + C], AUN[2 * d.N + C]};
+    fold_ring_into(a, AUN, d, i, j, lam);
+    double* AZP = wk(a, d, W_AZP);
+    double gzs = AZP[C];
+    const long long gs[4] = {i == 0 ? d.at(-1, j) : -1, i == d.nx - 1 ? d.at(d.nx, j) : -1,
+                             j == 0 ? d.at(i, -1) : -1, j == d.ny - 1 ? d.at(i, d.ny) : -1};
+    for (int k = 0; k < 4; ++k)
+        if (gs[k] >= 0) {
+            gzs += AZP[gs[k]];
+            AZP[gs[k]] = 0.0;
+        }
+    double gz = wk(a, d, W_GZ)[C] + gzs;
+    // this step's loss terms
     const double ed = a.ud[0][o], qx = a.ud[1][o], qy = a.ud[2][o];
     const double ef = ed;
     const bool clip = ef - zp < 0.0;
     const double en = clip ? zp : ef;
+    if (hobs) {
+        const int g = gmap[(long long)j * d.nx + i];
+        if (g >= 0) {
+            const double dd = (en - zp) - hobs[g];
+            lam[0] += dd + dd;
+            gz += 0.0 - (dd + dd);
+        }
+    }
+    wk(a, d, W_GZ)[C] = gz;
+    const double le = lam[0], lx = lam[1], ly = lam[2];
+    // S15 dry fix (S14 leaves eta as U^d's)
     const bool dry = !(en - zp > hdry);
     double azp = clip ? le : 0.0;
     const double efb = clip ? 0.0 : le;
@@ -215,7 +283,7 @@ __global__ void k_adj_a(AdjointArgs a) {
     double* AB = wk(a, d, W_AB);
     AD[C] = edb; AD[d.N + C] = qxdb; AD[2 * d.N + C] = qydb;
     AB[C] = 0.5 * edb; AB[d.N + C] = 0.5 * qxdb; AB[2 * d.N + C] = 0.5 * qydb;
-    wk(a, d, W_AZP)[C] = azp;
+    AZP[C] = azp;
 }
 
 // Adjoint of the flux-divergence update out = base - L_dir (S7 / inner S12)
@@ -223,15 +291,32 @@ __global__ void k_adj_a(AdjointArgs a) {
 // adjoint A of `out` on the two cells of the face (zero off the interior).
 struct FaceBar { double m, x, y, p; };
 
-__device__ __forceinline__ FaceBar face_bar(const double* A0, const double* A1, const double* A2,
+// The adjoint 3-vector A (padded, three arrays d.N apart) at cell (i, j):
+// zero off the interior; with `fold`, an edge cell also receives its ghost
+// cells' contributions (the S8 fold of U*-bar, applied where it is read).
+__device__ __forceinline__ void vec_at(const AdjointArgs& a, const double* A, const Pad& d, int i,
+                                       int j, bool fold, double* v) {
+    if (!d.interior(i, j)) {
+        v[0] = v[1] = v[2] = 0.0;
+        return;
+    }
+    const long long C = d.at(i, j);
+    v[0] = A[C];
+    v[1] = A[d.N + C];
+    v[2] = A[2 * d.N + C];
+    if (fold) fold_ring_into(a, A, d, i, j, v);
+}
+
+__device__ __forceinline__ FaceBar face_bar(const AdjointArgs& a, const double* A, bool fold,
                                             const Pad& d, int iL, int jL, int iR, int jR,
                                             double coef, int dir, bool xface) {
-    const bool inL = d.interior(iL, jL), inR = d.interior(iR, jR);
-    const long long L = d.at(iL, jL), R = d.at(iR, jR);
     FaceBar f;
-    const double aL0 = inL ? A0[L] : 0.0, aR0 = inR ? A0[R] : 0.0;
-    const double aL1 = inL ? A1[L] : 0.0, aR1 = inR ? A1[R] : 0.0;
-    const double aL2 = inL ? A2[L] : 0.0, aR2 = inR ? A2[R] : 0.0;
+    double vL[3], vR[3];
+    vec_at(a, A, d, iL, jL, fold, vL);
+    vec_at(a, A, d, iR, jR, fold, vR);
+    const double aL0 = vL[0], aR0 = vR[0];
+    const double aL1 = vL[1], aR1 = vR[1];
+    const double aL2 = vL[2], aR2 = vR[2];
     f.m = coef * aR0 - coef * aL0;
     f.x = coef * aR1 - coef * aL1;
     f.y = coef * aR2 - coef * aL2;
@@ -301,8 +386,8 @@ __device__ __forceinline__ int yface_kind(const Params& P, int i, int fj) {
 // adjoints, for the fluxes of state U (with inflow qin) whose cell `me` is,
 // donor direction dir, whose update's adjoint is A (three arrays).
 __device__ CellBar gather_faces(const AdjointArgs& a, const Pad& d, int i, int j, const Cell& me,
-                                const double* const* U, double qin, int dir, const double* A0,
-                                const double* A1, const double* A2, double rx, double ry) {
+                                const double* const* U, double qin, int dir, const double* A,
+                                bool fold, double rx, double ry) {
     CellBar cb = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const double hdry = a.P.h_dry, hg = 0.5 * a.P.g;
     const double zme = a.zp[d.at(i, j)];
@@ -311,7 +396,7 @@ __device__ CellBar gather_faces(const AdjointArgs& a, const Pad& d, int i, int j
             const int fi = side == 0 ? i : i - 1;    // me is L of face fi when side == 0
             if (fi < -1 || fi > d.nx - 1) continue;
             const int kind = xface_kind(a.P, fi, j);
-            const FaceBar fb = face_bar(A0, A1, A2, d, fi, j, fi + 1, j, rx, dir, true);
+            const FaceBar fb = face_bar(a, A, fold, d, fi, j, fi + 1, j, rx, dir, true);
             const int io = side == 0 ? i + 1 : i - 1;
             const Cell other = cell_at(a, d, U, qin, io, j);
             const double zo = a.zp[d.at(io, j)];
@@ -328,7 +413,7 @@ __device__ CellBar gather_faces(const AdjointArgs& a, const Pad& d, int i, int j
             const int fj = side == 0 ? j : j - 1;
             if (fj < -1 || fj > d.ny - 1) continue;
             const int kind = yface_kind(a.P, i, fj);
-            const FaceBar fb = face_bar(A0, A1, A2, d, i, fj, i, fj + 1, ry, dir, false);
+            const FaceBar fb = face_bar(a, A, fold, d, i, fj, i, fj + 1, ry, dir, false);
             const int jo = side == 0 ? j + 1 : j - 1;
             const Cell other = cell_at(a, d, U, qin, i, jo);
             const double zo = a.zp[d.at(i, jo)];
@@ -358,11 +443,10 @@ __global__ void k_adj_c(AdjointArgs a) {
     if (!padded_cell(d, blockIdx.x * kBX + threadIdx.x, blockIdx.y * kBY + threadIdx.y, i, j))
         return;
     const long long C = d.at(i, j);
-    const double qin1 = a.ctl->qin1;
+    const double qin1 = a.qin1;
     const double* AB = wk(a, d, W_AB);
     const Cell me = cell_at(a, d, a.us, qin1, i, j);
-    const CellBar cb = gather_faces(a, d, i, j, me, a.us, qin1, -a.sigma, AB, AB + d.N,
-                                    AB + 2 * d.N, a.rx, a.ry);
+    const CellBar cb = gather_faces(a, d, i, j, me, a.us, qin1, -a.sigma, AB, false, a.rx, a.ry);
     const bool in = d.interior(i, j);
     double eb = cb.e + (in ? AB[C] : 0.0);
     double qxb = cb.qx + (in ? AB[d.N + C] : 0.0);
@@ -379,44 +463,6 @@ __global__ void k_adj_c(AdjointArgs a) {
     AUS[d.N + C] = qxb;
     AUS[2 * d.N + C] = qyb;
     wk(a, d, W_AZP)[C] -= hb;
-}
-
-// Fold the adjoint of a ghost cell into its interior neighbour C (the ghost
-// ring copies eta, and copies, mirrors or replaces the discharges).
-__device__ __forceinline__ void fold_ghost(double* A, const Pad& d, long long C, long long g,
-                                           int kind, bool normal_is_x) {
-    A[C] += A[g];
-    if (kind == BC_OPEN) {
-        A[d.N + C] += A[d.N + g];
-        A[2 * d.N + C] += A[2 * d.N + g];
-    } else if (kind == BC_WALL) {
-        if (normal_is_x) {
-            A[d.N + C] -= A[d.N + g];
-            A[2 * d.N + C] += A[2 * d.N + g];
-        } else {
-            A[d.N + C] += A[d.N + g];
-            A[2 * d.N + C] -= A[2 * d.N + g];
-        }
-    }
-    // an inflow ghost's discharges are imposed: no adjoint flows back
-}
-
-__device__ __forceinline__ void fold_ring(const AdjointArgs& a, double* A, const Pad& d, int i,
-                                          int j) {
-    const long long C = d.at(i, j);
-    if (i == 0) fold_ghost(A, d, C, d.at(-1, j), face_kind(a.P, EDGE_W, j), true);
-    if (i == d.nx - 1) fold_ghost(A, d, C, d.at(d.nx, j), face_kind(a.P, EDGE_E, j), true);
-    if (j == 0) fold_ghost(A, d, C, d.at(i, -1), face_kind(a.P, EDGE_S, i), false);
-    if (j == d.ny - 1) fold_ghost(A, d, C, d.at(i, d.ny), face_kind(a.P, EDGE_N, i), false);
-}
-
-// S8: the ghost ring of U* folded into the edge cells.
-__global__ void k_adj_d(AdjointArgs a) {
-    const Pad d = pad_of(a.P);
-    const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y;
-    if (i >= d.nx || j >= d.ny) return;
-    if (i > 0 && i < d.nx - 1 && j > 0 && j < d.ny - 1) return;
-    fold_ring(a, wk(a, d, W_AUS), d, i, j);
 }
 
 // Face coefficient of S4 between cells L and R and the derivative of it
@@ -442,7 +488,7 @@ __global__ void k_adj_e1(AdjointArgs a) {
     if (i >= d.nx || j >= d.ny) return;
     const long long C = d.at(i, j);
     const double hdry = a.P.h_dry, kap = a.P.kappa, emax = a.P.eps_max;
-    const double qin0 = a.ctl->qin0;
+    const double qin0 = a.qin0;
     const double* AD = wk(a, d, W_AD);
     const double* AB = wk(a, d, W_AB);
     const Cell me = cell_at(a, d, a.un, qin0, i, j);
@@ -500,17 +546,18 @@ __global__ void k_adj_e2(AdjointArgs a) {
         return;
     const long long C = d.at(i, j);
     const bool in = d.interior(i, j);
-    const double qin0 = a.ctl->qin0;
+    const double qin0 = a.qin0;
     const double* AUS = wk(a, d, W_AUS);
     const Cell me = cell_at(a, d, a.un, qin0, i, j);
-    const CellBar cb = gather_faces(a, d, i, j, me, a.un, qin0, a.sigma, AUS, AUS + d.N,
-                                    AUS + 2 * d.N, a.rx, a.ry);
+    const CellBar cb = gather_faces(a, d, i, j, me, a.un, qin0, a.sigma, AUS, true, a.rx, a.ry);
     double* AUN = wk(a, d, W_AUN);
     double eb = cb.e, qxb = cb.qx, qyb = cb.qy;
     if (in) {
-        eb += AUN[C] + AUS[C];
-        qxb += AUN[d.N + C] + AUS[d.N + C];
-        qyb += AUN[2 * d.N + C] + AUS[2 * d.N + C];
+        double us[3];
+        vec_at(a, AUS, d, i, j, true, us);
+        eb += AUN[C] + us[0];
+        qxb += AUN[d.N + C] + us[1];
+        qyb += AUN[2 * d.N + C] + us[2];
     }
     // S3: nu = 0.25*(|d| r) at interior cells X; d reaches X-1, X, X+1
     const double* E = a.un[0];
@@ -585,6 +632,18 @@ __global__ void k_misfit(Params P, const T* eta, const T* z, const long long* ce
     out[g] = dd * dd;
 }
 
+// gmap[c] = -1 for every cell, then gmap[cells[g]] = g (gauge cells are
+// distinct).
+__global__ void k_gauge_clear(int* gmap, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
+        gmap[k] = -1;
+}
+__global__ void k_gauge_set(const long long* cells, int ngauge, int* gmap) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < ngauge) gmap[cells[g]] = g;
+}
+
 __global__ void k_promote(const float* src, double* dst, size_t n) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
@@ -604,19 +663,31 @@ inline dim3 grid2(int w, int h) { return dim3((w + kBX - 1) / kBX, (h + kBY - 1)
 
 int adjoint_work_arrays() { return 20; }
 
-hipError_t launch_adjoint_step(const AdjointArgs& a, const long long* cells, int ngauge,
-                               const double* hobs, hipStream_t s) {
+hipError_t launch_adjoint_step(const AdjointArgs& a, const int* gmap, const double* hobs,
+                               hipStream_t s) {
     const int nx = a.P.nx, ny = a.P.ny;
     const dim3 b2(kBX, kBY);
-    if (ngauge > 0 && hobs)
-        hipLaunchKernelGGL(k_adj_seed, dim3((ngauge + 255) / 256), dim3(256), 0, s, a, cells,
-                           ngauge, hobs);
-    hipLaunchKernelGGL(k_adj_a, grid2(nx, ny), b2, 0, s, a);
+    hipLaunchKernelGGL(k_adj_fa, grid2(nx, ny), b2, 0, s, a, gmap, hobs);
     hipLaunchKernelGGL(k_adj_c, grid2(nx + 2, ny + 2), b2, 0, s, a);
-    hipLaunchKernelGGL(k_adj_d, grid2(nx, ny), b2, 0, s, a);
     hipLaunchKernelGGL(k_adj_e1, grid2(nx, ny), b2, 0, s, a);
     hipLaunchKernelGGL(k_adj_e2, grid2(nx + 2, ny + 2), b2, 0, s, a);
-    hipLaunchKernelGGL(k_adj_f, grid2(nx, ny), b2, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_finish(const AdjointArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_f, grid2(a.P.nx, a.P.ny), dim3(kBX, kBY), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gauge_map(const Params& P, const long long* cells, int ngauge, int* gmap,
+                            hipStream_t s) {
+    const size_t n = (size_t)P.nx * (size_t)P.ny;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_gauge_clear, dim3((unsigned)blocks), dim3(256), 0, s, gmap, n);
+    if (ngauge > 0)
+        hipLaunchKernelGGL(k_gauge_set, dim3((ngauge + 255) / 256), dim3(256), 0, s, cells,
+                           ngauge, gmap);
     return hipGetLastError();
 }
 

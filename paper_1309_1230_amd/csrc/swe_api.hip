@@ -38,6 +38,7 @@ struct swe_handle {
     double* part = nullptr;    // 2 * nparts
     int nparts = 0;
     double* hydro = nullptr;   // device copy of (t, q)
+    std::vector<double> hydro_host;   // host copy: hydro_len times, then discharges
     void* trace = nullptr;     // unfused scratch: 47 padded arrays + zp + mp
     unsigned* dry = nullptr;   // dry-tile skip flags (2 * nparts words), or NULL
     void* fpart = nullptr;     // fused path: tile and group records, group tickets
@@ -109,7 +110,8 @@ hipError_t copy_back(swe_handle* h) {
 // Enqueue the k-th step of a call: sigma follows the global step index, and
 // even k read the caller's arrays (A) and write the library's (B).
 template <typename T>
-hipError_t enqueue_step(swe_handle* h, int64_t k, double t_end, bool unfused) {
+hipError_t enqueue_step(swe_handle* h, int64_t k, double t_end, bool unfused, double* log_dt,
+                        double* log_t) {
     const int sigma = ((h->step_host + k) & 1) ? -1 : 1;
     const int s = k & 1;  // 0: A -> B, 1: B -> A
     const T* src[3];
@@ -145,6 +147,8 @@ hipError_t enqueue_step(swe_handle* h, int64_t k, double t_end, bool unfused) {
     a.gy = h->gy;
     a.H = h->H;
     a.dry = h->dry;
+    a.log_dt = log_dt;
+    a.log_t = log_t;
     return swe::launch_fused<T>(a, sigma, h->stream);
 }
 
@@ -155,9 +159,11 @@ hipError_t begin_call(swe_handle* h, hipStream_t s) {
     return swe::launch_begin_call(h->ctl, s, h->dry, 2 * h->nparts);
 }
 
-hipError_t enqueue(swe_handle* h, int64_t k, double t_end, bool unfused) {
-    return h->dtype == SWE_F32 ? enqueue_step<float>(h, k, t_end, unfused)
-                               : enqueue_step<double>(h, k, t_end, unfused);
+// log_dt, log_t (fused path): where the step stores its dt^n and t^n, or NULL.
+hipError_t enqueue(swe_handle* h, int64_t k, double t_end, bool unfused,
+                   double* log_dt = nullptr, double* log_t = nullptr) {
+    return h->dtype == SWE_F32 ? enqueue_step<float>(h, k, t_end, unfused, log_dt, log_t)
+                               : enqueue_step<double>(h, k, t_end, unfused, log_dt, log_t);
 }
 
 hipError_t enqueue_copy_back(swe_handle* h) {
@@ -383,6 +389,7 @@ int swe_create(const swe_config* c, swe_handle** out) {
         hy[k] = c->hydro_t[k];
         hy[c->hydro_len + k] = c->hydro_q[k];
     }
+    h->hydro_host = hy;
     if ((e = hipMalloc((void**)&h->hydro, hy.size() * sizeof(double))) != hipSuccess) {
         fail(nullptr, SWE_ENOMEM, std::string("hipMalloc failed: ") + hip_text(e));
         return cleanup(SWE_ENOMEM);
@@ -584,13 +591,6 @@ struct DevBuf {
     double* d() const { return (double*)p; }
 };
 
-__global__ void k_log_ctl(const Ctl* ctl, double* dt_out, double* t_out) {
-    if (threadIdx.x == 0) {
-        *dt_out = ctl->dt;
-        *t_out = ctl->t;
-    }
-}
-
 // Elements of a pitched field that belong to it (the last row ends at nx).
 size_t state_elems(const swe_handle* h) {
     return (size_t)(h->P.ny - 1) * (size_t)h->P.pitch + (size_t)h->P.nx;
@@ -627,7 +627,7 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
     const size_t Npad = padded_elems(h);
     const int64_t C = std::max<int64_t>(1, std::min<int64_t>(ckpt_every, std::max<int64_t>(nsteps, 1)));
     const int64_t nseg = (nsteps + C - 1) / C;
-    DevBuf ck, seg, scratch, work, logs, mis, dcells, actl, prom, stat64, fwd, padst;
+    DevBuf ck, seg, scratch, work, logs, mis, dcells, actl, prom, stat64, fwd, padst, gmap;
     if ((e = ck.alloc((size_t)nseg * 3 * fe * sizeof(T))) != hipSuccess ||
         (e = seg.alloc((size_t)C * 3 * fe * sizeof(T))) != hipSuccess ||
         (e = scratch.alloc(3 * fe * sizeof(double))) != hipSuccess ||
@@ -635,9 +635,10 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
         (e = logs.alloc(2 * (size_t)std::max<int64_t>(nsteps, 1) * sizeof(double))) != hipSuccess ||
         (e = mis.alloc((size_t)std::max<int64_t>(nobs * ng, 1) * sizeof(double))) != hipSuccess ||
         (e = dcells.alloc((size_t)std::max(ng, 1) * sizeof(long long))) != hipSuccess ||
-        (e = actl.alloc(2 * sizeof(Ctl))) != hipSuccess ||
+        (e = actl.alloc(sizeof(Ctl))) != hipSuccess ||
         (e = fwd.alloc(6 * fe * sizeof(double))) != hipSuccess ||
-        (e = padst.alloc(2 * Npad * sizeof(double))) != hipSuccess)
+        (e = padst.alloc(2 * Npad * sizeof(double))) != hipSuccess ||
+        (e = gmap.alloc((size_t)h->P.nx * (size_t)h->P.ny * sizeof(int))) != hipSuccess)
         return fail(h, SWE_ENOMEM, std::string("swe_grad: hipMalloc failed: ") + hip_text(e));
     // FP64 handles keep U* and U^d of every step of a segment when that fits
     // in a third of the free device memory: the segment's recompute then runs
@@ -677,6 +678,8 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
     if (e == hipSuccess && ng > 0)
         e = hipMemcpyAsync(dcells.p, g->cells, (size_t)ng * sizeof(long long),
                            hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = swe::launch_gauge_map(h->P, (const long long*)dcells.p, ng, (int*)gmap.p, h->stream);
     double* dtlog = logs.d();
     double* tlog = logs.d() + std::max<int64_t>(nsteps, 1);
     auto slot = [&](void* base, int64_t m, T* U[3]) {
@@ -692,12 +695,7 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
             slot(ck.p, k / C, dst);
             e = copy_state<T>(h, dst, cur);
         }
-        if (e == hipSuccess) {
-            hipLaunchKernelGGL(k_log_ctl, dim3(1), dim3(64), 0, h->stream, h->ctl, dtlog + k,
-                               tlog + k);
-            e = hipGetLastError();
-        }
-        if (e == hipSuccess) e = enqueue(h, k, INFINITY, false);
+        if (e == hipSuccess) e = enqueue(h, k, INFINITY, false, dtlog + k, tlog + k);
         if (e == hipSuccess && ng > 0 && (k + 1) % g->obs_every == 0) {
             const int64_t row = (k + 1) / g->obs_every - 1;
             const T* nxt = (const T*)((k & 1) ? bufA(h, 0) : bufB(h, 0));
@@ -723,12 +721,10 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
     // ---- reverse sweep, segment by segment
     e = hipMemsetAsync(work.p, 0, (size_t)swe::adjoint_work_arrays() * Npad * sizeof(double), h->stream);
     Ctl* rc_ctl = (Ctl*)actl.p;
-    Ctl* adj_ctl = rc_ctl + 1;   // the step's control block for the adjoint kernels
     double* US = fwd.d();
     double* UD = fwd.d() + 3 * fe;
     swe::AdjointArgs aa;
     aa.P = h->P;
-    aa.ctl = adj_ctl;
     for (int f = 0; f < 3; ++f) {
         aa.us[f] = US + (size_t)f * fe;
         aa.ud[f] = UD + (size_t)f * fe;
@@ -806,10 +802,13 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
                     U64[f] = d;
                 }
             }
-            if (e == hipSuccess)
-                e = swe::launch_replay_ctl(h->P, adj_ctl, ht[(size_t)k], step0 + k,
-                                           hdt[(size_t)k], h->stream);
             if (e != hipSuccess) break;
+            // the step's inflow values, evaluated as the forward step's
+            // finalisation evaluated them (same expression, same operands)
+            const int L = h->P.hydro_len;
+            const double* hyt = h->hydro_host.data();
+            aa.qin0 = swe::q_inflow_at(hyt, hyt + std::max(0, L), L, ht[(size_t)k]);
+            aa.qin1 = swe::q_inflow_at(hyt, hyt + std::max(0, L), L, ht[(size_t)k] + hdt[(size_t)k]);
             const int sigma = ((step0 + k) & 1) ? -1 : 1;
             const double* US_k = US;
             const double* UD_k = UD;
@@ -852,9 +851,10 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
             aa.sigma = sigma;
             const bool obs = ng > 0 && (k + 1) % g->obs_every == 0;
             const double* hrow = obs ? g->hobs + ((k + 1) / g->obs_every - 1) * ng : nullptr;
-            e = swe::launch_adjoint_step(aa, (const long long*)dcells.p, ng, hrow, h->stream);
+            e = swe::launch_adjoint_step(aa, (const int*)gmap.p, hrow, h->stream);
         }
     }
+    if (e == hipSuccess && nsteps > 0) e = swe::launch_adjoint_finish(aa, h->stream);
     if (e == hipSuccess)
         e = swe::launch_unpad(h->P, work.d() + (size_t)swe::kAdjGradN * Npad, (double*)dJ_dn, h->stream);
     if (e == hipSuccess)

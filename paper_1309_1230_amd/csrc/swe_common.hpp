@@ -90,16 +90,21 @@ __host__ __device__ inline int face_kind(const Params& P, int edge, int k) {
     return kind;
 }
 
-// Piecewise-linear hydrograph, constant outside its points.
-__device__ inline double q_inflow(const Params& P, double t) {
-    int L = P.hydro_len;
+// Piecewise-linear hydrograph of L points (times ht, discharges hq),
+// constant outside its points.  Host and device evaluate the same IEEE
+// expression, so both give the same bits.
+__host__ __device__ inline double q_inflow_at(const double* ht, const double* hq, int L,
+                                              double t) {
     if (L <= 0) return 0.0;
-    if (t <= P.hydro_t[0]) return P.hydro_q[0];
-    if (t >= P.hydro_t[L - 1]) return P.hydro_q[L - 1];
+    if (t <= ht[0]) return hq[0];
+    if (t >= ht[L - 1]) return hq[L - 1];
     int k = 0;
-    while (k + 1 < L && !(t < P.hydro_t[k + 1])) ++k;
-    double w = (t - P.hydro_t[k]) / (P.hydro_t[k + 1] - P.hydro_t[k]);
-    return P.hydro_q[k] + w * (P.hydro_q[k + 1] - P.hydro_q[k]);
+    while (k + 1 < L && !(t < ht[k + 1])) ++k;
+    double w = (t - ht[k]) / (ht[k + 1] - ht[k]);
+    return hq[k] + w * (hq[k + 1] - hq[k]);
+}
+__device__ inline double q_inflow(const Params& P, double t) {
+    return q_inflow_at(P.hydro_t, P.hydro_q, P.hydro_len, t);
 }
 
 __device__ inline double next_dt(const Params& P, double lam) {

@@ -489,6 +489,10 @@ __device__ __forceinline__ void finish_step(const FusedArgs<T>& A, int tile, int
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) sk += __shfl_xor(sk, off, kWave);
     if (lane == 0) {
+        if (A.log_dt) {
+            *A.log_dt = ctl->dt;
+            *A.log_t = ctl->t;
+        }
         ctl->skipped = ctl->skipped + sk;
         finalize_scalars(ctl, A.P, sd, sv, lam_from_bits(lm, lam_is_f32), fl, 1);
     }

@@ -30,6 +30,10 @@ struct FusedArgs {
     // parity, tile index strip * gy + chunk), cleared at the start of every
     // host call.
     unsigned* dry = nullptr;
+    // when not NULL, the step's finalisation stores dt^n and t^n (the step's
+    // own time step and start time) here
+    double* log_dt = nullptr;
+    double* log_t = nullptr;
     // launch_fused_trace only: U* and U^d of every cell (pitched, 3 fields each)
     T* tus[3] = {nullptr, nullptr, nullptr};
     T* tud[3] = {nullptr, nullptr, nullptr};
@@ -117,13 +121,13 @@ hipError_t launch_init_ctl(Ctl* ctl, double t, long long step, unsigned flags, d
                            hipStream_t s);
 
 // Arguments of the adjoint of one step (FP64): the step's forward data U^n,
-// U* and U^d (pitched, as launch_fused_trace writes them), the control block
-// holding the step's inflow values, the padded static fields, and the
+// U* and U^d (pitched, as launch_fused_trace writes them), the step's inflow
+// values, the padded static fields, and the
 // adjoint work arrays (adjoint_work_arrays() padded arrays; lambda in slots
 // 15..17 on entry and exit, dJ/dn and dJ/dz accumulators in 18, 19).
 struct AdjointArgs {
     Params P;
-    const Ctl* ctl;          // q_in(t^n) and q_in(t^n + dt) of the step
+    double qin0, qin1;       // q_in(t^n) and q_in(t^n + dt) of the step
     const double* un[3];
     const double* us[3];
     const double* ud[3];
@@ -137,9 +141,16 @@ struct AdjointArgs {
 
 int adjoint_work_arrays();
 constexpr int kAdjLambda = 15, kAdjGradN = 18, kAdjGradZ = 19;
-// Adjoint of one step; adds the gauge terms first when hobs is not NULL.
-hipError_t launch_adjoint_step(const AdjointArgs& a, const long long* cells, int ngauge,
-                               const double* hobs, hipStream_t s);
+// Adjoint of one step.  It first completes the step reversed before it (the
+// ghost ring of its U^n adjoint; nothing on the first), then adds this
+// step's gauge terms when hobs is not NULL (gmap from launch_gauge_map).
+hipError_t launch_adjoint_step(const AdjointArgs& a, const int* gmap, const double* hobs,
+                               hipStream_t s);
+// Completes the last step reversed (lambda and dJ/dz of its ghost ring).
+hipError_t launch_adjoint_finish(const AdjointArgs& a, hipStream_t s);
+// gmap[j*nx + i] = gauge index of cell (i, j), or -1 (nx*ny ints).
+hipError_t launch_gauge_map(const Params& P, const long long* cells, int ngauge, int* gmap,
+                            hipStream_t s);
 // out[g] = ((eta - z)(cell g) - hobs[g])^2 on a pitched state, in FP64 (an FP32
 // state is promoted before the difference).
 template <typename T>
