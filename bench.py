@@ -218,14 +218,29 @@ def ensemble_throughput(torch, swe, W, count, nsteps):
     t_seq = time.perf_counter() - t0
     for s in solvers:
         s.close()
+    e = swe.Ensemble.from_problems(probs, dtype=torch.float32, tile_rows=H, dry_skip=True)
+    e.capture(nsteps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e.replay()
+    st_dry = e.stats()
+    t_dry = time.perf_counter() - t0
+    skipped = sum(x.cells_skipped for x in st_dry)
+    same = all(a.t == b.t and a.volume == b.volume for a, b in zip(st, st_dry))
+    e.close()
     cu = sum(p.nx * p.ny for p in probs) * nsteps
-    progress(f"ensemble: graph replay {t_ens * 1e3:.1f} ms, one grid at a time {t_seq * 1e3:.1f} ms")
+    progress(f"ensemble: graph replay {t_ens * 1e3:.1f} ms (dry-tile skip {t_dry * 1e3:.1f} ms), "
+             f"one grid at a time {t_seq * 1e3:.1f} ms")
     return {"workload": f"flood ensemble: {count} scenarios, grids 64..1024 x 64..512 (seeded), "
                         f"{cells} cells, FP32, {nsteps}-step run captured in a HIP graph",
             "metric": "ensemble cells/s", "value": cu / t_ens, "unit": "cell-updates/s",
             "sequential_value": cu / t_seq, "speedup_vs_sequential": t_seq / t_ens,
             "tile_rows": H, "ms": t_ens * 1e3, "sequential_ms": t_seq * 1e3,
-            "steps_taken": steps}
+            "steps_taken": steps,
+            "dry_skip": {"ms": t_dry * 1e3, "dense_equivalent_value": cu / t_dry,
+                         "active_value": (cu - skipped) / t_dry,
+                         "skipped_fraction": skipped / cu, "speedup_vs_dense": t_ens / t_dry,
+                         "stats_equal_to_dense": same}}
 
 
 def dry_skip_run(torch, swe, W, p, dtype, steps, warmup, tile_rows, dense_st, dense_ms):
@@ -270,6 +285,8 @@ def combined_run(torch, swe, W, nx, nsteps, ckpt, obs_every):
     del s
     progress("combined: timing the FP32 forward run")
     st, ms_fwd, _ = timed_run(torch, swe, W, p, "f32", nsteps, 0, 0)
+    st_dry, ms_dry, _ = timed_run(torch, swe, W, p, "f32", nsteps, 0, 0, dry_skip=True)
+    progress(f"combined: forward {ms_fwd:.0f} ms, with the dry-tile skip {ms_dry:.0f} ms")
     f = swe.Solver.from_problem(p, dtype=torch.float32)
     free0, total = torch.cuda.mem_get_info()
     fe = p.ny * p.nx
@@ -298,6 +315,9 @@ def combined_run(torch, swe, W, nx, nsteps, ckpt, obs_every):
            "forward_dtype": "f32", "adjoint_dtype": "f64", "steps": nsteps, "sim_time_s": st.t,
            "checkpoint_every": ckpt, "forward_ms": ms_fwd,
            "forward_cell_updates_per_s": cells * nsteps / (ms_fwd / 1e3),
+           "forward_dry_skip_ms": ms_dry,
+           "forward_dry_skip_skipped_fraction": st_dry.cells_skipped / (cells * nsteps),
+           "forward_dry_skip_state_equal": st_dry.t == st.t and st_dry.volume == st.volume,
            "grad_ms": grad_s * 1e3, "adjoint_fwd_ratio": grad_s * 1e3 / ms_fwd,
            "loss": fin(J), "gradient_finite": finite,
            "max_abs_dJ_dn": fin(float(gn.abs().max())),
