@@ -536,13 +536,24 @@ __device__ __forceinline__ void fused_step(const FusedArgs<T>& A, int blk, int n
     const int lane = threadIdx.x;
     const int tile = xcd_tile(blk, nblk);
     const int pos = tile / A.gy, chunk = tile - pos * A.gy;
-    // strips enumerated by residue class mod 8: each XCD's contiguous run of
-    // tiles covers strips spread over the whole domain
+    // strips in pairs of neighbours, the pairs enumerated by residue class
+    // mod 8: each XCD's contiguous run of tiles covers strip pairs spread
+    // over the whole domain (wet and dry strips balance across the XCDs), and
+    // the two strips of a pair share the row lines they overlap in one L2
     const int gx = (P.nx + kOutW - 1) / kOutW;
+    const int npair = (gx + 1) / 2;
     int strip = pos, base = 0;
-    for (int r = 0; r < 8; ++r) {
-        const int n_r = gx > r ? (gx - r + 7) / 8 : 0;
-        if (pos < base + n_r) { strip = r + 8 * (pos - base); break; }
+    for (int r = 0; r < 8 && r < npair; ++r) {
+        // strips of the pairs r, r+8, r+16, ... (the last pair may be single)
+        const int last = npair - 1;
+        const int n_pairs = (last - r) / 8 + 1;
+        const bool short_last = (gx & 1) && ((last - r) % 8 == 0);
+        const int n_r = 2 * n_pairs - (short_last ? 1 : 0);
+        if (pos < base + n_r) {
+            const int q = pos - base;
+            strip = 2 * (r + 8 * (q / 2)) + (q & 1);
+            break;
+        }
         base += n_r;
     }
     const int x0 = strip * kOutW;
