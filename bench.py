@@ -86,7 +86,8 @@ def parse():
                     help="run only the adjoint measurement (for profiling)")
     ap.add_argument("--adj-nx", type=int, default=1024)
     ap.add_argument("--adj-steps", type=int, default=2000)
-    ap.add_argument("--adj-ckpt", type=int, default=45)
+    ap.add_argument("--adj-ckpt", type=int, default=0,
+                    help="checkpoint spacing of swe_grad; 0 keeps the whole trajectory")
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the flood-ensemble throughput measurement")
     ap.add_argument("--ensemble-only", action="store_true",
@@ -147,11 +148,15 @@ def adjoint_ratio(torch, swe, W, nx, nsteps, ckpt):
     """Cost of the discrete adjoint against the forward run on the Manning
     calibration workload: synthetic gauge observations from the true field,
     then (a) the forward run at the first guess, timed, and (b) swe_grad of
-    the misfit loss over the same run (forward with checkpoints, segment
-    recompute, reverse sweep), timed on a fresh solver."""
+    the misfit loss over the same run, timed on a fresh solver.  ckpt = 0:
+    the whole FP64 trajectory is kept in device memory (forward run with the
+    tracing step, reverse sweep, no recompute); the checkpointed mode (every
+    45 steps: forward, segment recompute, reverse sweep) is timed beside it
+    and its gradient compared bit for bit."""
     c = W.calibration(nx=nx, ny=nx, nsteps=nsteps)
     p = c.problem
-    progress(f"adjoint: {p.nx}x{p.ny} calibration, {nsteps} steps, checkpoint every {ckpt}")
+    mode = "trajectory kept" if ckpt == 0 else f"checkpoint every {ckpt}"
+    progress(f"adjoint: {p.nx}x{p.ny} calibration, {nsteps} steps, {mode}")
     truth = p.copy()
     truth.n = c.n_true
     s = swe.Solver.from_problem(truth, dtype=torch.float64)
@@ -173,19 +178,30 @@ def adjoint_ratio(torch, swe, W, nx, nsteps, ckpt):
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
     f.close()
-    g = swe.Solver.from_problem(p, dtype=torch.float64)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    J, gn, gz = g.grad(nsteps, c.cells, c.obs_every, hobs, ckpt)
-    torch.cuda.synchronize()
-    t_grad = time.perf_counter() - t0
-    g.close()
-    progress(f"adjoint: forward {t_fwd * 1e3:.1f} ms, swe_grad {t_grad * 1e3:.1f} ms")
-    return {"workload": f"Manning calibration {p.nx}x{p.ny}, dx={p.dx:g} m, FP64, {nsteps} steps, "
-                        f"{len(c.cells)} gauges every {c.obs_every} steps, checkpoint every {ckpt}",
-            "metric": "adjoint/fwd cost ratio", "value": t_grad / t_fwd,
-            "higher_is_better": False, "fwd_ms": t_fwd * 1e3, "grad_ms": t_grad * 1e3,
-            "loss": J, "max_abs_dJ_dn": float(gn.abs().max()), "max_abs_dJ_dz": float(gz.abs().max())}
+    def timed_grad(ck):
+        g = swe.Solver.from_problem(p, dtype=torch.float64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = g.grad(nsteps, c.cells, c.obs_every, hobs, ck)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        g.close()
+        return out, t
+
+    (J, gn, gz), t_grad = timed_grad(ckpt)
+    progress(f"adjoint: forward {t_fwd * 1e3:.1f} ms, swe_grad {t_grad * 1e3:.1f} ms ({mode})")
+    out = {"workload": f"Manning calibration {p.nx}x{p.ny}, dx={p.dx:g} m, FP64, {nsteps} steps, "
+                       f"{len(c.cells)} gauges every {c.obs_every} steps, {mode}",
+           "metric": "adjoint/fwd cost ratio", "value": t_grad / t_fwd,
+           "higher_is_better": False, "fwd_ms": t_fwd * 1e3, "grad_ms": t_grad * 1e3,
+           "loss": J, "max_abs_dJ_dn": float(gn.abs().max()), "max_abs_dJ_dz": float(gz.abs().max())}
+    if ckpt == 0:
+        (J2, gn2, gz2), t2 = timed_grad(45)
+        progress(f"adjoint: swe_grad {t2 * 1e3:.1f} ms (checkpoint every 45)")
+        out["checkpointed"] = {"checkpoint_every": 45, "grad_ms": t2 * 1e3, "ratio": t2 / t_fwd,
+                               "gradient_equal": bool(J2 == J and torch.equal(gn2, gn)
+                                                      and torch.equal(gz2, gz))}
+    return out
 
 
 def ensemble_throughput(torch, swe, W, count, nsteps):

@@ -220,22 +220,29 @@ typedef struct swe_gauges {
  * fixed (dt is not differentiated).  The gradient is the exact derivative of
  * the discrete step (S1..S15 in reverse, branches as taken in the forward
  * run; max/min follow the argument they return, |x| and sqrt have
- * derivative 0 at 0).  Memory: states every ckpt_every steps are kept, and
- * each segment of ckpt_every steps is recomputed once during the reverse
- * sweep (about 2 + 1/ckpt_every forward passes in all); FP64 handles also
- * keep U* and U^d of each step of the segment being reversed (6 fields per
- * step) when that fits in a third of the free device memory, else each
- * step is replayed once more (SWE_GRAD_KEEP=0 in the environment forces the
- * replay; the gradient is the same bit for bit).  dJ_dn and dJ_dz
- * (device, FP64, caller-owned, the handle's pitch) receive the gradients;
+ * derivative 0 at 0).  Memory (ckpt_every >= 1): states every ckpt_every
+ * steps are kept, and each segment of ckpt_every steps is recomputed once
+ * during the reverse sweep (about 2 + 1/ckpt_every forward passes in all);
+ * FP64 handles also keep U* and U^d of each step of the segment being
+ * reversed (6 fields per step) when that fits in a third of the free device
+ * memory, else each step is replayed once more (SWE_GRAD_KEEP=0 in the
+ * environment forces the replay).  ckpt_every = 0: an FP64 handle keeps the
+ * whole trajectory (U^n, U* and U^d of every step, 9 fields per step) when it
+ * fits in three quarters of the free device memory, and then recomputes
+ * nothing; otherwise, and for FP32 handles, the spacing is
+ * round(sqrt(nsteps)).  The reverse step runs as one fused march
+ * (SWE_ADJOINT=gather in the environment selects four gather kernels
+ * instead).  The gradient is the same bit for bit in every one of these
+ * modes.  dJ_dn and dJ_dz (device, FP64, caller-owned, the handle's pitch)
+ * receive the gradients;
  * *loss (host) receives J.  FP32 handles: the forward run, its checkpoints
  * and the recomputed segments are FP32 (the state trajectory is that of
  * swe_run), and the reverse sweep is FP64, each step linearised at its FP32
  * state promoted to FP64 (with FP64 copies of z, n and m = g n^2); misfits
  * are formed in FP64 from the promoted depths.  Memory then holds FP32
- * checkpoints and segment states plus an FP64 replay scratch of 49 padded
- * arrays.  Synchronises.  Errors: SWE_EINVAL (arguments, gauge cells out of
- * range or repeated), SWE_ENOMEM, SWE_EDEVICE, SWE_EUNSTABLE (the forward
+ * checkpoints and segment states plus FP64 copies of one step's state, U* and
+ * U^d.  Synchronises.  Errors: SWE_EINVAL (arguments, ckpt_every < 0, gauge
+ * cells out of range or repeated), SWE_ENOMEM, SWE_EDEVICE, SWE_EUNSTABLE (the forward
  * run raised a fatal flag). */
 int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_every,
              double* loss, void* dJ_dn, void* dJ_dz);

@@ -20,6 +20,8 @@
 // they return (the second on a tie); |x| has derivative sign(x) (0 at 0);
 // sqrt has derivative 0 at 0; the cube root's first guess is a constant and
 // its two Halley steps are differentiated as executed.
+#include <algorithm>
+
 #include "swe_common.hpp"
 #include "swe_internal.hpp"
 
@@ -75,25 +77,48 @@ __device__ __forceinline__ double eta_at(const Params& P, const double* E, int i
 // with its primitives (S2, S9).
 struct Cell { double e, qx, qy, h, r, u, v; };
 
+// The ghost rule (S1, S8) and the primitives (S2, S9) of padded cell (i, j)
+// from the state at its clamped interior position (e, qx, qy) and its bed.
+// kW, kE: kinds of the west and east boundary faces of row j.  (Every edge
+// index here is a constant: a per-thread index into the parameter block would
+// make the compiler read it through vector memory.)
+__device__ __forceinline__ Cell make_cell(const Params& P, double e, double qx, double qy,
+                                          double qin, int i, int j, double zpv, int kW, int kE) {
+    Cell c;
+    c.e = e;
+    c.qx = qx;
+    c.qy = qy;
+    if (i < 0 || i >= P.nx)
+        ghost(i < 0 ? kW : kE, true, i < 0 ? qin : -qin, c.e, c.qx, c.qy, c.e, c.qx, c.qy);
+    else if (j < 0 || j >= P.ny)
+        ghost(j < 0 ? face_kind(P, EDGE_S, i) : face_kind(P, EDGE_N, i), false,
+              j < 0 ? qin : -qin, c.e, c.qx, c.qy, c.e, c.qx, c.qy);
+    c.h = c.e - zpv;
+    c.r = recip_depth(c.h, P.h_dry);
+    c.u = c.qx * c.r;
+    c.v = c.qy * c.r;
+    return c;
+}
+
+// A cell from carried values (the same products as make_cell).
+__device__ __forceinline__ Cell carried_cell(double e, double qx, double qy, double h, double r) {
+    Cell c;
+    c.e = e;
+    c.qx = qx;
+    c.qy = qy;
+    c.h = h;
+    c.r = r;
+    c.u = qx * r;
+    c.v = qy * r;
+    return c;
+}
+
 __device__ __forceinline__ Cell cell_at(const AdjointArgs& a, const Pad& d,
                                         const double* const* U, double qin, int i, int j) {
     const Params& P = a.P;
     const long long s = pitched(P, min(max(i, 0), P.nx - 1), min(max(j, 0), P.ny - 1));
-    Cell c;
-    c.e = U[0][s];
-    c.qx = U[1][s];
-    c.qy = U[2][s];
-    if (i < 0 || i >= P.nx)
-        ghost(face_kind(P, i < 0 ? EDGE_W : EDGE_E, j), true, i < 0 ? qin : -qin, c.e, c.qx,
-              c.qy, c.e, c.qx, c.qy);
-    else if (j < 0 || j >= P.ny)
-        ghost(face_kind(P, j < 0 ? EDGE_S : EDGE_N, i), false, j < 0 ? qin : -qin, c.e, c.qx,
-              c.qy, c.e, c.qx, c.qy);
-    c.h = c.e - a.zp[d.at(i, j)];
-    c.r = recip_depth(c.h, a.P.h_dry);
-    c.u = c.qx * c.r;
-    c.v = c.qy * c.r;
-    return c;
+    return make_cell(P, U[0][s], U[1][s], U[2][s], qin, i, j, a.zp[d.at(i, j)],
+                     face_kind(P, EDGE_W, j), face_kind(P, EDGE_E, j));
 }
 
 // S3: switch of U^n at interior cell (i, j) along x (xdir) or y.
@@ -185,12 +210,93 @@ __device__ __forceinline__ void fold_ghost_into(const double* A, const Pad& d, l
     }
 }
 
+// fold_ghost_into with the ghost's adjoint given as values.
+__device__ __forceinline__ void fold_value(double g0, double g1, double g2, int kind,
+                                           bool normal_is_x, double* a) {
+    a[0] += g0;
+    if (kind == BC_OPEN) {
+        a[1] += g1;
+        a[2] += g2;
+    } else if (kind == BC_WALL) {
+        if (normal_is_x) {
+            a[1] -= g1;
+            a[2] += g2;
+        } else {
+            a[1] += g1;
+            a[2] -= g2;
+        }
+    }
+}
+
 __device__ __forceinline__ void fold_ring_into(const AdjointArgs& a, const double* A, const Pad& d,
                                                int i, int j, double* v) {
     if (i == 0) fold_ghost_into(A, d, d.at(-1, j), face_kind(a.P, EDGE_W, j), true, v);
     if (i == d.nx - 1) fold_ghost_into(A, d, d.at(d.nx, j), face_kind(a.P, EDGE_E, j), true, v);
     if (j == 0) fold_ghost_into(A, d, d.at(i, -1), face_kind(a.P, EDGE_S, i), false, v);
     if (j == d.ny - 1) fold_ghost_into(A, d, d.at(i, d.ny), face_kind(a.P, EDGE_N, i), false, v);
+}
+
+// S15 and S14 reversed at one interior cell: U^d = (ed, qx, qy), the bed zp,
+// m = g n^2 (mp) and n, and the adjoint (le, lx, ly) of U^{n+1}.  Returns the
+// adjoint of U^d, the bed's share and, for a wet cell, the dJ/dn term.
+struct FaOut { double e, x, y, azp, gn; bool wet; };
+
+__device__ __forceinline__ FaOut fa_point(double ed, double qx, double qy, double zp, double mp,
+                                          double n, double le, double lx, double ly, double dt,
+                                          double hdry, double g) {
+    const double ef = ed;
+    const bool clip = ef - zp < 0.0;
+    const double en = clip ? zp : ef;
+    // S15 dry fix (S14 leaves eta as U^d's)
+    const bool dry = !(en - zp > hdry);
+    double azp = clip ? le : 0.0;
+    const double efb = clip ? 0.0 : le;
+    const double qxfb = dry ? 0.0 : lx, qyfb = dry ? 0.0 : ly;
+    // S14 friction
+    const double h = ed - zp;
+    double edb = efb, qxdb = qxfb, qydb = qyfb;
+    FaOut o;
+    o.wet = h > hdry;
+    o.gn = 0.0;
+    if (o.wet) {
+        const double r = 1.0 / h;
+        const double x2 = qx * qx + qy * qy;
+        const double w = sqrt(x2);
+        const double s = w * r;
+        const double c3 = tcbrt(r);
+        const double k = r * c3;
+        const double dtm = dt * mp;
+        const double A = dtm * s;
+        const double B = A * k;
+        const double phi = 1.0 + B;
+        const double psi = 1.0 / phi;
+        const double psib = qxfb * qx + qyfb * qy;
+        qxdb = qxfb * psi;
+        qydb = qyfb * psi;
+        const double phib = -(psib * psi) / phi;
+        const double Ab = phib * k, kb = phib * A;
+        const double dtmb = Ab * s, sb = Ab * dtm;
+        const double mb = dtmb * dt;
+        double rb = kb * c3 + sb * w;
+        rb += cbrt3_adjoint(r, kb * r);
+        const double wb = sb * r;
+        if (x2 > 0.0) {
+            const double x2b = wb * (0.5 / w);
+            qxdb += x2b * qx + x2b * qx;
+            qydb += x2b * qy + x2b * qy;
+        }
+        const double hb = -(rb * r) / h;
+        edb += hb;
+        azp -= hb;
+        // m = g n^2 at this cell
+        const double mg = mb * g;
+        o.gn = mg * n + mg * n;
+    }
+    o.e = edb;
+    o.x = qxdb;
+    o.y = qydb;
+    o.azp = azp;
+    return o;
 }
 
 // S1 of the step reversed before this one (its ghost ring of U^n folded into
@@ -234,50 +340,10 @@ __global__ void k_adj_fa(AdjointArgs a, const int* gmap, const double* hobs) {
         }
     }
     wk(a, d, W_GZ)[C] = gz;
-    const double le = lam[0], lx = lam[1], ly = lam[2];
-    // S15 dry fix (S14 leaves eta as U^d's)
-    const bool dry = !(en - zp > hdry);
-    double azp = clip ? le : 0.0;
-    const double efb = clip ? 0.0 : le;
-    const double qxfb = dry ? 0.0 : lx, qyfb = dry ? 0.0 : ly;
-    // S14 friction
-    const double h = ed - zp;
-    double edb = efb, qxdb = qxfb, qydb = qyfb;
-    if (h > hdry) {
-        const double r = 1.0 / h;
-        const double x2 = qx * qx + qy * qy;
-        const double w = sqrt(x2);
-        const double s = w * r;
-        const double c3 = tcbrt(r);
-        const double k = r * c3;
-        const double dtm = a.dt * a.mp[C];
-        const double A = dtm * s;
-        const double B = A * k;
-        const double phi = 1.0 + B;
-        const double psi = 1.0 / phi;
-        const double psib = qxfb * qx + qyfb * qy;
-        qxdb = qxfb * psi;
-        qydb = qyfb * psi;
-        const double phib = -(psib * psi) / phi;
-        const double Ab = phib * k, kb = phib * A;
-        const double dtmb = Ab * s, sb = Ab * dtm;
-        const double mb = dtmb * a.dt;
-        double rb = kb * c3 + sb * w;
-        rb += cbrt3_adjoint(r, kb * r);
-        const double wb = sb * r;
-        if (x2 > 0.0) {
-            const double x2b = wb * (0.5 / w);
-            qxdb += x2b * qx + x2b * qx;
-            qydb += x2b * qy + x2b * qy;
-        }
-        const double hb = -(rb * r) / h;
-        edb += hb;
-        azp -= hb;
-        // m = g n^2 at this cell
-        const double n = a.nman[o];
-        const double mg = mb * a.P.g;
-        wk(a, d, W_GN)[C] += mg * n + mg * n;
-    }
+    const FaOut f = fa_point(ed, qx, qy, zp, a.mp[C], a.nman[o], lam[0], lam[1], lam[2], a.dt,
+                             hdry, a.P.g);
+    if (f.wet) wk(a, d, W_GN)[C] += f.gn;
+    const double edb = f.e, qxdb = f.x, qydb = f.y, azp = f.azp;
     // S13: U^d = U^c + D; S12: U^c = 0.5*(U^n + a)
     double* AD = wk(a, d, W_AD);
     double* AB = wk(a, d, W_AB);
@@ -307,16 +373,10 @@ __device__ __forceinline__ void vec_at(const AdjointArgs& a, const double* A, co
     if (fold) fold_ring_into(a, A, d, i, j, v);
 }
 
-__device__ __forceinline__ FaceBar face_bar(const AdjointArgs& a, const double* A, bool fold,
-                                            const Pad& d, int iL, int jL, int iR, int jR,
-                                            double coef, int dir, bool xface) {
+__device__ __forceinline__ FaceBar face_bar_v(double aL0, double aL1, double aL2, double aR0,
+                                              double aR1, double aR2, double coef, int dir,
+                                              bool xface) {
     FaceBar f;
-    double vL[3], vR[3];
-    vec_at(a, A, d, iL, jL, fold, vL);
-    vec_at(a, A, d, iR, jR, fold, vR);
-    const double aL0 = vL[0], aR0 = vR[0];
-    const double aL1 = vL[1], aR1 = vR[1];
-    const double aL2 = vL[2], aR2 = vR[2];
     f.m = coef * aR0 - coef * aL0;
     f.x = coef * aR1 - coef * aL1;
     f.y = coef * aR2 - coef * aL2;
@@ -325,6 +385,15 @@ __device__ __forceinline__ FaceBar face_bar(const AdjointArgs& a, const double* 
     const double aPL = xface ? aL1 : aL2, aPR = xface ? aR1 : aR2;
     f.p = dir > 0 ? -(coef * aPL) : -(coef * aPR);
     return f;
+}
+
+__device__ __forceinline__ FaceBar face_bar(const AdjointArgs& a, const double* A, bool fold,
+                                            const Pad& d, int iL, int jL, int iR, int jR,
+                                            double coef, int dir, bool xface) {
+    double vL[3], vR[3];
+    vec_at(a, A, d, iL, jL, fold, vL);
+    vec_at(a, A, d, iR, jR, fold, vR);
+    return face_bar_v(vL[0], vL[1], vL[2], vR[0], vR[1], vR[2], coef, dir, xface);
 }
 
 // Contributions of one face's flux adjoint to the adjoints of the cell
@@ -600,13 +669,13 @@ __global__ void k_adj_f(AdjointArgs a) {
     const int i = blockIdx.x * kBX + threadIdx.x, j = blockIdx.y * kBY + threadIdx.y;
     if (i >= d.nx || j >= d.ny) return;
     const long long C = d.at(i, j);
-    double* AUN = wk(a, d, W_AUN);
+    double* AUN = wk(a, d, a.lam_slot);
     fold_ring(a, AUN, d, i, j);
     double* LAM = wk(a, d, W_LAM);
     LAM[C] = AUN[C];
     LAM[d.N + C] = AUN[d.N + C];
     LAM[2 * d.N + C] = AUN[2 * d.N + C];
-    double* AZP = wk(a, d, W_AZP);
+    double* AZP = wk(a, d, a.azp_slot);
     double gz = AZP[C];
     AZP[C] = 0.0;
     const long long gs[4] = {i == 0 ? d.at(-1, j) : -1, i == d.nx - 1 ? d.at(d.nx, j) : -1,
@@ -657,6 +726,470 @@ __global__ void k_unpad(Params P, const double* src, double* dst) {
     dst[(long long)j * P.pitch + i] = src[(long long)(j + 1) * (P.nx + 2) + (i + 1)];
 }
 
+// ------------------------------------------------------------ reverse march
+//
+// The four gather kernels above as one pass.  A 64-lane wave owns a strip of
+// padded columns and marches up a chunk of rows, ingesting one row of U^n,
+// U*, U^d, the bed and lambda per iteration; earlier rows stay in the lane's
+// registers and x neighbours come from the adjacent lanes by DPP shifts.  The
+// phases trail the ingested row R:
+//   row R    : S15, S14, S13 and the U^n share of S12 (kernel A's work);
+//   row R-1  : the flux part of S12, S11, S10, S9 (the U* adjoint, kernel C);
+//   row R-2  : the S8 fold of the U* adjoint, S4 (kernel E1) and the switch
+//              derivatives of S3;
+//   row R-3  : S7, S6, S5, S3 and S2 (kernel E2): lambda^n and the bed's share.
+// Each phase reaches one cell further than the one before it, so of the 64
+// lanes the middle 58 are output columns.  The expressions, and the order in
+// which each cell sums its terms, are those of the gather kernels, so the
+// results agree bit for bit.  The adjoint of U^{n+1} is read from one slot of
+// a pair and lambda^n written to the other; dJ/dn and dJ/dz are updated in
+// place by the cell's owner only.
+
+constexpr int kMarchOutW = kWave - 6;   // output columns per strip
+
+// Padded cell (i, j) that is not a corner.
+__device__ __forceinline__ bool padded_ok(const Pad& d, int i, int j) {
+    if (i < -1 || i > d.nx || j < -1 || j > d.ny) return false;
+    return !((i < 0 || i >= d.nx) && (j < 0 || j >= d.ny));
+}
+
+// One neighbour of a cell for the face sums: its cell, bed and adjoint
+// vector (zero off the interior).
+struct Nbr { Cell c; double z, a0, a1, a2; };
+
+// gather_faces from values: the faces of padded cell (i, j) in the same
+// order, with the same face rules.
+__device__ __forceinline__ CellBar gather_values(const Params& P, int i, int j, const Cell& me,
+                                                 double zme, double am0, double am1, double am2,
+                                                 const Nbr& E, const Nbr& W, const Nbr& N,
+                                                 const Nbr& S, int dir, double rx, double ry,
+                                                 double hdry, double hg) {
+    CellBar cb = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (j >= 0 && j < P.ny) {
+        if (i >= -1 && i <= P.nx - 1) {   // face i: this cell is L
+            const FaceBar fb = face_bar_v(am0, am1, am2, E.a0, E.a1, E.a2, rx, dir, true);
+            face_flux_adjoint(fb, xface_kind(P, i, j), dir, i == P.nx - 1, true, true, me, E.c,
+                              zme, E.z, hdry, hg, cb);
+        }
+        if (i - 1 >= -1 && i - 1 <= P.nx - 1) {   // face i-1: this cell is R
+            const FaceBar fb = face_bar_v(W.a0, W.a1, W.a2, am0, am1, am2, rx, dir, true);
+            face_flux_adjoint(fb, xface_kind(P, i - 1, j), dir, i - 1 == P.nx - 1, false, true,
+                              W.c, me, W.z, zme, hdry, hg, cb);
+        }
+    }
+    if (i >= 0 && i < P.nx) {
+        if (j >= -1 && j <= P.ny - 1) {
+            const FaceBar fb = face_bar_v(am0, am1, am2, N.a0, N.a1, N.a2, ry, dir, false);
+            face_flux_adjoint(fb, yface_kind(P, i, j), dir, j == P.ny - 1, true, false, me, N.c,
+                              zme, N.z, hdry, hg, cb);
+        }
+        if (j - 1 >= -1 && j - 1 <= P.ny - 1) {
+            const FaceBar fb = face_bar_v(S.a0, S.a1, S.a2, am0, am1, am2, ry, dir, false);
+            face_flux_adjoint(fb, yface_kind(P, i, j - 1), dir, j - 1 == P.ny - 1, false, false,
+                              S.c, me, S.z, zme, hdry, hg, cb);
+        }
+    }
+    return cb;
+}
+
+// The lane's neighbour from the east (lane + 1) or west (lane - 1).
+__device__ __forceinline__ Nbr nbr_east(double e, double qx, double qy, double h, double r,
+                                        double z, double a0, double a1, double a2) {
+    Nbr n;
+    n.c = carried_cell(from_east(e), from_east(qx), from_east(qy), from_east(h), from_east(r));
+    n.z = from_east(z);
+    n.a0 = from_east(a0);
+    n.a1 = from_east(a1);
+    n.a2 = from_east(a2);
+    return n;
+}
+__device__ __forceinline__ Nbr nbr_west(double e, double qx, double qy, double h, double r,
+                                        double z, double a0, double a1, double a2) {
+    Nbr n;
+    n.c = carried_cell(from_west(e), from_west(qx), from_west(qy), from_west(h), from_west(r));
+    n.z = from_west(z);
+    n.a0 = from_west(a0);
+    n.a1 = from_west(a1);
+    n.a2 = from_west(a2);
+    return n;
+}
+__device__ __forceinline__ Nbr nbr_here(double e, double qx, double qy, double h, double r,
+                                        double z, double a0, double a1, double a2) {
+    Nbr n;
+    n.c = carried_cell(e, qx, qy, h, r);
+    n.z = z;
+    n.a0 = a0;
+    n.a1 = a1;
+    n.a2 = a2;
+    return n;
+}
+
+// Inputs of one row at the lane's column (clamped into the arrays).
+struct MarchRow {
+    double ue, ux, uy, se, sx, sy, z, de, dx, dy, m, n, l0, l1, l2, azi, gz, gn;
+    int gm;
+};
+
+template <bool HOBS>
+struct AdjMarch {
+    const AdjointArgs& a;
+    const int* gmap;
+    const double* hobs;
+    Pad d;
+    const double* LIN;
+    const double* AZI;
+    double* LOUT;
+    double* AZO;
+    double* GZ;
+    double* GN;
+    int i, ii, ic, j0, j1;
+    bool colOut, edgeStrip;
+    double hdry, hg, kap, emax;
+    // outputs of the previous iteration, stored at the start of the next one
+    // (ahead of its prefetch, so that waiting for the prefetch never waits
+    // for stores): dJ/dz and dJ/dn of row R-1, lambda^n and the bed's share
+    // of row R-4
+    double o_gz = 0.0, o_gn = 0.0, o_l0 = 0.0, o_l1 = 0.0, o_l2 = 0.0, o_az = 0.0;
+    bool o_fa = false, o_wet = false, o_e2 = false;
+
+    // carried rows; index k holds row R - k (ue..zz, ab, ad, azp), R-1-k (aus),
+    // R-2-k (fs, un, db)
+    double ue[5], ux[5], uy[5], uh[5], ur[5], zz[5];   // U^n cells
+    double se[3], sx[3], sy[3], sh[3], sr[3];          // U* cells
+    double abe[3], abx[3], aby[3];                     // S12's inner adjoint (0.5 D-bar)
+    double ade[4], adx[4], ady[4];                     // U^d adjoint (D-bar)
+    double azp[4];                                     // bed's share
+    double ause[3], ausx[3], ausy[3];                  // U* adjoint
+    double fse[3], fsx[3], fsy[3];                     // U* adjoint, S8 fold applied
+    double une[2], unx[2], uny[2];                     // U^n adjoint, S12 and S4 terms
+    double dbx[3], dby[3], atx[3], aty[3];             // switch derivatives of S3
+    MarchRow pf;
+
+    __device__ AdjMarch(const AdjointArgs& a_, const int* g, const double* h) : a(a_), gmap(g), hobs(h) {}
+
+    __device__ __forceinline__ void prefetch(int R) {
+        const int jj = min(max(R, 0), d.ny - 1);
+        const long long o = pitched(a.P, ii, jj);
+        const long long C = d.at(ic, min(max(R, -1), d.ny));
+        pf.ue = a.un[0][o]; pf.ux = a.un[1][o]; pf.uy = a.un[2][o];
+        pf.se = a.us[0][o]; pf.sx = a.us[1][o]; pf.sy = a.us[2][o];
+        pf.de = a.ud[0][o]; pf.dx = a.ud[1][o]; pf.dy = a.ud[2][o];
+        pf.z = a.zp[C];
+        pf.m = a.mp[C];
+        pf.n = a.nman[o];
+        pf.l0 = LIN[C]; pf.l1 = LIN[d.N + C]; pf.l2 = LIN[2 * d.N + C];
+        pf.azi = AZI[C];
+        pf.gz = GZ[C];
+        pf.gn = GN[C];
+        pf.gm = HOBS ? gmap[(long long)jj * d.nx + ii] : -1;
+    }
+
+    template <int K>
+    __device__ __forceinline__ static void shift(double* x) {
+#pragma unroll
+        for (int k = K - 1; k > 0; --k) x[k] = x[k - 1];
+    }
+
+    __device__ __forceinline__ bool interior(int x, int y) const { return d.interior(x, y); }
+
+    __device__ __forceinline__ void store_previous(int R) {
+        if (o_fa) {
+            const long long C = d.at(i, R - 1);
+            GZ[C] = o_gz;
+            if (o_wet) GN[C] = o_gn;
+        }
+        if (o_e2) {
+            const long long C = d.at(i, R - 4);
+            LOUT[C] = o_l0;
+            LOUT[d.N + C] = o_l1;
+            LOUT[2 * d.N + C] = o_l2;
+            AZO[C] = o_az;
+        }
+    }
+
+    __device__ __forceinline__ void iter(int R) {
+        const MarchRow q = pf;
+        store_previous(R);
+        prefetch(R + 1);
+        const int kW = face_kind(a.P, EDGE_W, R), kE = face_kind(a.P, EDGE_E, R);
+        shift<5>(ue); shift<5>(ux); shift<5>(uy); shift<5>(uh); shift<5>(ur); shift<5>(zz);
+        shift<3>(se); shift<3>(sx); shift<3>(sy); shift<3>(sh); shift<3>(sr);
+        shift<3>(abe); shift<3>(abx); shift<3>(aby);
+        shift<4>(ade); shift<4>(adx); shift<4>(ady);
+        shift<4>(azp);
+        shift<3>(ause); shift<3>(ausx); shift<3>(ausy);
+        shift<3>(fse); shift<3>(fsx); shift<3>(fsy);
+        shift<2>(une); shift<2>(unx); shift<2>(uny);
+        shift<3>(dbx); shift<3>(dby); shift<3>(atx); shift<3>(aty);
+
+        // ---- ingest row R: U^n and U* cells (ghost rule, primitives), bed
+        zz[0] = q.z;
+        {
+            const Cell c = make_cell(a.P, q.ue, q.ux, q.uy, a.qin0, i, R, q.z, kW, kE);
+            ue[0] = c.e; ux[0] = c.qx; uy[0] = c.qy; uh[0] = c.h; ur[0] = c.r;
+        }
+        {
+            const Cell c = make_cell(a.P, q.se, q.sx, q.sy, a.qin1, i, R, q.z, kW, kE);
+            se[0] = c.e; sx[0] = c.qx; sy[0] = c.qy; sh[0] = c.h; sr[0] = c.r;
+        }
+
+        // ---- row R: S15, S14, S13, S12's U^n share (with the step reversed
+        // before this one's S1 fold and this step's gauge terms)
+        {
+            // the west and east ghosts of lambda and of the bed's share are
+            // the neighbouring lanes' values of this row
+            double lw0 = 0.0, lw1 = 0.0, lw2 = 0.0, le0 = 0.0, le1 = 0.0, le2 = 0.0;
+            double zw = 0.0, ze = 0.0;
+            if (edgeStrip) {
+                lw0 = from_west(q.l0); lw1 = from_west(q.l1); lw2 = from_west(q.l2);
+                le0 = from_east(q.l0); le1 = from_east(q.l1); le2 = from_east(q.l2);
+                zw = from_west(q.azi); ze = from_east(q.azi);
+            }
+            double o0 = 0.0, o1 = 0.0, o2 = 0.0, oz = 0.0;
+            o_fa = false;
+            o_wet = false;
+            if (interior(i, R)) {
+                double lam[3] = {q.l0, q.l1, q.l2};
+                if (i == 0) fold_value(lw0, lw1, lw2, kW, true, lam);
+                if (i == d.nx - 1) fold_value(le0, le1, le2, kE, true, lam);
+                if (R == 0) {
+                    const long long g = d.at(i, -1);
+                    fold_value(LIN[g], LIN[d.N + g], LIN[2 * d.N + g], face_kind(a.P, EDGE_S, i),
+                               false, lam);
+                }
+                if (R == d.ny - 1) {
+                    const long long g = d.at(i, d.ny);
+                    fold_value(LIN[g], LIN[d.N + g], LIN[2 * d.N + g], face_kind(a.P, EDGE_N, i),
+                               false, lam);
+                }
+                const bool own = colOut && R >= j0 && R < j1;
+                double gz = 0.0;
+                if (own) {
+                    double gzs = q.azi;
+                    if (i == 0) gzs += zw;
+                    if (i == d.nx - 1) gzs += ze;
+                    if (R == 0) gzs += AZI[d.at(i, -1)];
+                    if (R == d.ny - 1) gzs += AZI[d.at(i, d.ny)];
+                    gz = q.gz + gzs;
+                }
+                if (HOBS && q.gm >= 0) {
+                    const double ef = q.de;
+                    const bool clip = ef - q.z < 0.0;
+                    const double en = clip ? q.z : ef;
+                    const double dd = (en - q.z) - hobs[q.gm];
+                    lam[0] += dd + dd;
+                    gz += 0.0 - (dd + dd);
+                }
+                const FaOut f = fa_point(q.de, q.dx, q.dy, q.z, q.m, q.n, lam[0], lam[1], lam[2],
+                                         a.dt, hdry, a.P.g);
+                o_fa = own;
+                o_wet = own && f.wet;
+                o_gz = gz;
+                o_gn = q.gn + f.gn;
+                o0 = f.e; o1 = f.x; o2 = f.y; oz = f.azp;
+            }
+            ade[0] = o0; adx[0] = o1; ady[0] = o2;
+            abe[0] = 0.5 * o0; abx[0] = 0.5 * o1; aby[0] = 0.5 * o2;
+            azp[0] = oz;
+        }
+
+        // ---- row R-1: flux part of S12, S11, S10, S9 (the U* adjoint)
+        {
+            const int j = R - 1;
+            const Nbr E = nbr_east(se[1], sx[1], sy[1], sh[1], sr[1], zz[1], abe[1], abx[1], aby[1]);
+            const Nbr W = nbr_west(se[1], sx[1], sy[1], sh[1], sr[1], zz[1], abe[1], abx[1], aby[1]);
+            double eb = 0.0, qxb = 0.0, qyb = 0.0;
+            if (padded_ok(d, i, j)) {
+                const Nbr N = nbr_here(se[0], sx[0], sy[0], sh[0], sr[0], zz[0], abe[0], abx[0], aby[0]);
+                const Nbr S = nbr_here(se[2], sx[2], sy[2], sh[2], sr[2], zz[2], abe[2], abx[2], aby[2]);
+                const Cell me = carried_cell(se[1], sx[1], sy[1], sh[1], sr[1]);
+                const CellBar cb = gather_values(a.P, i, j, me, zz[1], abe[1], abx[1], aby[1], E, W,
+                                                 N, S, -a.sigma, a.rx, a.ry, hdry, hg);
+                const bool in = interior(i, j);
+                eb = cb.e + (in ? abe[1] : 0.0);
+                qxb = cb.qx + (in ? abx[1] : 0.0);
+                qyb = cb.qy + (in ? aby[1] : 0.0);
+                const double h = me.h, r = me.r;
+                qxb += cb.u * r;
+                qyb += cb.v * r;
+                const double rb = cb.u * me.qx + cb.v * me.qy;
+                const double hb = cb.h + (h > hdry ? -(rb * r) / h : 0.0);
+                eb += hb;
+                azp[1] -= hb;
+            }
+            ause[0] = eb; ausx[0] = qxb; ausy[0] = qyb;
+        }
+
+        // ---- row R-2: the S8 fold of the U* adjoint
+        {
+            const int j = R - 2;
+            const double we = from_west(ause[1]), wx = from_west(ausx[1]), wy = from_west(ausy[1]);
+            const double ee = from_east(ause[1]), ex = from_east(ausx[1]), ey = from_east(ausy[1]);
+            double v[3] = {0.0, 0.0, 0.0};
+            if (interior(i, j)) {
+                v[0] = ause[1]; v[1] = ausx[1]; v[2] = ausy[1];
+                if (i == 0) fold_value(we, wx, wy, face_kind(a.P, EDGE_W, j), true, v);
+                if (i == d.nx - 1) fold_value(ee, ex, ey, face_kind(a.P, EDGE_E, j), true, v);
+                if (j == 0) fold_value(ause[2], ausx[2], ausy[2], face_kind(a.P, EDGE_S, i), false, v);
+                if (j == d.ny - 1) fold_value(ause[0], ausx[0], ausy[0], face_kind(a.P, EDGE_N, i), false, v);
+            }
+            fse[0] = v[0]; fsx[0] = v[1]; fsy[0] = v[2];
+        }
+
+        // ---- row R-2: S4 (nu-bar and the U^n adjoint's first terms), then
+        // the switch derivatives of S3
+        {
+            const int j = R - 2;
+            const Cell me = carried_cell(ue[2], ux[2], uy[2], uh[2], ur[2]);
+            const double eW = from_west(ue[2]), eE = from_east(ue[2]);
+            const double nux = curv_switch(eW, me.e, eE, me.r);
+            const double nuy = curv_switch(ue[3], me.e, ue[1], me.r);
+            const double nuE = from_east(nux), nuW = from_west(nux);
+            const Cell cE = carried_cell(eE, from_east(ux[2]), from_east(uy[2]), from_east(uh[2]), 0.0);
+            const Cell cW = carried_cell(eW, from_west(ux[2]), from_west(uy[2]), from_west(uh[2]), 0.0);
+            const double dE[3] = {from_east(ade[2]), from_east(adx[2]), from_east(ady[2])};
+            const double dW[3] = {from_west(ade[2]), from_west(adx[2]), from_west(ady[2])};
+            double un[3] = {0.0, 0.0, 0.0};
+            double dbxv = 0.0, atxv = 0.0, dbyv = 0.0, atyv = 0.0;
+            if (interior(i, j)) {
+                const double dC[3] = {ade[2], adx[2], ady[2]};
+                const double dN[3] = {ade[1], adx[1], ady[1]};
+                const double dS[3] = {ade[3], adx[3], ady[3]};
+                const Cell cN = carried_cell(ue[1], ux[1], uy[1], uh[1], ur[1]);
+                const Cell cS = carried_cell(ue[3], ux[3], uy[3], uh[3], ur[3]);
+                const double nuN = curv_switch(ue[2], ue[1], ue[0], ur[1]);
+                const double nuS = curv_switch(ue[4], ue[3], ue[2], ur[3]);
+                un[0] = abe[2]; un[1] = abx[2]; un[2] = aby[2];
+                double nub[2] = {0.0, 0.0};
+#pragma unroll
+                for (int f = 0; f < 4; ++f) {
+                    const bool xf = f < 2;
+                    const int ni = xf ? (f == 0 ? i + 1 : i - 1) : i;
+                    const int nj = xf ? j : (f == 2 ? j + 1 : j - 1);
+                    if (!interior(ni, nj)) continue;   // boundary face: eps = 0
+                    const Cell& on = f == 0 ? cE : (f == 1 ? cW : (f == 2 ? cN : cS));
+                    const double nuOn = f == 0 ? nuE : (f == 1 ? nuW : (f == 2 ? nuN : nuS));
+                    const double* dn = f == 0 ? dE : (f == 1 ? dW : (f == 2 ? dN : dS));
+                    const double nuMe = xf ? nux : nuy;
+                    const bool meL = f == 0 || f == 2;
+                    const Cell& cL = meL ? me : on;
+                    const Cell& cR = meL ? on : me;
+                    const double nuL = meL ? nuMe : nuOn, nuR = meL ? nuOn : nuMe;
+                    int arg;
+                    const double eps = eps_and_arg(cL.h, cR.h, nuL, nuR, hdry, kap, emax, arg);
+                    const double qL[3] = {cL.e, cL.qx, cL.qy}, qR[3] = {cR.e, cR.qx, cR.qy};
+                    double epsb = 0.0;
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const double adL = meL ? dC[k] : dn[k], adR = meL ? dn[k] : dC[k];
+                        epsb += (adL - adR) * (qR[k] - qL[k]);
+                        un[k] += eps * (dn[k] - dC[k]);
+                    }
+                    if (arg == (meL ? 0 : 1)) nub[xf ? 0 : 1] += epsb * kap;
+                }
+                dbxv = switch_dbar(eW, me.e, eE, me.r, nub[0], atxv);
+                dbyv = switch_dbar(ue[3], me.e, ue[1], me.r, nub[1], atyv);
+            }
+            une[0] = un[0]; unx[0] = un[1]; uny[0] = un[2];
+            dbx[0] = dbxv; atx[0] = atxv; dby[0] = dbyv; aty[0] = atyv;
+        }
+
+        // ---- row R-3: S7, S6, S5, S3, S2: lambda^n and the bed's share
+        {
+            const int j = R - 3;
+            const Nbr E = nbr_east(ue[3], ux[3], uy[3], uh[3], ur[3], zz[3], fse[1], fsx[1], fsy[1]);
+            const Nbr W = nbr_west(ue[3], ux[3], uy[3], uh[3], ur[3], zz[3], fse[1], fsx[1], fsy[1]);
+            const double dbW = from_west(dbx[1]), dbE = from_east(dbx[1]);
+            o_e2 = colOut && j >= j0 && j < j1 && padded_ok(d, i, j);
+            if (o_e2) {
+                const Nbr N = nbr_here(ue[2], ux[2], uy[2], uh[2], ur[2], zz[2], fse[0], fsx[0], fsy[0]);
+                const Nbr S = nbr_here(ue[4], ux[4], uy[4], uh[4], ur[4], zz[4], fse[2], fsx[2], fsy[2]);
+                const Cell me = carried_cell(ue[3], ux[3], uy[3], uh[3], ur[3]);
+                const CellBar cb = gather_values(a.P, i, j, me, zz[3], fse[1], fsx[1], fsy[1], E, W,
+                                                 N, S, a.sigma, a.rx, a.ry, hdry, hg);
+                const bool in = interior(i, j);
+                double eb = cb.e, qxb = cb.qx, qyb = cb.qy;
+                if (in) {
+                    eb += une[1] + fse[1];
+                    qxb += unx[1] + fsx[1];
+                    qyb += uny[1] + fsy[1];
+                }
+                double rb = cb.u * me.qx + cb.v * me.qy;
+                if (interior(i - 1, j)) eb += dbW;
+                if (in) {
+                    eb += -dbx[1] - dbx[1];
+                    rb += atx[1];
+                }
+                if (interior(i + 1, j)) eb += dbE;
+                if (interior(i, j - 1)) eb += dby[2];
+                if (in) {
+                    eb += -dby[1] - dby[1];
+                    rb += aty[1];
+                }
+                if (interior(i, j + 1)) eb += dby[0];
+                const double h = me.h, r = me.r;
+                qxb += cb.u * r;
+                qyb += cb.v * r;
+                const double hb = cb.h + (h > hdry ? -(rb * r) / h : 0.0);
+                eb += hb;
+                o_l0 = eb;
+                o_l1 = qxb;
+                o_l2 = qyb;
+                o_az = azp[3] - hb;
+            }
+        }
+    }
+};
+
+template <bool HOBS>
+__global__ void __launch_bounds__(kWave, 1)
+k_adj_march(AdjointArgs a, const int* gmap, const double* hobs, int H, int gy, int lout, int zout) {
+    AdjMarch<HOBS> M(a, gmap, hobs);
+    M.d = pad_of(a.P);
+    M.LIN = wk(a, M.d, a.lam_slot);
+    M.AZI = wk(a, M.d, a.azp_slot);
+    M.LOUT = wk(a, M.d, lout);
+    M.AZO = wk(a, M.d, zout);
+    M.GZ = wk(a, M.d, W_GZ);
+    M.GN = wk(a, M.d, W_GN);
+    M.hdry = a.P.h_dry;
+    M.hg = 0.5 * a.P.g;
+    M.kap = a.P.kappa;
+    M.emax = a.P.eps_max;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int strip = tile / gy, chunk = tile % gy;
+    const int lane = threadIdx.x;
+    const int pc = strip * kMarchOutW - 3 + lane;   // padded column of the lane
+    M.i = pc - 1;
+    M.ii = min(max(M.i, 0), a.P.nx - 1);
+    M.ic = min(max(M.i, -1), a.P.nx);
+    M.colOut = lane >= 3 && lane < 3 + kMarchOutW && pc <= a.P.nx + 1;
+    const int py0 = chunk * H, py1 = min(py0 + H, a.P.ny + 2);
+    M.j0 = py0 - 1;
+    M.j1 = py1 - 1;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) M.ue[k] = M.ux[k] = M.uy[k] = M.uh[k] = M.ur[k] = M.zz[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        M.se[k] = M.sx[k] = M.sy[k] = M.sh[k] = M.sr[k] = 0.0;
+        M.abe[k] = M.abx[k] = M.aby[k] = 0.0;
+        M.ause[k] = M.ausx[k] = M.ausy[k] = 0.0;
+        M.fse[k] = M.fsx[k] = M.fsy[k] = 0.0;
+        M.dbx[k] = M.dby[k] = M.atx[k] = M.aty[k] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) M.ade[k] = M.adx[k] = M.ady[k] = M.azp[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) M.une[k] = M.unx[k] = M.uny[k] = 0.0;
+    // rows j0-3 .. j0-1 fill the pipeline; row R's iteration writes lambda^n
+    // of row R-3
+    const int i0 = M.i - lane;   // column of lane 0
+    M.edgeStrip = i0 <= 0 || i0 + kWave - 1 >= a.P.nx - 1;
+    M.prefetch(M.j0 - 3);
+    for (int R = M.j0 - 3; R <= M.j1 + 2; ++R) M.iter(R);
+    M.store_previous(M.j1 + 3);
+}
+
 inline dim3 grid2(int w, int h) { return dim3((w + kBX - 1) / kBX, (h + kBY - 1) / kBY); }
 
 }  // namespace
@@ -671,6 +1204,30 @@ hipError_t launch_adjoint_step(const AdjointArgs& a, const int* gmap, const doub
     hipLaunchKernelGGL(k_adj_c, grid2(nx + 2, ny + 2), b2, 0, s, a);
     hipLaunchKernelGGL(k_adj_e1, grid2(nx, ny), b2, 0, s, a);
     hipLaunchKernelGGL(k_adj_e2, grid2(nx + 2, ny + 2), b2, 0, s, a);
+    return hipGetLastError();
+}
+
+int adjoint_march_rows(const Params& P, int ncu) {
+    // about one wave per SIMD (four per compute unit), chunks of 8 .. 256 rows
+    const long long strips = (P.nx + 2 + kMarchOutW - 1) / kMarchOutW;
+    const long long waves = 4LL * std::max(ncu, 1);
+    long long H = ((long long)(P.ny + 2) * strips + waves - 1) / waves;
+    return (int)std::min<long long>(256, std::max<long long>(8, H));
+}
+
+hipError_t launch_adjoint_march(const AdjointArgs& a, const int* gmap, const double* hobs, int H,
+                                hipStream_t s) {
+    if (H < 1) return hipErrorInvalidValue;
+    const int strips = (a.P.nx + 2 + kMarchOutW - 1) / kMarchOutW;
+    const int gy = (a.P.ny + 2 + H - 1) / H;
+    const int lout = a.lam_slot == kAdjLamSlot[0] ? kAdjLamSlot[1] : kAdjLamSlot[0];
+    const int zout = a.azp_slot == kAdjZpSlot[0] ? kAdjZpSlot[1] : kAdjZpSlot[0];
+    if (hobs)
+        hipLaunchKernelGGL(k_adj_march<true>, dim3(strips * gy), dim3(kWave), 0, s, a, gmap,
+                           hobs, H, gy, lout, zout);
+    else
+        hipLaunchKernelGGL(k_adj_march<false>, dim3(strips * gy), dim3(kWave), 0, s, a, gmap,
+                           hobs, H, gy, lout, zout);
     return hipGetLastError();
 }
 

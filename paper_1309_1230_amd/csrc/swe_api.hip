@@ -625,11 +625,29 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
     const long long step0 = c0.step;
     const size_t fe = (size_t)h->P.ny * (size_t)h->P.pitch;   // elements of a field slot
     const size_t Npad = padded_elems(h);
-    const int64_t C = std::max<int64_t>(1, std::min<int64_t>(ckpt_every, std::max<int64_t>(nsteps, 1)));
+    // ckpt_every = 0: an FP64 handle keeps the whole trajectory (U^n, U* and
+    // U^d of every step, 9 fields a step) when it fits in three quarters of
+    // the free device memory: the forward run writes it, and the reverse
+    // sweep recomputes nothing.  Otherwise, and for FP32 handles, checkpoints
+    // every round(sqrt(nsteps)) steps.
+    DevBuf traj;
+    bool store_all = false;
+    if (ckpt_every == 0 && !mixed && nsteps > 0) {
+        size_t freeb = 0, totalb = 0;
+        const double need = (double)nsteps * 9.0 * (double)fe * sizeof(double);
+        if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && need <= 0.75 * (double)freeb)
+            store_all = traj.alloc((size_t)nsteps * 9 * fe * sizeof(double)) == hipSuccess;
+        (void)hipGetLastError();
+    }
+    const int64_t spacing =
+        ckpt_every > 0 ? ckpt_every
+                       : std::max<int64_t>(1, (int64_t)std::llround(std::sqrt((double)nsteps)));
+    const int64_t C = store_all ? std::max<int64_t>(nsteps, 1)
+                                : std::max<int64_t>(1, std::min<int64_t>(spacing, std::max<int64_t>(nsteps, 1)));
     const int64_t nseg = (nsteps + C - 1) / C;
     DevBuf ck, seg, scratch, work, logs, mis, dcells, actl, prom, stat64, fwd, padst, gmap;
-    if ((e = ck.alloc((size_t)nseg * 3 * fe * sizeof(T))) != hipSuccess ||
-        (e = seg.alloc((size_t)C * 3 * fe * sizeof(T))) != hipSuccess ||
+    if ((!store_all && (e = ck.alloc((size_t)nseg * 3 * fe * sizeof(T))) != hipSuccess) ||
+        (!store_all && (e = seg.alloc((size_t)C * 3 * fe * sizeof(T))) != hipSuccess) ||
         (e = scratch.alloc(3 * fe * sizeof(double))) != hipSuccess ||
         (e = work.alloc((size_t)swe::adjoint_work_arrays() * Npad * sizeof(double))) != hipSuccess ||
         (e = logs.alloc(2 * (size_t)std::max<int64_t>(nsteps, 1) * sizeof(double))) != hipSuccess ||
@@ -647,7 +665,7 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
     DevBuf segtr;
     bool keep = false;
     const char* keep_env = std::getenv("SWE_GRAD_KEEP");
-    if (!mixed && !(keep_env && keep_env[0] == '0')) {
+    if (!mixed && !store_all && !(keep_env && keep_env[0] == '0')) {
         size_t freeb = 0, totalb = 0;
         const size_t need = (size_t)C * 6 * fe * sizeof(double);
         if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && need <= freeb / 3)
@@ -685,11 +703,59 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
     auto slot = [&](void* base, int64_t m, T* U[3]) {
         for (int f = 0; f < 3; ++f) U[f] = (T*)base + ((size_t)m * 3 + f) * fe;
     };
+    // the kept trajectory: step k holds U^k, then U*, then U^d
+    auto traj_state = [&](int64_t k, int f) { return traj.d() + ((size_t)k * 9 + f) * fe; };
     // ---- forward: the run itself, with checkpoints, time steps and misfits
     if (e == hipSuccess) e = begin_call(h, h->stream);
+    if constexpr (!mixed) {
+        if (store_all && e == hipSuccess) {
+            double* S0[3] = {traj_state(0, 0), traj_state(0, 1), traj_state(0, 2)};
+            double* A0[3] = {(double*)bufA(h, 0), (double*)bufA(h, 1), (double*)bufA(h, 2)};
+            e = copy_state<double>(h, S0, A0);
+        }
+    }
     for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) {
         T* cur[3];
         for (int f = 0; f < 3; ++f) cur[f] = (T*)((k & 1) ? bufB(h, f) : bufA(h, f));
+        if constexpr (!mixed) {
+            if (store_all) {
+                // the tracing step from the kept U^k into U^{k+1} (the last
+                // into the buffer the step would have written), U* and U^d
+                // kept beside it; the handle's control block advances as in
+                // swe_run
+                T* last = (T*)((k & 1) ? bufA(h, 0) : bufB(h, 0));
+                swe::FusedArgs<double> fa;
+                fa.P = h->P;
+                fa.ctl = h->ctl;
+                fa.t_end = INFINITY;
+                fa.eta = traj_state(k, 0); fa.qx = traj_state(k, 1); fa.qy = traj_state(k, 2);
+                fa.z = (const double*)h->z;
+                fa.m = (const double*)bufB(h, 3);
+                for (int f = 0; f < 3; ++f) {
+                    double* o = k + 1 < nsteps ? traj_state(k + 1, f)
+                                               : (double*)((k & 1) ? bufA(h, f) : bufB(h, f));
+                    (f == 0 ? fa.eta1 : (f == 1 ? fa.qx1 : fa.qy1)) = o;
+                    fa.tus[f] = traj_state(k, 3 + f);
+                    fa.tud[f] = traj_state(k, 6 + f);
+                }
+                swe::fused_part_layout(fa, h->fpart, h->nparts);
+                fa.gy = h->gy;
+                fa.H = h->H;
+                fa.log_dt = dtlog + k;
+                fa.log_t = tlog + k;
+                const int sig = ((step0 + k) & 1) ? -1 : 1;
+                e = swe::launch_fused_trace(fa, sig, h->stream);
+                if (e == hipSuccess && ng > 0 && (k + 1) % g->obs_every == 0) {
+                    const int64_t row = (k + 1) / g->obs_every - 1;
+                    const double* nxt = k + 1 < nsteps ? traj_state(k + 1, 0) : (const double*)last;
+                    e = swe::launch_misfit<double>(h->P, nxt, (const double*)h->z,
+                                                   (const long long*)dcells.p, ng,
+                                                   g->hobs + row * ng, mis.d() + row * ng,
+                                                   h->stream);
+                }
+                continue;
+            }
+        }
         if (k % C == 0) {
             T* dst[3];
             slot(ck.p, k / C, dst);
@@ -733,6 +799,20 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
     aa.mp = padst.d() + Npad;
     aa.nman = n64;
     aa.work = work.d();
+    // the reverse step runs as one fused march (default) or as the four
+    // gather kernels (SWE_ADJOINT=gather in the environment); both give the
+    // same bits
+    const char* adj_env = std::getenv("SWE_ADJOINT");
+    const bool march = !(adj_env && std::strcmp(adj_env, "gather") == 0);
+    int march_rows = 0;
+    if (march) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) !=
+            hipSuccess)
+            cus = 0;
+        (void)hipGetLastError();
+        march_rows = swe::adjoint_march_rows(h->P, cus);
+    }
     // SWE_VERBOSE=1 in the environment: a line on stderr after the forward run
     // and after each reverse segment (each waits for the device)
     const char* verbose_env = std::getenv("SWE_VERBOSE");
@@ -749,14 +829,16 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
         }
         const int64_t s0 = sg * C, s1 = std::min(s0 + C, nsteps);
         T *U0[3], *CK[3];
-        slot(seg.p, 0, U0);
-        slot(ck.p, sg, CK);
-        e = copy_state<T>(h, U0, CK);
+        if (!store_all) {
+            slot(seg.p, 0, U0);
+            slot(ck.p, sg, CK);
+            e = copy_state<T>(h, U0, CK);
+        }
         // the fused kernel's own finalisation carries dt from step to step
-        if (e == hipSuccess && (keep || s1 - s0 > 1))
+        if (e == hipSuccess && !store_all && (keep || s1 - s0 > 1))
             e = swe::launch_replay_ctl(h->P, rc_ctl, ht[(size_t)s0], step0 + s0, hdt[(size_t)s0],
                                        h->stream);
-        const int64_t srec = keep ? s1 : s1 - 1;   // steps recomputed
+        const int64_t srec = store_all ? s0 : (keep ? s1 : s1 - 1);   // steps recomputed
         for (int64_t k = s0; k < srec && e == hipSuccess; ++k) {
             T *Uk[3], *Un[3];
             slot(seg.p, k - s0, Uk);
@@ -792,7 +874,10 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
         }
         for (int64_t k = s1 - 1; k >= s0 && e == hipSuccess; --k) {
             T* Uk[3];
-            slot(seg.p, k - s0, Uk);
+            if (store_all)
+                for (int f = 0; f < 3; ++f) Uk[f] = (T*)traj_state(k, f);
+            else
+                slot(seg.p, k - s0, Uk);
             const double* U64[3] = {(const double*)Uk[0], (const double*)Uk[1],
                                     (const double*)Uk[2]};
             if (mixed) {
@@ -812,7 +897,11 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
             const int sigma = ((step0 + k) & 1) ? -1 : 1;
             const double* US_k = US;
             const double* UD_k = UD;
-            if (keep) {
+            if (store_all) {
+                // U* and U^d were kept by the forward run
+                US_k = traj_state(k, 3);
+                UD_k = traj_state(k, 6);
+            } else if (keep) {
                 // U* and U^d were kept by the segment's recompute
                 US_k = segtr.d() + (size_t)(k - s0) * 6 * fe;
                 UD_k = US_k + 3 * fe;
@@ -851,7 +940,17 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
             aa.sigma = sigma;
             const bool obs = ng > 0 && (k + 1) % g->obs_every == 0;
             const double* hrow = obs ? g->hobs + ((k + 1) / g->obs_every - 1) * ng : nullptr;
-            e = swe::launch_adjoint_step(aa, (const int*)gmap.p, hrow, h->stream);
+            if (march) {
+                e = swe::launch_adjoint_march(aa, (const int*)gmap.p, hrow, march_rows,
+                                              h->stream);
+                // lambda^n and the bed's share are now in the other slot of each pair
+                aa.lam_slot = aa.lam_slot == swe::kAdjLamSlot[0] ? swe::kAdjLamSlot[1]
+                                                                 : swe::kAdjLamSlot[0];
+                aa.azp_slot = aa.azp_slot == swe::kAdjZpSlot[0] ? swe::kAdjZpSlot[1]
+                                                                : swe::kAdjZpSlot[0];
+            } else {
+                e = swe::launch_adjoint_step(aa, (const int*)gmap.p, hrow, h->stream);
+            }
         }
     }
     if (e == hipSuccess && nsteps > 0) e = swe::launch_adjoint_finish(aa, h->stream);
@@ -872,7 +971,7 @@ extern "C" {
 int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_every,
              double* loss, void* dJ_dn, void* dJ_dz) {
     if (!h) return fail(nullptr, SWE_EINVAL, "handle is NULL");
-    if (nsteps < 0 || !g || !loss || !dJ_dn || !dJ_dz || ckpt_every < 1)
+    if (nsteps < 0 || !g || !loss || !dJ_dn || !dJ_dz || ckpt_every < 0)
         return fail(h, SWE_EINVAL, "swe_grad: bad arguments");
     if (g->ngauge < 0 || g->obs_every < 1) return fail(h, SWE_EINVAL, "swe_grad: bad gauges");
     const int64_t nobs = nsteps / g->obs_every;

@@ -34,28 +34,6 @@ namespace swe {
 
 constexpr int kOutW = kWave - 4;   // output columns per strip
 
-// DPP wavefront shifts: lane l receives the value of lane l+1 (from_east) or
-// l-1 (from_west).  The end lanes (63, resp. 0) receive 0; they are halo
-// lanes whose shifted values feed no output column.
-__device__ __forceinline__ int dpp_from_east(int v) {
-    return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true);   // wave_shl:1
-}
-__device__ __forceinline__ int dpp_from_west(int v) {
-    return __builtin_amdgcn_mov_dpp(v, 0x138, 0xF, 0xF, true);   // wave_shr:1
-}
-__device__ __forceinline__ float from_east(float x) {
-    return __int_as_float(dpp_from_east(__float_as_int(x)));
-}
-__device__ __forceinline__ float from_west(float x) {
-    return __int_as_float(dpp_from_west(__float_as_int(x)));
-}
-__device__ __forceinline__ double from_east(double x) {
-    return __hiloint2double(dpp_from_east(__double2hiint(x)), dpp_from_east(__double2loint(x)));
-}
-__device__ __forceinline__ double from_west(double x) {
-    return __hiloint2double(dpp_from_west(__double2hiint(x)), dpp_from_west(__double2loint(x)));
-}
-
 __device__ __forceinline__ bool is_neg_zero(float x) { return __float_as_uint(x) == 0x80000000u; }
 __device__ __forceinline__ bool is_neg_zero(double x) {
     return (unsigned long long)__double_as_longlong(x) == 0x8000000000000000ull;
@@ -73,15 +51,6 @@ __device__ __forceinline__ bool is_neg_zero(double x) {
 constexpr unsigned kDryStill = 1u;    // after the step every output cell is dry
                                       // (h <= h_dry), finite and not eta = -0
 constexpr unsigned kDrySkipped = 2u;  // the step skipped the tile
-
-// Workgroup id -> tile id so that each XCD (workgroups are dealt round-robin
-// over the 8 XCDs) receives one contiguous run of tiles: vertically adjacent
-// chunks of a strip, and neighbouring strips, then share an L2.
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-    const int per = nb / 8, rem = nb % 8;
-    const int xcd = b % 8, loc = b / 8;
-    return xcd < rem ? xcd * (per + 1) + loc : rem * (per + 1) + (xcd - rem) * per + loc;
-}
 
 template <typename T>
 struct XDiv { T m, x, y; };     // x part of the flux divergence (pressure included)

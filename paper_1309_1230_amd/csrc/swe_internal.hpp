@@ -137,15 +137,30 @@ struct AdjointArgs {
     double* work;
     double dt, rx, ry;
     int sigma;
+    // work-array slots holding the adjoint of U^{n+1} (lambda, before the
+    // fold of its ghost ring) and the bed's padded adjoint of the step
+    // reversed before this one; the reverse march writes the other slot of
+    // each pair (kAdjLamSlot, kAdjZpSlot), the gather kernels keep the first
+    int lam_slot = 9, azp_slot = 14;
 };
 
 int adjoint_work_arrays();
 constexpr int kAdjLambda = 15, kAdjGradN = 18, kAdjGradZ = 19;
+constexpr int kAdjLamSlot[2] = {9, 0}, kAdjZpSlot[2] = {14, 12};
 // Adjoint of one step.  It first completes the step reversed before it (the
 // ghost ring of its U^n adjoint; nothing on the first), then adds this
 // step's gauge terms when hobs is not NULL (gmap from launch_gauge_map).
 hipError_t launch_adjoint_step(const AdjointArgs& a, const int* gmap, const double* hobs,
                                hipStream_t s);
+// The same step as one fused reverse march (one wave per strip of columns,
+// chunks of H rows): reads lambda and the bed adjoint from a.lam_slot and
+// a.azp_slot, writes them to the other slot of each pair.  The result is bit
+// for bit the one launch_adjoint_step gives.
+hipError_t launch_adjoint_march(const AdjointArgs& a, const int* gmap, const double* hobs, int H,
+                                hipStream_t s);
+// Chunk height of the reverse march for a grid on a device with ncu compute
+// units.
+int adjoint_march_rows(const Params& P, int ncu);
 // Completes the last step reversed (lambda and dJ/dz of its ghost ring).
 hipError_t launch_adjoint_finish(const AdjointArgs& a, hipStream_t s);
 // gmap[j*nx + i] = gauge index of cell (i, j), or -1 (nx*ny ints).

@@ -307,14 +307,17 @@ class Solver:
         return ({nm: buf[k] for k, nm in enumerate(TRACE_NAMES)},
                 {nm: sc[k] for k, nm in enumerate(SCALAR_NAMES)})
 
-    def grad(self, nsteps: int, cells, obs_every: int, hobs, ckpt_every: int = 45):
+    def grad(self, nsteps: int, cells, obs_every: int, hobs, ckpt_every: int = 0):
         """Discrete adjoint: run nsteps steps (the state advances, as with
         run) and return (J, dJ/dn, dJ/dz) of the gauge-misfit loss, the time
         steps of the run held fixed.  cells: distinct flattened cells j*nx+i;
         hobs: (nsteps // obs_every, len(cells)) float64 device tensor of
-        observed depths.  FP32 solvers run the forward in FP32 and the reverse
-        sweep in FP64, linearised at the promoted FP32 states; the gradients
-        are float64 either way."""
+        observed depths.  ckpt_every: checkpoint spacing of the forward run;
+        0 keeps the whole FP64 trajectory when it fits in device memory (no
+        recompute), else checkpoints every round(sqrt(nsteps)) steps; the
+        gradient does not depend on it.  FP32 solvers run the forward in FP32
+        and the reverse sweep in FP64, linearised at the promoted FP32 states;
+        the gradients are float64 either way."""
         torch = _torch()
         import numpy as np
         cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int64).ravel())
@@ -382,7 +385,7 @@ def _make_loss_function():
 
         @staticmethod
         def forward(ctx, n, z, eta0, qx0, qy0, solver_kwargs, nsteps, cells, obs_every, hobs,
-                    ckpt_every=45):
+                    ckpt_every=0):
             s = Solver(z.detach().contiguous(), n.detach().contiguous(), eta0.detach().clone(),
                        qx0.detach().clone(), qy0.detach().clone(), **solver_kwargs)
             try:

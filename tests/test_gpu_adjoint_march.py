@@ -1,0 +1,139 @@
+"""The fused reverse march of the adjoint step against the four gather
+kernels.
+
+Both evaluate the same expressions and sum each cell's terms in the same
+order, so the gradients must agree bit for bit (the gather kernels are in
+turn held to the oracle's reverse-mode gradient in test_gpu_adjoint.py).
+The cases span one and several strips of the march, chunks of its minimum
+height, every boundary kind on every edge, wet/dry fronts, observation
+steps, several checkpoint spacings, and the FP32-forward mixed path.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_1309_1230_amd import swe
+from paper_1309_1230_amd import workloads as W
+
+
+def note(msg):
+    print(f"[gpu-adjoint-march] {msg}", flush=True)
+
+
+def grads(p, nsteps, every, ncell, ckpt, seed, mode, monkeypatch, dtype=torch.float64):
+    rng = np.random.default_rng(seed)
+    cells = rng.choice(p.nx * p.ny, ncell, replace=False)
+    hobs = torch.as_tensor(rng.uniform(0.0, 1.0, (nsteps // every, ncell)),
+                           dtype=torch.float64, device="cuda")
+    monkeypatch.setenv("SWE_ADJOINT", mode)
+    s = swe.Solver.from_problem(p, dtype=dtype)
+    J, gn, gz = s.grad(nsteps, cells, every, hobs, ckpt)
+    return J, gn.cpu().numpy(), gz.cpu().numpy()
+
+
+def where_differs(a, b):
+    d = np.argwhere(~((a == b) | (np.isnan(a) & np.isnan(b))))
+    return d[:5].tolist(), len(d)
+
+
+def check_equal(p, nsteps, every, ncell, ckpt, seed, monkeypatch, dtype=torch.float64):
+    g = grads(p, nsteps, every, ncell, ckpt, seed, "gather", monkeypatch, dtype)
+    m = grads(p, nsteps, every, ncell, ckpt, seed, "march", monkeypatch, dtype)
+    assert np.isfinite(g[1]).all() and np.isfinite(g[2]).all()
+    # over one step n changes only the discharges, which the loss does not see
+    assert nsteps == 1 or np.abs(g[1]).max() > 0
+    assert np.abs(g[2]).max() > 0
+    assert m[0] == g[0]
+    for k, name in ((1, "dJ/dn"), (2, "dJ/dz")):
+        cells, count = where_differs(m[k], g[k])
+        assert count == 0, (name, count, "first (j, i):", cells,
+                            float(np.abs(m[k] - g[k]).max()), float(np.abs(g[k]).max()))
+
+
+def rotated(p, bc, lo, hi):
+    p.bc = bc
+    p.inflow_lo = lo
+    p.inflow_hi = hi
+    return p
+
+
+CASES = {
+    "random45x33": lambda: W.random_valid_state(45, 33, seed=21),
+    "random190x140": lambda: W.random_valid_state(190, 140, seed=4),
+    "random_rotated_bc": lambda: rotated(W.random_valid_state(175, 122, seed=8),
+                                         (W.OPEN, W.INFLOW, W.INFLOW, W.WALL),
+                                         (0, 3, 5, 0), (122, 110, 170, 175)),
+    "walls_everywhere": lambda: rotated(W.random_valid_state(117, 61, seed=12),
+                                        (W.WALL, W.WALL, W.WALL, W.WALL),
+                                        (0, 0, 0, 0), (61, 61, 117, 117)),
+    "inflow_channel": lambda: W.inflow_channel(130, 70, seed=3, q_peak=2.0, dry=True,
+                                               t_peak=2.0, t_end=6.0),
+}
+
+
+# the east edge column on the last lanes of a strip's wave (58 output columns,
+# three halo lanes on each side): nx = 116, 117, 118 put it on lanes 61, 62, 63
+for _nx in (116, 118, 176):
+    CASES[f"random{_nx}x50"] = (lambda n: lambda: W.random_valid_state(n, 50, seed=n))(_nx)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_march_equals_gather_fp64(name, monkeypatch):
+    p = CASES[name]()
+    note(f"{name} {p.nx}x{p.ny} f64: 16 steps, march vs gather")
+    check_equal(p, 16, 4, 20, 5, seed=3, monkeypatch=monkeypatch)
+
+
+def test_march_equals_gather_flood_several_chunks(monkeypatch):
+    p = W.flood_scenario(2, 400, 300)
+    note(f"flood {p.nx}x{p.ny} f64: 30 steps, march vs gather")
+    check_equal(p, 30, 3, 40, 7, seed=5, monkeypatch=monkeypatch)
+
+
+def test_march_equals_gather_mixed_fp32(monkeypatch):
+    p = W.random_valid_state(130, 100, seed=17)
+    note(f"random {p.nx}x{p.ny} f32 forward: 12 steps, march vs gather")
+    check_equal(p, 12, 3, 15, 4, seed=9, monkeypatch=monkeypatch, dtype=torch.float32)
+
+
+def test_march_checkpoint_spacing_and_single_step(monkeypatch):
+    p = W.random_valid_state(150, 90, seed=2)
+    note("march: checkpoint spacing 1, 4, 9; one step")
+    outs = [grads(p, 9, 3, 12, c, 1, "march", monkeypatch) for c in (1, 4, 9)]
+    for o in outs[1:]:
+        assert o[0] == outs[0][0]
+        assert np.array_equal(o[1], outs[0][1]) and np.array_equal(o[2], outs[0][2])
+    check_equal(p, 1, 1, 12, 1, seed=4, monkeypatch=monkeypatch)
+
+
+def test_kept_trajectory_equals_checkpointed(monkeypatch):
+    """ckpt_every = 0 keeps the whole trajectory (the forward run writes U*
+    and U^d of every step, the reverse sweep recomputes nothing): the same
+    gradient bit for bit, and the same state and statistics afterwards."""
+    p = W.random_valid_state(150, 90, seed=6)
+    note("kept trajectory vs checkpoint spacing 4, march and gather")
+    outs = {}
+    for mode in ("march", "gather"):
+        for ck in (0, 4):
+            rng = np.random.default_rng(2)
+            cells = rng.choice(p.nx * p.ny, 12, replace=False)
+            hobs = torch.as_tensor(rng.uniform(0.0, 1.0, (5, 12)), dtype=torch.float64,
+                                   device="cuda")
+            monkeypatch.setenv("SWE_ADJOINT", mode)
+            s = swe.Solver.from_problem(p, dtype=torch.float64)
+            J, gn, gz = s.grad(15, cells, 3, hobs, ck)
+            st = s.stats()
+            outs[(mode, ck)] = (J, gn.cpu().numpy(), gz.cpu().numpy(),
+                                [t.cpu().numpy() for t in (s.eta, s.qx, s.qy)], st)
+    ref = swe.Solver.from_problem(p, dtype=torch.float64)
+    sr = ref.run(15)
+    base = outs[("march", 0)]
+    for key, o in outs.items():
+        assert o[0] == base[0], key
+        assert np.array_equal(o[1], base[1]) and np.array_equal(o[2], base[2]), key
+        for a, b in zip(o[3], (ref.eta, ref.qx, ref.qy)):
+            assert np.array_equal(a, b.cpu().numpy()), key
+        for f in ("t", "dt", "step", "volume", "lambda_max"):
+            assert getattr(o[4], f) == getattr(sr, f), (key, f)
