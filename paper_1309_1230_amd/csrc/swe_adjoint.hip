@@ -82,13 +82,15 @@ struct Cell { double e, qx, qy, h, r, u, v; };
 // kW, kE: kinds of the west and east boundary faces of row j.  (Every edge
 // index here is a constant: a per-thread index into the parameter block would
 // make the compiler read it through vector memory.)
+// XEDGE = false: the caller knows that i is an interior column.
+template <bool XEDGE = true>
 __device__ __forceinline__ Cell make_cell(const Params& P, double e, double qx, double qy,
                                           double qin, int i, int j, double zpv, int kW, int kE) {
     Cell c;
     c.e = e;
     c.qx = qx;
     c.qy = qy;
-    if (i < 0 || i >= P.nx)
+    if (XEDGE && (i < 0 || i >= P.nx))
         ghost(i < 0 ? kW : kE, true, i < 0 ? qin : -qin, c.e, c.qx, c.qy, c.e, c.qx, c.qy);
     else if (j < 0 || j >= P.ny)
         ghost(j < 0 ? face_kind(P, EDGE_S, i) : face_kind(P, EDGE_N, i), false,
@@ -758,7 +760,9 @@ __device__ __forceinline__ bool padded_ok(const Pad& d, int i, int j) {
 struct Nbr { Cell c; double z, a0, a1, a2; };
 
 // gather_faces from values: the faces of padded cell (i, j) in the same
-// order, with the same face rules.
+// order, with the same face rules.  EDGE = false: column i and its x
+// neighbours are interior, so every x face is an interior face.
+template <bool EDGE>
 __device__ __forceinline__ CellBar gather_values(const Params& P, int i, int j, const Cell& me,
                                                  double zme, double am0, double am1, double am2,
                                                  const Nbr& E, const Nbr& W, const Nbr& N,
@@ -766,18 +770,19 @@ __device__ __forceinline__ CellBar gather_values(const Params& P, int i, int j, 
                                                  double hdry, double hg) {
     CellBar cb = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (j >= 0 && j < P.ny) {
-        if (i >= -1 && i <= P.nx - 1) {   // face i: this cell is L
+        if (!EDGE || (i >= -1 && i <= P.nx - 1)) {   // face i: this cell is L
             const FaceBar fb = face_bar_v(am0, am1, am2, E.a0, E.a1, E.a2, rx, dir, true);
-            face_flux_adjoint(fb, xface_kind(P, i, j), dir, i == P.nx - 1, true, true, me, E.c,
-                              zme, E.z, hdry, hg, cb);
+            face_flux_adjoint(fb, EDGE ? xface_kind(P, i, j) : -1, dir, EDGE && i == P.nx - 1,
+                              true, true, me, E.c, zme, E.z, hdry, hg, cb);
         }
-        if (i - 1 >= -1 && i - 1 <= P.nx - 1) {   // face i-1: this cell is R
+        if (!EDGE || (i - 1 >= -1 && i - 1 <= P.nx - 1)) {   // face i-1: this cell is R
             const FaceBar fb = face_bar_v(W.a0, W.a1, W.a2, am0, am1, am2, rx, dir, true);
-            face_flux_adjoint(fb, xface_kind(P, i - 1, j), dir, i - 1 == P.nx - 1, false, true,
-                              W.c, me, W.z, zme, hdry, hg, cb);
+            face_flux_adjoint(fb, EDGE ? xface_kind(P, i - 1, j) : -1, dir,
+                              EDGE && i - 1 == P.nx - 1, false, true, W.c, me, W.z, zme, hdry,
+                              hg, cb);
         }
     }
-    if (i >= 0 && i < P.nx) {
+    if (!EDGE || (i >= 0 && i < P.nx)) {
         if (j >= -1 && j <= P.ny - 1) {
             const FaceBar fb = face_bar_v(am0, am1, am2, N.a0, N.a1, N.a2, ry, dir, false);
             face_flux_adjoint(fb, yface_kind(P, i, j), dir, j == P.ny - 1, true, false, me, N.c,
@@ -792,31 +797,35 @@ __device__ __forceinline__ CellBar gather_values(const Params& P, int i, int j, 
     return cb;
 }
 
-// The lane's neighbour from the east (lane + 1) or west (lane - 1).
-__device__ __forceinline__ Nbr nbr_east(double e, double qx, double qy, double h, double r,
-                                        double z, double a0, double a1, double a2) {
+// The neighbour in the lane to the east (lane + 1), to the west, or in this
+// lane (another row).  Depths are formed as e - z from the carried values,
+// the expression the cell was built with.
+__device__ __forceinline__ Nbr nbr_east(double e, double qx, double qy, double r, double z,
+                                        double a0, double a1, double a2) {
     Nbr n;
-    n.c = carried_cell(from_east(e), from_east(qx), from_east(qy), from_east(h), from_east(r));
-    n.z = from_east(z);
+    const double ee = from_east(e), ze = from_east(z);
+    n.c = carried_cell(ee, from_east(qx), from_east(qy), ee - ze, from_east(r));
+    n.z = ze;
     n.a0 = from_east(a0);
     n.a1 = from_east(a1);
     n.a2 = from_east(a2);
     return n;
 }
-__device__ __forceinline__ Nbr nbr_west(double e, double qx, double qy, double h, double r,
-                                        double z, double a0, double a1, double a2) {
+__device__ __forceinline__ Nbr nbr_west(double e, double qx, double qy, double r, double z,
+                                        double a0, double a1, double a2) {
     Nbr n;
-    n.c = carried_cell(from_west(e), from_west(qx), from_west(qy), from_west(h), from_west(r));
-    n.z = from_west(z);
+    const double ew = from_west(e), zw = from_west(z);
+    n.c = carried_cell(ew, from_west(qx), from_west(qy), ew - zw, from_west(r));
+    n.z = zw;
     n.a0 = from_west(a0);
     n.a1 = from_west(a1);
     n.a2 = from_west(a2);
     return n;
 }
-__device__ __forceinline__ Nbr nbr_here(double e, double qx, double qy, double h, double r,
-                                        double z, double a0, double a1, double a2) {
+__device__ __forceinline__ Nbr nbr_here(double e, double qx, double qy, double r, double z,
+                                        double a0, double a1, double a2) {
     Nbr n;
-    n.c = carried_cell(e, qx, qy, h, r);
+    n.c = carried_cell(e, qx, qy, e - z, r);
     n.z = z;
     n.a0 = a0;
     n.a1 = a1;
@@ -830,7 +839,10 @@ struct MarchRow {
     int gm;
 };
 
-template <bool HOBS>
+// EDGE: the strip holds the west or the east edge column (its lanes may be
+// ghost or outside columns); otherwise every lane is an interior column and
+// the column tests are compiled out.
+template <bool HOBS, bool EDGE>
 struct AdjMarch {
     const AdjointArgs& a;
     const int* gmap;
@@ -843,7 +855,7 @@ struct AdjMarch {
     double* GZ;
     double* GN;
     int i, ii, ic, j0, j1;
-    bool colOut, edgeStrip;
+    bool colOut;
     double hdry, hg, kap, emax;
     // outputs of the previous iteration, stored at the start of the next one
     // (ahead of its prefetch, so that waiting for the prefetch never waits
@@ -852,36 +864,45 @@ struct AdjMarch {
     double o_gz = 0.0, o_gn = 0.0, o_l0 = 0.0, o_l1 = 0.0, o_l2 = 0.0, o_az = 0.0;
     bool o_fa = false, o_wet = false, o_e2 = false;
 
-    // carried rows; index k holds row R - k (ue..zz, ab, ad, azp), R-1-k (aus),
-    // R-2-k (fs, un, db)
-    double ue[5], ux[5], uy[5], uh[5], ur[5], zz[5];   // U^n cells
-    double se[3], sx[3], sy[3], sh[3], sr[3];          // U* cells
-    double abe[3], abx[3], aby[3];                     // S12's inner adjoint (0.5 D-bar)
-    double ade[4], adx[4], ady[4];                     // U^d adjoint (D-bar)
-    double azp[4];                                     // bed's share
-    double ause[3], ausx[3], ausy[3];                  // U* adjoint
-    double fse[3], fsx[3], fsy[3];                     // U* adjoint, S8 fold applied
-    double une[2], unx[2], uny[2];                     // U^n adjoint, S12 and S4 terms
-    double dbx[3], dby[3], atx[3], aty[3];             // switch derivatives of S3
+    // carried rows; index k holds row R - k (ue..zz, ad, azp), R-1-k (aus),
+    // R-2-k (fs, un, db, at).  S12's inner adjoint is 0.5 times the U^d
+    // adjoint (the product kernel A forms), depths are e - z.
+    double ue[5], ux[5], uy[5], ur[5], zz[5];   // U^n cells
+    double se[3], sx[3], sy[3], sr[3];          // U* cells
+    double ade[4], adx[4], ady[4];              // U^d adjoint (D-bar)
+    double azp[4];                              // bed's share
+    double ause[3], ausx[3], ausy[3];           // U* adjoint
+    double fse[3], fsx[3], fsy[3];              // U* adjoint, S8 fold applied
+    double une[2], unx[2], uny[2];              // U^n adjoint, S12 and S4 terms
+    double dbx[2], atx[2], aty[2], dby[3];      // switch derivatives of S3
     MarchRow pf;
 
-    __device__ AdjMarch(const AdjointArgs& a_, const int* g, const double* h) : a(a_), gmap(g), hobs(h) {}
+    __device__ AdjMarch(const AdjointArgs& a_, const int* g, const double* h)
+        : a(a_), gmap(g), hobs(h) {}
+
+    // Loads at a 32-bit byte offset from a uniform base (every array here is
+    // below 4 GiB), so that no per-lane 64-bit address is formed.
+    template <typename V>
+    __device__ __forceinline__ static V at_off(const V* base, unsigned off) {
+        return *(const V*)((const char*)base + off);
+    }
 
     __device__ __forceinline__ void prefetch(int R) {
         const int jj = min(max(R, 0), d.ny - 1);
-        const long long o = pitched(a.P, ii, jj);
-        const long long C = d.at(ic, min(max(R, -1), d.ny));
-        pf.ue = a.un[0][o]; pf.ux = a.un[1][o]; pf.uy = a.un[2][o];
-        pf.se = a.us[0][o]; pf.sx = a.us[1][o]; pf.sy = a.us[2][o];
-        pf.de = a.ud[0][o]; pf.dx = a.ud[1][o]; pf.dy = a.ud[2][o];
-        pf.z = a.zp[C];
-        pf.m = a.mp[C];
-        pf.n = a.nman[o];
-        pf.l0 = LIN[C]; pf.l1 = LIN[d.N + C]; pf.l2 = LIN[2 * d.N + C];
-        pf.azi = AZI[C];
-        pf.gz = GZ[C];
-        pf.gn = GN[C];
-        pf.gm = HOBS ? gmap[(long long)jj * d.nx + ii] : -1;
+        const unsigned o = (unsigned)(jj * (int)a.P.pitch + ii) * 8u;
+        const unsigned C = (unsigned)((min(max(R, -1), d.ny) + 1) * d.P2 + ic + 1) * 8u;
+        const unsigned NB = (unsigned)d.N * 8u;
+        pf.ue = at_off(a.un[0], o); pf.ux = at_off(a.un[1], o); pf.uy = at_off(a.un[2], o);
+        pf.se = at_off(a.us[0], o); pf.sx = at_off(a.us[1], o); pf.sy = at_off(a.us[2], o);
+        pf.de = at_off(a.ud[0], o); pf.dx = at_off(a.ud[1], o); pf.dy = at_off(a.ud[2], o);
+        pf.z = at_off(a.zp, C);
+        pf.m = at_off(a.mp, C);
+        pf.n = at_off(a.nman, o);
+        pf.l0 = at_off(LIN, C); pf.l1 = at_off(LIN, C + NB); pf.l2 = at_off(LIN, C + 2 * NB);
+        pf.azi = at_off(AZI, C);
+        pf.gz = at_off(GZ, C);
+        pf.gn = at_off(GN, C);
+        pf.gm = HOBS ? at_off(gmap, (unsigned)(jj * d.nx + ii) * 4u) : -1;
     }
 
     template <int K>
@@ -890,7 +911,13 @@ struct AdjMarch {
         for (int k = K - 1; k > 0; --k) x[k] = x[k - 1];
     }
 
-    __device__ __forceinline__ bool interior(int x, int y) const { return d.interior(x, y); }
+    __device__ __forceinline__ bool col_in(int x) const { return !EDGE || (x >= 0 && x < d.nx); }
+    __device__ __forceinline__ bool in(int x, int y) const {
+        return col_in(x) && y >= 0 && y < d.ny;
+    }
+    __device__ __forceinline__ bool pad_ok(int y) const {
+        return EDGE ? padded_ok(d, i, y) : (y >= -1 && y <= d.ny);
+    }
 
     __device__ __forceinline__ void store_previous(int R) {
         if (o_fa) {
@@ -907,30 +934,34 @@ struct AdjMarch {
         }
     }
 
+    // Iteration R forms row R of kernel A's work, row R-1 of C, row R-2 of
+    // the fold and E1 and row R-3 of E2.
     __device__ __forceinline__ void iter(int R) {
         const MarchRow q = pf;
         store_previous(R);
         prefetch(R + 1);
-        const int kW = face_kind(a.P, EDGE_W, R), kE = face_kind(a.P, EDGE_E, R);
-        shift<5>(ue); shift<5>(ux); shift<5>(uy); shift<5>(uh); shift<5>(ur); shift<5>(zz);
-        shift<3>(se); shift<3>(sx); shift<3>(sy); shift<3>(sh); shift<3>(sr);
-        shift<3>(abe); shift<3>(abx); shift<3>(aby);
-        shift<4>(ade); shift<4>(adx); shift<4>(ady);
-        shift<4>(azp);
+        int kW = BC_WALL, kE = BC_WALL;
+        if (EDGE) {
+            kW = face_kind(a.P, EDGE_W, R);
+            kE = face_kind(a.P, EDGE_E, R);
+        }
+        shift<5>(ue); shift<5>(ux); shift<5>(uy); shift<5>(ur); shift<5>(zz);
+        shift<3>(se); shift<3>(sx); shift<3>(sy); shift<3>(sr);
+        shift<4>(ade); shift<4>(adx); shift<4>(ady); shift<4>(azp);
         shift<3>(ause); shift<3>(ausx); shift<3>(ausy);
         shift<3>(fse); shift<3>(fsx); shift<3>(fsy);
         shift<2>(une); shift<2>(unx); shift<2>(uny);
-        shift<3>(dbx); shift<3>(dby); shift<3>(atx); shift<3>(aty);
+        shift<2>(dbx); shift<2>(atx); shift<2>(aty); shift<3>(dby);
 
         // ---- ingest row R: U^n and U* cells (ghost rule, primitives), bed
         zz[0] = q.z;
         {
-            const Cell c = make_cell(a.P, q.ue, q.ux, q.uy, a.qin0, i, R, q.z, kW, kE);
-            ue[0] = c.e; ux[0] = c.qx; uy[0] = c.qy; uh[0] = c.h; ur[0] = c.r;
+            const Cell c = make_cell<EDGE>(a.P, q.ue, q.ux, q.uy, a.qin0, i, R, q.z, kW, kE);
+            ue[0] = c.e; ux[0] = c.qx; uy[0] = c.qy; ur[0] = c.r;
         }
         {
-            const Cell c = make_cell(a.P, q.se, q.sx, q.sy, a.qin1, i, R, q.z, kW, kE);
-            se[0] = c.e; sx[0] = c.qx; sy[0] = c.qy; sh[0] = c.h; sr[0] = c.r;
+            const Cell c = make_cell<EDGE>(a.P, q.se, q.sx, q.sy, a.qin1, i, R, q.z, kW, kE);
+            se[0] = c.e; sx[0] = c.qx; sy[0] = c.qy; sr[0] = c.r;
         }
 
         // ---- row R: S15, S14, S13, S12's U^n share (with the step reversed
@@ -940,7 +971,7 @@ struct AdjMarch {
             // the neighbouring lanes' values of this row
             double lw0 = 0.0, lw1 = 0.0, lw2 = 0.0, le0 = 0.0, le1 = 0.0, le2 = 0.0;
             double zw = 0.0, ze = 0.0;
-            if (edgeStrip) {
+            if (EDGE) {
                 lw0 = from_west(q.l0); lw1 = from_west(q.l1); lw2 = from_west(q.l2);
                 le0 = from_east(q.l0); le1 = from_east(q.l1); le2 = from_east(q.l2);
                 zw = from_west(q.azi); ze = from_east(q.azi);
@@ -948,10 +979,10 @@ struct AdjMarch {
             double o0 = 0.0, o1 = 0.0, o2 = 0.0, oz = 0.0;
             o_fa = false;
             o_wet = false;
-            if (interior(i, R)) {
+            if (in(i, R)) {
                 double lam[3] = {q.l0, q.l1, q.l2};
-                if (i == 0) fold_value(lw0, lw1, lw2, kW, true, lam);
-                if (i == d.nx - 1) fold_value(le0, le1, le2, kE, true, lam);
+                if (EDGE && i == 0) fold_value(lw0, lw1, lw2, kW, true, lam);
+                if (EDGE && i == d.nx - 1) fold_value(le0, le1, le2, kE, true, lam);
                 if (R == 0) {
                     const long long g = d.at(i, -1);
                     fold_value(LIN[g], LIN[d.N + g], LIN[2 * d.N + g], face_kind(a.P, EDGE_S, i),
@@ -966,8 +997,8 @@ struct AdjMarch {
                 double gz = 0.0;
                 if (own) {
                     double gzs = q.azi;
-                    if (i == 0) gzs += zw;
-                    if (i == d.nx - 1) gzs += ze;
+                    if (EDGE && i == 0) gzs += zw;
+                    if (EDGE && i == d.nx - 1) gzs += ze;
                     if (R == 0) gzs += AZI[d.at(i, -1)];
                     if (R == d.ny - 1) gzs += AZI[d.at(i, d.ny)];
                     gz = q.gz + gzs;
@@ -989,26 +1020,28 @@ struct AdjMarch {
                 o0 = f.e; o1 = f.x; o2 = f.y; oz = f.azp;
             }
             ade[0] = o0; adx[0] = o1; ady[0] = o2;
-            abe[0] = 0.5 * o0; abx[0] = 0.5 * o1; aby[0] = 0.5 * o2;
             azp[0] = oz;
         }
 
         // ---- row R-1: flux part of S12, S11, S10, S9 (the U* adjoint)
         {
             const int j = R - 1;
-            const Nbr E = nbr_east(se[1], sx[1], sy[1], sh[1], sr[1], zz[1], abe[1], abx[1], aby[1]);
-            const Nbr W = nbr_west(se[1], sx[1], sy[1], sh[1], sr[1], zz[1], abe[1], abx[1], aby[1]);
+            const double b0 = 0.5 * ade[1], b1 = 0.5 * adx[1], b2 = 0.5 * ady[1];
+            const Nbr E = nbr_east(se[1], sx[1], sy[1], sr[1], zz[1], b0, b1, b2);
+            const Nbr W = nbr_west(se[1], sx[1], sy[1], sr[1], zz[1], b0, b1, b2);
             double eb = 0.0, qxb = 0.0, qyb = 0.0;
-            if (padded_ok(d, i, j)) {
-                const Nbr N = nbr_here(se[0], sx[0], sy[0], sh[0], sr[0], zz[0], abe[0], abx[0], aby[0]);
-                const Nbr S = nbr_here(se[2], sx[2], sy[2], sh[2], sr[2], zz[2], abe[2], abx[2], aby[2]);
-                const Cell me = carried_cell(se[1], sx[1], sy[1], sh[1], sr[1]);
-                const CellBar cb = gather_values(a.P, i, j, me, zz[1], abe[1], abx[1], aby[1], E, W,
-                                                 N, S, -a.sigma, a.rx, a.ry, hdry, hg);
-                const bool in = interior(i, j);
-                eb = cb.e + (in ? abe[1] : 0.0);
-                qxb = cb.qx + (in ? abx[1] : 0.0);
-                qyb = cb.qy + (in ? aby[1] : 0.0);
+            if (pad_ok(j)) {
+                const Nbr N = nbr_here(se[0], sx[0], sy[0], sr[0], zz[0], 0.5 * ade[0],
+                                       0.5 * adx[0], 0.5 * ady[0]);
+                const Nbr S = nbr_here(se[2], sx[2], sy[2], sr[2], zz[2], 0.5 * ade[2],
+                                       0.5 * adx[2], 0.5 * ady[2]);
+                const Cell me = carried_cell(se[1], sx[1], sy[1], se[1] - zz[1], sr[1]);
+                const CellBar cb = gather_values<EDGE>(a.P, i, j, me, zz[1], b0, b1, b2, E, W, N,
+                                                       S, -a.sigma, a.rx, a.ry, hdry, hg);
+                const bool inC = in(i, j);
+                eb = cb.e + (inC ? b0 : 0.0);
+                qxb = cb.qx + (inC ? b1 : 0.0);
+                qyb = cb.qy + (inC ? b2 : 0.0);
                 const double h = me.h, r = me.r;
                 qxb += cb.u * r;
                 qyb += cb.v * r;
@@ -1023,15 +1056,21 @@ struct AdjMarch {
         // ---- row R-2: the S8 fold of the U* adjoint
         {
             const int j = R - 2;
-            const double we = from_west(ause[1]), wx = from_west(ausx[1]), wy = from_west(ausy[1]);
-            const double ee = from_east(ause[1]), ex = from_east(ausx[1]), ey = from_east(ausy[1]);
+            double we = 0.0, wx = 0.0, wy = 0.0, ee = 0.0, ex = 0.0, ey = 0.0;
+            if (EDGE) {
+                we = from_west(ause[1]); wx = from_west(ausx[1]); wy = from_west(ausy[1]);
+                ee = from_east(ause[1]); ex = from_east(ausx[1]); ey = from_east(ausy[1]);
+            }
             double v[3] = {0.0, 0.0, 0.0};
-            if (interior(i, j)) {
+            if (in(i, j)) {
                 v[0] = ause[1]; v[1] = ausx[1]; v[2] = ausy[1];
-                if (i == 0) fold_value(we, wx, wy, face_kind(a.P, EDGE_W, j), true, v);
-                if (i == d.nx - 1) fold_value(ee, ex, ey, face_kind(a.P, EDGE_E, j), true, v);
-                if (j == 0) fold_value(ause[2], ausx[2], ausy[2], face_kind(a.P, EDGE_S, i), false, v);
-                if (j == d.ny - 1) fold_value(ause[0], ausx[0], ausy[0], face_kind(a.P, EDGE_N, i), false, v);
+                if (EDGE && i == 0) fold_value(we, wx, wy, face_kind(a.P, EDGE_W, j), true, v);
+                if (EDGE && i == d.nx - 1)
+                    fold_value(ee, ex, ey, face_kind(a.P, EDGE_E, j), true, v);
+                if (j == 0)
+                    fold_value(ause[2], ausx[2], ausy[2], face_kind(a.P, EDGE_S, i), false, v);
+                if (j == d.ny - 1)
+                    fold_value(ause[0], ausx[0], ausy[0], face_kind(a.P, EDGE_N, i), false, v);
             }
             fse[0] = v[0]; fsx[0] = v[1]; fsy[0] = v[2];
         }
@@ -1040,33 +1079,34 @@ struct AdjMarch {
         // the switch derivatives of S3
         {
             const int j = R - 2;
-            const Cell me = carried_cell(ue[2], ux[2], uy[2], uh[2], ur[2]);
+            const Cell me = carried_cell(ue[2], ux[2], uy[2], ue[2] - zz[2], ur[2]);
             const double eW = from_west(ue[2]), eE = from_east(ue[2]);
+            const double zW = from_west(zz[2]), zE = from_east(zz[2]);
             const double nux = curv_switch(eW, me.e, eE, me.r);
             const double nuy = curv_switch(ue[3], me.e, ue[1], me.r);
             const double nuE = from_east(nux), nuW = from_west(nux);
-            const Cell cE = carried_cell(eE, from_east(ux[2]), from_east(uy[2]), from_east(uh[2]), 0.0);
-            const Cell cW = carried_cell(eW, from_west(ux[2]), from_west(uy[2]), from_west(uh[2]), 0.0);
+            const Cell cE = carried_cell(eE, from_east(ux[2]), from_east(uy[2]), eE - zE, 0.0);
+            const Cell cW = carried_cell(eW, from_west(ux[2]), from_west(uy[2]), eW - zW, 0.0);
             const double dE[3] = {from_east(ade[2]), from_east(adx[2]), from_east(ady[2])};
             const double dW[3] = {from_west(ade[2]), from_west(adx[2]), from_west(ady[2])};
             double un[3] = {0.0, 0.0, 0.0};
             double dbxv = 0.0, atxv = 0.0, dbyv = 0.0, atyv = 0.0;
-            if (interior(i, j)) {
+            if (in(i, j)) {
                 const double dC[3] = {ade[2], adx[2], ady[2]};
                 const double dN[3] = {ade[1], adx[1], ady[1]};
                 const double dS[3] = {ade[3], adx[3], ady[3]};
-                const Cell cN = carried_cell(ue[1], ux[1], uy[1], uh[1], ur[1]);
-                const Cell cS = carried_cell(ue[3], ux[3], uy[3], uh[3], ur[3]);
+                const Cell cN = carried_cell(ue[1], ux[1], uy[1], ue[1] - zz[1], ur[1]);
+                const Cell cS = carried_cell(ue[3], ux[3], uy[3], ue[3] - zz[3], ur[3]);
                 const double nuN = curv_switch(ue[2], ue[1], ue[0], ur[1]);
                 const double nuS = curv_switch(ue[4], ue[3], ue[2], ur[3]);
-                un[0] = abe[2]; un[1] = abx[2]; un[2] = aby[2];
+                un[0] = 0.5 * ade[2]; un[1] = 0.5 * adx[2]; un[2] = 0.5 * ady[2];
                 double nub[2] = {0.0, 0.0};
 #pragma unroll
                 for (int f = 0; f < 4; ++f) {
                     const bool xf = f < 2;
                     const int ni = xf ? (f == 0 ? i + 1 : i - 1) : i;
                     const int nj = xf ? j : (f == 2 ? j + 1 : j - 1);
-                    if (!interior(ni, nj)) continue;   // boundary face: eps = 0
+                    if (!in(ni, nj)) continue;   // boundary face: eps = 0
                     const Cell& on = f == 0 ? cE : (f == 1 ? cW : (f == 2 ? cN : cS));
                     const double nuOn = f == 0 ? nuE : (f == 1 ? nuW : (f == 2 ? nuN : nuS));
                     const double* dn = f == 0 ? dE : (f == 1 ? dW : (f == 2 ? dN : dS));
@@ -1097,36 +1137,37 @@ struct AdjMarch {
         // ---- row R-3: S7, S6, S5, S3, S2: lambda^n and the bed's share
         {
             const int j = R - 3;
-            const Nbr E = nbr_east(ue[3], ux[3], uy[3], uh[3], ur[3], zz[3], fse[1], fsx[1], fsy[1]);
-            const Nbr W = nbr_west(ue[3], ux[3], uy[3], uh[3], ur[3], zz[3], fse[1], fsx[1], fsy[1]);
+            const Nbr E = nbr_east(ue[3], ux[3], uy[3], ur[3], zz[3], fse[1], fsx[1], fsy[1]);
+            const Nbr W = nbr_west(ue[3], ux[3], uy[3], ur[3], zz[3], fse[1], fsx[1], fsy[1]);
             const double dbW = from_west(dbx[1]), dbE = from_east(dbx[1]);
-            o_e2 = colOut && j >= j0 && j < j1 && padded_ok(d, i, j);
+            o_e2 = colOut && j >= j0 && j < j1 && pad_ok(j);
             if (o_e2) {
-                const Nbr N = nbr_here(ue[2], ux[2], uy[2], uh[2], ur[2], zz[2], fse[0], fsx[0], fsy[0]);
-                const Nbr S = nbr_here(ue[4], ux[4], uy[4], uh[4], ur[4], zz[4], fse[2], fsx[2], fsy[2]);
-                const Cell me = carried_cell(ue[3], ux[3], uy[3], uh[3], ur[3]);
-                const CellBar cb = gather_values(a.P, i, j, me, zz[3], fse[1], fsx[1], fsy[1], E, W,
-                                                 N, S, a.sigma, a.rx, a.ry, hdry, hg);
-                const bool in = interior(i, j);
+                const Nbr N = nbr_here(ue[2], ux[2], uy[2], ur[2], zz[2], fse[0], fsx[0], fsy[0]);
+                const Nbr S = nbr_here(ue[4], ux[4], uy[4], ur[4], zz[4], fse[2], fsx[2], fsy[2]);
+                const Cell me = carried_cell(ue[3], ux[3], uy[3], ue[3] - zz[3], ur[3]);
+                const CellBar cb = gather_values<EDGE>(a.P, i, j, me, zz[3], fse[1], fsx[1],
+                                                       fsy[1], E, W, N, S, a.sigma, a.rx, a.ry,
+                                                       hdry, hg);
+                const bool inC = in(i, j);
                 double eb = cb.e, qxb = cb.qx, qyb = cb.qy;
-                if (in) {
+                if (inC) {
                     eb += une[1] + fse[1];
                     qxb += unx[1] + fsx[1];
                     qyb += uny[1] + fsy[1];
                 }
                 double rb = cb.u * me.qx + cb.v * me.qy;
-                if (interior(i - 1, j)) eb += dbW;
-                if (in) {
+                if (in(i - 1, j)) eb += dbW;
+                if (inC) {
                     eb += -dbx[1] - dbx[1];
                     rb += atx[1];
                 }
-                if (interior(i + 1, j)) eb += dbE;
-                if (interior(i, j - 1)) eb += dby[2];
-                if (in) {
+                if (in(i + 1, j)) eb += dbE;
+                if (in(i, j - 1)) eb += dby[2];
+                if (inC) {
                     eb += -dby[1] - dby[1];
                     rb += aty[1];
                 }
-                if (interior(i, j + 1)) eb += dby[0];
+                if (in(i, j + 1)) eb += dby[0];
                 const double h = me.h, r = me.r;
                 qxb += cb.u * r;
                 qyb += cb.v * r;
@@ -1139,55 +1180,91 @@ struct AdjMarch {
             }
         }
     }
+
+    __device__ __forceinline__ void run(int lane, int strip, int chunk, int H, int lout,
+                                        int zout) {
+        d = pad_of(a.P);
+        LIN = wk(a, d, a.lam_slot);
+        AZI = wk(a, d, a.azp_slot);
+        LOUT = wk(a, d, lout);
+        AZO = wk(a, d, zout);
+        GZ = wk(a, d, W_GZ);
+        GN = wk(a, d, W_GN);
+        hdry = a.P.h_dry;
+        hg = 0.5 * a.P.g;
+        kap = a.P.kappa;
+        emax = a.P.eps_max;
+        const int pc = strip * kMarchOutW - 3 + lane;   // padded column of the lane
+        i = pc - 1;
+        ii = min(max(i, 0), a.P.nx - 1);
+        ic = min(max(i, -1), a.P.nx);
+        colOut = lane >= 3 && lane < 3 + kMarchOutW && pc <= a.P.nx + 1;
+        const int py0 = chunk * H, py1 = min(py0 + H, a.P.ny + 2);
+        j0 = py0 - 1;
+        j1 = py1 - 1;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) ue[k] = ux[k] = uy[k] = ur[k] = zz[k] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            se[k] = sx[k] = sy[k] = sr[k] = 0.0;
+            ause[k] = ausx[k] = ausy[k] = 0.0;
+            fse[k] = fsx[k] = fsy[k] = 0.0;
+            dby[k] = 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) ade[k] = adx[k] = ady[k] = azp[k] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) une[k] = unx[k] = uny[k] = dbx[k] = atx[k] = aty[k] = 0.0;
+        // iterations j0-3 .. j0+2 fill the pipeline; from j0+3 on, iteration
+        // R forms lambda^n of row R-3 (stored by the next iteration).  (Leaving
+        // the unneeded phases out of the filling iterations was measured
+        // slower: the extra code raises the main loop's register pressure.)
+        prefetch(j0 - 3);
+        for (int R = j0 - 3; R <= j1 + 2; ++R) iter(R);
+        store_previous(j1 + 3);
+    }
+};
+
+// Strips holding an edge column: strip 0 and strips from `se` on (a lane of
+// strip s sits in column 58 s - 4 + lane).
+__host__ __device__ inline int march_first_east_strip(int nx) {
+    const int v = nx - (kWave - 4);
+    return v <= 0 ? 0 : (v + kMarchOutW - 1) / kMarchOutW;
+}
+
+// Tiles: strip 0 in chunks of He rows, the interior strips in chunks of H,
+// the east edge strips in chunks of He (an edge strip's iteration costs more,
+// so its chunks are shorter and its waves end with the others).
+struct MarchTiles {
+    int H, He, gy, gye, strips, se;
+    __host__ __device__ int count() const {
+        return se <= 1 ? strips * gye : gye + (se - 1) * gy + (strips - se) * gye;
+    }
 };
 
 template <bool HOBS>
 __global__ void __launch_bounds__(kWave, 1)
-k_adj_march(AdjointArgs a, const int* gmap, const double* hobs, int H, int gy, int lout, int zout) {
-    AdjMarch<HOBS> M(a, gmap, hobs);
-    M.d = pad_of(a.P);
-    M.LIN = wk(a, M.d, a.lam_slot);
-    M.AZI = wk(a, M.d, a.azp_slot);
-    M.LOUT = wk(a, M.d, lout);
-    M.AZO = wk(a, M.d, zout);
-    M.GZ = wk(a, M.d, W_GZ);
-    M.GN = wk(a, M.d, W_GN);
-    M.hdry = a.P.h_dry;
-    M.hg = 0.5 * a.P.g;
-    M.kap = a.P.kappa;
-    M.emax = a.P.eps_max;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int strip = tile / gy, chunk = tile % gy;
-    const int lane = threadIdx.x;
-    const int pc = strip * kMarchOutW - 3 + lane;   // padded column of the lane
-    M.i = pc - 1;
-    M.ii = min(max(M.i, 0), a.P.nx - 1);
-    M.ic = min(max(M.i, -1), a.P.nx);
-    M.colOut = lane >= 3 && lane < 3 + kMarchOutW && pc <= a.P.nx + 1;
-    const int py0 = chunk * H, py1 = min(py0 + H, a.P.ny + 2);
-    M.j0 = py0 - 1;
-    M.j1 = py1 - 1;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) M.ue[k] = M.ux[k] = M.uy[k] = M.uh[k] = M.ur[k] = M.zz[k] = 0.0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        M.se[k] = M.sx[k] = M.sy[k] = M.sh[k] = M.sr[k] = 0.0;
-        M.abe[k] = M.abx[k] = M.aby[k] = 0.0;
-        M.ause[k] = M.ausx[k] = M.ausy[k] = 0.0;
-        M.fse[k] = M.fsx[k] = M.fsy[k] = 0.0;
-        M.dbx[k] = M.dby[k] = M.atx[k] = M.aty[k] = 0.0;
+k_adj_march(AdjointArgs a, const int* gmap, const double* hobs, MarchTiles T, int lout, int zout) {
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    int strip, chunk, H;
+    if (T.se <= 1) {
+        strip = t / T.gye; chunk = t % T.gye; H = T.He;
+    } else if (t < T.gye) {
+        strip = 0; chunk = t; H = T.He;
+    } else if (t < T.gye + (T.se - 1) * T.gy) {
+        strip = 1 + (t - T.gye) / T.gy; chunk = (t - T.gye) % T.gy; H = T.H;
+    } else {
+        const int u = t - T.gye - (T.se - 1) * T.gy;
+        strip = T.se + u / T.gye; chunk = u % T.gye; H = T.He;
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) M.ade[k] = M.adx[k] = M.ady[k] = M.azp[k] = 0.0;
-#pragma unroll
-    for (int k = 0; k < 2; ++k) M.une[k] = M.unx[k] = M.uny[k] = 0.0;
-    // rows j0-3 .. j0-1 fill the pipeline; row R's iteration writes lambda^n
-    // of row R-3
-    const int i0 = M.i - lane;   // column of lane 0
-    M.edgeStrip = i0 <= 0 || i0 + kWave - 1 >= a.P.nx - 1;
-    M.prefetch(M.j0 - 3);
-    for (int R = M.j0 - 3; R <= M.j1 + 2; ++R) M.iter(R);
-    M.store_previous(M.j1 + 3);
+    const int lane = threadIdx.x;
+    if (strip == 0 || strip >= T.se) {
+        AdjMarch<HOBS, true> M(a, gmap, hobs);
+        M.run(lane, strip, chunk, H, lout, zout);
+    } else {
+        AdjMarch<HOBS, false> M(a, gmap, hobs);
+        M.run(lane, strip, chunk, H, lout, zout);
+    }
 }
 
 inline dim3 grid2(int w, int h) { return dim3((w + kBX - 1) / kBX, (h + kBY - 1) / kBY); }
@@ -1207,27 +1284,52 @@ hipError_t launch_adjoint_step(const AdjointArgs& a, const int* gmap, const doub
     return hipGetLastError();
 }
 
+namespace {
+
+// Edge strips' rows cost about 1.45 interior rows (measured on 1024 x 1024);
+// every chunk also pays 6 rows of pipeline fill.
+MarchTiles march_tiles(const Params& P, int H) {
+    MarchTiles T;
+    T.H = H;
+    T.He = std::max(4, (int)std::lround((H + 6) / 1.45) - 6);
+    T.strips = (P.nx + 2 + kMarchOutW - 1) / kMarchOutW;
+    T.se = std::min(march_first_east_strip(P.nx), T.strips);
+    T.gy = (P.ny + 2 + T.H - 1) / T.H;
+    T.gye = (P.ny + 2 + T.He - 1) / T.He;
+    return T;
+}
+
+}  // namespace
+
+bool adjoint_march_fits(const Params& P) {
+    // the march addresses its arrays by 32-bit byte offsets: three padded
+    // fields from one base, and one pitched field
+    const double pad = (double)(P.nx + 2) * (double)(P.ny + 2) * 8.0;
+    const double pit = (double)P.ny * (double)P.pitch * 8.0;
+    return 3.0 * pad < 4294967296.0 && pit < 4294967296.0;
+}
+
 int adjoint_march_rows(const Params& P, int ncu) {
-    // about one wave per SIMD (four per compute unit), chunks of 8 .. 256 rows
-    const long long strips = (P.nx + 2 + kMarchOutW - 1) / kMarchOutW;
-    const long long waves = 4LL * std::max(ncu, 1);
-    long long H = ((long long)(P.ny + 2) * strips + waves - 1) / waves;
-    return (int)std::min<long long>(256, std::max<long long>(8, H));
+    // the smallest chunk height (8 .. 256) whose tiles fit one wave per SIMD
+    // (four per compute unit) in one round
+    const long long slots = 4LL * std::max(ncu, 1);
+    int H = 8;
+    while (H < 256 && march_tiles(P, H).count() > slots) ++H;
+    return H;
 }
 
 hipError_t launch_adjoint_march(const AdjointArgs& a, const int* gmap, const double* hobs, int H,
                                 hipStream_t s) {
     if (H < 1) return hipErrorInvalidValue;
-    const int strips = (a.P.nx + 2 + kMarchOutW - 1) / kMarchOutW;
-    const int gy = (a.P.ny + 2 + H - 1) / H;
+    const MarchTiles T = march_tiles(a.P, H);
     const int lout = a.lam_slot == kAdjLamSlot[0] ? kAdjLamSlot[1] : kAdjLamSlot[0];
     const int zout = a.azp_slot == kAdjZpSlot[0] ? kAdjZpSlot[1] : kAdjZpSlot[0];
     if (hobs)
-        hipLaunchKernelGGL(k_adj_march<true>, dim3(strips * gy), dim3(kWave), 0, s, a, gmap,
-                           hobs, H, gy, lout, zout);
+        hipLaunchKernelGGL(k_adj_march<true>, dim3(T.count()), dim3(kWave), 0, s, a, gmap, hobs,
+                           T, lout, zout);
     else
-        hipLaunchKernelGGL(k_adj_march<false>, dim3(strips * gy), dim3(kWave), 0, s, a, gmap,
-                           hobs, H, gy, lout, zout);
+        hipLaunchKernelGGL(k_adj_march<false>, dim3(T.count()), dim3(kWave), 0, s, a, gmap,
+                           hobs, T, lout, zout);
     return hipGetLastError();
 }
 

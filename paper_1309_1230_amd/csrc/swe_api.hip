@@ -803,7 +803,8 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
     // gather kernels (SWE_ADJOINT=gather in the environment); both give the
     // same bits
     const char* adj_env = std::getenv("SWE_ADJOINT");
-    const bool march = !(adj_env && std::strcmp(adj_env, "gather") == 0);
+    const bool march =
+        !(adj_env && std::strcmp(adj_env, "gather") == 0) && swe::adjoint_march_fits(h->P);
     int march_rows = 0;
     if (march) {
         int cus = 0;

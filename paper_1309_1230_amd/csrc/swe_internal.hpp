@@ -161,6 +161,9 @@ hipError_t launch_adjoint_march(const AdjointArgs& a, const int* gmap, const dou
 // Chunk height of the reverse march for a grid on a device with ncu compute
 // units.
 int adjoint_march_rows(const Params& P, int ncu);
+// Whether the reverse march can address the grid's arrays (below about
+// 13000 x 13000 cells); launch_adjoint_step serves the others.
+bool adjoint_march_fits(const Params& P);
 // Completes the last step reversed (lambda and dJ/dz of its ghost ring).
 hipError_t launch_adjoint_finish(const AdjointArgs& a, hipStream_t s);
 // gmap[j*nx + i] = gauge index of cell (i, j), or -1 (nx*ny ints).
