@@ -168,8 +168,11 @@ def adjoint_ratio(torch, swe, W, nx, nsteps, ckpt):
         obs.append(s.eta.reshape(-1)[cells] - zc)
     hobs = torch.stack(obs).contiguous()
     s.close()
+    # warm-up of both paths (kernel code objects, the binding's first torch
+    # calls): 20 forward steps and a 20-step gradient
     w = swe.Solver.from_problem(p, dtype=torch.float64)
     w.run(20)
+    w.grad(20, c.cells, c.obs_every, hobs[: 20 // c.obs_every].contiguous(), ckpt)
     w.close()
     f = swe.Solver.from_problem(p, dtype=torch.float64)
     torch.cuda.synchronize()

@@ -229,7 +229,8 @@ typedef struct swe_gauges {
  * environment forces the replay).  ckpt_every = 0: an FP64 handle keeps the
  * whole trajectory (U^n, U* and U^d of every step, 9 fields per step) when it
  * fits in three quarters of the free device memory, and then recomputes
- * nothing; otherwise, and for FP32 handles, the spacing is
+ * nothing; the buffer stays with the handle for later calls and is released
+ * by swe_destroy.  Otherwise, and for FP32 handles, the spacing is
  * round(sqrt(nsteps)).  The reverse step runs as one fused march
  * (SWE_ADJOINT=gather in the environment selects four gather kernels
  * instead).  The gradient is the same bit for bit in every one of these

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -42,6 +43,11 @@ struct swe_handle {
     void* trace = nullptr;     // unfused scratch: 47 padded arrays + zp + mp
     unsigned* dry = nullptr;   // dry-tile skip flags (2 * nparts words), or NULL
     void* fpart = nullptr;     // fused path: tile and group records, group tickets
+    // swe_grad's kept trajectory (U^n, U*, U^d of every step), kept for the
+    // next call: freeing a large buffer that kernels have written costs tens
+    // of milliseconds per 100 GB, and more when another such free is pending
+    void* traj = nullptr;
+    size_t traj_bytes = 0;
     long long step_host = 0;
     std::string err;
 };
@@ -456,6 +462,7 @@ void swe_destroy(swe_handle* h) {
     if (h->trace) (void)hipFree(h->trace);
     if (h->dry) (void)hipFree(h->dry);
     if (h->fpart) (void)hipFree(h->fpart);
+    if (h->traj) (void)hipFree(h->traj);
     delete h;
 }
 
@@ -614,6 +621,16 @@ template <typename T>
 int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_every,
               double* loss, void* dJ_dn, void* dJ_dz) {
     constexpr bool mixed = sizeof(T) == 4;
+    // SWE_VERBOSE=1 in the environment: lines on stderr with the elapsed time
+    // after the set-up, the forward run, each reverse segment and the end
+    // (each waits for the device)
+    const char* verbose_env = std::getenv("SWE_VERBOSE");
+    const bool verbose = verbose_env && verbose_env[0] == '1';
+    const auto t_start = std::chrono::steady_clock::now();
+    auto ms_since = [](std::chrono::steady_clock::time_point t0) {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+            .count();
+    };
     const int64_t nobs = nsteps / g->obs_every;
     const int ng = g->ngauge;
     int rc = fill_stats(h, nullptr);
@@ -630,15 +647,29 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
     // the free device memory: the forward run writes it, and the reverse
     // sweep recomputes nothing.  Otherwise, and for FP32 handles, checkpoints
     // every round(sqrt(nsteps)) steps.
-    DevBuf traj;
     bool store_all = false;
     if (ckpt_every == 0 && !mixed && nsteps > 0) {
-        size_t freeb = 0, totalb = 0;
-        const double need = (double)nsteps * 9.0 * (double)fe * sizeof(double);
-        if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && need <= 0.75 * (double)freeb)
-            store_all = traj.alloc((size_t)nsteps * 9 * fe * sizeof(double)) == hipSuccess;
-        (void)hipGetLastError();
+        const size_t need = (size_t)nsteps * 9 * fe * sizeof(double);
+        if (h->traj_bytes >= need) {
+            store_all = true;
+        } else {
+            size_t freeb = 0, totalb = 0;
+            if (hipMemGetInfo(&freeb, &totalb) == hipSuccess &&
+                (double)need <= 0.75 * (double)(freeb + h->traj_bytes)) {
+                if (h->traj) (void)hipFree(h->traj);
+                h->traj = nullptr;
+                h->traj_bytes = 0;
+                if (hipMalloc(&h->traj, need) == hipSuccess) {
+                    h->traj_bytes = need;
+                    store_all = true;
+                } else {
+                    h->traj = nullptr;
+                }
+            }
+            (void)hipGetLastError();
+        }
     }
+    double* const traj_base = (double*)h->traj;
     const int64_t spacing =
         ckpt_every > 0 ? ckpt_every
                        : std::max<int64_t>(1, (int64_t)std::llround(std::sqrt((double)nsteps)));
@@ -700,11 +731,15 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
         e = swe::launch_gauge_map(h->P, (const long long*)dcells.p, ng, (int*)gmap.p, h->stream);
     double* dtlog = logs.d();
     double* tlog = logs.d() + std::max<int64_t>(nsteps, 1);
+    if (verbose) {
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        std::fprintf(stderr, "swe_grad: %.1f ms: set-up done\n", ms_since(t_start));
+    }
     auto slot = [&](void* base, int64_t m, T* U[3]) {
         for (int f = 0; f < 3; ++f) U[f] = (T*)base + ((size_t)m * 3 + f) * fe;
     };
     // the kept trajectory: step k holds U^k, then U*, then U^d
-    auto traj_state = [&](int64_t k, int f) { return traj.d() + ((size_t)k * 9 + f) * fe; };
+    auto traj_state = [&](int64_t k, int f) { return traj_base + ((size_t)k * 9 + f) * fe; };
     // ---- forward: the run itself, with checkpoints, time steps and misfits
     if (e == hipSuccess) e = begin_call(h, h->stream);
     if constexpr (!mixed) {
@@ -814,18 +849,16 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
         (void)hipGetLastError();
         march_rows = swe::adjoint_march_rows(h->P, cus);
     }
-    // SWE_VERBOSE=1 in the environment: a line on stderr after the forward run
-    // and after each reverse segment (each waits for the device)
-    const char* verbose_env = std::getenv("SWE_VERBOSE");
-    const bool verbose = verbose_env && verbose_env[0] == '1';
     if (verbose)
-        std::fprintf(stderr, "swe_grad: forward run of %lld steps done, %lld reverse segments\n",
-                     (long long)nsteps, (long long)nseg);
+        std::fprintf(stderr,
+                     "swe_grad: %.1f ms: forward run of %lld steps done, %lld reverse segments%s\n",
+                     ms_since(t_start), (long long)nsteps, (long long)nseg,
+                     store_all ? " (trajectory kept)" : "");
     for (int64_t sg = nseg - 1; sg >= 0 && e == hipSuccess; --sg) {
         if (verbose && sg < nseg - 1) {
             e = hipStreamSynchronize(h->stream);
-            std::fprintf(stderr, "swe_grad: reverse segment %lld of %lld done\n",
-                         (long long)(nseg - 1 - sg), (long long)nseg);
+            std::fprintf(stderr, "swe_grad: %.1f ms: reverse segment %lld of %lld done\n",
+                         ms_since(t_start), (long long)(nseg - 1 - sg), (long long)nseg);
             if (e != hipSuccess) break;
         }
         const int64_t s0 = sg * C, s1 = std::min(s0 + C, nsteps);
@@ -961,6 +994,7 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
         e = swe::launch_unpad(h->P, work.d() + (size_t)swe::kAdjGradZ * Npad, (double*)dJ_dz, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "swe_grad: reverse sweep");
+    if (verbose) std::fprintf(stderr, "swe_grad: %.1f ms: reverse sweep done\n", ms_since(t_start));
     *loss = J;
     return SWE_OK;
 }
@@ -990,8 +1024,16 @@ int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_ev
     if (!is_device_ptr(dJ_dn, h->device) || !is_device_ptr(dJ_dz, h->device) ||
         (ng > 0 && nobs > 0 && !is_device_ptr(g->hobs, h->device)))
         return fail(h, SWE_EINVAL, "swe_grad: gradients and observations must be device memory");
-    return h->dtype == SWE_F32 ? grad_impl<float>(h, nsteps, g, ckpt_every, loss, dJ_dn, dJ_dz)
-                               : grad_impl<double>(h, nsteps, g, ckpt_every, loss, dJ_dn, dJ_dz);
+    const auto t0 = std::chrono::steady_clock::now();
+    const int rc = h->dtype == SWE_F32
+                       ? grad_impl<float>(h, nsteps, g, ckpt_every, loss, dJ_dn, dJ_dz)
+                       : grad_impl<double>(h, nsteps, g, ckpt_every, loss, dJ_dn, dJ_dz);
+    const char* verbose_env = std::getenv("SWE_VERBOSE");
+    if (verbose_env && verbose_env[0] == '1')
+        std::fprintf(stderr, "swe_grad: %.1f ms: returned (scratch freed)\n",
+                     std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                         .count());
+    return rc;
 }
 
 }  // extern "C"
