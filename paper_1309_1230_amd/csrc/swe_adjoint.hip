@@ -759,29 +759,85 @@ __device__ __forceinline__ bool padded_ok(const Pad& d, int i, int j) {
 // vector (zero off the interior).
 struct Nbr { Cell c; double z, a0, a1, a2; };
 
-// gather_faces from values: the faces of padded cell (i, j) in the same
-// order, with the same face rules.  EDGE = false: column i and its x
-// neighbours are interior, so every x face is an interior face.
-template <bool EDGE>
-__device__ __forceinline__ CellBar gather_values(const Params& P, int i, int j, const Cell& me,
-                                                 double zme, double am0, double am1, double am2,
-                                                 const Nbr& E, const Nbr& W, const Nbr& N,
-                                                 const Nbr& S, int dir, double rx, double ry,
-                                                 double hdry, double hg) {
-    CellBar cb = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (j >= 0 && j < P.ny) {
-        if (!EDGE || (i >= -1 && i <= P.nx - 1)) {   // face i: this cell is L
-            const FaceBar fb = face_bar_v(am0, am1, am2, E.a0, E.a1, E.a2, rx, dir, true);
-            face_flux_adjoint(fb, EDGE ? xface_kind(P, i, j) : -1, dir, EDGE && i == P.nx - 1,
-                              true, true, me, E.c, zme, E.z, hdry, hg, cb);
-        }
-        if (!EDGE || (i - 1 >= -1 && i - 1 <= P.nx - 1)) {   // face i-1: this cell is R
-            const FaceBar fb = face_bar_v(W.a0, W.a1, W.a2, am0, am1, am2, rx, dir, true);
-            face_flux_adjoint(fb, EDGE ? xface_kind(P, i - 1, j) : -1, dir,
-                              EDGE && i - 1 == P.nx - 1, false, true, W.c, me, W.z, zme, hdry,
-                              hg, cb);
-        }
+// The terms an x face passes to the cell east of it (the only fields an x
+// face changes).
+struct XDelta { double e, qx, u, v, h; };
+
+// face_flux_adjoint of an x face for both of its cells at once: the west
+// cell's terms are added to cb, the east cell's are returned in d (started
+// at zero), with the expressions of face_flux_adjoint for me_is_L true and
+// false.
+__device__ __forceinline__ void xface_both(const FaceBar& fb, int kind, int dir, bool ghost_is_R,
+                                           const Cell& L, const Cell& R, double zL, double zR,
+                                           double hdry, double hg, CellBar& cb, XDelta& d) {
+    if (kind == BC_WALL) return;
+    bool dnR, pass;
+    if (kind == BC_INFLOW) {
+        dnR = ghost_is_R;
+        pass = true;
+    } else {
+        dnR = dir > 0;
+        pass = (dnR ? R.h : L.h) > hdry;
     }
+    const Cell& D = dnR ? R : L;
+    const double fm = pass ? D.qx : 0.0;
+    const double fmb = (fb.m + fb.x * D.u) + fb.y * D.v;
+    if (dnR) {
+        d.u += fb.x * fm;
+        d.v += fb.y * fm;
+        if (pass) d.qx += fmb;
+    } else {
+        cb.u += fb.x * fm;
+        cb.v += fb.y * fm;
+        if (pass) cb.qx += fmb;
+    }
+    if (kind >= 0) return;   // boundary faces carry no pressure
+    const bool wetL = L.h > hdry, wetR = R.h > hdry;
+    const bool bank = (!wetL && zL > R.e) || (!wetR && zR > L.e);
+    if (bank) return;
+    const double A = hg * (hpos(L.h) + hpos(R.h));
+    const double del = R.e - L.e;
+    const double Ab = fb.p * del, delb = fb.p * A;
+    const double Sb = Ab * hg;
+    cb.e -= delb;
+    cb.h += L.h > 0.0 ? Sb : 0.0;
+    d.e += delb;
+    d.h += R.h > 0.0 ? Sb : 0.0;
+}
+
+// The x faces of padded cell (i, j) in gather_faces' order: face i (this
+// cell west of it, computed here) then face i-1 (computed by the west lane,
+// its east terms shifted in).  Every lane of the wave must call it (a DPP
+// shift).  EDGE = false: column i and its x neighbours are interior.
+template <bool EDGE>
+__device__ __forceinline__ void x_faces(const Params& P, int i, int j, const Cell& me, double zme,
+                                        double am0, double am1, double am2, const Nbr& E, int dir,
+                                        double rx, double hdry, double hg, CellBar& cb) {
+    if (!(j >= 0 && j < P.ny)) return;   // uniform: rows -1 and ny have no x faces
+    XDelta d = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (!EDGE || (i >= -1 && i <= P.nx - 1)) {
+        const FaceBar fb = face_bar_v(am0, am1, am2, E.a0, E.a1, E.a2, rx, dir, true);
+        xface_both(fb, EDGE ? xface_kind(P, i, j) : -1, dir, EDGE && i == P.nx - 1, me, E.c, zme,
+                   E.z, hdry, hg, cb, d);
+    }
+    const double we = from_west(d.e), wqx = from_west(d.qx), wu = from_west(d.u),
+                 wv = from_west(d.v), wh = from_west(d.h);
+    if (!EDGE || (i - 1 >= -1 && i - 1 <= P.nx - 1)) {
+        cb.u += wu;
+        cb.v += wv;
+        cb.qx += wqx;
+        cb.e += we;
+        cb.h += wh;
+    }
+}
+
+// The y faces of padded cell (i, j), after its x faces, in gather_faces'
+// order and with its face rules.
+template <bool EDGE>
+__device__ __forceinline__ void y_faces(const Params& P, int i, int j, const Cell& me, double zme,
+                                        double am0, double am1, double am2, const Nbr& N,
+                                        const Nbr& S, int dir, double ry, double hdry, double hg,
+                                        CellBar& cb) {
     if (!EDGE || (i >= 0 && i < P.nx)) {
         if (j >= -1 && j <= P.ny - 1) {
             const FaceBar fb = face_bar_v(am0, am1, am2, N.a0, N.a1, N.a2, ry, dir, false);
@@ -794,11 +850,10 @@ __device__ __forceinline__ CellBar gather_values(const Params& P, int i, int j, 
                               S.c, me, S.z, zme, hdry, hg, cb);
         }
     }
-    return cb;
 }
 
-// The neighbour in the lane to the east (lane + 1), to the west, or in this
-// lane (another row).  Depths are formed as e - z from the carried values,
+// The neighbour in the lane to the east (lane + 1) or in this lane (another
+// row).  Depths are formed as e - z from the carried values,
 // the expression the cell was built with.
 __device__ __forceinline__ Nbr nbr_east(double e, double qx, double qy, double r, double z,
                                         double a0, double a1, double a2) {
@@ -809,17 +864,6 @@ __device__ __forceinline__ Nbr nbr_east(double e, double qx, double qy, double r
     n.a0 = from_east(a0);
     n.a1 = from_east(a1);
     n.a2 = from_east(a2);
-    return n;
-}
-__device__ __forceinline__ Nbr nbr_west(double e, double qx, double qy, double r, double z,
-                                        double a0, double a1, double a2) {
-    Nbr n;
-    const double ew = from_west(e), zw = from_west(z);
-    n.c = carried_cell(ew, from_west(qx), from_west(qy), ew - zw, from_west(r));
-    n.z = zw;
-    n.a0 = from_west(a0);
-    n.a1 = from_west(a1);
-    n.a2 = from_west(a2);
     return n;
 }
 __device__ __forceinline__ Nbr nbr_here(double e, double qx, double qy, double r, double z,
@@ -1028,16 +1072,17 @@ struct AdjMarch {
             const int j = R - 1;
             const double b0 = 0.5 * ade[1], b1 = 0.5 * adx[1], b2 = 0.5 * ady[1];
             const Nbr E = nbr_east(se[1], sx[1], sy[1], sr[1], zz[1], b0, b1, b2);
-            const Nbr W = nbr_west(se[1], sx[1], sy[1], sr[1], zz[1], b0, b1, b2);
+            const Cell me = carried_cell(se[1], sx[1], sy[1], se[1] - zz[1], sr[1]);
+            CellBar cb = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            x_faces<EDGE>(a.P, i, j, me, zz[1], b0, b1, b2, E, -a.sigma, a.rx, hdry, hg, cb);
             double eb = 0.0, qxb = 0.0, qyb = 0.0;
             if (pad_ok(j)) {
                 const Nbr N = nbr_here(se[0], sx[0], sy[0], sr[0], zz[0], 0.5 * ade[0],
                                        0.5 * adx[0], 0.5 * ady[0]);
                 const Nbr S = nbr_here(se[2], sx[2], sy[2], sr[2], zz[2], 0.5 * ade[2],
                                        0.5 * adx[2], 0.5 * ady[2]);
-                const Cell me = carried_cell(se[1], sx[1], sy[1], se[1] - zz[1], sr[1]);
-                const CellBar cb = gather_values<EDGE>(a.P, i, j, me, zz[1], b0, b1, b2, E, W, N,
-                                                       S, -a.sigma, a.rx, a.ry, hdry, hg);
+                y_faces<EDGE>(a.P, i, j, me, zz[1], b0, b1, b2, N, S, -a.sigma, a.ry, hdry, hg,
+                              cb);
                 const bool inC = in(i, j);
                 eb = cb.e + (inC ? b0 : 0.0);
                 qxb = cb.qx + (inC ? b1 : 0.0);
@@ -1138,16 +1183,17 @@ struct AdjMarch {
         {
             const int j = R - 3;
             const Nbr E = nbr_east(ue[3], ux[3], uy[3], ur[3], zz[3], fse[1], fsx[1], fsy[1]);
-            const Nbr W = nbr_west(ue[3], ux[3], uy[3], ur[3], zz[3], fse[1], fsx[1], fsy[1]);
             const double dbW = from_west(dbx[1]), dbE = from_east(dbx[1]);
+            const Cell me = carried_cell(ue[3], ux[3], uy[3], ue[3] - zz[3], ur[3]);
+            CellBar cb = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            x_faces<EDGE>(a.P, i, j, me, zz[3], fse[1], fsx[1], fsy[1], E, a.sigma, a.rx, hdry, hg,
+                          cb);
             o_e2 = colOut && j >= j0 && j < j1 && pad_ok(j);
             if (o_e2) {
                 const Nbr N = nbr_here(ue[2], ux[2], uy[2], ur[2], zz[2], fse[0], fsx[0], fsy[0]);
                 const Nbr S = nbr_here(ue[4], ux[4], uy[4], ur[4], zz[4], fse[2], fsx[2], fsy[2]);
-                const Cell me = carried_cell(ue[3], ux[3], uy[3], ue[3] - zz[3], ur[3]);
-                const CellBar cb = gather_values<EDGE>(a.P, i, j, me, zz[3], fse[1], fsx[1],
-                                                       fsy[1], E, W, N, S, a.sigma, a.rx, a.ry,
-                                                       hdry, hg);
+                y_faces<EDGE>(a.P, i, j, me, zz[3], fse[1], fsx[1], fsy[1], N, S, a.sigma, a.ry,
+                              hdry, hg, cb);
                 const bool inC = in(i, j);
                 double eb = cb.e, qxb = cb.qx, qyb = cb.qy;
                 if (inC) {
