@@ -82,8 +82,9 @@ struct Cell { double e, qx, qy, h, r, u, v; };
 // kW, kE: kinds of the west and east boundary faces of row j.  (Every edge
 // index here is a constant: a per-thread index into the parameter block would
 // make the compiler read it through vector memory.)
-// XEDGE = false: the caller knows that i is an interior column.
-template <bool XEDGE = true>
+// XEDGE = false: the caller knows that i is an interior column; YEDGE =
+// false: that j is an interior row.
+template <bool XEDGE = true, bool YEDGE = true>
 __device__ __forceinline__ Cell make_cell(const Params& P, double e, double qx, double qy,
                                           double qin, int i, int j, double zpv, int kW, int kE) {
     Cell c;
@@ -92,7 +93,7 @@ __device__ __forceinline__ Cell make_cell(const Params& P, double e, double qx, 
     c.qy = qy;
     if (XEDGE && (i < 0 || i >= P.nx))
         ghost(i < 0 ? kW : kE, true, i < 0 ? qin : -qin, c.e, c.qx, c.qy, c.e, c.qx, c.qy);
-    else if (j < 0 || j >= P.ny)
+    else if (YEDGE && (j < 0 || j >= P.ny))
         ghost(j < 0 ? face_kind(P, EDGE_S, i) : face_kind(P, EDGE_N, i), false,
               j < 0 ? qin : -qin, c.e, c.qx, c.qy, c.e, c.qx, c.qy);
     c.h = c.e - zpv;
@@ -809,11 +810,11 @@ __device__ __forceinline__ void xface_both(const FaceBar& fb, int kind, int dir,
 // cell west of it, computed here) then face i-1 (computed by the west lane,
 // its east terms shifted in).  Every lane of the wave must call it (a DPP
 // shift).  EDGE = false: column i and its x neighbours are interior.
-template <bool EDGE>
+template <bool EDGE, bool BND>
 __device__ __forceinline__ void x_faces(const Params& P, int i, int j, const Cell& me, double zme,
                                         double am0, double am1, double am2, const Nbr& E, int dir,
                                         double rx, double hdry, double hg, CellBar& cb) {
-    if (!(j >= 0 && j < P.ny)) return;   // uniform: rows -1 and ny have no x faces
+    if (BND && !(j >= 0 && j < P.ny)) return;   // uniform: rows -1 and ny have no x faces
     XDelta d = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (!EDGE || (i >= -1 && i <= P.nx - 1)) {
         const FaceBar fb = face_bar_v(am0, am1, am2, E.a0, E.a1, E.a2, rx, dir, true);
@@ -832,22 +833,24 @@ __device__ __forceinline__ void x_faces(const Params& P, int i, int j, const Cel
 }
 
 // The y faces of padded cell (i, j), after its x faces, in gather_faces'
-// order and with its face rules.
-template <bool EDGE>
+// order and with its face rules.  BND = false: rows j-1 .. j+1 are interior,
+// so both y faces are interior faces.
+template <bool EDGE, bool BND>
 __device__ __forceinline__ void y_faces(const Params& P, int i, int j, const Cell& me, double zme,
                                         double am0, double am1, double am2, const Nbr& N,
                                         const Nbr& S, int dir, double ry, double hdry, double hg,
                                         CellBar& cb) {
     if (!EDGE || (i >= 0 && i < P.nx)) {
-        if (j >= -1 && j <= P.ny - 1) {
+        if (!BND || (j >= -1 && j <= P.ny - 1)) {
             const FaceBar fb = face_bar_v(am0, am1, am2, N.a0, N.a1, N.a2, ry, dir, false);
-            face_flux_adjoint(fb, yface_kind(P, i, j), dir, j == P.ny - 1, true, false, me, N.c,
-                              zme, N.z, hdry, hg, cb);
+            face_flux_adjoint(fb, BND ? yface_kind(P, i, j) : -1, dir, BND && j == P.ny - 1, true,
+                              false, me, N.c, zme, N.z, hdry, hg, cb);
         }
-        if (j - 1 >= -1 && j - 1 <= P.ny - 1) {
+        if (!BND || (j - 1 >= -1 && j - 1 <= P.ny - 1)) {
             const FaceBar fb = face_bar_v(S.a0, S.a1, S.a2, am0, am1, am2, ry, dir, false);
-            face_flux_adjoint(fb, yface_kind(P, i, j - 1), dir, j - 1 == P.ny - 1, false, false,
-                              S.c, me, S.z, zme, hdry, hg, cb);
+            face_flux_adjoint(fb, BND ? yface_kind(P, i, j - 1) : -1, dir,
+                              BND && j - 1 == P.ny - 1, false, false, S.c, me, S.z, zme, hdry,
+                              hg, cb);
         }
     }
 }
@@ -955,11 +958,16 @@ struct AdjMarch {
         for (int k = K - 1; k > 0; --k) x[k] = x[k - 1];
     }
 
+    // BND = false: every row an iteration touches is interior (1 .. ny-2),
+    // so the row tests are compiled out as well
     __device__ __forceinline__ bool col_in(int x) const { return !EDGE || (x >= 0 && x < d.nx); }
+    template <bool BND>
     __device__ __forceinline__ bool in(int x, int y) const {
-        return col_in(x) && y >= 0 && y < d.ny;
+        return col_in(x) && (!BND || (y >= 0 && y < d.ny));
     }
+    template <bool BND>
     __device__ __forceinline__ bool pad_ok(int y) const {
+        if (!BND) return !EDGE || (i >= -1 && i <= d.nx);
         return EDGE ? padded_ok(d, i, y) : (y >= -1 && y <= d.ny);
     }
 
@@ -980,6 +988,7 @@ struct AdjMarch {
 
     // Iteration R forms row R of kernel A's work, row R-1 of C, row R-2 of
     // the fold and E1 and row R-3 of E2.
+    template <bool BND>
     __device__ __forceinline__ void iter(int R) {
         const MarchRow q = pf;
         store_previous(R);
@@ -1000,11 +1009,11 @@ struct AdjMarch {
         // ---- ingest row R: U^n and U* cells (ghost rule, primitives), bed
         zz[0] = q.z;
         {
-            const Cell c = make_cell<EDGE>(a.P, q.ue, q.ux, q.uy, a.qin0, i, R, q.z, kW, kE);
+            const Cell c = make_cell<EDGE, BND>(a.P, q.ue, q.ux, q.uy, a.qin0, i, R, q.z, kW, kE);
             ue[0] = c.e; ux[0] = c.qx; uy[0] = c.qy; ur[0] = c.r;
         }
         {
-            const Cell c = make_cell<EDGE>(a.P, q.se, q.sx, q.sy, a.qin1, i, R, q.z, kW, kE);
+            const Cell c = make_cell<EDGE, BND>(a.P, q.se, q.sx, q.sy, a.qin1, i, R, q.z, kW, kE);
             se[0] = c.e; sx[0] = c.qx; sy[0] = c.qy; sr[0] = c.r;
         }
 
@@ -1023,16 +1032,16 @@ struct AdjMarch {
             double o0 = 0.0, o1 = 0.0, o2 = 0.0, oz = 0.0;
             o_fa = false;
             o_wet = false;
-            if (in(i, R)) {
+            if (in<BND>(i, R)) {
                 double lam[3] = {q.l0, q.l1, q.l2};
                 if (EDGE && i == 0) fold_value(lw0, lw1, lw2, kW, true, lam);
                 if (EDGE && i == d.nx - 1) fold_value(le0, le1, le2, kE, true, lam);
-                if (R == 0) {
+                if (BND && R == 0) {
                     const long long g = d.at(i, -1);
                     fold_value(LIN[g], LIN[d.N + g], LIN[2 * d.N + g], face_kind(a.P, EDGE_S, i),
                                false, lam);
                 }
-                if (R == d.ny - 1) {
+                if (BND && R == d.ny - 1) {
                     const long long g = d.at(i, d.ny);
                     fold_value(LIN[g], LIN[d.N + g], LIN[2 * d.N + g], face_kind(a.P, EDGE_N, i),
                                false, lam);
@@ -1043,8 +1052,8 @@ struct AdjMarch {
                     double gzs = q.azi;
                     if (EDGE && i == 0) gzs += zw;
                     if (EDGE && i == d.nx - 1) gzs += ze;
-                    if (R == 0) gzs += AZI[d.at(i, -1)];
-                    if (R == d.ny - 1) gzs += AZI[d.at(i, d.ny)];
+                    if (BND && R == 0) gzs += AZI[d.at(i, -1)];
+                    if (BND && R == d.ny - 1) gzs += AZI[d.at(i, d.ny)];
                     gz = q.gz + gzs;
                 }
                 if (HOBS && q.gm >= 0) {
@@ -1074,16 +1083,16 @@ struct AdjMarch {
             const Nbr E = nbr_east(se[1], sx[1], sy[1], sr[1], zz[1], b0, b1, b2);
             const Cell me = carried_cell(se[1], sx[1], sy[1], se[1] - zz[1], sr[1]);
             CellBar cb = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            x_faces<EDGE>(a.P, i, j, me, zz[1], b0, b1, b2, E, -a.sigma, a.rx, hdry, hg, cb);
+            x_faces<EDGE, BND>(a.P, i, j, me, zz[1], b0, b1, b2, E, -a.sigma, a.rx, hdry, hg, cb);
             double eb = 0.0, qxb = 0.0, qyb = 0.0;
-            if (pad_ok(j)) {
+            if (pad_ok<BND>(j)) {
                 const Nbr N = nbr_here(se[0], sx[0], sy[0], sr[0], zz[0], 0.5 * ade[0],
                                        0.5 * adx[0], 0.5 * ady[0]);
                 const Nbr S = nbr_here(se[2], sx[2], sy[2], sr[2], zz[2], 0.5 * ade[2],
                                        0.5 * adx[2], 0.5 * ady[2]);
-                y_faces<EDGE>(a.P, i, j, me, zz[1], b0, b1, b2, N, S, -a.sigma, a.ry, hdry, hg,
+                y_faces<EDGE, BND>(a.P, i, j, me, zz[1], b0, b1, b2, N, S, -a.sigma, a.ry, hdry, hg,
                               cb);
-                const bool inC = in(i, j);
+                const bool inC = in<BND>(i, j);
                 eb = cb.e + (inC ? b0 : 0.0);
                 qxb = cb.qx + (inC ? b1 : 0.0);
                 qyb = cb.qy + (inC ? b2 : 0.0);
@@ -1107,14 +1116,14 @@ struct AdjMarch {
                 ee = from_east(ause[1]); ex = from_east(ausx[1]); ey = from_east(ausy[1]);
             }
             double v[3] = {0.0, 0.0, 0.0};
-            if (in(i, j)) {
+            if (in<BND>(i, j)) {
                 v[0] = ause[1]; v[1] = ausx[1]; v[2] = ausy[1];
                 if (EDGE && i == 0) fold_value(we, wx, wy, face_kind(a.P, EDGE_W, j), true, v);
                 if (EDGE && i == d.nx - 1)
                     fold_value(ee, ex, ey, face_kind(a.P, EDGE_E, j), true, v);
-                if (j == 0)
+                if (BND && j == 0)
                     fold_value(ause[2], ausx[2], ausy[2], face_kind(a.P, EDGE_S, i), false, v);
-                if (j == d.ny - 1)
+                if (BND && j == d.ny - 1)
                     fold_value(ause[0], ausx[0], ausy[0], face_kind(a.P, EDGE_N, i), false, v);
             }
             fse[0] = v[0]; fsx[0] = v[1]; fsy[0] = v[2];
@@ -1136,7 +1145,7 @@ struct AdjMarch {
             const double dW[3] = {from_west(ade[2]), from_west(adx[2]), from_west(ady[2])};
             double un[3] = {0.0, 0.0, 0.0};
             double dbxv = 0.0, atxv = 0.0, dbyv = 0.0, atyv = 0.0;
-            if (in(i, j)) {
+            if (in<BND>(i, j)) {
                 const double dC[3] = {ade[2], adx[2], ady[2]};
                 const double dN[3] = {ade[1], adx[1], ady[1]};
                 const double dS[3] = {ade[3], adx[3], ady[3]};
@@ -1151,7 +1160,7 @@ struct AdjMarch {
                     const bool xf = f < 2;
                     const int ni = xf ? (f == 0 ? i + 1 : i - 1) : i;
                     const int nj = xf ? j : (f == 2 ? j + 1 : j - 1);
-                    if (!in(ni, nj)) continue;   // boundary face: eps = 0
+                    if (!in<BND>(ni, nj)) continue;   // boundary face: eps = 0
                     const Cell& on = f == 0 ? cE : (f == 1 ? cW : (f == 2 ? cN : cS));
                     const double nuOn = f == 0 ? nuE : (f == 1 ? nuW : (f == 2 ? nuN : nuS));
                     const double* dn = f == 0 ? dE : (f == 1 ? dW : (f == 2 ? dN : dS));
@@ -1186,15 +1195,15 @@ struct AdjMarch {
             const double dbW = from_west(dbx[1]), dbE = from_east(dbx[1]);
             const Cell me = carried_cell(ue[3], ux[3], uy[3], ue[3] - zz[3], ur[3]);
             CellBar cb = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            x_faces<EDGE>(a.P, i, j, me, zz[3], fse[1], fsx[1], fsy[1], E, a.sigma, a.rx, hdry, hg,
+            x_faces<EDGE, BND>(a.P, i, j, me, zz[3], fse[1], fsx[1], fsy[1], E, a.sigma, a.rx, hdry, hg,
                           cb);
-            o_e2 = colOut && j >= j0 && j < j1 && pad_ok(j);
+            o_e2 = colOut && j >= j0 && j < j1 && pad_ok<BND>(j);
             if (o_e2) {
                 const Nbr N = nbr_here(ue[2], ux[2], uy[2], ur[2], zz[2], fse[0], fsx[0], fsy[0]);
                 const Nbr S = nbr_here(ue[4], ux[4], uy[4], ur[4], zz[4], fse[2], fsx[2], fsy[2]);
-                y_faces<EDGE>(a.P, i, j, me, zz[3], fse[1], fsx[1], fsy[1], N, S, a.sigma, a.ry,
+                y_faces<EDGE, BND>(a.P, i, j, me, zz[3], fse[1], fsx[1], fsy[1], N, S, a.sigma, a.ry,
                               hdry, hg, cb);
-                const bool inC = in(i, j);
+                const bool inC = in<BND>(i, j);
                 double eb = cb.e, qxb = cb.qx, qyb = cb.qy;
                 if (inC) {
                     eb += une[1] + fse[1];
@@ -1202,18 +1211,18 @@ struct AdjMarch {
                     qyb += uny[1] + fsy[1];
                 }
                 double rb = cb.u * me.qx + cb.v * me.qy;
-                if (in(i - 1, j)) eb += dbW;
+                if (in<BND>(i - 1, j)) eb += dbW;
                 if (inC) {
                     eb += -dbx[1] - dbx[1];
                     rb += atx[1];
                 }
-                if (in(i + 1, j)) eb += dbE;
-                if (in(i, j - 1)) eb += dby[2];
+                if (in<BND>(i + 1, j)) eb += dbE;
+                if (in<BND>(i, j - 1)) eb += dby[2];
                 if (inC) {
                     eb += -dby[1] - dby[1];
                     rb += aty[1];
                 }
-                if (in(i, j + 1)) eb += dby[0];
+                if (in<BND>(i, j + 1)) eb += dby[0];
                 const double h = me.h, r = me.r;
                 qxb += cb.u * r;
                 qyb += cb.v * r;
@@ -1266,7 +1275,12 @@ struct AdjMarch {
         // the unneeded phases out of the filling iterations was measured
         // slower: the extra code raises the main loop's register pressure.)
         prefetch(j0 - 3);
-        for (int R = j0 - 3; R <= j1 + 2; ++R) iter(R);
+        // rows that reach the domain's first or last two rows take the
+        // general iteration, the others the interior one
+        int R = j0 - 3;
+        for (; R <= j1 + 2 && R < 5; ++R) iter<true>(R);
+        for (; R <= j1 + 2 && R <= d.ny - 3; ++R) iter<false>(R);
+        for (; R <= j1 + 2; ++R) iter<true>(R);
         store_previous(j1 + 3);
     }
 };
@@ -1332,12 +1346,12 @@ hipError_t launch_adjoint_step(const AdjointArgs& a, const int* gmap, const doub
 
 namespace {
 
-// Edge strips' rows cost about 1.45 interior rows (measured on 1024 x 1024);
+// Edge strips' rows cost about 1.75 interior rows (the best of 1.3 .. 2.3 on 1024 x 1024);
 // every chunk also pays 6 rows of pipeline fill.
 MarchTiles march_tiles(const Params& P, int H) {
     MarchTiles T;
     T.H = H;
-    T.He = std::max(4, (int)std::lround((H + 6) / 1.45) - 6);
+    T.He = std::max(4, (int)std::lround((H + 6) / 1.75) - 6);
     T.strips = (P.nx + 2 + kMarchOutW - 1) / kMarchOutW;
     T.se = std::min(march_first_east_strip(P.nx), T.strips);
     T.gy = (P.ny + 2 + T.H - 1) / T.H;
