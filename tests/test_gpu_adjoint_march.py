@@ -137,3 +137,29 @@ def test_kept_trajectory_equals_checkpointed(monkeypatch):
             assert np.array_equal(a, b.cpu().numpy()), key
         for f in ("t", "dt", "step", "volume", "lambda_max"):
             assert getattr(o[4], f) == getattr(sr, f), (key, f)
+
+
+def test_trajectory_buffer_reused_across_calls():
+    """The kept trajectory stays with the handle: later swe_grad calls on the
+    same handle (from the state the earlier ones left; the second of the same
+    length, the third longer, so a larger buffer) equal swe_grad on a fresh
+    handle that first runs to that state."""
+    p = W.random_valid_state(140, 96, seed=31)
+    rng = np.random.default_rng(7)
+    cells = rng.choice(p.nx * p.ny, 10, replace=False)
+    hobs = torch.as_tensor(rng.uniform(0.0, 1.0, (8, 10)), dtype=torch.float64, device="cuda")
+    note("one handle: grad(12), grad(12), grad(24), against fresh handles")
+    s = swe.Solver.from_problem(p, dtype=torch.float64)
+    done = 0
+    for n in (12, 12, 24):
+        J, gn, gz = s.grad(n, cells, 3, hobs[: n // 3].contiguous(), 0)
+        g = swe.Solver.from_problem(p, dtype=torch.float64)
+        if done:
+            g.run(done)
+        J2, gn2, gz2 = g.grad(n, cells, 3, hobs[: n // 3].contiguous(), 0)
+        done += n
+        assert g.stats().t == s.stats().t and g.stats().step == s.stats().step == done
+        assert J2 == J
+        assert torch.equal(gn2, gn) and torch.equal(gz2, gz)
+        g.close()
+    s.close()
