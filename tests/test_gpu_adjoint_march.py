@@ -163,3 +163,12 @@ def test_trajectory_buffer_reused_across_calls():
         assert torch.equal(gn2, gn) and torch.equal(gz2, gz)
         g.close()
     s.close()
+
+
+@pytest.mark.parametrize("nx,ny", [(5, 5), (6, 40), (40, 6), (9, 130)])
+def test_march_equals_gather_on_small_grids(nx, ny, monkeypatch):
+    """Grids of the minimum size and thin ones: one strip holds both x edges,
+    and the chunks' boundary and interior row loops meet or are empty."""
+    p = W.random_valid_state(nx, ny, seed=nx * 1000 + ny)
+    note(f"random {nx}x{ny} f64: 10 steps, march vs gather")
+    check_equal(p, 10, 2, min(6, nx * ny), 3, seed=2, monkeypatch=monkeypatch)
