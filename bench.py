@@ -311,7 +311,7 @@ def combined_run(torch, swe, W, nx, nsteps, ckpt, obs_every):
     st, ms_fwd, _ = timed_run(torch, swe, W, p, "f32", nsteps, 0, 0)
     st_dry, ms_dry, _ = timed_run(torch, swe, W, p, "f32", nsteps, 0, 0, dry_skip=True)
     progress(f"combined: forward {ms_fwd:.0f} ms, with the dry-tile skip {ms_dry:.0f} ms")
-    f = swe.Solver.from_problem(p, dtype=torch.float32)
+    f = swe.Solver.from_problem(p, dtype=torch.float32, dry_skip=True)
     free0, total = torch.cuda.mem_get_info()
     fe = p.ny * p.nx
     npad = (p.nx + 2) * (p.ny + 2)

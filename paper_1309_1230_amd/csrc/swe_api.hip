@@ -868,7 +868,12 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
             slot(ck.p, sg, CK);
             e = copy_state<T>(h, U0, CK);
         }
-        // the fused kernel's own finalisation carries dt from step to step
+        // the fused kernel's own finalisation carries dt from step to step;
+        // with the dry-tile skip on, the plain recompute skips dry tiles as the
+        // forward run did (bit-exact), its flags cleared at the segment start
+        const bool seg_dry = h->dry && !keep && s1 - s0 > 1;
+        if (e == hipSuccess && seg_dry)
+            e = swe::launch_begin_call(rc_ctl, h->stream, h->dry, 2 * h->nparts);
         if (e == hipSuccess && !store_all && (keep || s1 - s0 > 1))
             e = swe::launch_replay_ctl(h->P, rc_ctl, ht[(size_t)s0], step0 + s0, hdt[(size_t)s0],
                                        h->stream);
@@ -892,6 +897,7 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
             swe::fused_part_layout(fa, h->fpart, h->nparts);
             fa.gy = h->gy;
             fa.H = h->H;
+            if (seg_dry) fa.dry = h->dry;
             const int sig = ((step0 + k) & 1) ? -1 : 1;
             if constexpr (!mixed) {
                 if (keep) {

@@ -172,3 +172,27 @@ def test_march_equals_gather_on_small_grids(nx, ny, monkeypatch):
     p = W.random_valid_state(nx, ny, seed=nx * 1000 + ny)
     note(f"random {nx}x{ny} f64: 10 steps, march vs gather")
     check_equal(p, 10, 2, min(6, nx * ny), 3, seed=2, monkeypatch=monkeypatch)
+
+
+@pytest.mark.parametrize("dtype,keep", [("f32", "1"), ("f64", "0")])
+def test_dry_skip_handle_gives_the_same_gradient(dtype, keep, monkeypatch):
+    """A handle with the dry-tile skip on runs swe_grad's forward run and its
+    plain segment recompute with the skip (FP32 handles; FP64 handles that
+    replay each step instead of keeping traces): the gradient is the same
+    bit for bit."""
+    p = W.flood_scenario(1, 300, 200)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    rng = np.random.default_rng(3)
+    cells = rng.choice(p.nx * p.ny, 12, replace=False)
+    hobs = torch.as_tensor(rng.uniform(0.0, 1.0, (10, 12)), dtype=torch.float64, device="cuda")
+    monkeypatch.setenv("SWE_GRAD_KEEP", keep)
+    note(f"flood 300x200 {dtype}: swe_grad with and without the dry-tile skip")
+    out = []
+    for dry in (False, True):
+        s = swe.Solver.from_problem(p, dtype=tdt, tile_rows=16, dry_skip=dry)
+        J, gn, gz = s.grad(40, cells, 4, hobs, 10)
+        out.append((J, gn, gz, s.stats()))
+        s.close()
+    (Ja, gna, gza, sa), (Jb, gnb, gzb, sb) = out
+    assert Ja == Jb and torch.equal(gna, gnb) and torch.equal(gza, gzb)
+    assert sb.cells_skipped > 0 and sa.t == sb.t
