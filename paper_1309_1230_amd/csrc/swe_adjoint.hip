@@ -136,34 +136,43 @@ __device__ __forceinline__ double nu_at(const AdjointArgs& a, int i, int j, bool
     return curv_switch(eM, eC, eP, rC);
 }
 
-// Reverse of the friction cube root y = cbrt3(x): returns x-bar given y-bar.
-__device__ double cbrt3_adjoint(double x, double ybar) {
+// The friction cube root y = cbrt3(x) with its Halley steps kept: the same
+// operations as tcbrt, so y[2] is tcbrt(x) bit for bit.
+struct CbrtTape { double y[3], q[2], den[2]; };
+
+__device__ __forceinline__ CbrtTape cbrt3_tape(double x) {
+    CbrtTape c;
     const unsigned w = (unsigned)__double2hiint(x);
-    double y[3];
-    y[0] = __hiloint2double((int)(w / 3u + 0x2A9F7893u), 0);
-    double tt[2], num[2], den[2], q[2];
+    c.y[0] = __hiloint2double((int)(w / 3u + 0x2A9F7893u), 0);
+#pragma unroll
     for (int k = 0; k < 2; ++k) {
-        tt[k] = (y[k] * y[k]) * y[k];
-        num[k] = tt[k] + (x + x);
-        den[k] = (tt[k] + tt[k]) + x;
-        q[k] = num[k] / den[k];
-        y[k + 1] = y[k] * q[k];
+        const double tt = (c.y[k] * c.y[k]) * c.y[k];
+        const double num = tt + (x + x);
+        c.den[k] = (tt + tt) + x;
+        c.q[k] = num / c.den[k];
+        c.y[k + 1] = c.y[k] * c.q[k];
     }
+    return c;
+}
+
+// Reverse of the cube root: x-bar given y-bar and the tape of x.
+__device__ __forceinline__ double cbrt3_adjoint(const CbrtTape& c, double ybar) {
     double xbar = 0.0;
+#pragma unroll
     for (int k = 1; k >= 0; --k) {
-        const double qbar = ybar * y[k];
-        ybar = ybar * q[k];
-        const double numbar = qbar / den[k];
-        const double denbar = -(numbar * q[k]);   // -(qbar q)/den
+        const double qbar = ybar * c.y[k];
+        ybar = ybar * c.q[k];
+        const double numbar = qbar / c.den[k];
+        const double denbar = -(numbar * c.q[k]);   // -(qbar q)/den
         // den = (t + t) + x, num = t + (x + x)
         xbar += denbar;
         double tbar = denbar + denbar + numbar;
         xbar += numbar + numbar;
         // t = (y*y)*y
-        const double yy = y[k] * y[k];
-        const double yybar = tbar * y[k];
+        const double yy = c.y[k] * c.y[k];
+        const double yybar = tbar * c.y[k];
         ybar += tbar * yy;
-        ybar += yybar * y[k] + yybar * y[k];
+        ybar += yybar * c.y[k] + yybar * c.y[k];
     }
     return xbar;
 }
@@ -269,7 +278,8 @@ __device__ __forceinline__ FaOut fa_point(double ed, double qx, double qy, doubl
         const double x2 = qx * qx + qy * qy;
         const double w = sqrt(x2);
         const double s = w * r;
-        const double c3 = tcbrt(r);
+        const CbrtTape ct = cbrt3_tape(r);
+        const double c3 = ct.y[2];   // tcbrt(r)
         const double k = r * c3;
         const double dtm = dt * mp;
         const double A = dtm * s;
@@ -284,7 +294,7 @@ __device__ __forceinline__ FaOut fa_point(double ed, double qx, double qy, doubl
         const double dtmb = Ab * s, sb = Ab * dtm;
         const double mb = dtmb * dt;
         double rb = kb * c3 + sb * w;
-        rb += cbrt3_adjoint(r, kb * r);
+        rb += cbrt3_adjoint(ct, kb * r);
         const double wb = sb * r;
         if (x2 > 0.0) {
             const double x2b = wb * (0.5 / w);
