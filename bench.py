@@ -379,7 +379,7 @@ def main():
         print(kernel_source_hash())
         return
     if a.gpus != 1:
-        print(f"bench.py: --gpus {a.gpus} requested, but this build measures one GPU only "
+        print(f"bench.py: --gpus {a.gpus} requested, but the library runs on one GPU only "
               "(the row-slab multi-GPU split is a design, not built); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)

@@ -44,7 +44,7 @@ typedef enum swe_status {
     SWE_ENOMEM = -2,       /* device or host allocation failed */
     SWE_EDEVICE = -3,      /* no usable GPU, or a HIP call failed (text in last_error) */
     SWE_EUNSTABLE = -4,    /* a step produced NaN/Inf or an invalid time step */
-    SWE_EUNSUPPORTED = -5  /* valid request this build does not implement */
+    SWE_EUNSUPPORTED = -5  /* valid request the library does not implement */
 } swe_status;
 
 typedef enum swe_dtype { SWE_F32 = 1, SWE_F64 = 2 } swe_dtype;
