@@ -1249,6 +1249,57 @@ struct AdjMarch {
         }
     }
 
+    // Dry tile.  Where U^n, U* and U^d are dry (0 <= h <= h_dry for U^d, h <=
+    // h_dry for the others) on every cell within two cells of the tile's
+    // output cells, and the tile is away from the domain edges, the reversed
+    // step reduces to: lambda_eta passes through (with this step's gauge
+    // term), lambda_q and the bed's share vanish, and dJ/dz takes the bed
+    // share of the step reversed before (no donor flux, no dissipation, no
+    // friction and no clipping act there, and every pressure term is
+    // multiplied by a zero momentum adjoint).  The values equal the full
+    // march's; only the sign of a zero can differ.  The test reads three
+    // depths per cell row by row and stops at the first row with a wet
+    // cell.
+    __device__ __forceinline__ bool dry_tile(int lane) const {
+        const double* E0 = a.un[0];
+        const double* E1 = a.us[0];
+        const double* E2 = a.ud[0];
+        for (int j = j0 - 2; j <= j1 + 1; ++j) {
+            const long long o = pitched(a.P, ii, j);
+            const double z = a.zp[d.at(ic, j)];
+            const double hn = E0[o] - z, hs = E1[o] - z, hd = E2[o] - z;
+            const bool dry = lane < 1 || lane > kWave - 2 ||
+                             (hn <= hdry && hs <= hdry && hd <= hdry && hd >= 0.0);
+            if (__ballot(!dry) != 0ull) return false;
+        }
+        return true;
+    }
+
+    __device__ __forceinline__ void dry_rows() {
+        if (!colOut) return;
+        for (int j = j0; j < j1; ++j) {
+            const long long C = d.at(i, j);
+            double l0 = LIN[C];
+            double gz = GZ[C] + AZI[C];
+            if (HOBS) {
+                const int g = gmap[(long long)j * d.nx + i];
+                if (g >= 0) {
+                    const double ef = a.ud[0][pitched(a.P, i, j)], z = a.zp[C];
+                    const bool clip = ef - z < 0.0;
+                    const double en = clip ? z : ef;
+                    const double dd = (en - z) - hobs[g];
+                    l0 += dd + dd;
+                    gz += 0.0 - (dd + dd);
+                }
+            }
+            LOUT[C] = l0;
+            LOUT[d.N + C] = 0.0;
+            LOUT[2 * d.N + C] = 0.0;
+            AZO[C] = 0.0;
+            GZ[C] = gz;
+        }
+    }
+
     __device__ __forceinline__ void run(int lane, int strip, int chunk, int H, int lout,
                                         int zout) {
         d = pad_of(a.P);
@@ -1270,6 +1321,12 @@ struct AdjMarch {
         const int py0 = chunk * H, py1 = min(py0 + H, a.P.ny + 2);
         j0 = py0 - 1;
         j1 = py1 - 1;
+        // a tile of an interior strip at least five rows from the south and
+        // north edges may be a dry tile
+        if (!EDGE && j0 - 5 >= 0 && j1 + 4 <= d.ny - 1 && dry_tile(lane)) {
+            dry_rows();
+            return;
+        }
 #pragma unroll
         for (int k = 0; k < 5; ++k) ue[k] = ux[k] = uy[k] = ur[k] = zz[k] = 0.0;
 #pragma unroll
