@@ -868,12 +868,10 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
             slot(ck.p, sg, CK);
             e = copy_state<T>(h, U0, CK);
         }
-        // the fused kernel's own finalisation carries dt from step to step;
-        // with the dry-tile skip on, the plain recompute skips dry tiles as the
-        // forward run did (bit-exact), its flags cleared at the segment start
-        const bool seg_dry = h->dry && !keep && s1 - s0 > 1;
-        if (e == hipSuccess && seg_dry)
-            e = swe::launch_begin_call(rc_ctl, h->stream, h->dry, 2 * h->nparts);
+        // the fused kernel's own finalisation carries dt from step to step.
+        // (The recompute runs dense: the dry-tile skip leaves a tile unwritten
+        // when the previous step skipped it too, which only a pair of
+        // alternating buffers tolerates, not a slot per step.)
         if (e == hipSuccess && !store_all && (keep || s1 - s0 > 1))
             e = swe::launch_replay_ctl(h->P, rc_ctl, ht[(size_t)s0], step0 + s0, hdt[(size_t)s0],
                                        h->stream);
@@ -897,7 +895,6 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
             swe::fused_part_layout(fa, h->fpart, h->nparts);
             fa.gy = h->gy;
             fa.H = h->H;
-            if (seg_dry) fa.dry = h->dry;
             const int sig = ((step0 + k) & 1) ? -1 : 1;
             if constexpr (!mixed) {
                 if (keep) {

@@ -176,10 +176,11 @@ def test_march_equals_gather_on_small_grids(nx, ny, monkeypatch):
 
 @pytest.mark.parametrize("dtype,keep", [("f32", "1"), ("f64", "0")])
 def test_dry_skip_handle_gives_the_same_gradient(dtype, keep, monkeypatch):
-    """A handle with the dry-tile skip on runs swe_grad's forward run and its
-    plain segment recompute with the skip (FP32 handles; FP64 handles that
-    replay each step instead of keeping traces): the gradient is the same
-    bit for bit."""
+    """A handle with the dry-tile skip on runs swe_grad's forward run with
+    the skip (its checkpoints come from the solver's own pair of buffers);
+    the segment recompute stays dense, since the skip leaves a tile unwritten
+    when it skipped the step before too.  The gradient is the same bit for
+    bit (FP32 handles; FP64 handles that replay each step)."""
     p = W.flood_scenario(1, 300, 200)
     tdt = torch.float64 if dtype == "f64" else torch.float32
     rng = np.random.default_rng(3)
