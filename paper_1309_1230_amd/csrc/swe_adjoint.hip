@@ -1258,45 +1258,69 @@ struct AdjMarch {
     // friction and no clipping act there, and every pressure term is
     // multiplied by a zero momentum adjoint).  The values equal the full
     // march's; only the sign of a zero can differ.  The test reads three
-    // depths per cell row by row and stops at the first row with a wet
-    // cell.
+    // depths per cell and stops at the first batch of rows with a wet cell.
+    // Both loops work in batches of kBatch rows, all loads of a batch issued
+    // before its test or its stores, so that they do not wait on memory row
+    // after row.
+    static constexpr int kBatch = 8;
+
     __device__ __forceinline__ bool dry_tile(int lane) const {
         const double* E0 = a.un[0];
         const double* E1 = a.us[0];
         const double* E2 = a.ud[0];
-        for (int j = j0 - 2; j <= j1 + 1; ++j) {
-            const long long o = pitched(a.P, ii, j);
-            const double z = a.zp[d.at(ic, j)];
-            const double hn = E0[o] - z, hs = E1[o] - z, hd = E2[o] - z;
-            const bool dry = lane < 1 || lane > kWave - 2 ||
-                             (hn <= hdry && hs <= hdry && hd <= hdry && hd >= 0.0);
-            if (__ballot(!dry) != 0ull) return false;
+        const bool edgeLane = lane < 1 || lane > kWave - 2;
+        for (int j = j0 - 2; j <= j1 + 1; j += kBatch) {
+            bool wet = false;
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int jj = j + u;
+                if (jj <= j1 + 1) {
+                    const long long o = pitched(a.P, ii, jj);
+                    const double z = a.zp[d.at(ic, jj)];
+                    const double hn = E0[o] - z, hs = E1[o] - z, hd = E2[o] - z;
+                    wet = wet ||
+                          !(edgeLane || (hn <= hdry && hs <= hdry && hd <= hdry && hd >= 0.0));
+                }
+            }
+            if (__ballot(wet) != 0ull) return false;
         }
         return true;
     }
 
     __device__ __forceinline__ void dry_rows() {
         if (!colOut) return;
-        for (int j = j0; j < j1; ++j) {
-            const long long C = d.at(i, j);
-            double l0 = LIN[C];
-            double gz = GZ[C] + AZI[C];
-            if (HOBS) {
-                const int g = gmap[(long long)j * d.nx + i];
-                if (g >= 0) {
-                    const double ef = a.ud[0][pitched(a.P, i, j)], z = a.zp[C];
-                    const bool clip = ef - z < 0.0;
-                    const double en = clip ? z : ef;
-                    const double dd = (en - z) - hobs[g];
-                    l0 += dd + dd;
-                    gz += 0.0 - (dd + dd);
+        for (int j = j0; j < j1; j += kBatch) {
+            double l0[kBatch], gz[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                if (j + u < j1) {
+                    const long long C = d.at(i, j + u);
+                    l0[u] = LIN[C];
+                    gz[u] = GZ[C] + AZI[C];
                 }
             }
-            LOUT[C] = l0;
-            LOUT[d.N + C] = 0.0;
-            LOUT[2 * d.N + C] = 0.0;
-            AZO[C] = 0.0;
-            GZ[C] = gz;
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                if (j + u >= j1) continue;
+                const int jj = j + u;
+                const long long C = d.at(i, jj);
+                if (HOBS) {
+                    const int g = gmap[(long long)jj * d.nx + i];
+                    if (g >= 0) {
+                        const double ef = a.ud[0][pitched(a.P, i, jj)], z = a.zp[C];
+                        const bool clip = ef - z < 0.0;
+                        const double en = clip ? z : ef;
+                        const double dd = (en - z) - hobs[g];
+                        l0[u] += dd + dd;
+                        gz[u] += 0.0 - (dd + dd);
+                    }
+                }
+                LOUT[C] = l0[u];
+                LOUT[d.N + C] = 0.0;
+                LOUT[2 * d.N + C] = 0.0;
+                AZO[C] = 0.0;
+                GZ[C] = gz[u];
+            }
         }
     }
 
