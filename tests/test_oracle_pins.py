@@ -7,9 +7,12 @@ closed forms (Stoker's dam break, the linear wave speed sqrt(g h), the first
 seiche period, the Manning friction decay ODE, the first time step of a still
 dam break) and exact symmetries.  A plausible slip anywhere in the scheme (a
 dropped or sign-flipped term, a wrong index or a transposed operand) breaks at
-least one of them.  The dissipation form and its coefficient are the one part
-that has no pin beyond mass conservation and the loose Stoker accuracy (the
-paper defers the equations to a thesis that is not available).
+least one of them.  The switch and dissipation sub-steps (S3, S4) and the
+time-step speed sum (S16) are also pinned value by value on small inputs
+worked out by hand, so that the oracle is held to its written reading of the
+scheme; that reading itself (the switch's form and the coefficient kappa)
+has no source beyond the loose Stoker accuracy, since the paper defers the
+equations to a thesis that is not available.
 """
 import math
 import os
@@ -316,3 +319,113 @@ def test_friction_cube_root_accuracy():
     assert np.max(np.abs(got / np.cbrt(xs) - 1.0)) < 1e-14
     assert O.cbrt3(8.0) == pytest.approx(2.0, rel=1e-15)
     assert O.cbrt3(1e3) == pytest.approx(10.0, rel=1e-15)
+
+
+# ------------------------------------------------ hand-computed sub-steps
+
+def test_cfl_speed_sum_of_a_moving_state():
+    """S16 on a uniform moving state: every wet cell has u = -1.5, v = 0.7
+    and c = sqrt(2 g), so lam = (|u| + c)/dx + (|v| + c)/dy and
+    dt^0 = cfl/lam.  dx != dy and u != v make a dropped |u| or |v|, a
+    missing absolute value, or the two speeds paired with the wrong cell
+    size change dt by 3% to 20%.  A dry cell with a huge discharge (h below
+    h_dry) must not count."""
+    nx, ny, dx, dy, h = 6, 5, 2.0, 5.0, 2.0
+    eta = np.full((ny, nx), h)
+    qx = np.full((ny, nx), -1.5 * h)
+    qy = np.full((ny, nx), 0.7 * h)
+    z = np.zeros((ny, nx))
+    z[2, 3] = 10.0
+    eta[2, 3] = 10.0 + 0.5e-3          # a thin film: dry at h_dry = 1e-3
+    qx[2, 3] = 50.0
+    p = W.Problem(nx=nx, ny=ny, dx=dx, dy=dy, z=z, n=np.zeros((ny, nx)), eta=eta, qx=qx, qy=qy,
+                  cfl=0.5, h_dry=1e-3, dt_max=100.0)
+    c = math.sqrt(9.81 * h)
+    lam = (1.5 + c) / dx + (0.7 + c) / dy
+    _, lam_o = O.volume_and_lambda(p, p.eta, p.qx, p.qy)
+    assert lam_o == pytest.approx(lam, rel=1e-14)
+    assert O.initial_dt(p) == pytest.approx(0.5 / lam, rel=1e-14)
+    # the slips this pin excludes, each far outside the tolerance above
+    for wrong in ((c / dx + (0.7 + c) / dy), ((1.5 + c) / dy + (0.7 + c) / dx),
+                  ((-1.5 + c) / dx + (0.7 + c) / dy), ((1.5 + c) / dx + c / dy)):
+        assert abs(wrong / lam - 1.0) > 0.03
+    # the fastest wet cell sets lam: one cell twice as fast along y
+    p2 = p.copy()
+    p2.qy[4, 0] = -2.0 * 0.7 * h
+    _, lam2 = O.volume_and_lambda(p2, p2.eta, p2.qx, p2.qy)
+    assert lam2 == pytest.approx((1.5 + c) / dx + (1.4 + c) / dy, rel=1e-14)
+    # dt_max caps the step; dt_fixed replaces it
+    p3 = p.copy()
+    p3.dt_max = 0.01
+    assert O.initial_dt(p3) == 0.01
+    p3.dt_fixed = 0.037
+    assert O.initial_dt(p3) == 0.037
+
+
+def _four_by_four():
+    """A 4 x 4 walled basin, dx = dy = 1, flat bed except one dry cell (z =
+    eta = 5 at i = 0, j = 3) and depths 1, 2 or 4, so that every reciprocal
+    depth, switch, coefficient and dissipation term is a short binary
+    fraction and the values below are exact.  Rows are j = 0 (south) up."""
+    eta = np.array([[1.0, 2.0, 4.0, 2.0],
+                    [2.0, 2.0, 2.0, 1.0],
+                    [4.0, 1.0, 2.0, 2.0],
+                    [5.0, 1.0, 1.0, 4.0]])
+    z = np.zeros((4, 4))
+    z[3, 0] = 5.0
+    qx = np.zeros((4, 4))
+    qx[1, 1] = 1.0
+    qx[2, 2] = 2.0
+    qy = np.zeros((4, 4))
+    qy[1, 3] = -1.0
+    return W.Problem(nx=4, ny=4, dx=1.0, dy=1.0, z=z, n=np.zeros((4, 4)), eta=eta, qx=qx, qy=qy,
+                     kappa=0.5, eps_max=0.25, h_dry=1e-3)
+
+
+def test_switch_and_dissipation_hand_computed():
+    """S3 and S4 of the scheme's reading, worked out by hand on the 4 x 4
+    basin above (the ghost ring copies eta, so a boundary second difference
+    has one term).  S3: nu_x = 0.25 |(eta_E - eta_C) - (eta_C - eta_W)| r_C
+    with r_C = 1/h_C of the centre cell (0 when dry), nu_y alike.  S4: the
+    face coefficient eps = min(kappa max(nu_L, nu_R), eps_max) when both
+    sides are wet, 0 on boundary faces and at the dry cell; then
+    D = (eps_E dU_E - eps_W dU_W) + (eps_N dU_N - eps_S dU_S) for eta, qx, qy.
+    Example, cell (1, 2): nu_x = 0.25 |(2 - 1) - (1 - 4)| * 1 = 1, so both its
+    x faces have eps = min(0.5 * 1, 0.25) = 0.25 (the cap), and
+    D_eta = (0.25 (2 - 1) - 0.25 (1 - 4)) + (0.125 (1 - 1) - 0.125 (1 - 2))
+          = 1.125.
+    Dropping the 0.25, taking r of a neighbour instead of the centre, the
+    cap, the wet test or a sign breaks these values."""
+    p = _four_by_four()
+    tr, _ = O.State(p).trace()
+    inner = lambda nm: tr[nm][1:-1, 1:-1]
+    nux = np.array([[0.25, 0.125, 0.25, 0.25],
+                    [0.0, 0.0, 0.125, 0.25],
+                    [0.1875, 1.0, 0.125, 0.0],
+                    [0.0, 1.0, 0.75, 0.1875]])
+    nuy = np.array([[0.25, 0.0, 0.125, 0.125],
+                    [0.125, 0.125, 0.25, 0.5],
+                    [0.0625, 0.25, 0.125, 0.125],
+                    [0.0, 0.0, 0.25, 0.125]])
+    d_eta = np.array([[0.25, 0.125, -0.75, 0.0],
+                      [0.0, -0.125, 0.125, 0.625],
+                      [-0.875, 1.125, -0.375, -0.125],
+                      [0.0, 0.0, 0.875, -0.875]])
+    d_qx = np.array([[0.0, 0.0625, 0.0, 0.0],
+                     [0.0, -0.25, 0.3125, 0.0],
+                     [0.0, 0.625, -1.125, 0.125],
+                     [0.0, 0.0, 0.25, 0.0]])
+    d_qy = np.array([[0.0, 0.0, 0.0, -0.25],
+                     [0.0, 0.0, -0.125, 0.625],
+                     [0.0, 0.0, 0.0, -0.25],
+                     [0.0, 0.0, 0.0, 0.0]])
+    r = np.array([[1.0, 0.5, 0.25, 0.5],
+                  [0.5, 0.5, 0.5, 1.0],
+                  [0.25, 1.0, 0.5, 0.5],
+                  [0.0, 1.0, 1.0, 0.25]])
+    assert np.array_equal(inner("S2.r"), r)
+    assert np.array_equal(inner("S3.nux"), nux)
+    assert np.array_equal(inner("S3.nuy"), nuy)
+    assert np.array_equal(inner("S4.Deta"), d_eta)
+    assert np.array_equal(inner("S4.Dqx"), d_qx)
+    assert np.array_equal(inner("S4.Dqy"), d_qy)
