@@ -52,7 +52,8 @@ class _Cfg(ctypes.Structure):
                 (f, ctypes.c_double) for f in
                 ("dx", "dy", "g", "cfl", "h_dry", "kappa", "eps_max", "dt_max", "dt_fixed")] + [
                 ("hydro_t", ctypes.POINTER(ctypes.c_double)),
-                ("hydro_q", ctypes.POINTER(ctypes.c_double))]
+                ("hydro_q", ctypes.POINTER(ctypes.c_double)),
+                ("h_switch", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -83,6 +84,8 @@ def lib():
         L.orc_initial_dt.restype = ctypes.c_double
         L.orc_cbrt3.argtypes = [ctypes.c_double]
         L.orc_cbrt3.restype = ctypes.c_double
+        L.orc_run_f32.argtypes = L.orc_run.argtypes
+        L.orc_run_f32.restype = ctypes.c_int
         L.orc_run_record.argtypes = L.orc_run.argtypes + [dp]
         L.orc_run_record.restype = ctypes.c_int
         i64p = ctypes.POINTER(ctypes.c_int64)
@@ -116,6 +119,7 @@ def _cfg(p, keep):
     c.hydro_q = _ptr(hq) if len(hq) else None
     for f in ("dx", "dy", "g", "cfl", "h_dry", "kappa", "eps_max", "dt_max", "dt_fixed"):
         setattr(c, f, float(getattr(p, f)))
+    c.h_switch = float(getattr(p, "h_switch", 0.0))
     return c
 
 
@@ -136,14 +140,21 @@ class Stats:
 
 
 class State:
-    """Oracle state of one problem: (eta, qx, qy), t^n, n and dt^n."""
+    """Oracle state of one problem: (eta, qx, qy), t^n, n and dt^n.
+    binary32=True runs the same steps with every operation rounded to float
+    (orc_run_f32: a rounding reference for FP32 state, not the oracle)."""
 
-    def __init__(self, problem, t0: float = 0.0, step0: int = 0):
+    def __init__(self, problem, t0: float = 0.0, step0: int = 0, binary32: bool = False):
         self.p = problem
+        self.binary32 = bool(binary32)
         self.eta, self.qx, self.qy = problem.state()
+        if self.binary32:
+            for a in (self.eta, self.qx, self.qy):
+                a[...] = a.astype(np.float32)
         self.t = float(t0)
         self.step = int(step0)
-        self.dt = initial_dt(problem, self.eta, self.qx, self.qy)
+        # dt^0 (binary32: computed by the first orc_run_f32 call)
+        self.dt = 0.0 if self.binary32 else initial_dt(problem, self.eta, self.qx, self.qy)
 
     def run(self, nsteps: int, t_end: float = math.inf) -> Stats:
         keep = []
@@ -152,7 +163,8 @@ class State:
         n = ctypes.c_int64(self.step)
         dt = ctypes.c_double(self.dt)
         st = _Stats()
-        rc = lib().orc_run(ctypes.byref(c), _ptr(self.eta), _ptr(self.qx), _ptr(self.qy),
+        fn = lib().orc_run_f32 if self.binary32 else lib().orc_run
+        rc = fn(ctypes.byref(c), _ptr(self.eta), _ptr(self.qx), _ptr(self.qy),
                            _ptr(self.p.z), _ptr(self.p.n), ctypes.byref(t), ctypes.byref(n),
                            ctypes.byref(dt), int(nsteps), float(t_end), ctypes.byref(st))
         if rc < 0:

@@ -47,7 +47,12 @@
  *   S2  PRIM(U^n): h = eta - z; wet <=> h > h_dry; r = wet ? 1/h : 0;
  *       u = qx*r; v = qy*r.  Over every padded cell.
  *   S3  SWITCH: nu_x = 0.25*(|(eta_E - eta_C) - (eta_C - eta_W)| * r_C), nu_y
- *       likewise with N/S.  Interior cells.
+ *       likewise with N/S.  Interior cells.  With the thin-film reading
+ *       (h_switch > 0) r_C is replaced by min(r_C, 1/h_switch), i.e. the
+ *       surface curvature is measured against max(h_C, h_switch): in films
+ *       thinner than h_switch the switch no longer grows as 1/h.  (Its
+ *       derivative with respect to the depth, |d2 eta|/h^2, is what makes
+ *       the discrete adjoint of a flood over dry land grow without bound.)
  *   S4  DISS: face coefficient eps = (wet_L && wet_R) ?
  *       min(kappa*max(nu_L, nu_R), eps_max) : 0 on interior faces, 0 on
  *       boundary faces; for each of eta, qx, qy:
@@ -143,6 +148,7 @@ typedef struct orc_cfg {
     int32_t pad_;
     double dx, dy, g, cfl, h_dry, kappa, eps_max, dt_max, dt_fixed;
     const double *hydro_t, *hydro_q;
+    double h_switch;    /* > 0: depth floor of the S3 switch (thin-film reading); 0: off */
 } orc_cfg;
 
 typedef struct orc_stats {
@@ -214,15 +220,39 @@ inline Rev operator/(Rev a, Rev b) {
     return rnode(q, a.id, 1.0 / b.v, b.id, -q / b.v);
 }
 
+/* Single precision: value rounded to IEEE-754 binary32 after every
+ * operation (constants are rounded when they enter an operation).  The step
+ * instantiated with it is a rounding reference for FP32 state: how far plain
+ * float arithmetic, correctly rounded, drifts from the double step on a given
+ * workload (orc_run_f32). */
+struct F32 {
+    float v;
+    F32() : v(0.0f) {}
+    F32(double x) : v((float)x) {}
+};
+inline F32 mkf(float x) {
+    F32 r;
+    r.v = x;
+    return r;
+}
+inline F32 operator+(F32 a, F32 b) { return mkf(a.v + b.v); }
+inline F32 operator-(F32 a, F32 b) { return mkf(a.v - b.v); }
+inline F32 operator-(F32 a) { return mkf(-a.v); }
+inline F32 operator*(F32 a, F32 b) { return mkf(a.v * b.v); }
+inline F32 operator/(F32 a, F32 b) { return mkf(a.v / b.v); }
+
 inline double val(double x) { return x; }
 inline double val(Dual x) { return x.v; }
 inline double val(Rev x) { return x.v; }
+inline double val(F32 x) { return (double)x.v; }
 
 inline double sfabs(double x) { return fabs(x); }
 inline Dual sfabs(Dual x) { return Dual(fabs(x.v), x.v > 0.0 ? x.d : (x.v < 0.0 ? -x.d : 0.0)); }
 inline Rev sfabs(Rev x) {
     return rnode(fabs(x.v), x.id, x.v > 0.0 ? 1.0 : (x.v < 0.0 ? -1.0 : 0.0), -1, 0.0);
 }
+inline F32 sfabs(F32 x) { return mkf(fabsf(x.v)); }
+inline F32 ssqrt(F32 x) { return mkf(sqrtf(x.v)); }
 inline double ssqrt(double x) { return sqrt(x); }
 inline Dual ssqrt(Dual x) {
     double s = sqrt(x.v);
@@ -415,7 +445,8 @@ void prim(const orc_cfg* c, const Grid* G, S* const U[3], const S* zp, S* h, S* 
 
 /* S3: dissipation switch from the curvature of the water surface. */
 template <typename S>
-void switch_nu(const Grid* G, const S* eta, const S* r, S* nux, S* nuy) {
+void switch_nu(const orc_cfg* c, const Grid* G, const S* eta, const S* r, S* nux, S* nuy) {
+    const double rcap = c->h_switch > 0.0 ? 1.0 / c->h_switch : 0.0;
     for (int j = 0; j < G->ny; ++j)
         for (int i = 0; i < G->nx; ++i) {
             size_t C = at(G, i, j);
@@ -423,8 +454,10 @@ void switch_nu(const Grid* G, const S* eta, const S* r, S* nux, S* nuy) {
             S bx = eta[C] - eta[at(G, i - 1, j)];
             S ay = eta[at(G, i, j + 1)] - eta[C];
             S by = eta[C] - eta[at(G, i, j - 1)];
-            nux[C] = S(0.25) * (sfabs(ax - bx) * r[C]);
-            nuy[C] = S(0.25) * (sfabs(ay - by) * r[C]);
+            /* the switch's reciprocal depth: r_C, or 1/max(h_C, h_switch) */
+            S rs = c->h_switch > 0.0 ? dmin(r[C], S(rcap)) : r[C];
+            nux[C] = S(0.25) * (sfabs(ax - bx) * rs);
+            nuy[C] = S(0.25) * (sfabs(ay - by) * rs);
         }
 }
 
@@ -638,6 +671,29 @@ void cfl_scan(const orc_cfg* c, int nx, int ny, const double* eta, const double*
     *hsum = vs;
 }
 
+/* S16 in the arithmetic of S (the binary32 run): lam_max and the volume sum
+ * of h, both returned in double. */
+template <typename S>
+void cfl_scan_s(const orc_cfg* c, int nx, int ny, const S* eta, const S* qx, const S* qy,
+                const S* z, double* lam_max, double* hsum) {
+    S idx = S(1.0 / c->dx), idy = S(1.0 / c->dy), g = S(c->g);
+    double lmax = 0.0, vs = 0.0;
+    size_t N = (size_t)nx * (size_t)ny;
+    for (size_t s = 0; s < N; ++s) {
+        S h = eta[s] - z[s];
+        vs += val(h);
+        if (val(h) > c->h_dry) {
+            S r = S(1.0) / h;
+            S u = qx[s] * r, v = qy[s] * r;
+            S cc = ssqrt(g * h);
+            double lam = val((sfabs(u) + cc) * idx + (sfabs(v) + cc) * idy);
+            if (!(lam <= lmax)) lmax = lam;
+        }
+    }
+    *lam_max = lmax;
+    *hsum = vs;
+}
+
 double next_dt(const orc_cfg* c, double lam_max) {
     if (c->dt_fixed > 0.0) return c->dt_fixed;
     if (lam_max > 0.0) return dmin(c->cfl / lam_max, c->dt_max);
@@ -671,7 +727,7 @@ void step_body(const orc_cfg* c, const Grid* G, Work<S>* w, S* eta, S* qx, S* qy
         }
     fill_ghosts(c, G, qin0, w->Un[0], w->Un[1], w->Un[2]);
     prim(c, G, w->Un, w->zp, w->h, w->r, w->u, w->v);                       /* S2 */
-    switch_nu(G, w->Un[0], w->r, w->nux, w->nuy);                           /* S3 */
+    switch_nu(c, G, w->Un[0], w->r, w->nux, w->nuy);                        /* S3 */
     dissipation(c, G, w->Un, w->h, w->nux, w->nuy, w->D);                   /* S4 */
     xflux(c, G, sigma, w->Un, w->h, w->u, w->v, w->zp, w->F);               /* S5 */
     yflux(c, G, sigma, w->Un, w->h, w->u, w->v, w->zp, w->G);               /* S6 */
@@ -872,6 +928,85 @@ int orc_run(const orc_cfg* c, double* eta, double* qx, double* qy, const double*
             const double* nman, double* t, int64_t* step, double* dt, int64_t nsteps,
             double t_end, orc_stats* st) {
     return orc_run_record(c, eta, qx, qy, z, nman, t, step, dt, nsteps, t_end, st, NULL);
+}
+
+/* orc_run in binary32: the same sixteen sub-steps with every operation
+ * rounded to float (inputs, which should already be float values, are
+ * rounded on entry; g, h_dry, kappa and eps_max are rounded to float, as a
+ * float implementation holds them).  t, dt and the volume stay double, and
+ * dt^{n+1} is formed in double from the float lam_max.  A rounding
+ * reference for FP32 state, not a parity target: a float implementation
+ * that rounds differently (approximate reciprocals, another cube root)
+ * drifts from the double step by an amount of the same order.  Returns as
+ * orc_run. */
+int orc_run_f32(const orc_cfg* c0, double* eta, double* qx, double* qy, const double* z,
+                const double* nman, double* t, int64_t* step, double* dt, int64_t nsteps,
+                double t_end, orc_stats* st) {
+    if (check_cfg(c0) || !eta || !qx || !qy || !z || !nman || !t || !step || !dt) return -1;
+    orc_cfg cf = *c0;
+    cf.g = (double)(float)c0->g;
+    cf.h_dry = (double)(float)c0->h_dry;
+    cf.kappa = (double)(float)c0->kappa;
+    cf.eps_max = (double)(float)c0->eps_max;
+    const orc_cfg* c = &cf;
+    Grid G = {c->nx, c->ny, c->nx + 2};
+    const size_t N = (size_t)c->nx * (size_t)c->ny;
+    std::vector<F32> e(N), a(N), b(N), zf(N), nf(N);
+    for (size_t s = 0; s < N; ++s) {
+        e[s] = F32(eta[s]);
+        a[s] = F32(qx[s]);
+        b[s] = F32(qy[s]);
+        zf[s] = F32(z[s]);
+        nf[s] = F32(nman[s]);
+    }
+    Work<F32> w;
+    w.init(&G, nullptr);
+    static_fields(c, &G, zf.data(), nf.data(), w.zp, w.mp);
+    orc_stats S;
+    memset(&S, 0, sizeof S);
+    S.bad_step = -1;
+    S.dt_min = INFINITY;
+    S.dt_max = 0.0;
+    double lam = 0.0, hs = 0.0;
+    cfl_scan_s(c, c->nx, c->ny, e.data(), a.data(), b.data(), zf.data(), &lam, &hs);
+    if (!(*dt > 0.0)) *dt = next_dt(c, lam);
+    S.volume = hs * (c->dx * c->dy);
+    S.lambda_max = lam;
+    int rc = 0;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        if (!(*t < t_end)) break;
+        StepOut so;
+        step_body(c, &G, &w, e.data(), a.data(), b.data(), *t, *step, *dt, &so);
+        cfl_scan_s(c, c->nx, c->ny, e.data(), a.data(), b.data(), zf.data(), &lam, &hs);
+        double dtn = next_dt(c, lam);
+        uint32_t flags = so.flags;
+        if (!isfinite(lam)) flags |= ORC_FLAG_NAN;
+        if (!(dtn > 0.0) || !isfinite(dtn)) flags |= ORC_FLAG_BADDT;
+        S.dt_min = dmin(S.dt_min, *dt);
+        S.dt_max = dmax(S.dt_max, *dt);
+        S.defect += so.defect * (c->dx * c->dy);
+        S.flags |= flags;
+        S.volume = hs * (c->dx * c->dy);
+        S.lambda_max = lam;
+        S.steps += 1;
+        *t = *t + *dt;
+        *dt = dtn;
+        *step += 1;
+        if (flags & (ORC_FLAG_NAN | ORC_FLAG_BADDT)) {
+            S.bad_step = *step - 1;
+            rc = 1;
+            break;
+        }
+    }
+    for (size_t s = 0; s < N; ++s) {
+        eta[s] = val(e[s]);
+        qx[s] = val(a[s]);
+        qy[s] = val(b[s]);
+    }
+    S.t = *t;
+    S.dt = *dt;
+    if (st) *st = S;
+    return rc;
 }
 
 /* One step with every intermediate exposed.  `arrays` receives ORC_NTRACE

@@ -429,3 +429,36 @@ def test_switch_and_dissipation_hand_computed():
     assert np.array_equal(inner("S4.Deta"), d_eta)
     assert np.array_equal(inner("S4.Dqx"), d_qx)
     assert np.array_equal(inner("S4.Dqy"), d_qy)
+
+
+# ------------------------------------------- binary32 rounding reference
+
+def test_binary32_run_keeps_still_water_still():
+    """The oracle's binary32 instantiation (every operation rounded to float)
+    keeps a lake at rest bitwise still, dry banks included: the same exact
+    cancellation as in double."""
+    p = W.lake_at_rest(120, 90, seed=8, dry_banks=True)
+    s = O.State(p, binary32=True)
+    e0 = s.eta.copy()
+    st = s.run(200)
+    assert np.array_equal(s.eta, e0)
+    assert not np.any(s.qx) and not np.any(s.qy)
+    assert st.defect == 0.0
+
+
+def test_binary32_run_is_float_rounding_of_the_double_step():
+    """On the dam break the binary32 run stays within float rounding of the
+    double run (relative L1 depth difference of order 1e-7, far below the
+    scheme's own error) and holds float values only; a double operation
+    leaking into it, or a float one into the double step, would show as an
+    exact match or as non-float values."""
+    p = W.stoker()
+    o, st = O.run(p, 200)
+    f = O.State(p, binary32=True)
+    sf = f.run(200)
+    for a in (f.eta, f.qx, f.qy):
+        assert np.array_equal(a, a.astype(np.float32).astype(np.float64))
+    h64, h32 = o.eta - p.z, f.eta - p.z
+    d = float(np.abs(h32 - h64).sum() / np.abs(h64).sum())
+    assert 1e-9 < d < 1e-5
+    assert sf.t == pytest.approx(st.t, rel=1e-6)
