@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define SWE_ABI_VERSION 2
+#define SWE_ABI_VERSION 3
 
 typedef enum swe_status {
     SWE_OK = 0,
@@ -108,6 +108,16 @@ typedef struct swe_config {
                               * from a dense first step at the start of every call
                               * (swe_run, swe_step, ensemble run or replay), so the
                               * caller may change the state between calls. */
+    double h_switch;         /* thin-film reading of the dissipation switch (S3): > 0
+                              * measures the surface curvature against
+                              * max(h, h_switch) instead of h, i.e. the switch's
+                              * reciprocal depth is min(1/h, 1/h_switch); 0 (the
+                              * default) is the plain scheme.  The paper leaves dry
+                              * and drying cells to future work (§6.2); without this
+                              * the discrete adjoint of a flood over dry land grows
+                              * without bound through the switch's 1/h^2 depth
+                              * derivative in thin films.  Cells deeper than h_switch
+                              * are unaffected. */
 } swe_config;
 
 /* Progress and diagnostics of a handle. */
@@ -172,6 +182,16 @@ int swe_step(swe_handle* h, double* dt_used);
  * arrays and fills *out (may be NULL).  Returns SWE_EUNSTABLE if a fatal flag
  * was raised (out->bad_step names the step). */
 int swe_run(swe_handle* h, int64_t nsteps, double t_end, swe_stats* out);
+
+/* nsteps steps on a prescribed time grid: step k takes dts[k] (host array of
+ * nsteps finite values > 0) instead of the step the CFL condition (§3.1) or
+ * dt_fixed would choose; t advances by the same sums as in swe_run.  Meant
+ * for replaying the time grid of an earlier run: swe_grad differentiates
+ * with the run's dt^n held fixed, so a finite-difference check of its
+ * gradient, or a line search, must reuse those steps.  The dt that the
+ * stats report afterwards is the CFL step of the final state.  Synchronises
+ * once; errors as swe_run, plus SWE_EINVAL for a NULL or invalid dts. */
+int swe_run_dt(swe_handle* h, int64_t nsteps, const double* dts, swe_stats* out);
 
 /* Synchronise the stream and report the current statistics. */
 int swe_get_stats(swe_handle* h, swe_stats* out);

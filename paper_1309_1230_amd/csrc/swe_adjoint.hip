@@ -133,7 +133,7 @@ __device__ __forceinline__ double nu_at(const AdjointArgs& a, int i, int j, bool
     const double* E = a.un[0];
     const double eM = xdir ? eta_at(a.P, E, i - 1, j) : eta_at(a.P, E, i, j - 1);
     const double eP = xdir ? eta_at(a.P, E, i + 1, j) : eta_at(a.P, E, i, j + 1);
-    return curv_switch(eM, eC, eP, rC);
+    return curv_switch(eM, eC, eP, rC, a.P.rcap);
 }
 
 // The friction cube root y = cbrt3(x) with its Halley steps kept: the same
@@ -613,13 +613,15 @@ __global__ void k_adj_e1(AdjointArgs a) {
 }
 
 // d-bar of the curvature switch at interior cell X (x or y direction), and
-// its |d| for the r-bar term.
+// its |d| for the r-bar term.  Under the thin-film reading the switch used
+// min(rX, rcap): the r-bar term exists only where it used rX itself.
 __device__ __forceinline__ double switch_dbar(double eXm, double eX, double eXp, double rX,
-                                              double nubX, double& absd_t) {
+                                              double rcap, double nubX, double& absd_t) {
     const double dd = (eXp - eX) - (eX - eXm);
     const double t = 0.25 * nubX;
-    absd_t = t * __builtin_fabs(dd);
-    const double absb = t * rX;
+    const bool live = rX < rcap;
+    absd_t = live ? t * __builtin_fabs(dd) : 0.0;
+    const double absb = t * (live ? rX : rcap);
     return dd > 0.0 ? absb : (dd < 0.0 ? -absb : 0.0);
 }
 
@@ -657,7 +659,7 @@ __global__ void k_adj_e2(AdjointArgs a) {
             const double eXp = dirn == 0 ? eta_at(a.P, E, xi + 1, xj) : eta_at(a.P, E, xi, xj + 1);
             const double rX = recip_depth(eX - a.zp[d.at(xi, xj)], a.P.h_dry);
             double absd_t;
-            const double db = switch_dbar(eXm, eX, eXp, rX, NUB[d.at(xi, xj)], absd_t);
+            const double db = switch_dbar(eXm, eX, eXp, rX, a.P.rcap, NUB[d.at(xi, xj)], absd_t);
             if (o == 0) {
                 eb += -db - db;
                 rb += absd_t;
@@ -916,7 +918,7 @@ struct AdjMarch {
     double* GN;
     int i, ii, ic, j0, j1;
     bool colOut;
-    double hdry, hg, kap, emax;
+    double hdry, hg, kap, emax, rcap;
     // outputs of the previous iteration, stored at the start of the next one
     // (ahead of its prefetch, so that waiting for the prefetch never waits
     // for stores): dJ/dz and dJ/dn of row R-1, lambda^n and the bed's share
@@ -1149,8 +1151,8 @@ struct AdjMarch {
             const Cell me = carried_cell(ue[2], ux[2], uy[2], ue[2] - zz[2], ur[2]);
             const double eW = from_west(ue[2]), eE = from_east(ue[2]);
             const double zW = from_west(zz[2]), zE = from_east(zz[2]);
-            const double nux = curv_switch(eW, me.e, eE, me.r);
-            const double nuy = curv_switch(ue[3], me.e, ue[1], me.r);
+            const double nux = curv_switch(eW, me.e, eE, me.r, rcap);
+            const double nuy = curv_switch(ue[3], me.e, ue[1], me.r, rcap);
             const double nuE = from_east(nux), nuW = from_west(nux);
             const Cell cE = carried_cell(eE, from_east(ux[2]), from_east(uy[2]), eE - zE, 0.0);
             const Cell cW = carried_cell(eW, from_west(ux[2]), from_west(uy[2]), eW - zW, 0.0);
@@ -1164,8 +1166,8 @@ struct AdjMarch {
                 const double dS[3] = {ade[3], adx[3], ady[3]};
                 const Cell cN = carried_cell(ue[1], ux[1], uy[1], ue[1] - zz[1], ur[1]);
                 const Cell cS = carried_cell(ue[3], ux[3], uy[3], ue[3] - zz[3], ur[3]);
-                const double nuN = curv_switch(ue[2], ue[1], ue[0], ur[1]);
-                const double nuS = curv_switch(ue[4], ue[3], ue[2], ur[3]);
+                const double nuN = curv_switch(ue[2], ue[1], ue[0], ur[1], rcap);
+                const double nuS = curv_switch(ue[4], ue[3], ue[2], ur[3], rcap);
                 un[0] = 0.5 * ade[2]; un[1] = 0.5 * adx[2]; un[2] = 0.5 * ady[2];
                 double nub[2] = {0.0, 0.0};
 #pragma unroll
@@ -1194,8 +1196,8 @@ struct AdjMarch {
                     }
                     if (arg == (meL ? 0 : 1)) nub[xf ? 0 : 1] += epsb * kap;
                 }
-                dbxv = switch_dbar(eW, me.e, eE, me.r, nub[0], atxv);
-                dbyv = switch_dbar(ue[3], me.e, ue[1], me.r, nub[1], atyv);
+                dbxv = switch_dbar(eW, me.e, eE, me.r, rcap, nub[0], atxv);
+                dbyv = switch_dbar(ue[3], me.e, ue[1], me.r, rcap, nub[1], atyv);
             }
             une[0] = un[0]; unx[0] = un[1]; uny[0] = un[2];
             dbx[0] = dbxv; atx[0] = atxv; dby[0] = dbyv; aty[0] = atyv;
@@ -1334,6 +1336,7 @@ struct AdjMarch {
         GZ = wk(a, d, W_GZ);
         GN = wk(a, d, W_GN);
         hdry = a.P.h_dry;
+        rcap = a.P.rcap;
         hg = 0.5 * a.P.g;
         kap = a.P.kappa;
         emax = a.P.eps_max;

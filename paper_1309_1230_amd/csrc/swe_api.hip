@@ -284,6 +284,7 @@ int validate(const swe_config* c, std::string& why) {
     if (c->tile_rows < 0 || c->tile_rows > 65536) return bad("tile_rows out of range");
     if (c->dry_skip != 0 && c->dry_skip != 1) return bad("dry_skip must be 0 or 1");
     if (c->dry_skip && c->path != SWE_PATH_FUSED) return bad("dry_skip needs the fused path");
+    if (!(c->h_switch >= 0.0) || !std::isfinite(c->h_switch)) return bad("h_switch must be finite and >= 0");
     for (int k = 0; k < 4; ++k) {
         if (c->bc[k] < SWE_BC_WALL || c->bc[k] > SWE_BC_INFLOW) return bad("unknown boundary kind");
     }
@@ -299,6 +300,95 @@ int validate(const swe_config* c, std::string& why) {
     }
     if (!c->z || !c->n || !c->eta || !c->qx || !c->qy) return bad("a field pointer is NULL");
     return SWE_OK;
+}
+
+// A device is present and every field is device memory of the current one.
+int check_device(const swe_config* c, int* dev, std::string& why) {
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        why = "no HIP device is available";
+        return SWE_EDEVICE;
+    }
+    if ((e = hipGetDevice(dev)) != hipSuccess) {
+        why = std::string("hipGetDevice: ") + hip_text(e);
+        return SWE_EDEVICE;
+    }
+    const void* ptrs[5] = {c->z, c->n, c->eta, c->qx, c->qy};
+    for (const void* p : ptrs)
+        if (!is_device_ptr(p, *dev)) {
+            why = "a field pointer is not device memory of the current device";
+            return SWE_EDEVICE;
+        }
+    return SWE_OK;
+}
+
+// Host-side part of a handle: the caller's pointers, the parameter block,
+// the tile layout and the host copy of the hydrograph (no device memory).
+void prepare_handle(swe_handle* h, const swe_config* c, int dev) {
+    h->dtype = c->dtype;
+    h->elem = c->dtype == SWE_F32 ? 4 : 8;
+    h->path = c->path;
+    h->stream = (hipStream_t)c->stream;
+    h->device = dev;
+    h->eta = c->eta;
+    h->qx = c->qx;
+    h->qy = c->qy;
+    h->z = c->z;
+    h->n = c->n;
+    Params& P = h->P;
+    P.nx = c->nx;
+    P.ny = c->ny;
+    P.pitch = c->pitch;
+    for (int k = 0; k < 4; ++k) {
+        P.bc[k] = c->bc[k];
+        P.lo[k] = c->inflow_lo[k];
+        P.hi[k] = c->inflow_hi[k];
+    }
+    P.hydro_len = c->hydro_len;
+    P.dx = c->dx; P.dy = c->dy; P.g = c->g; P.cfl = c->cfl; P.h_dry = c->h_dry;
+    P.kappa = c->kappa; P.eps_max = c->eps_max; P.dt_max = c->dt_max; P.dt_fixed = c->dt_fixed;
+    P.idx = 1.0 / c->dx;
+    P.idy = 1.0 / c->dy;
+    P.rcap = c->h_switch > 0.0 ? 1.0 / c->h_switch : INFINITY;
+    h->H = c->tile_rows > 0 ? c->tile_rows : auto_tile_rows(h, dev, c->dry_skip != 0);
+    h->gy = (c->ny + h->H - 1) / h->H;
+    h->nparts = std::max(swe::fused_blocks(c->nx, c->ny, h->H), swe::scan_partials(c->nx, c->ny));
+    std::vector<double> hy(2 * (size_t)std::max(1, c->hydro_len), 0.0);
+    for (int k = 0; k < c->hydro_len; ++k) {
+        hy[k] = c->hydro_t[k];
+        hy[c->hydro_len + k] = c->hydro_q[k];
+    }
+    h->hydro_host = hy;
+}
+
+// Device-side start of a handle whose scratch pointers are set: the
+// hydrograph, m = g n^2, the control block at t0 and dt^0 from the state.
+hipError_t init_device_state(swe_handle* h, const swe_config* c) {
+    Params& P = h->P;
+    hipError_t e = hipMemcpyAsync(h->hydro, h->hydro_host.data(),
+                                  h->hydro_host.size() * sizeof(double), hipMemcpyHostToDevice,
+                                  h->stream);
+    P.hydro_t = h->hydro;
+    P.hydro_q = h->hydro + std::max(0, c->hydro_len);
+    if (e == hipSuccess)
+        e = h->dtype == SWE_F32
+                ? swe::launch_manning_m<float>(P, (const float*)c->n, (float*)bufB(h, 3), h->stream)
+                : swe::launch_manning_m<double>(P, (const double*)c->n, (double*)bufB(h, 3),
+                                                h->stream);
+    if (e == hipSuccess) e = swe::launch_init_ctl(h->ctl, c->t0, 0, 0u, 0.0, h->stream);
+    if (e == hipSuccess)
+        e = h->dtype == SWE_F32
+                ? swe::launch_scan<float>(P, h->ctl, INFINITY, (const float*)c->eta,
+                                          (const float*)c->qx, (const float*)c->qy,
+                                          (const float*)c->z, h->part, h->part + h->nparts, 0,
+                                          h->stream)
+                : swe::launch_scan<double>(P, h->ctl, INFINITY, (const double*)c->eta,
+                                           (const double*)c->qx, (const double*)c->qy,
+                                           (const double*)c->z, h->part, h->part + h->nparts, 0,
+                                           h->stream);
+    return e;
 }
 
 }  // namespace
@@ -333,53 +423,18 @@ int swe_create(const swe_config* c, swe_handle** out) {
     std::string why;
     int rc = validate(c, why);
     if (rc) return fail(nullptr, rc, why);
-    int ndev = 0;
-    hipError_t e = hipGetDeviceCount(&ndev);
-    if (e != hipSuccess || ndev <= 0) {
-        (void)hipGetLastError();
-        return fail(nullptr, SWE_EDEVICE, "no HIP device is available");
-    }
     int dev = 0;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(nullptr, e, "hipGetDevice");
-    const void* ptrs[5] = {c->z, c->n, c->eta, c->qx, c->qy};
-    for (const void* p : ptrs)
-        if (!is_device_ptr(p, dev))
-            return fail(nullptr, SWE_EDEVICE, "a field pointer is not device memory of the current device");
+    if ((rc = check_device(c, &dev, why)) != SWE_OK) return fail(nullptr, rc, why);
 
     swe_handle* h = new (std::nothrow) swe_handle();
     if (!h) return fail(nullptr, SWE_ENOMEM, "host allocation failed");
-    h->dtype = c->dtype;
-    h->elem = c->dtype == SWE_F32 ? 4 : 8;
-    h->path = c->path;
-    h->stream = (hipStream_t)c->stream;
-    h->device = dev;
-    h->eta = c->eta;
-    h->qx = c->qx;
-    h->qy = c->qy;
-    h->z = c->z;
-    h->n = c->n;
-    Params& P = h->P;
-    P.nx = c->nx;
-    P.ny = c->ny;
-    P.pitch = c->pitch;
-    for (int k = 0; k < 4; ++k) {
-        P.bc[k] = c->bc[k];
-        P.lo[k] = c->inflow_lo[k];
-        P.hi[k] = c->inflow_hi[k];
-    }
-    P.hydro_len = c->hydro_len;
-    P.dx = c->dx; P.dy = c->dy; P.g = c->g; P.cfl = c->cfl; P.h_dry = c->h_dry;
-    P.kappa = c->kappa; P.eps_max = c->eps_max; P.dt_max = c->dt_max; P.dt_fixed = c->dt_fixed;
-    P.idx = 1.0 / c->dx;
-    P.idy = 1.0 / c->dy;
-    h->H = c->tile_rows > 0 ? c->tile_rows : auto_tile_rows(h, dev, c->dry_skip != 0);
-    h->gy = (c->ny + h->H - 1) / h->H;
-    h->nparts = std::max(swe::fused_blocks(c->nx, c->ny, h->H), swe::scan_partials(c->nx, c->ny));
+    prepare_handle(h, c, dev);
 
     auto cleanup = [&](int code) {
         swe_destroy(h);
         return code;
     };
+    hipError_t e;
     if ((e = hipMalloc(&h->buf, 4 * field_bytes(h))) != hipSuccess) {
         h->buf = nullptr;
         fail(nullptr, SWE_ENOMEM, std::string("hipMalloc of the state buffer failed: ") + hip_text(e));
@@ -390,20 +445,10 @@ int swe_create(const swe_config* c, swe_handle** out) {
         fail(nullptr, SWE_ENOMEM, std::string("hipMalloc failed: ") + hip_text(e));
         return cleanup(SWE_ENOMEM);
     }
-    std::vector<double> hy(2 * (size_t)std::max(1, c->hydro_len), 0.0);
-    for (int k = 0; k < c->hydro_len; ++k) {
-        hy[k] = c->hydro_t[k];
-        hy[c->hydro_len + k] = c->hydro_q[k];
-    }
-    h->hydro_host = hy;
-    if ((e = hipMalloc((void**)&h->hydro, hy.size() * sizeof(double))) != hipSuccess) {
+    if ((e = hipMalloc((void**)&h->hydro, h->hydro_host.size() * sizeof(double))) != hipSuccess) {
         fail(nullptr, SWE_ENOMEM, std::string("hipMalloc failed: ") + hip_text(e));
         return cleanup(SWE_ENOMEM);
     }
-    e = hipMemcpyAsync(h->hydro, hy.data(), hy.size() * sizeof(double), hipMemcpyHostToDevice,
-                       h->stream);
-    P.hydro_t = h->hydro;
-    P.hydro_q = h->hydro + std::max(0, c->hydro_len);
     if (c->dry_skip) {
         if ((e = hipMalloc((void**)&h->dry, 2 * sizeof(unsigned) * (size_t)h->nparts)) != hipSuccess) {
             h->dry = nullptr;
@@ -418,22 +463,7 @@ int swe_create(const swe_config* c, swe_handle** out) {
     }
     e = hipMemsetAsync(h->fpart, 0, swe::fused_part_bytes(h->nparts), h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->part, 0, 2 * sizeof(double) * h->nparts, h->stream);
-    if (e == hipSuccess)
-        e = h->dtype == SWE_F32
-                ? swe::launch_manning_m<float>(P, (const float*)c->n, (float*)bufB(h, 3), h->stream)
-                : swe::launch_manning_m<double>(P, (const double*)c->n, (double*)bufB(h, 3),
-                                                h->stream);
-    if (e == hipSuccess) e = swe::launch_init_ctl(h->ctl, c->t0, 0, 0u, 0.0, h->stream);
-    if (e == hipSuccess)
-        e = h->dtype == SWE_F32
-                ? swe::launch_scan<float>(P, h->ctl, INFINITY, (const float*)c->eta,
-                                          (const float*)c->qx, (const float*)c->qy,
-                                          (const float*)c->z, h->part, h->part + h->nparts, 0,
-                                          h->stream)
-                : swe::launch_scan<double>(P, h->ctl, INFINITY, (const double*)c->eta,
-                                           (const double*)c->qx, (const double*)c->qy,
-                                           (const double*)c->z, h->part, h->part + h->nparts, 0,
-                                           h->stream);
+    if (e == hipSuccess) e = init_device_state(h, c);
     if (e == hipSuccess && h->path == SWE_PATH_UNFUSED) {
         int rc2 = ensure_trace(h);
         if (rc2) {
@@ -473,6 +503,24 @@ int swe_run(swe_handle* h, int64_t nsteps, double t_end, swe_stats* out) {
     const bool unfused = h->path == SWE_PATH_UNFUSED;
     hipError_t e = begin_call(h, h->stream);
     for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) e = enqueue(h, k, t_end, unfused);
+    if (e == hipSuccess) e = enqueue_copy_back(h);
+    if (e != hipSuccess) return hip_fail(h, e, "launching the step kernels");
+    return fill_stats(h, out);
+}
+
+int swe_run_dt(swe_handle* h, int64_t nsteps, const double* dts, swe_stats* out) {
+    if (!h) return fail(nullptr, SWE_EINVAL, "handle is NULL");
+    if (nsteps < 0) return fail(h, SWE_EINVAL, "nsteps must be >= 0");
+    if (nsteps > 0 && !dts) return fail(h, SWE_EINVAL, "dts is NULL");
+    for (int64_t k = 0; k < nsteps; ++k)
+        if (!(dts[k] > 0.0) || !std::isfinite(dts[k]))
+            return fail(h, SWE_EINVAL, "every prescribed time step must be finite and > 0");
+    const bool unfused = h->path == SWE_PATH_UNFUSED;
+    hipError_t e = begin_call(h, h->stream);
+    for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) {
+        e = swe::launch_set_dt(h->P, h->ctl, dts[k], h->stream);
+        if (e == hipSuccess) e = enqueue(h, k, INFINITY, unfused);
+    }
     if (e == hipSuccess) e = enqueue_copy_back(h);
     if (e != hipSuccess) return hip_fail(h, e, "launching the step kernels");
     return fill_stats(h, out);

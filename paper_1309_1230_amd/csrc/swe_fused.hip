@@ -60,7 +60,7 @@ struct YFace { T m, x, y, p; }; // fluxes through one y face
 // Per-wave constants of one step.
 template <typename T>
 struct Consts {
-    T rx, ry, dt, qin0, qin1, hdry, hg, g, kap, emax, idx, idy;
+    T rx, ry, dt, qin0, qin1, hdry, hg, g, kap, emax, idx, idy, rcap;
 };
 
 // Override the fluxes of the west (i == 0) or east (i == nx-1) boundary face
@@ -179,6 +179,26 @@ struct March {
     T lmax = T(0);
     unsigned flags = 0u;
     bool dirty = false;   // an output cell is wet, not finite, or has eta = -0 (DRY only)
+    // The output row of an iteration is stored at the start of the next one,
+    // right after its ingested row has arrived.  On gfx9 one counter tracks
+    // loads and stores, and with both in flight a wait for a load waits for
+    // every store as well: stored at the end of the iteration, the row's
+    // stores would be waited for by the next iteration's first load use
+    // after barely having been issued.  Issued a whole iteration earlier,
+    // they complete while the iteration computes.
+    T oe = 0, oa = 0, ob = 0;   // U^{n+1} of row orow (valid in output columns when opend)
+    int orow = 0;
+    bool opend = false;
+
+    __device__ __forceinline__ void flush() {
+        if (opend) {
+            const long long so = (long long)orow * pitch + i;
+            eta1[so] = oe;
+            qx1[so] = oa;
+            qy1[so] = ob;
+        }
+        opend = false;
+    }
 
     __device__ __forceinline__ long long rowoff(int R) const {
         return (long long)min(max(R, 0), ny - 1) * pitch + ic;
@@ -199,6 +219,7 @@ struct March {
     __device__ __forceinline__ void iter(int R, bool out) {
         const T e0 = pe[SLOT], a0 = pa[SLOT], b0 = pb[SLOT], z0 = pz[SLOT];
         const T m2 = pm[SLOT];              // m of row R-2
+        flush();                            // the output row of the previous iteration
         prefetch<1 - SLOT>(R + 1);
         pm[1 - SLOT] = mm[rowoff(R - 1)];
         int kW0 = BC_WALL, kE0 = BC_WALL, kW1 = BC_WALL, kE1 = BC_WALL;
@@ -217,7 +238,7 @@ struct March {
         // ---- S3/S4 in x on row R
         const T eE = from_east(e0), eW = from_west(e0);
         const T hE = from_east(h0);
-        const T nux0 = curv_switch(eW, e0, eE, r0);
+        const T nux0 = curv_switch(eW, e0, eE, r0, c.rcap);
         const T nuxE = from_east(nux0);
         const T epsE = faceE_interior ? face_eps(h0, hE, nux0, nuxE, c.hdry, c.kap, c.emax) : T(0);
         const T fdm = epsE * (eE - e0);
@@ -236,7 +257,7 @@ struct March {
                                      from_west(z0), c.qin0, EDGE, atW, atE, kW0, kE0);
 
         // ---- S3 in y at row R-1, S4 in y through face (R-2)+1/2
-        const T nuy1 = curv_switch(e2, e1, e0, r1);
+        const T nuy1 = curv_switch(e2, e1, e0, r1, c.rcap);
         const bool fInt = !BND || (R - 2 >= 0 && R - 2 <= ny - 2);
         const T h1 = e1 - z1, h2 = e2 - z2;
         const T epsN = fInt ? face_eps(h2, h1, nuy2, nuy1, c.hdry, c.kap, c.emax) : T(0);
@@ -316,11 +337,12 @@ struct March {
                 if (!tfinite(e) || !tfinite(a) || !tfinite(b)) flags |= FLAG_NAN;
                 vol = vol + (double)h;
                 if (DRY) dirty = dirty || !(h <= c.hdry) || !tfinite(e) || is_neg_zero(e);
-                const long long so = (long long)(R - 2) * pitch + i;
-                eta1[so] = e;
-                qx1[so] = a;
-                qy1[so] = b;
             }
+            oe = e;
+            oa = a;
+            ob = b;
+            orow = R - 2;
+            opend = colOut;
         }
 
         // ---- rotate the carried rows
@@ -356,6 +378,7 @@ struct March {
             iter<EDGE, true, 0>(R, true);
             if (R + 1 <= yEnd + 1) iter<EDGE, true, 1>(R + 1, true);
         }
+        flush();
     }
 };
 
@@ -495,6 +518,7 @@ __device__ __forceinline__ void fused_step(const FusedArgs<T>& A, int blk, int n
     M.c.hdry = T(P.h_dry); M.c.g = T(P.g); M.c.hg = T(0.5 * P.g);
     M.c.kap = T(P.kappa); M.c.emax = T(P.eps_max);
     M.c.idx = T(P.idx); M.c.idy = T(P.idy);
+    M.c.rcap = T(P.rcap);
     M.P = &A.P;
     M.eta = A.eta; M.qx = A.qx; M.qy = A.qy; M.zb = A.z; M.mm = A.m;
     M.eta1 = A.eta1; M.qx1 = A.qx1; M.qy1 = A.qy1;

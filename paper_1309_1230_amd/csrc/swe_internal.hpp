@@ -115,6 +115,8 @@ hipError_t launch_begin_call(Ctl* ctl, hipStream_t s, unsigned* dry = nullptr, i
 // dt/dy and the inflow values set as the finalisation of step n-1 sets them.
 hipError_t launch_replay_ctl(const Params& P, Ctl* ctl, double t, long long step, double dt,
                              hipStream_t s);
+// The next step takes dt (its dt/dx, dt/dy and q_in(t^n + dt) follow).
+hipError_t launch_set_dt(const Params& P, Ctl* ctl, double dt, hipStream_t s);
 // Set the control block from host values (t, step, flags, defect) and clear
 // the accumulators.
 hipError_t launch_init_ctl(Ctl* ctl, double t, long long step, unsigned flags, double defect,

@@ -132,8 +132,9 @@ __global__ void k_s3(UnfusedArgs<T> a) {
     const T* E = arr(a.trace, d, T_UN);
     const T* R = arr(a.trace, d, T_R);
     const long long C = d.at(i, j);
-    arr(a.trace, d, T_NUX)[C] = curv_switch(E[d.at(i - 1, j)], E[C], E[d.at(i + 1, j)], R[C]);
-    arr(a.trace, d, T_NUY)[C] = curv_switch(E[d.at(i, j - 1)], E[C], E[d.at(i, j + 1)], R[C]);
+    const T rcap = T(a.P.rcap);
+    arr(a.trace, d, T_NUX)[C] = curv_switch(E[d.at(i - 1, j)], E[C], E[d.at(i + 1, j)], R[C], rcap);
+    arr(a.trace, d, T_NUY)[C] = curv_switch(E[d.at(i, j - 1)], E[C], E[d.at(i, j + 1)], R[C], rcap);
 }
 
 // S4: switched dissipation of U^n.
@@ -393,6 +394,18 @@ __global__ void k_replay_ctl(Params P, Ctl* ctl, double t, long long step, doubl
     }
 }
 
+// The next step takes the prescribed dt instead of the one the previous
+// finalisation chose: dt, dt/dx, dt/dy and q_in(t^n + dt) as that
+// finalisation would have set them for this dt.
+__global__ void k_set_dt(Params P, Ctl* ctl, double dt) {
+    if (threadIdx.x == 0) {
+        ctl->dt = dt;
+        ctl->rx = dt / P.dx;
+        ctl->ry = dt / P.dy;
+        ctl->qin1 = q_inflow(P, ctl->t + dt);
+    }
+}
+
 __global__ void k_init_ctl(Ctl* ctl, double t, long long step, unsigned flags, double defect) {
     if (threadIdx.x == 0) {
         ctl->t = t;
@@ -529,6 +542,11 @@ hipError_t launch_begin_call(Ctl* ctl, hipStream_t s, unsigned* dry, int ndry) {
 hipError_t launch_replay_ctl(const Params& P, Ctl* ctl, double t, long long step, double dt,
                              hipStream_t s) {
     hipLaunchKernelGGL(k_replay_ctl, dim3(1), dim3(kWave), 0, s, P, ctl, t, step, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_dt(const Params& P, Ctl* ctl, double dt, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(kWave), 0, s, P, ctl, dt);
     return hipGetLastError();
 }
 

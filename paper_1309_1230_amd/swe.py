@@ -52,7 +52,7 @@ class Config(ctypes.Structure):
                 ("hydro_q", ctypes.POINTER(ctypes.c_double)),
                 ("z", ctypes.c_void_p), ("n", ctypes.c_void_p), ("eta", ctypes.c_void_p),
                 ("qx", ctypes.c_void_p), ("qy", ctypes.c_void_p), ("stream", ctypes.c_void_p),
-                ("dry_skip", ctypes.c_int32)]
+                ("dry_skip", ctypes.c_int32), ("h_switch", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -91,7 +91,7 @@ class Gauges(ctypes.Structure):
 
 #: every function include/swe.h declares
 EXPORTS = ("swe_abi_version", "swe_config_init", "swe_create", "swe_destroy", "swe_step",
-           "swe_run", "swe_get_stats", "swe_trace_step", "swe_trace_bytes", "swe_save",
+           "swe_run", "swe_run_dt", "swe_get_stats", "swe_trace_step", "swe_trace_bytes", "swe_save",
            "swe_load", "swe_last_error", "swe_probe_copy", "swe_grad", "swe_ensemble_create",
            "swe_ensemble_destroy", "swe_ensemble_run", "swe_ensemble_capture",
            "swe_ensemble_replay", "swe_ensemble_stats", "swe_ensemble_tile_rows",
@@ -120,6 +120,9 @@ def lib():
         L.swe_step.restype = ctypes.c_int
         L.swe_run.argtypes = [H, ctypes.c_int64, ctypes.c_double, ctypes.POINTER(_Stats)]
         L.swe_run.restype = ctypes.c_int
+        L.swe_run_dt.argtypes = [H, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(_Stats)]
+        L.swe_run_dt.restype = ctypes.c_int
         L.swe_get_stats.argtypes = [H, ctypes.POINTER(_Stats)]
         L.swe_get_stats.restype = ctypes.c_int
         L.swe_trace_step.argtypes = [H, ctypes.c_void_p, ctypes.c_size_t,
@@ -187,7 +190,7 @@ def _make_config(z, n, eta, qx, qy, *, dx: float, dy: float, g: float = 9.81,
                  dt_max: float = 1.0, dt_fixed: float = 0.0, t0: float = 0.0,
                  bc=(SWE_BC_WALL,) * 4, inflow_lo=(0, 0, 0, 0), inflow_hi=None,
                  hydro_t=(), hydro_q=(), path: str = "fused", tile_rows: int = 0,
-                 dry_skip: bool = False):
+                 dry_skip: bool = False, h_switch: float = 0.0):
     """Validate five field tensors and build a swe_config for them; returns
     (config, objects the config points into)."""
     torch = _torch()
@@ -214,6 +217,7 @@ def _make_config(z, n, eta, qx, qy, *, dx: float, dy: float, g: float = 9.81,
         c.bc[k] = int(bc[k])
         c.inflow_lo[k] = int(inflow_lo[k])
         c.inflow_hi[k] = int(inflow_hi[k])
+    c.h_switch = float(h_switch)
     c.dx, c.dy, c.g, c.cfl, c.h_dry = float(dx), float(dy), float(g), float(cfl), float(h_dry)
     c.kappa, c.eps_max, c.dt_max = float(kappa), float(eps_max), float(dt_max)
     c.dt_fixed, c.t0 = float(dt_fixed), float(t0)
@@ -233,7 +237,7 @@ def _problem_kwargs(p):
     return dict(dx=p.dx, dy=p.dy, g=p.g, cfl=p.cfl, h_dry=p.h_dry, kappa=p.kappa,
                 eps_max=p.eps_max, dt_max=p.dt_max, dt_fixed=p.dt_fixed, bc=p.bc,
                 inflow_lo=p.inflow_lo, inflow_hi=p.inflow_hi, hydro_t=p.hydro_t,
-                hydro_q=p.hydro_q)
+                hydro_q=p.hydro_q, h_switch=getattr(p, "h_switch", 0.0))
 
 
 class Solver:
@@ -273,6 +277,18 @@ class Solver:
     def run(self, nsteps: int, t_end: float = math.inf, check: bool = True) -> Stats:
         st = _Stats()
         rc = lib().swe_run(self._h, int(nsteps), float(t_end), ctypes.byref(st))
+        if check:
+            self._check(rc)
+        return self._stats(st)
+
+    def run_dt(self, dts, check: bool = True) -> Stats:
+        """Steps on a prescribed time grid: step k takes dts[k] (swe_run_dt)."""
+        import numpy as np
+        d = np.ascontiguousarray(np.asarray(dts, dtype=np.float64).ravel())
+        st = _Stats()
+        rc = lib().swe_run_dt(self._h, int(d.size),
+                              d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                              ctypes.byref(st))
         if check:
             self._check(rc)
         return self._stats(st)

@@ -208,3 +208,29 @@ def test_mixed_state_and_checkpoint_spacing():
     s = outs[0][3]
     for a, b in ((s.eta, r.eta), (s.qx, r.qx), (s.qy, r.qy)):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("name,nx,ny,nsteps", [("smooth", 64, 64, 60), ("random", 64, 64, 60),
+                                               ("smooth", 128, 128, 100),
+                                               ("random", 128, 128, 100)])
+def test_gradient_matches_oracle_elementwise(name, nx, ny, nsteps):
+    """64 x 64 and 128 x 128, up to 100 steps: every entry of both gradients
+    against the oracle's reverse-mode gradient, relative to the entry itself
+    with a floor of 1e-6 of the largest entry (below that, an entry is a sum
+    of cancelling terms whose rounding is not its own size), at most 1e-10."""
+    if name == "smooth":
+        p = W.smooth_wet(nx, ny, seed=9)
+    else:
+        p = W.random_valid_state(nx, ny, seed=21)
+    every = 4
+    G = gauges_for(p, nsteps, every, 24, seed=5)
+    note(f"{name} {nx}x{ny}: {nsteps} steps, elementwise adjoint vs oracle")
+    J, gn, gz, _ = gpu_grad(p, G, nsteps, 10)
+    Jo, gno, gzo = O.loss_gradient(p, G)
+    assert J == pytest.approx(Jo, rel=1e-13)
+    for nm, a, b in (("dJ/dn", gn, gno), ("dJ/dz", gz, gzo)):
+        floor = 1e-6 * np.abs(b).max()
+        err = np.abs(a - b) / np.maximum(np.abs(b), floor)
+        note(f"{nm}: max elementwise rel error {err.max():.2e} (floor {floor:.2e}), "
+             f"max err / max |grad| {np.abs(a - b).max() / np.abs(b).max():.2e}")
+        assert err.max() <= 1e-10, nm

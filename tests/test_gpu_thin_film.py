@@ -1,0 +1,104 @@
+"""The thin-film reading of the dissipation switch (h_switch > 0: the surface
+curvature is measured against max(h, h_switch), i.e. S3's reciprocal depth
+is min(1/h, 1/h_switch)) on the GPU against the oracle.
+
+The case is the large combined run's channel flood on a 128 m x 128 m corner
+(128 x 128 cells, dx = 1 m): the inflow overtops the channel and floods dry
+land as thin films, where the cap is active.  With the plain switch the
+discrete adjoint of this flood grows without bound (the oracle's own pins
+show it); with h_switch = 0.1 m it stays O(10^2) over 600 steps.
+
+Bars: the forward step and every sub-step bit for bit as the oracle (the same
+correctly rounded operations); the FP64 gradient elementwise within 1e-10
+of the oracle's (floor 1e-6 of the largest entry); the mixed path (FP32
+forward, FP64 adjoint linearised along the FP32 trajectory) within 1e-3 of
+the largest entry, the size of the FP32 trajectory's own departure.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1309_1230_amd import swe
+from paper_1309_1230_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def note(msg):
+    print(f"[thin-film] {msg}", flush=True)
+
+
+def flood(h_switch, nsteps, every=10):
+    c = W.channel_flood(nx=128, ny=128, dx=1.0, nsteps=nsteps, obs_every=every)
+    p = c.problem
+    p.h_switch = h_switch
+    _, dts = O.run_record(p, nsteps)
+    q = p.copy()
+    q.n = c.n_true
+    st = O.State(q)
+    hobs = []
+    for _ in range(nsteps // every):
+        st.run(every)
+        hobs.append((st.eta - p.z).ravel()[c.cells])
+    return p, O.Gauges(cells=c.cells, every=every, hobs=np.array(hobs), dts=dts)
+
+
+def test_thin_film_ladder_bitwise():
+    """Every intermediate of three unfused steps of a rough state with thin
+    and dry cells, with the cap active in part of them."""
+    p = W.random_valid_state(70, 45, seed=21)
+    p.h_switch = 0.5
+    h = p.eta - p.z
+    assert np.count_nonzero((h > p.h_dry) & (h < p.h_switch)) > 50
+    note("trace ladder, h_switch = 0.5")
+    g = swe.Solver.from_problem(p, dtype=torch.float64, path="unfused")
+    o = O.State(p)
+    for step in range(3):
+        ta, _ = g.trace_step()
+        oa, _ = o.trace()
+        for nm in swe.TRACE_NAMES:
+            a = ta[nm].double().cpu().numpy()
+            assert np.array_equal(a, oa[nm]), f"step {step} {nm}"
+    g.close()
+
+
+def test_thin_film_flood_forward_matches_oracle():
+    p, _ = flood(0.1, 10)
+    note("channel flood 128x128, h_switch = 0.1: 400 fused FP64 steps")
+    g = swe.Solver.from_problem(p, dtype=torch.float64)
+    st = g.run(400)
+    o, ost = O.run(p, 400)
+    for a, b in zip((g.eta, g.qx, g.qy), (o.eta, o.qx, o.qy)):
+        a = a.cpu().numpy()
+        assert np.max(np.abs(a - b) / np.maximum(np.abs(b), 1.0)) <= 1e-11
+    assert st.t == ost.t and st.dt == ost.dt
+    g.close()
+
+
+def test_thin_film_flood_gradient_matches_oracle():
+    nsteps = 300
+    p, G = flood(0.1, nsteps)
+    note(f"channel flood 128x128, h_switch = 0.1: gradient over {nsteps} steps")
+    Jo, gno, gzo = O.loss_gradient(p, G)
+    s = swe.Solver.from_problem(p, dtype=torch.float64)
+    hobs = torch.as_tensor(G.hobs, dtype=torch.float64, device="cuda")
+    J, gn, gz = s.grad(nsteps, G.cells, G.every, hobs, 17)
+    s.close()
+    gn, gz = gn.cpu().numpy(), gz.cpu().numpy()
+    assert J == pytest.approx(Jo, rel=1e-13)
+    assert np.abs(gno).max() < 1e3
+    for nm, a, b in (("dJ/dn", gn, gno), ("dJ/dz", gz, gzo)):
+        floor = 1e-6 * np.abs(b).max()
+        err = np.abs(a - b) / np.maximum(np.abs(b), floor)
+        note(f"{nm}: max |grad| {np.abs(b).max():.3e}, max elementwise rel error {err.max():.2e}")
+        assert err.max() <= 1e-10, nm
+    # the mixed path: FP32 forward, FP64 adjoint along the FP32 trajectory
+    s32 = swe.Solver.from_problem(p, dtype=torch.float32)
+    J32, gn32, _ = s32.grad(nsteps, G.cells, G.every, hobs, 17)
+    s32.close()
+    d = np.abs(gn32.cpu().numpy() - gno).max() / np.abs(gno).max()
+    note(f"mixed FP32/FP64 gradient vs oracle: max diff / max |grad| {d:.2e}, "
+         f"J {J32:.6e} vs {Jo:.6e}")
+    assert d <= 1e-3
