@@ -193,6 +193,24 @@ int swe_run(swe_handle* h, int64_t nsteps, double t_end, swe_stats* out);
  * once; errors as swe_run, plus SWE_EINVAL for a NULL or invalid dts. */
 int swe_run_dt(swe_handle* h, int64_t nsteps, const double* dts, swe_stats* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture of its own work, tight serving loops, harnesses that forbid
+ * hipMalloc): swe_create + swe_run(nsteps, t_end) + swe_destroy in one call
+ * that allocates nothing.  The caller's z, n, eta, qx, qy (cfg) are read and
+ * eta, qx, qy written as by swe_run, with the same kernels and the same
+ * results bit for bit.  The library's scratch (second state buffer, m, control
+ * block, partial sums, hydrograph) is a static device array of about 35 MiB,
+ * one per device that loads the library, held until the process ends.
+ * Limits: pitch * ny <= 1048576 elements (either dtype), at most 65536 tiles,
+ * FUSED path, dry_skip = 0.  The array keeps the previous call's contents and
+ * each call clears what must start at zero; calls that overlap on one device
+ * (two host threads, or two streams in flight at once) race on it.
+ * Synchronises the stream once at the end and fills *out (may be NULL).
+ * Errors (read with swe_last_error(NULL)): as swe_create and swe_run, plus
+ * SWE_EINVAL for a grid or tile count beyond the limits, another path or the
+ * dry-tile skip. */
+int swe_run_noalloc(const swe_config* cfg, int64_t nsteps, double t_end, swe_stats* out);
+
 /* Synchronise the stream and report the current statistics. */
 int swe_get_stats(swe_handle* h, swe_stats* out);
 

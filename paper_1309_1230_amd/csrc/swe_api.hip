@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -391,6 +392,61 @@ hipError_t init_device_state(swe_handle* h, const swe_config* c) {
     return e;
 }
 
+// ---------------------------------------------------- allocation-free run
+//
+// swe_run_noalloc keeps all of its device scratch (the second state buffer
+// and m = g n^2, the control block, the partial sums and tickets, the
+// hydrograph) in the file-scope array below instead of allocating it.
+// Its largest grid has pitch * ny <= kNoAllocMaxElems and at most
+// kNoAllocMaxTiles tiles.  The array exists once per device that loads this
+// library and lives until the process ends.  Host code never passes its name
+// to a kernel: the name is a host-side stand-in, and the device address comes
+// from hipGetSymbolAddress, once per device (noalloc_scratch).
+constexpr size_t kNoAllocMaxElems = size_t(1) << 20;
+constexpr int kNoAllocMaxTiles = 1 << 16;
+constexpr size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+constexpr size_t kNoAllocStateBytes = al256(4 * kNoAllocMaxElems * sizeof(double));
+constexpr size_t kNoAllocCtlBytes = al256(sizeof(Ctl));
+constexpr size_t kNoAllocPartBytes = al256(2 * sizeof(double) * kNoAllocMaxTiles);
+constexpr size_t kNoAllocGroups = (kNoAllocMaxTiles + swe::kGroup - 1) / swe::kGroup;
+constexpr size_t kNoAllocFpartBytes =
+    al256((kNoAllocMaxTiles + kNoAllocGroups) * sizeof(swe::TilePart) + kNoAllocGroups * sizeof(unsigned));
+constexpr size_t kNoAllocHydroBytes = al256(2 * sizeof(double) * swe::kMaxHydro);
+constexpr size_t kNoAllocBytes = kNoAllocStateBytes + kNoAllocCtlBytes + kNoAllocPartBytes +
+                                 kNoAllocFpartBytes + kNoAllocHydroBytes;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+__global__ void k_zero16(uint4* p, size_t n16) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += stride)
+        p[k] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;   // device address of `scratch` per device
+
+// Device address of this device's copy of `scratch` (the current device).
+int noalloc_scratch(int dev, void** out, std::string& why) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev < 0) {
+        why = "bad device index";
+        return SWE_EDEVICE;
+    }
+    if ((size_t)dev >= g_scratch_ptr.size()) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+    if (!g_scratch_ptr[(size_t)dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            why = std::string("hipGetSymbolAddress of the static scratch: ") + hip_text(e);
+            return SWE_EDEVICE;
+        }
+        g_scratch_ptr[(size_t)dev] = p;
+    }
+    *out = g_scratch_ptr[(size_t)dev];
+    return SWE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -506,6 +562,54 @@ int swe_run(swe_handle* h, int64_t nsteps, double t_end, swe_stats* out) {
     if (e == hipSuccess) e = enqueue_copy_back(h);
     if (e != hipSuccess) return hip_fail(h, e, "launching the step kernels");
     return fill_stats(h, out);
+}
+
+int swe_run_noalloc(const swe_config* c, int64_t nsteps, double t_end, swe_stats* out) {
+    std::string why;
+    int rc = validate(c, why);
+    if (rc) return fail(nullptr, rc, why);
+    if (c->path != SWE_PATH_FUSED) return fail(nullptr, SWE_EINVAL, "swe_run_noalloc runs the fused path only");
+    if (c->dry_skip) return fail(nullptr, SWE_EINVAL, "swe_run_noalloc does not take the dry-tile skip");
+    if (nsteps < 0) return fail(nullptr, SWE_EINVAL, "nsteps must be >= 0");
+    if (std::isnan(t_end)) return fail(nullptr, SWE_EINVAL, "t_end is NaN");
+    if ((size_t)c->pitch * (size_t)c->ny > kNoAllocMaxElems)
+        return fail(nullptr, SWE_EINVAL,
+                    "grid too large for swe_run_noalloc: pitch * ny must be <= 1048576");
+    int dev = 0;
+    if ((rc = check_device(c, &dev, why)) != SWE_OK) return fail(nullptr, rc, why);
+    void* base = nullptr;
+    if ((rc = noalloc_scratch(dev, &base, why)) != SWE_OK) return fail(nullptr, rc, why);
+
+    swe_handle h;   // host-side only: its device pointers all point into `scratch`
+    prepare_handle(&h, c, dev);
+    if (h.nparts > kNoAllocMaxTiles)
+        return fail(nullptr, SWE_EINVAL, "too many tiles for swe_run_noalloc (tile_rows too small)");
+    char* p = (char*)base;
+    h.buf = p;
+    p += kNoAllocStateBytes;
+    h.ctl = (Ctl*)p;
+    p += kNoAllocCtlBytes;
+    h.part = (double*)p;
+    p += kNoAllocPartBytes;
+    h.fpart = p;
+    p += kNoAllocFpartBytes;
+    h.hydro = (double*)p;
+    // every call shares the array: the tickets and partial sums of the last
+    // call are cleared (a fill kernel, no memset node)
+    const size_t nz16 = (kNoAllocPartBytes + kNoAllocFpartBytes) / 16;
+    hipLaunchKernelGGL(k_zero16, dim3(256), dim3(256), 0, h.stream, (uint4*)h.part, nz16);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = init_device_state(&h, c);
+    if (e == hipSuccess) e = begin_call(&h, h.stream);
+    for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) e = enqueue(&h, k, t_end, false);
+    if (e == hipSuccess) e = enqueue_copy_back(&h);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(h.stream);
+        return fail(nullptr, SWE_EDEVICE, std::string("swe_run_noalloc: ") + hip_text(e));
+    }
+    rc = fill_stats(&h, out);   // synchronises (the hydrograph copy reads h's host vector)
+    if (rc != SWE_OK) fail(nullptr, rc, h.err);
+    return rc;
 }
 
 int swe_run_dt(swe_handle* h, int64_t nsteps, const double* dts, swe_stats* out) {

@@ -91,7 +91,7 @@ class Gauges(ctypes.Structure):
 
 #: every function include/swe.h declares
 EXPORTS = ("swe_abi_version", "swe_config_init", "swe_create", "swe_destroy", "swe_step",
-           "swe_run", "swe_run_dt", "swe_get_stats", "swe_trace_step", "swe_trace_bytes", "swe_save",
+           "swe_run", "swe_run_dt", "swe_run_noalloc", "swe_get_stats", "swe_trace_step", "swe_trace_bytes", "swe_save",
            "swe_load", "swe_last_error", "swe_probe_copy", "swe_grad", "swe_ensemble_create",
            "swe_ensemble_destroy", "swe_ensemble_run", "swe_ensemble_capture",
            "swe_ensemble_replay", "swe_ensemble_stats", "swe_ensemble_tile_rows",
@@ -123,6 +123,9 @@ def lib():
         L.swe_run_dt.argtypes = [H, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(_Stats)]
         L.swe_run_dt.restype = ctypes.c_int
+        L.swe_run_noalloc.argtypes = [ctypes.POINTER(Config), ctypes.c_int64, ctypes.c_double,
+                                      ctypes.POINTER(_Stats)]
+        L.swe_run_noalloc.restype = ctypes.c_int
         L.swe_get_stats.argtypes = [H, ctypes.POINTER(_Stats)]
         L.swe_get_stats.restype = ctypes.c_int
         L.swe_trace_step.argtypes = [H, ctypes.c_void_p, ctypes.c_size_t,
@@ -238,6 +241,23 @@ def _problem_kwargs(p):
                 eps_max=p.eps_max, dt_max=p.dt_max, dt_fixed=p.dt_fixed, bc=p.bc,
                 inflow_lo=p.inflow_lo, inflow_hi=p.inflow_hi, hydro_t=p.hydro_t,
                 hydro_q=p.hydro_q, h_switch=getattr(p, "h_switch", 0.0))
+
+
+def run_noalloc(z, n, eta, qx, qy, nsteps: int, t_end: float = math.inf, *, tile_rows: int = 0,
+                stream=None, check: bool = True, **kw) -> "Stats":
+    """swe_run_noalloc: nsteps steps of the fused path over caller-owned
+    tensors (eta, qx, qy advanced in place) without any device allocation;
+    returns the statistics."""
+    torch = _torch()
+    c, keep = _make_config(z, n, eta, qx, qy, path="fused", tile_rows=tile_rows, **kw)
+    st = _Stats()
+    with torch.cuda.device(eta.device):
+        c.stream = _stream_ptr(stream)
+        rc = lib().swe_run_noalloc(ctypes.byref(c), int(nsteps), float(t_end), ctypes.byref(st))
+    del keep
+    if check and rc != SWE_OK:
+        raise SweError(rc, last_error(None))
+    return Solver._stats(st)
 
 
 class Solver:
