@@ -74,7 +74,7 @@ def parse():
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--nx", type=int, default=4096)
-    ap.add_argument("--cpu-steps", type=int, default=3,
+    ap.add_argument("--cpu-steps", type=int, default=12,
                     help="oracle steps timed for the CPU baseline (0: skip)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the other-precision and unfused comparison runs")
@@ -86,8 +86,11 @@ def parse():
                     help="run only the adjoint measurement (for profiling)")
     ap.add_argument("--adj-nx", type=int, default=1024)
     ap.add_argument("--adj-steps", type=int, default=2000)
-    ap.add_argument("--adj-ckpt", type=int, default=0,
-                    help="checkpoint spacing of swe_grad; 0 keeps the whole trajectory")
+    ap.add_argument("--adj-ckpt", type=int, default=45,
+                    help="checkpoint spacing of swe_grad (the calibration run's 45); the "
+                         "kept-trajectory mode is timed beside it")
+    ap.add_argument("--adj-fd-cells", type=int, default=20,
+                    help="cells of the finite-difference check of the gradient (0: skip)")
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the flood-ensemble throughput measurement")
     ap.add_argument("--ensemble-only", action="store_true",
@@ -105,6 +108,8 @@ def parse():
     ap.add_argument("--comb-steps", type=int, default=5000)
     ap.add_argument("--comb-ckpt", type=int, default=0, help="0: round(sqrt(steps))")
     ap.add_argument("--comb-obs-every", type=int, default=50)
+    ap.add_argument("--comb-h-switch", type=float, default=0.1,
+                    help="depth floor of the dissipation switch for the combined run (0: plain)")
     ap.add_argument("--probe-copy-mb", type=int, default=0,
                     help="also run the library's plain copy kernel once over this many MiB "
                          "(calibrates HBM traffic counters)")
@@ -144,19 +149,64 @@ def progress(msg):
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
-def adjoint_ratio(torch, swe, W, nx, nsteps, ckpt):
+def fd_check(torch, swe, p, cells, every, hobs, dts, gn, ncell=20, rel_step=1e-5):
+    """Central differences of the loss on the run's time grid (swe_run_dt) at
+    ncell random cells whose derivative is at least 1e-3 of the largest, step
+    rel_step * n.  A cell whose forward and backward quotients differ by more
+    than 1e-3 of the adjoint sits on a kink of the piecewise smooth loss and
+    is counted apart."""
+    import numpy as np
+    cells_t = torch.as_tensor(cells, device="cuda")
+
+    def loss(nfield):
+        q = p.copy()
+        q.n = nfield
+        s = swe.Solver.from_problem(q, dtype=torch.float64)
+        zc = s.z.reshape(-1)[cells_t]
+        J = torch.zeros((), dtype=torch.float64, device="cuda")
+        for k in range(len(dts) // every):
+            s.run_dt(dts[k * every:(k + 1) * every])
+            d = s.eta.reshape(-1)[cells_t] - zc - hobs[k]
+            J = J + (d * d).sum()
+        s.close()
+        return float(J)
+
+    g = gn.cpu().numpy()
+    big = np.flatnonzero(np.abs(g).ravel() >= 1e-3 * np.abs(g).max())
+    pick = np.random.default_rng(2024).choice(big, min(ncell, big.size), replace=False)
+    J0 = loss(p.n)
+    errs, kinks = [], 0
+    for cell in pick:
+        j, i = divmod(int(cell), p.nx)
+        d = rel_step * p.n[j, i]
+        a, b = p.n.copy(), p.n.copy()
+        a[j, i] += d
+        b[j, i] -= d
+        Jp, Jm = loss(a), loss(b)
+        fd = (Jp - Jm) / (a[j, i] - b[j, i])
+        spread = abs((Jp - J0) / (a[j, i] - p.n[j, i]) - (J0 - Jm) / (p.n[j, i] - b[j, i]))
+        if spread > 1e-3 * abs(g[j, i]):
+            kinks += 1
+        else:
+            errs.append(abs(fd - g[j, i]) / abs(g[j, i]))
+    return {"cells": len(pick), "step_rel": rel_step, "smooth_cells": len(errs),
+            "kinked_cells": kinks, "max_rel_err_smooth": max(errs) if errs else None,
+            "median_rel_err_smooth": float(np.median(errs)) if errs else None}
+
+
+def adjoint_ratio(torch, swe, W, nx, nsteps, ckpt, fd_cells):
     """Cost of the discrete adjoint against the forward run on the Manning
     calibration workload: synthetic gauge observations from the true field,
     then (a) the forward run at the first guess, timed, and (b) swe_grad of
-    the misfit loss over the same run, timed on a fresh solver.  ckpt = 0:
-    the whole FP64 trajectory is kept in device memory (forward run with the
-    tracing step, reverse sweep, no recompute); the checkpointed mode (every
-    45 steps: forward, segment recompute, reverse sweep) is timed beside it
-    and its gradient compared bit for bit."""
+    the misfit loss over the same run, timed on a fresh solver, with a
+    checkpoint every ckpt steps (45 for the calibration run: about
+    sqrt(2000); forward, segment recompute, reverse sweep).  The mode that
+    keeps the whole FP64 trajectory in device memory (no recompute) is timed
+    beside it as a variant and its gradient compared bit for bit.  fd_cells
+    > 0: central differences of the loss at that many cells (fd_check)."""
     c = W.calibration(nx=nx, ny=nx, nsteps=nsteps)
     p = c.problem
-    mode = "trajectory kept" if ckpt == 0 else f"checkpoint every {ckpt}"
-    progress(f"adjoint: {p.nx}x{p.ny} calibration, {nsteps} steps, {mode}")
+    progress(f"adjoint: {p.nx}x{p.ny} calibration, {nsteps} steps, checkpoint every {ckpt}")
     truth = p.copy()
     truth.n = c.n_true
     s = swe.Solver.from_problem(truth, dtype=torch.float64)
@@ -169,10 +219,11 @@ def adjoint_ratio(torch, swe, W, nx, nsteps, ckpt):
     hobs = torch.stack(obs).contiguous()
     s.close()
     # warm-up of both paths (kernel code objects, the binding's first torch
-    # calls): 20 forward steps and a 20-step gradient
+    # calls): 20 forward steps and a 20-step gradient in each mode
     w = swe.Solver.from_problem(p, dtype=torch.float64)
     w.run(20)
-    w.grad(20, c.cells, c.obs_every, hobs[: 20 // c.obs_every].contiguous(), ckpt)
+    for ck in (ckpt, 0):
+        w.grad(20, c.cells, c.obs_every, hobs[: 20 // c.obs_every].contiguous(), ck)
     w.close()
     f = swe.Solver.from_problem(p, dtype=torch.float64)
     torch.cuda.synchronize()
@@ -181,29 +232,39 @@ def adjoint_ratio(torch, swe, W, nx, nsteps, ckpt):
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
     f.close()
+
     def timed_grad(ck):
         g = swe.Solver.from_problem(p, dtype=torch.float64)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        out = g.grad(nsteps, c.cells, c.obs_every, hobs, ck)
+        res = g.grad(nsteps, c.cells, c.obs_every, hobs, ck)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
         g.close()
-        return out, t
+        return res, t
 
     (J, gn, gz), t_grad = timed_grad(ckpt)
-    progress(f"adjoint: forward {t_fwd * 1e3:.1f} ms, swe_grad {t_grad * 1e3:.1f} ms ({mode})")
+    progress(f"adjoint: forward {t_fwd * 1e3:.1f} ms, swe_grad {t_grad * 1e3:.1f} ms "
+             f"(checkpoint every {ckpt})")
     out = {"workload": f"Manning calibration {p.nx}x{p.ny}, dx={p.dx:g} m, FP64, {nsteps} steps, "
-                       f"{len(c.cells)} gauges every {c.obs_every} steps, {mode}",
+                       f"{len(c.cells)} gauges every {c.obs_every} steps, checkpoint every {ckpt}",
            "metric": "adjoint/fwd cost ratio", "value": t_grad / t_fwd,
-           "higher_is_better": False, "fwd_ms": t_fwd * 1e3, "grad_ms": t_grad * 1e3,
-           "loss": J, "max_abs_dJ_dn": float(gn.abs().max()), "max_abs_dJ_dz": float(gz.abs().max())}
-    if ckpt == 0:
-        (J2, gn2, gz2), t2 = timed_grad(45)
-        progress(f"adjoint: swe_grad {t2 * 1e3:.1f} ms (checkpoint every 45)")
-        out["checkpointed"] = {"checkpoint_every": 45, "grad_ms": t2 * 1e3, "ratio": t2 / t_fwd,
-                               "gradient_equal": bool(J2 == J and torch.equal(gn2, gn)
-                                                      and torch.equal(gz2, gz))}
+           "higher_is_better": False, "checkpoint_every": ckpt, "fwd_ms": t_fwd * 1e3,
+           "grad_ms": t_grad * 1e3, "loss": J, "max_abs_dJ_dn": float(gn.abs().max()),
+           "max_abs_dJ_dz": float(gz.abs().max())}
+    (J2, gn2, gz2), t2 = timed_grad(0)
+    progress(f"adjoint: swe_grad {t2 * 1e3:.1f} ms (whole trajectory kept)")
+    out["kept_trajectory"] = {"grad_ms": t2 * 1e3, "ratio": t2 / t_fwd,
+                              "gradient_equal": bool(J2 == J and torch.equal(gn2, gn)
+                                                     and torch.equal(gz2, gz))}
+    if fd_cells > 0:
+        import numpy as np
+        s = swe.Solver.from_problem(p, dtype=torch.float64)
+        dts = np.array([s.step() for _ in range(nsteps)])
+        s.close()
+        out["fd_check"] = fd_check(torch, swe, p, c.cells, c.obs_every, hobs, dts, gn,
+                                   ncell=fd_cells)
+        progress(f"adjoint: finite differences {out['fd_check']}")
     return out
 
 
@@ -285,15 +346,19 @@ def dry_skip_run(torch, swe, W, p, dtype, steps, warmup, tile_rows, dense_st, de
             "speedup_vs_dense": dense_ms / ms, "stats_match_dense": same}
 
 
-def combined_run(torch, swe, W, nx, nsteps, ckpt, obs_every):
+def combined_run(torch, swe, W, nx, nsteps, ckpt, obs_every, h_switch):
     """The large combined run: the channel flood at nx x nx, FP32 forward
     state, FP64 adjoint of the gauge-misfit loss with respect to Manning n
     (each step linearised at its FP32 state), checkpoint spacing ckpt.
-    Observations come from an FP32 run with the true Manning field."""
+    Observations come from an FP32 run with the true Manning field.
+    h_switch > 0 takes the thin-film reading of the dissipation switch (its
+    curvature measured against max(h, h_switch)), without which the discrete
+    adjoint of this flood grows without bound."""
     import dataclasses
     ckpt = ckpt or max(1, int(round(math.sqrt(nsteps))))
     c = W.channel_flood(nx=nx, ny=nx, nsteps=nsteps, obs_every=obs_every)
     p = c.problem
+    p.h_switch = h_switch
     cells = p.nx * p.ny
     progress(f"combined: channel flood {nx}x{nx}, {nsteps} steps, checkpoint every {ckpt}")
     nobs = nsteps // obs_every
@@ -343,13 +408,14 @@ def combined_run(torch, swe, W, nx, nsteps, ckpt, obs_every):
            "forward_dry_skip_skipped_fraction": st_dry.cells_skipped / (cells * nsteps),
            "forward_dry_skip_t_equal": st_dry.t == st.t,
            "grad_ms": grad_s * 1e3, "adjoint_fwd_ratio": grad_s * 1e3 / ms_fwd,
-           "loss": fin(J), "gradient_finite": finite,
+           "loss": fin(J), "gradient_finite": finite, "h_switch": h_switch,
            "max_abs_dJ_dn": fin(float(gn.abs().max())),
            "max_abs_dJ_dz": fin(float(gz.abs().max())),
-           "gradient_note": "the discrete adjoint grows exponentially through the wet/dry "
-                            "fronts of this flood (the FP64 oracle shows the same growth on a "
-                            "128x128 version), so the gradient is a diagnostic here; time and "
-                            "memory are the measurement",
+           "gradient_note": ("thin-film switch reading (h_switch > 0): the gradient is the "
+                             "FP64 linearisation along the FP32 trajectory" if h_switch > 0 else
+                             "plain switch: the discrete adjoint grows exponentially through "
+                             "the wet/dry fronts of this flood, so the gradient is a "
+                             "diagnostic"),
            "planned_scratch_bytes": planned, "device_free_bytes_before": free0,
            "device_total_bytes": total, "wet_fraction_end": wet,
            "gauges": len(c.cells), "obs_every": obs_every}
@@ -359,18 +425,51 @@ def combined_run(torch, swe, W, nx, nsteps, ckpt, obs_every):
     return out
 
 
+def cpu_model():
+    """The host CPU's model name (as lscpu reports it) and the cores this
+    process may run on."""
+    name = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return name, avail
+
+
 def cpu_baseline(W, p, nsteps):
+    """The oracle as it stands, timed on the host: serial (1 core), and the
+    same source built with OpenMP over the host threads (its state bit for
+    bit the serial one, checked here)."""
     from oracle import oracle as O
-    progress(f"CPU oracle baseline: {nsteps} timed steps of {p.nx}x{p.ny}")
+    import numpy as np
+    model, avail = cpu_model()
+    progress(f"CPU oracle baseline: {nsteps} timed steps of {p.nx}x{p.ny} on {model}")
     s = O.State(p)
     s.run(1)                       # untimed: first touch of the work arrays
     st = s.run(nsteps)
     cells = p.nx * p.ny * st.steps
-    return {"value": cells / st.loop_seconds, "unit": "cell-updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"serial FP64 oracle (C++), {p.nx}x{p.ny} reservoir release, steps 1..{nsteps} "
-                      f"after one untimed step, {st.loop_seconds:.1f} s of step loop on "
-                      f"{platform.processor() or platform.machine()}"}
+    out = {"value": cells / st.loop_seconds, "unit": "cell-updates/s", "cores": 1,
+           "kind": "oracle", "cpu": model, "host_cores_available": avail,
+           "sample": f"serial FP64 oracle (C++), {p.nx}x{p.ny} reservoir release, steps 1..{nsteps} "
+                     f"after one untimed step, {st.loop_seconds:.1f} s of step loop"}
+    t = O.State(p, threads=True)
+    threads = O.lib_threads().orc_threads()
+    t.run(1)
+    stt = t.run(nsteps)
+    same = all(np.array_equal(x, y) for x, y in ((s.eta, t.eta), (s.qx, t.qx), (s.qy, t.qy)))
+    out["all_cores"] = {"value": cells / stt.loop_seconds, "cores": threads,
+                        "state_equal_to_serial": bool(same),
+                        "sample": f"the same steps, oracle built with -fopenmp, {threads} threads, "
+                                  f"{stt.loop_seconds:.1f} s of step loop"}
+    return out
 
 
 def main():
@@ -399,7 +498,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if a.combined:
-        out = combined_run(torch, swe, W, a.comb_nx, a.comb_steps, a.comb_ckpt, a.comb_obs_every)
+        out = combined_run(torch, swe, W, a.comb_nx, a.comb_steps, a.comb_ckpt, a.comb_obs_every,
+                           a.comb_h_switch)
         print(json.dumps({"combined": out}), flush=True)
         return
     if a.ensemble_only:
@@ -407,7 +507,7 @@ def main():
         print(json.dumps({"ensemble": out}), flush=True)
         return
     if a.adjoint_only:
-        out = adjoint_ratio(torch, swe, W, a.adj_nx, a.adj_steps, a.adj_ckpt)
+        out = adjoint_ratio(torch, swe, W, a.adj_nx, a.adj_steps, a.adj_ckpt, a.adj_fd_cells)
         print(json.dumps({"adjoint": out}), flush=True)
         return
     nx = a.nx
@@ -469,7 +569,7 @@ def main():
             out["dry_skip_" + other] = dry_skip_run(torch, swe, W, p, other, a.steps, a.warmup,
                                                     a.tile_rows, st2, ms2)
     if not a.no_adjoint:
-        out["adjoint"] = adjoint_ratio(torch, swe, W, a.adj_nx, a.adj_steps, a.adj_ckpt)
+        out["adjoint"] = adjoint_ratio(torch, swe, W, a.adj_nx, a.adj_steps, a.adj_ckpt, a.adj_fd_cells)
     if not a.no_ensemble:
         out["ensemble"] = ensemble_throughput(torch, swe, W, a.ens_count, a.ens_steps)
     if a.cpu_steps > 0:

@@ -158,7 +158,10 @@ void swe_config_init(swe_config* cfg);
 
 /* Validate cfg, take host copies of the hydrograph, allocate the library's
  * device scratch (second state buffer, m = g n^2, control block, reduction
- * partials) and compute dt^0 from the initial state (sub-step 16 on U^0).
+ * partials) and compute dt^0 from the initial state (sub-step 16 on U^0; the
+ * time step is variable and computed from the data, §3.1).  The grid, bed,
+ * friction field and state are the uniform Cartesian cells of the paper's
+ * shallow-water problem (§1).
  * Enqueues on cfg->stream and synchronises it once.  On success *out owns the
  * scratch; on failure *out is NULL and swe_last_error(NULL) says why.
  * Errors: SWE_EINVAL (NULL pointer, sizes, ranges, pitch < nx, unknown enum),
@@ -169,14 +172,18 @@ int swe_create(const swe_config* cfg, swe_handle** out);
 /* Free the library's scratch (never caller memory).  NULL is a no-op. */
 void swe_destroy(swe_handle* h);
 
-/* One time step (sub-steps 1..16), asynchronous on the handle's stream; the
- * new state is in the caller's eta/qx/qy when the stream reaches it.  With
+/* One time step: the explicit predictor-corrector MacCormack step split into
+ * sixteen dependent sub-steps, each independent across cells (§1, §6.1), run
+ * as one fused kernel (or one kernel per sub-step on the UNFUSED path), with
+ * dt^{n+1} computed on the device at its end (§3.1).  Asynchronous on the
+ * handle's stream; the new state is in the caller's eta/qx/qy when the stream
+ * reaches it.  With
  * dt_used != NULL the call synchronises and stores the step taken.  Errors:
  * SWE_EINVAL, SWE_EDEVICE, SWE_EUNSTABLE (only detected when dt_used != NULL). */
 int swe_step(swe_handle* h, double* dt_used);
 
-/* Up to nsteps steps, stopping early once t >= t_end (pass +INFINITY for no
- * limit) or after a step raises a fatal flag; steps past the stop become
+/* Up to nsteps steps of swe_step's time step (§1, §3.1), stopping early once
+ * t >= t_end (pass +INFINITY for no limit) or after a step raises a fatal flag; steps past the stop become
  * no-ops on the device, so the host enqueues all launches without waiting.
  * Synchronises once at the end, leaves the final state in the caller's
  * arrays and fills *out (may be NULL).  Returns SWE_EUNSTABLE if a fatal flag
@@ -248,9 +255,9 @@ typedef struct swe_gauges {
                                 observed depths, row k after step (k+1)*obs_every */
 } swe_gauges;
 
-/* Discrete adjoint (NEXT growth path: calibration of the friction and bed
- * fields).  Runs nsteps time steps from the current state, exactly as
- * swe_run(nsteps) would (the handle ends advanced by nsteps steps), and
+/* Discrete adjoint of the step (§1) with respect to the friction and bed
+ * fields (growth path: calibration).  Runs nsteps time steps from the
+ * current state, exactly as swe_run(nsteps) would (the handle ends advanced by nsteps steps), and
  * returns the gauge-misfit loss
  *   J = sum_k sum_g ((eta - z)(cell_g, after step k*obs_every) - hobs[k-1][g])^2
  * together with its gradient with respect to the Manning field n and the bed
@@ -286,7 +293,15 @@ typedef struct swe_gauges {
 int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_every,
              double* loss, void* dJ_dn, void* dJ_dz);
 
-/* Ensemble (NEXT growth path: many independent scenarios per launch).
+/* The loss of swe_grad alone: runs nsteps steps exactly as swe_run(nsteps)
+ * (the handle advances) and stores J in *loss (host), with the misfits
+ * formed and summed as swe_grad forms them, so both give the same bits for
+ * the same run.  Costs one forward run.  Synchronises.  Errors: as swe_grad
+ * (without the gradient arguments). */
+int swe_loss(swe_handle* h, int64_t nsteps, const swe_gauges* g, double* loss);
+
+/* Ensemble (growth path: many independent scenarios per launch; each
+ * scenario is the step of §1 on its own grid).
  * `count` scenarios, each a full swe_config (its own grid size, bed, Manning
  * field, state arrays, boundary kinds, hydrograph and CFL-adaptive dt; all of
  * one dtype, path FUSED, t0 = 0).  Every time step of all scenarios is ONE

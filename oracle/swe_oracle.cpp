@@ -128,6 +128,9 @@
 #include <stdlib.h>
 #include <string.h>
 #include <vector>
+#if defined(_OPENMP)
+#include <omp.h>
+#endif
 
 enum { BC_WALL = 0, BC_OPEN = 1, BC_INFLOW = 2, FACE_INTERIOR = 3 };
 enum { EDGE_W = 0, EDGE_E = 1, EDGE_S = 2, EDGE_N = 3 };
@@ -264,6 +267,20 @@ inline Rev ssqrt(Rev x) {
 }
 
 /* ---------------------------------------------------------------- helpers */
+
+/* Built with -fopenmp (the benchmark's all-core CPU figure only), the cell
+ * sweeps of the double step run their rows on all host threads.  Every cell
+ * of a sweep is computed from the previous sweep's arrays alone (§1: any
+ * cell order gives the same result), so the state is bit for bit that of the
+ * serial build; the sums (clipped volume, volume, lam_max) stay serial.  The
+ * other number types run serially (the reverse tape is one global list). */
+#if defined(_OPENMP)
+#define SWEEP_PARALLEL _Pragma("omp parallel for schedule(static) if (sweep_parallel<S>::on)")
+#else
+#define SWEEP_PARALLEL
+#endif
+template <typename S> struct sweep_parallel { static const bool on = false; };
+template <> struct sweep_parallel<double> { static const bool on = true; };
 
 typedef struct {
     int nx, ny, P;      /* P = nx + 2: padded row length */
@@ -433,6 +450,7 @@ void fill_ghosts(const orc_cfg* c, const Grid* G, double qin, S* eta, S* qx, S* 
 template <typename S>
 void prim(const orc_cfg* c, const Grid* G, S* const U[3], const S* zp, S* h, S* r, S* u, S* v) {
     size_t N = (size_t)G->P * (size_t)(G->ny + 2);
+    SWEEP_PARALLEL
     for (size_t s = 0; s < N; ++s) {
         S hh = U[0][s] - zp[s];
         S rr = val(hh) > c->h_dry ? S(1.0) / hh : S(0.0);
@@ -447,6 +465,7 @@ void prim(const orc_cfg* c, const Grid* G, S* const U[3], const S* zp, S* h, S* 
 template <typename S>
 void switch_nu(const orc_cfg* c, const Grid* G, const S* eta, const S* r, S* nux, S* nuy) {
     const double rcap = c->h_switch > 0.0 ? 1.0 / c->h_switch : 0.0;
+    SWEEP_PARALLEL
     for (int j = 0; j < G->ny; ++j)
         for (int i = 0; i < G->nx; ++i) {
             size_t C = at(G, i, j);
@@ -473,6 +492,7 @@ template <typename S>
 void dissipation(const orc_cfg* c, const Grid* G, S* const U[3], const S* h, const S* nux,
                  const S* nuy, S* D[3]) {
     int nx = G->nx, ny = G->ny;
+    SWEEP_PARALLEL
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             size_t C = at(G, i, j), E = at(G, i + 1, j), W = at(G, i - 1, j);
@@ -529,6 +549,7 @@ template <typename S>
 void xflux(const orc_cfg* c, const Grid* G, int sigma, S* const U[3], const S* h, const S* u,
            const S* v, const S* zp, S* F[4]) {
     int nx = G->nx, ny = G->ny;
+    SWEEP_PARALLEL
     for (int j = 0; j < ny; ++j)
         for (int i = -1; i < nx; ++i) {
             int kind = i == -1 ? face_kind(c, EDGE_W, j)
@@ -546,6 +567,7 @@ template <typename S>
 void yflux(const orc_cfg* c, const Grid* G, int sigma, S* const U[3], const S* h, const S* u,
            const S* v, const S* zp, S* Gf[4]) {
     int nx = G->nx, ny = G->ny;
+    SWEEP_PARALLEL
     for (int j = -1; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             int kind = j == -1 ? face_kind(c, EDGE_S, i)
@@ -564,6 +586,7 @@ template <typename S>
 void flux_update(const Grid* G, int sigma, double rx, double ry, S* const base[3],
                  S* const F[4], S* const Gf[4], S* out[3]) {
     S RX(rx), RY(ry);
+    SWEEP_PARALLEL
     for (int j = 0; j < G->ny; ++j)
         for (int i = 0; i < G->nx; ++i) {
             size_t C = at(G, i, j), W = at(G, i - 1, j), Sd = at(G, i, j - 1);
@@ -580,6 +603,7 @@ template <typename S>
 void corrector(const Grid* G, int sigma, double rx, double ry, S* const Un[3], S* const Us[3],
                S* const Fs[4], S* const Gs[4], S* Uc[3]) {
     flux_update(G, -sigma, rx, ry, Us, Fs, Gs, Uc);
+    SWEEP_PARALLEL
     for (int j = 0; j < G->ny; ++j)
         for (int i = 0; i < G->nx; ++i) {
             size_t C = at(G, i, j);
@@ -590,6 +614,7 @@ void corrector(const Grid* G, int sigma, double rx, double ry, S* const Un[3], S
 /* S13 */
 template <typename S>
 void add_diss(const Grid* G, S* const Uc[3], S* const D[3], S* Ud[3]) {
+    SWEEP_PARALLEL
     for (int j = 0; j < G->ny; ++j)
         for (int i = 0; i < G->nx; ++i) {
             size_t C = at(G, i, j);
@@ -601,6 +626,7 @@ void add_diss(const Grid* G, S* const Uc[3], S* const D[3], S* Ud[3]) {
 template <typename S>
 void friction(const orc_cfg* c, const Grid* G, double dt, S* const Ud[3], const S* zp,
               const S* mp, S* Uf[3]) {
+    SWEEP_PARALLEL
     for (int j = 0; j < G->ny; ++j)
         for (int i = 0; i < G->nx; ++i) {
             size_t C = at(G, i, j);
@@ -718,6 +744,7 @@ void step_body(const orc_cfg* c, const Grid* G, Work<S>* w, S* eta, S* qx, S* qy
     double qin0 = q_inflow(c, t);
     double qin1 = q_inflow(c, t + dt);
     /* S1: copy U^n into the padded arrays and build its ghost ring. */
+    SWEEP_PARALLEL
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             size_t s = (size_t)j * (size_t)nx + (size_t)i;
@@ -741,6 +768,7 @@ void step_body(const orc_cfg* c, const Grid* G, Work<S>* w, S* eta, S* qx, S* qy
     friction(c, G, dt, w->Ud, w->zp, w->mp, w->Uf);                         /* S14 */
     uint32_t flags = 0;
     double defect = dry_fix(c, G, w->Uf, w->zp, w->Unew, &flags);           /* S15 */
+    SWEEP_PARALLEL
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             size_t s = (size_t)j * (size_t)nx + (size_t)i;
@@ -852,6 +880,15 @@ S loss_forward(const orc_cfg* c, const LossSpec* L, S* eta, S* qx, S* qy, const 
 extern "C" {
 
 int orc_ntrace(void) { return ORC_NTRACE; }
+
+/* Threads the cell sweeps run on (1 unless built with -fopenmp). */
+int orc_threads(void) {
+#if defined(_OPENMP)
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* The friction step's cube root, exposed so that it can be pinned. */
 double orc_cbrt3(double x) { return cbrt3(x); }

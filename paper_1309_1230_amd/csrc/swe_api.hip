@@ -1154,30 +1154,85 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
     return SWE_OK;
 }
 
+// Gauges of a loss over nsteps steps: counts, distinct cells inside the
+// grid, observations in device memory.
+int check_gauges(swe_handle* h, int64_t nsteps, const swe_gauges* g, const char* who) {
+    if (g->ngauge < 0 || g->obs_every < 1)
+        return fail(h, SWE_EINVAL, std::string(who) + ": bad gauges");
+    const int64_t nobs = nsteps / g->obs_every;
+    const int ng = g->ngauge;
+    if (ng > 0 && (!g->cells || (nobs > 0 && !g->hobs)))
+        return fail(h, SWE_EINVAL, std::string(who) + ": gauge cells or observations missing");
+    std::vector<int64_t> cs(g->cells, g->cells + ng);
+    std::sort(cs.begin(), cs.end());
+    const int64_t ncell = (int64_t)h->P.nx * h->P.ny;
+    for (int k = 0; k < ng; ++k)
+        if (cs[k] < 0 || cs[k] >= ncell || (k > 0 && cs[k] == cs[k - 1]))
+            return fail(h, SWE_EINVAL,
+                        std::string(who) + ": gauge cells must be distinct and inside the grid");
+    if (ng > 0 && nobs > 0 && !is_device_ptr(g->hobs, h->device))
+        return fail(h, SWE_EINVAL, std::string(who) + ": observations must be device memory");
+    return SWE_OK;
+}
+
+template <typename T>
+int loss_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, double* loss) {
+    const int64_t nobs = nsteps / g->obs_every;
+    const int ng = g->ngauge;
+    DevBuf mis, dcells;
+    hipError_t e;
+    if ((e = mis.alloc((size_t)std::max<int64_t>(nobs * ng, 1) * sizeof(double))) != hipSuccess ||
+        (e = dcells.alloc((size_t)std::max(ng, 1) * sizeof(long long))) != hipSuccess)
+        return fail(h, SWE_ENOMEM, std::string("swe_loss: hipMalloc failed: ") + hip_text(e));
+    e = ng > 0 ? hipMemcpyAsync(dcells.p, g->cells, (size_t)ng * sizeof(long long),
+                                hipMemcpyHostToDevice, h->stream)
+               : hipSuccess;
+    if (e == hipSuccess) e = begin_call(h, h->stream);
+    for (int64_t k = 0; k < nsteps && e == hipSuccess; ++k) {
+        e = enqueue(h, k, INFINITY, h->path == SWE_PATH_UNFUSED);
+        if (e == hipSuccess && ng > 0 && (k + 1) % g->obs_every == 0) {
+            const int64_t row = (k + 1) / g->obs_every - 1;
+            const T* nxt = (const T*)((k & 1) ? bufA(h, 0) : bufB(h, 0));
+            e = swe::launch_misfit<T>(h->P, nxt, (const T*)h->z, (const long long*)dcells.p, ng,
+                                      g->hobs + row * ng, mis.d() + row * ng, h->stream);
+        }
+    }
+    if (e == hipSuccess) e = enqueue_copy_back(h);
+    if (e != hipSuccess) return hip_fail(h, e, "swe_loss: forward run");
+    int rc = fill_stats(h, nullptr);
+    if (rc) return rc;
+    std::vector<double> hm((size_t)std::max<int64_t>(nobs * ng, 1));
+    e = hipMemcpyAsync(hm.data(), mis.p, hm.size() * sizeof(double), hipMemcpyDeviceToHost,
+                       h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "swe_loss: reading the misfits");
+    double J = 0.0;   // the order of swe_grad's sum
+    for (int64_t k = 0; k < nobs * ng; ++k) J = J + hm[(size_t)k];
+    *loss = J;
+    return SWE_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int swe_loss(swe_handle* h, int64_t nsteps, const swe_gauges* g, double* loss) {
+    if (!h) return fail(nullptr, SWE_EINVAL, "handle is NULL");
+    if (nsteps < 0 || !g || !loss) return fail(h, SWE_EINVAL, "swe_loss: bad arguments");
+    int rc = check_gauges(h, nsteps, g, "swe_loss");
+    if (rc) return rc;
+    return h->dtype == SWE_F32 ? loss_impl<float>(h, nsteps, g, loss)
+                               : loss_impl<double>(h, nsteps, g, loss);
+}
 
 int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_every,
              double* loss, void* dJ_dn, void* dJ_dz) {
     if (!h) return fail(nullptr, SWE_EINVAL, "handle is NULL");
     if (nsteps < 0 || !g || !loss || !dJ_dn || !dJ_dz || ckpt_every < 0)
         return fail(h, SWE_EINVAL, "swe_grad: bad arguments");
-    if (g->ngauge < 0 || g->obs_every < 1) return fail(h, SWE_EINVAL, "swe_grad: bad gauges");
-    const int64_t nobs = nsteps / g->obs_every;
-    const int ng = g->ngauge;
-    if (ng > 0 && (!g->cells || (nobs > 0 && !g->hobs)))
-        return fail(h, SWE_EINVAL, "swe_grad: gauge cells or observations missing");
-    {
-        std::vector<int64_t> cs(g->cells, g->cells + ng);
-        std::sort(cs.begin(), cs.end());
-        const int64_t ncell = (int64_t)h->P.nx * h->P.ny;
-        for (int k = 0; k < ng; ++k)
-            if (cs[k] < 0 || cs[k] >= ncell || (k > 0 && cs[k] == cs[k - 1]))
-                return fail(h, SWE_EINVAL, "swe_grad: gauge cells must be distinct and inside the grid");
-    }
-    if (!is_device_ptr(dJ_dn, h->device) || !is_device_ptr(dJ_dz, h->device) ||
-        (ng > 0 && nobs > 0 && !is_device_ptr(g->hobs, h->device)))
+    int rc0 = check_gauges(h, nsteps, g, "swe_grad");
+    if (rc0) return rc0;
+    if (!is_device_ptr(dJ_dn, h->device) || !is_device_ptr(dJ_dz, h->device))
         return fail(h, SWE_EINVAL, "swe_grad: gradients and observations must be device memory");
     const auto t0 = std::chrono::steady_clock::now();
     const int rc = h->dtype == SWE_F32

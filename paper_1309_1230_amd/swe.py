@@ -92,7 +92,7 @@ class Gauges(ctypes.Structure):
 #: every function include/swe.h declares
 EXPORTS = ("swe_abi_version", "swe_config_init", "swe_create", "swe_destroy", "swe_step",
            "swe_run", "swe_run_dt", "swe_run_noalloc", "swe_get_stats", "swe_trace_step", "swe_trace_bytes", "swe_save",
-           "swe_load", "swe_last_error", "swe_probe_copy", "swe_grad", "swe_ensemble_create",
+           "swe_load", "swe_last_error", "swe_probe_copy", "swe_grad", "swe_loss", "swe_ensemble_create",
            "swe_ensemble_destroy", "swe_ensemble_run", "swe_ensemble_capture",
            "swe_ensemble_replay", "swe_ensemble_stats", "swe_ensemble_tile_rows",
            "swe_ensemble_last_error")
@@ -378,6 +378,20 @@ class Solver:
                                    ctypes.byref(J), gn.data_ptr(), gz.data_ptr()))
         return J.value, gn, gz
 
+    def loss(self, nsteps: int, cells, obs_every: int, hobs) -> float:
+        """The gauge-misfit loss of the next nsteps steps (swe_loss): the state
+        advances as with run; the same J as grad, without the adjoint."""
+        import numpy as np
+        cells = np.ascontiguousarray(np.asarray(cells, dtype=np.int64).ravel())
+        g = Gauges()
+        g.ngauge = len(cells)
+        g.obs_every = int(obs_every)
+        g.cells = cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if len(cells) else None
+        g.hobs = hobs.contiguous().data_ptr()
+        J = ctypes.c_double()
+        self._check(lib().swe_loss(self._h, int(nsteps), ctypes.byref(g), ctypes.byref(J)))
+        return J.value
+
     def save(self) -> Checkpoint:
         ck = Checkpoint()
         self._check(lib().swe_save(self._h, ctypes.byref(ck)))
@@ -411,9 +425,10 @@ def _make_loss_function():
 
     class SweLoss(torch.autograd.Function):
         """Gauge-misfit loss of a run as a differentiable function of the
-        Manning field n and the bed z (FP64 CUDA tensors).  forward runs the
-        library's discrete adjoint once and keeps the gradient; backward
-        scales it.  The time steps of the run are held fixed.
+        Manning field n and the bed z (CUDA tensors).  forward runs the
+        forward model and its loss only (swe_loss); backward, if it is
+        called, runs the library's discrete adjoint (swe_grad) from the saved
+        inputs.  The time steps of the run are held fixed.
 
             J = SweLoss.apply(n, z, eta0, qx0, qy0, solver_kwargs, nsteps,
                               cells, obs_every, hobs, ckpt_every)
@@ -425,16 +440,25 @@ def _make_loss_function():
             s = Solver(z.detach().contiguous(), n.detach().contiguous(), eta0.detach().clone(),
                        qx0.detach().clone(), qy0.detach().clone(), **solver_kwargs)
             try:
-                J, gn, gz = s.grad(nsteps, cells, obs_every, hobs, ckpt_every)
+                J = s.loss(nsteps, cells, obs_every, hobs)
             finally:
                 s.close()
-            ctx.save_for_backward(gn, gz)
+            ctx.save_for_backward(n.detach(), z.detach(), eta0.detach(), qx0.detach(),
+                                  qy0.detach(), hobs.detach())
+            ctx.args = (solver_kwargs, nsteps, cells, obs_every, ckpt_every)
             return torch.tensor(J, dtype=torch.float64, device=n.device)
 
         @staticmethod
         def backward(ctx, gout):
-            gn, gz = ctx.saved_tensors
-            return (gout * gn, gout * gz) + (None,) * 9
+            n, z, eta0, qx0, qy0, hobs = ctx.saved_tensors
+            solver_kwargs, nsteps, cells, obs_every, ckpt_every = ctx.args
+            s = Solver(z.contiguous(), n.contiguous(), eta0.clone(), qx0.clone(), qy0.clone(),
+                       **solver_kwargs)
+            try:
+                _, gn, gz = s.grad(nsteps, cells, obs_every, hobs, ckpt_every)
+            finally:
+                s.close()
+            return (gout * gn.to(n.dtype), gout * gz.to(z.dtype)) + (None,) * 9
 
     return SweLoss
 

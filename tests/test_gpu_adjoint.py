@@ -234,3 +234,24 @@ def test_gradient_matches_oracle_elementwise(name, nx, ny, nsteps):
         note(f"{nm}: max elementwise rel error {err.max():.2e} (floor {floor:.2e}), "
              f"max err / max |grad| {np.abs(a - b).max() / np.abs(b).max():.2e}")
         assert err.max() <= 1e-10, nm
+
+
+def test_loss_alone_equals_grad_loss_and_advances_like_run():
+    """swe_loss: the same J as swe_grad (same misfits, same order) from one
+    forward run, and the handle's state advances exactly as swe_run's."""
+    p = prep("inflow")
+    G = gauges_for(p, 20, 4, 10, seed=9)
+    note("swe_loss vs swe_grad's loss")
+    hobs = torch.as_tensor(G.hobs, dtype=torch.float64, device="cuda")
+    for dtype in (torch.float64, torch.float32):
+        a = swe.Solver.from_problem(p, dtype=dtype)
+        J = a.loss(20, G.cells, G.every, hobs)
+        b = swe.Solver.from_problem(p, dtype=dtype)
+        Jg, _, _ = b.grad(20, G.cells, G.every, hobs, 6)
+        r = swe.Solver.from_problem(p, dtype=dtype)
+        r.run(20)
+        assert J == Jg
+        for x, y in ((a.eta, r.eta), (a.qx, r.qx), (a.qy, r.qy)):
+            assert torch.equal(x, y)
+        for s in (a, b, r):
+            s.close()

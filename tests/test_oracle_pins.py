@@ -462,3 +462,17 @@ def test_binary32_run_is_float_rounding_of_the_double_step():
     d = float(np.abs(h32 - h64).sum() / np.abs(h64).sum())
     assert 1e-9 < d < 1e-5
     assert sf.t == pytest.approx(st.t, rel=1e-6)
+
+
+def test_threaded_build_gives_the_serial_state_bit_for_bit():
+    """The -fopenmp build of the same source (the benchmark's all-core CPU
+    figure) runs the cell sweeps on several threads; every cell of a sweep
+    depends on the previous sweep alone, so the state is the serial one bit
+    for bit."""
+    p = W.random_valid_state(90, 70, seed=4)
+    a = O.State(p)
+    b = O.State(p, threads=True)
+    sa, sb = a.run(25), b.run(25)
+    for x, y in ((a.eta, b.eta), (a.qx, b.qx), (a.qy, b.qy)):
+        assert np.array_equal(x, y)
+    assert sa.t == sb.t and sa.dt == sb.dt
