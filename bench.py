@@ -108,7 +108,7 @@ def parse():
     ap.add_argument("--comb-steps", type=int, default=5000)
     ap.add_argument("--comb-ckpt", type=int, default=0, help="0: round(sqrt(steps))")
     ap.add_argument("--comb-obs-every", type=int, default=50)
-    ap.add_argument("--comb-h-switch", type=float, default=0.1,
+    ap.add_argument("--comb-h-film", type=float, default=0.1,
                     help="depth floor of the dissipation switch for the combined run (0: plain)")
     ap.add_argument("--probe-copy-mb", type=int, default=0,
                     help="also run the library's plain copy kernel once over this many MiB "
@@ -346,19 +346,19 @@ def dry_skip_run(torch, swe, W, p, dtype, steps, warmup, tile_rows, dense_st, de
             "speedup_vs_dense": dense_ms / ms, "stats_match_dense": same}
 
 
-def combined_run(torch, swe, W, nx, nsteps, ckpt, obs_every, h_switch):
+def combined_run(torch, swe, W, nx, nsteps, ckpt, obs_every, h_film):
     """The large combined run: the channel flood at nx x nx, FP32 forward
     state, FP64 adjoint of the gauge-misfit loss with respect to Manning n
     (each step linearised at its FP32 state), checkpoint spacing ckpt.
     Observations come from an FP32 run with the true Manning field.
-    h_switch > 0 takes the thin-film reading of the dissipation switch (its
-    curvature measured against max(h, h_switch)), without which the discrete
+    h_film > 0 takes the thin-film reading of the dissipation switch (its
+    curvature measured against max(h, h_film)), without which the discrete
     adjoint of this flood grows without bound."""
     import dataclasses
     ckpt = ckpt or max(1, int(round(math.sqrt(nsteps))))
     c = W.channel_flood(nx=nx, ny=nx, nsteps=nsteps, obs_every=obs_every)
     p = c.problem
-    p.h_switch = h_switch
+    p.h_film = h_film
     cells = p.nx * p.ny
     progress(f"combined: channel flood {nx}x{nx}, {nsteps} steps, checkpoint every {ckpt}")
     nobs = nsteps // obs_every
@@ -408,11 +408,11 @@ def combined_run(torch, swe, W, nx, nsteps, ckpt, obs_every, h_switch):
            "forward_dry_skip_skipped_fraction": st_dry.cells_skipped / (cells * nsteps),
            "forward_dry_skip_t_equal": st_dry.t == st.t,
            "grad_ms": grad_s * 1e3, "adjoint_fwd_ratio": grad_s * 1e3 / ms_fwd,
-           "loss": fin(J), "gradient_finite": finite, "h_switch": h_switch,
+           "loss": fin(J), "gradient_finite": finite, "h_film": h_film,
            "max_abs_dJ_dn": fin(float(gn.abs().max())),
            "max_abs_dJ_dz": fin(float(gz.abs().max())),
-           "gradient_note": ("thin-film switch reading (h_switch > 0): the gradient is the "
-                             "FP64 linearisation along the FP32 trajectory" if h_switch > 0 else
+           "gradient_note": ("thin-film switch reading (h_film > 0): the gradient is the "
+                             "FP64 linearisation along the FP32 trajectory" if h_film > 0 else
                              "plain switch: the discrete adjoint grows exponentially through "
                              "the wet/dry fronts of this flood, so the gradient is a "
                              "diagnostic"),
@@ -423,6 +423,35 @@ def combined_run(torch, swe, W, nx, nsteps, ckpt, obs_every, h_switch):
     progress(f"combined: forward {ms_fwd:.0f} ms, swe_grad {grad_s * 1e3:.0f} ms, "
              f"ratio {out['adjoint_fwd_ratio']:.1f}, wet fraction {wet:.4f}")
     return out
+
+
+def stream_probe(torch, swe, dtype, cells, reps=7):
+    """The achievable-bandwidth ceiling for the step's traffic: the library's
+    stream kernel reading five and writing three arrays of the workload's
+    size (one pass per launch), with and without non-temporal hints; median
+    of reps launches timed with HIP events."""
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    ins = [torch.ones(cells, dtype=tdt, device="cuda") for _ in range(5)]
+    outs = [torch.empty(cells, dtype=tdt, device="cuda") for _ in range(3)]
+    nbytes = 8 * cells * ins[0].element_size()
+    res = {}
+    for nt in (False, True):
+        swe.probe_stream(ins, outs, nontemporal=nt)
+        ts = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            swe.probe_stream(ins, outs, nontemporal=nt)
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        ms = sorted(ts)[len(ts) // 2]
+        res["nontemporal_GBps" if nt else "plain_GBps"] = nbytes / (ms / 1e3) / 1e9
+    res["bytes_per_launch"] = nbytes
+    res["note"] = "5 arrays read + 3 written, 16 B per lane, grid-stride (swe_probe_stream)"
+    del ins, outs
+    return res
 
 
 def cpu_model():
@@ -499,7 +528,7 @@ def main():
         del src, dst
     if a.combined:
         out = combined_run(torch, swe, W, a.comb_nx, a.comb_steps, a.comb_ckpt, a.comb_obs_every,
-                           a.comb_h_switch)
+                           a.comb_h_film)
         print(json.dumps({"combined": out}), flush=True)
         return
     if a.ensemble_only:
@@ -547,6 +576,8 @@ def main():
                      "bytes_per_cell_update": bpc},
         "wall_s": wall,
     }
+    out["stream_probe"] = stream_probe(torch, swe, a.dtype, cells)
+    out["roofline"]["frac_of_stream_probe"] = achieved / out["stream_probe"]["plain_GBps"]
     if a.dry_only:
         out["dry_skip"] = dry_skip_run(torch, swe, W, p, a.dtype, a.steps, a.warmup, a.tile_rows,
                                        st, ms)

@@ -108,16 +108,17 @@ typedef struct swe_config {
                               * from a dense first step at the start of every call
                               * (swe_run, swe_step, ensemble run or replay), so the
                               * caller may change the state between calls. */
-    double h_switch;         /* thin-film reading of the dissipation switch (S3): > 0
-                              * measures the surface curvature against
-                              * max(h, h_switch) instead of h, i.e. the switch's
-                              * reciprocal depth is min(1/h, 1/h_switch); 0 (the
-                              * default) is the plain scheme.  The paper leaves dry
-                              * and drying cells to future work (§6.2); without this
-                              * the discrete adjoint of a flood over dry land grows
-                              * without bound through the switch's 1/h^2 depth
-                              * derivative in thin films.  Cells deeper than h_switch
-                              * are unaffected. */
+    double h_film;           /* thin-film reading (m): > 0 makes the reciprocal depth
+                              * of sub-steps 2 and 9 min(1/h, 1/h_film), so films
+                              * thinner than h_film take their velocities (q/h_film)
+                              * and their dissipation switch from that depth; mass
+                              * fluxes, friction and the CFL step keep the true
+                              * depth.  0 (the default) is the plain scheme.  The
+                              * paper leaves dry and drying cells to future work
+                              * (§6.2); without this the discrete adjoint of a flood
+                              * over dry land grows without bound through the 1/h^2
+                              * depth derivative in thin films.  Cells deeper than
+                              * h_film are unaffected. */
 } swe_config;
 
 /* Progress and diagnostics of a handle. */
@@ -340,6 +341,16 @@ const char* swe_ensemble_last_error(const swe_ensemble* e);
  * pointers 16-byte aligned) on `stream`: the bandwidth probe the HBM traffic
  * counters are calibrated against.  Asynchronous.  SWE_EINVAL on misuse. */
 int swe_probe_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+/* The fused step's memory traffic as a plain stream: five device arrays of
+ * `bytes` bytes read (in[0..4]) and three written (out[0..2]), one pass,
+ * grid-stride, 16 bytes per lane; nontemporal != 0 adds the non-temporal
+ * hint to every load and store.  The achievable-bandwidth ceiling that the
+ * step's 8-array traffic is measured against (the paper's GPU was bound by
+ * its global-memory accesses, §3.2).  Arrays 16-byte aligned, bytes a
+ * multiple of 16.  Asynchronous.  SWE_EINVAL on misuse. */
+int swe_probe_stream(const void* const* in, void* const* out, size_t bytes, int nontemporal,
+                     void* stream);
 
 #ifdef __cplusplus
 }

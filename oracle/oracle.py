@@ -59,7 +59,7 @@ class _Cfg(ctypes.Structure):
                 ("dx", "dy", "g", "cfl", "h_dry", "kappa", "eps_max", "dt_max", "dt_fixed")] + [
                 ("hydro_t", ctypes.POINTER(ctypes.c_double)),
                 ("hydro_q", ctypes.POINTER(ctypes.c_double)),
-                ("h_switch", ctypes.c_double)]
+                ("h_film", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -144,7 +144,7 @@ def _cfg(p, keep):
     c.hydro_q = _ptr(hq) if len(hq) else None
     for f in ("dx", "dy", "g", "cfl", "h_dry", "kappa", "eps_max", "dt_max", "dt_fixed"):
         setattr(c, f, float(getattr(p, f)))
-    c.h_switch = float(getattr(p, "h_switch", 0.0))
+    c.h_film = float(getattr(p, "h_film", 0.0))
     return c
 
 

@@ -45,14 +45,14 @@
  *       domain, tangential 0.  An INFLOW edge acts as WALL outside its face
  *       band [lo, hi).  z of a ghost = z of the adjacent cell.
  *   S2  PRIM(U^n): h = eta - z; wet <=> h > h_dry; r = wet ? 1/h : 0;
- *       u = qx*r; v = qy*r.  Over every padded cell.
- *   S3  SWITCH: nu_x = 0.25*(|(eta_E - eta_C) - (eta_C - eta_W)| * r_C), nu_y
- *       likewise with N/S.  Interior cells.  With the thin-film reading
- *       (h_switch > 0) r_C is replaced by min(r_C, 1/h_switch), i.e. the
- *       surface curvature is measured against max(h_C, h_switch): in films
- *       thinner than h_switch the switch no longer grows as 1/h.  (Its
- *       derivative with respect to the depth, |d2 eta|/h^2, is what makes
+ *       u = qx*r; v = qy*r.  Over every padded cell.  With the thin-film
+ *       reading (h_film > 0) r = wet ? min(1/h, 1/h_film) : 0: in films
+ *       thinner than h_film the velocities are q/h_film and S3 measures the
+ *       curvature against h_film.  (In such films 1/h, and its depth
+ *       derivative 1/h^2 through the velocities and the switch, is what makes
  *       the discrete adjoint of a flood over dry land grow without bound.)
+ *   S3  SWITCH: nu_x = 0.25*(|(eta_E - eta_C) - (eta_C - eta_W)| * r_C), nu_y
+ *       likewise with N/S.  Interior cells.
  *   S4  DISS: face coefficient eps = (wet_L && wet_R) ?
  *       min(kappa*max(nu_L, nu_R), eps_max) : 0 on interior faces, 0 on
  *       boundary faces; for each of eta, qx, qy:
@@ -151,7 +151,7 @@ typedef struct orc_cfg {
     int32_t pad_;
     double dx, dy, g, cfl, h_dry, kappa, eps_max, dt_max, dt_fixed;
     const double *hydro_t, *hydro_q;
-    double h_switch;    /* > 0: depth floor of the S3 switch (thin-film reading); 0: off */
+    double h_film;      /* > 0: thin-film depth of S2/S9's reciprocal (reading); 0: off */
 } orc_cfg;
 
 typedef struct orc_stats {
@@ -454,6 +454,7 @@ void prim(const orc_cfg* c, const Grid* G, S* const U[3], const S* zp, S* h, S* 
     for (size_t s = 0; s < N; ++s) {
         S hh = U[0][s] - zp[s];
         S rr = val(hh) > c->h_dry ? S(1.0) / hh : S(0.0);
+        if (c->h_film > 0.0) rr = dmin(rr, S(1.0 / c->h_film));   /* thin-film reading */
         h[s] = hh;
         r[s] = rr;
         u[s] = U[1][s] * rr;
@@ -463,8 +464,7 @@ void prim(const orc_cfg* c, const Grid* G, S* const U[3], const S* zp, S* h, S* 
 
 /* S3: dissipation switch from the curvature of the water surface. */
 template <typename S>
-void switch_nu(const orc_cfg* c, const Grid* G, const S* eta, const S* r, S* nux, S* nuy) {
-    const double rcap = c->h_switch > 0.0 ? 1.0 / c->h_switch : 0.0;
+void switch_nu(const Grid* G, const S* eta, const S* r, S* nux, S* nuy) {
     SWEEP_PARALLEL
     for (int j = 0; j < G->ny; ++j)
         for (int i = 0; i < G->nx; ++i) {
@@ -473,10 +473,8 @@ void switch_nu(const orc_cfg* c, const Grid* G, const S* eta, const S* r, S* nux
             S bx = eta[C] - eta[at(G, i - 1, j)];
             S ay = eta[at(G, i, j + 1)] - eta[C];
             S by = eta[C] - eta[at(G, i, j - 1)];
-            /* the switch's reciprocal depth: r_C, or 1/max(h_C, h_switch) */
-            S rs = c->h_switch > 0.0 ? dmin(r[C], S(rcap)) : r[C];
-            nux[C] = S(0.25) * (sfabs(ax - bx) * rs);
-            nuy[C] = S(0.25) * (sfabs(ay - by) * rs);
+            nux[C] = S(0.25) * (sfabs(ax - bx) * r[C]);
+            nuy[C] = S(0.25) * (sfabs(ay - by) * r[C]);
         }
 }
 
@@ -754,7 +752,7 @@ void step_body(const orc_cfg* c, const Grid* G, Work<S>* w, S* eta, S* qx, S* qy
         }
     fill_ghosts(c, G, qin0, w->Un[0], w->Un[1], w->Un[2]);
     prim(c, G, w->Un, w->zp, w->h, w->r, w->u, w->v);                       /* S2 */
-    switch_nu(c, G, w->Un[0], w->r, w->nux, w->nuy);                        /* S3 */
+    switch_nu(G, w->Un[0], w->r, w->nux, w->nuy);                           /* S3 */
     dissipation(c, G, w->Un, w->h, w->nux, w->nuy, w->D);                   /* S4 */
     xflux(c, G, sigma, w->Un, w->h, w->u, w->v, w->zp, w->F);               /* S5 */
     yflux(c, G, sigma, w->Un, w->h, w->u, w->v, w->zp, w->G);               /* S6 */

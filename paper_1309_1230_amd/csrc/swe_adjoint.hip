@@ -100,7 +100,7 @@ __device__ __forceinline__ Cell make_cell(const Params& P, double e, double qx, 
         ghost(j < 0 ? face_kind(P, EDGE_S, i) : face_kind(P, EDGE_N, i), false,
               j < 0 ? qin : -qin, c.e, c.qx, c.qy, c.e, c.qx, c.qy);
     c.h = c.e - zpv;
-    c.r = recip_depth(c.h, P.h_dry);
+    c.r = recip_prim(c.h, P.h_dry, P.rcap);
     c.u = c.qx * c.r;
     c.v = c.qy * c.r;
     return c;
@@ -133,7 +133,7 @@ __device__ __forceinline__ double nu_at(const AdjointArgs& a, int i, int j, bool
     const double* E = a.un[0];
     const double eM = xdir ? eta_at(a.P, E, i - 1, j) : eta_at(a.P, E, i, j - 1);
     const double eP = xdir ? eta_at(a.P, E, i + 1, j) : eta_at(a.P, E, i, j + 1);
-    return curv_switch(eM, eC, eP, rC, a.P.rcap);
+    return curv_switch(eM, eC, eP, rC);
 }
 
 // The friction cube root y = cbrt3(x) with its Halley steps kept: the same
@@ -541,7 +541,8 @@ __global__ void k_adj_c(AdjointArgs a) {
     qxb += cb.u * r;
     qyb += cb.v * r;
     const double rb = cb.u * me.qx + cb.v * me.qy;
-    const double hb = cb.h + (h > a.P.h_dry ? -(rb * r) * r : 0.0);
+    // r = min(1/h, rcap): its depth derivative vanishes where the cap was taken
+    const double hb = cb.h + (h > a.P.h_dry && r < a.P.rcap ? -(rb * r) * r : 0.0);
     eb += hb;
     double* AUS = wk(a, d, W_AUS);
     AUS[C] = eb;
@@ -613,15 +614,13 @@ __global__ void k_adj_e1(AdjointArgs a) {
 }
 
 // d-bar of the curvature switch at interior cell X (x or y direction), and
-// its |d| for the r-bar term.  Under the thin-film reading the switch used
-// min(rX, rcap): the r-bar term exists only where it used rX itself.
+// its |d| for the r-bar term.
 __device__ __forceinline__ double switch_dbar(double eXm, double eX, double eXp, double rX,
-                                              double rcap, double nubX, double& absd_t) {
+                                              double nubX, double& absd_t) {
     const double dd = (eXp - eX) - (eX - eXm);
     const double t = 0.25 * nubX;
-    const bool live = rX < rcap;
-    absd_t = live ? t * __builtin_fabs(dd) : 0.0;
-    const double absb = t * (live ? rX : rcap);
+    absd_t = t * __builtin_fabs(dd);
+    const double absb = t * rX;
     return dd > 0.0 ? absb : (dd < 0.0 ? -absb : 0.0);
 }
 
@@ -657,9 +656,9 @@ __global__ void k_adj_e2(AdjointArgs a) {
             const double eX = E[pitched(a.P, xi, xj)];
             const double eXm = dirn == 0 ? eta_at(a.P, E, xi - 1, xj) : eta_at(a.P, E, xi, xj - 1);
             const double eXp = dirn == 0 ? eta_at(a.P, E, xi + 1, xj) : eta_at(a.P, E, xi, xj + 1);
-            const double rX = recip_depth(eX - a.zp[d.at(xi, xj)], a.P.h_dry);
+            const double rX = recip_prim(eX - a.zp[d.at(xi, xj)], a.P.h_dry, a.P.rcap);
             double absd_t;
-            const double db = switch_dbar(eXm, eX, eXp, rX, a.P.rcap, NUB[d.at(xi, xj)], absd_t);
+            const double db = switch_dbar(eXm, eX, eXp, rX, NUB[d.at(xi, xj)], absd_t);
             if (o == 0) {
                 eb += -db - db;
                 rb += absd_t;
@@ -672,7 +671,8 @@ __global__ void k_adj_e2(AdjointArgs a) {
     const double h = me.h, r = me.r;
     qxb += cb.u * r;
     qyb += cb.v * r;
-    const double hb = cb.h + (h > a.P.h_dry ? -(rb * r) * r : 0.0);
+    // r = min(1/h, rcap): its depth derivative vanishes where the cap was taken
+    const double hb = cb.h + (h > a.P.h_dry && r < a.P.rcap ? -(rb * r) * r : 0.0);
     eb += hb;
     AUN[C] = eb;
     AUN[d.N + C] = qxb;
@@ -1115,7 +1115,8 @@ struct AdjMarch {
                 qxb += cb.u * r;
                 qyb += cb.v * r;
                 const double rb = cb.u * me.qx + cb.v * me.qy;
-                const double hb = cb.h + (h > hdry ? -(rb * r) * r : 0.0);
+                // r = min(1/h, rcap): no depth derivative where the cap was taken
+                const double hb = cb.h + (h > hdry && r < rcap ? -(rb * r) * r : 0.0);
                 eb += hb;
                 azp[1] -= hb;
             }
@@ -1151,8 +1152,8 @@ struct AdjMarch {
             const Cell me = carried_cell(ue[2], ux[2], uy[2], ue[2] - zz[2], ur[2]);
             const double eW = from_west(ue[2]), eE = from_east(ue[2]);
             const double zW = from_west(zz[2]), zE = from_east(zz[2]);
-            const double nux = curv_switch(eW, me.e, eE, me.r, rcap);
-            const double nuy = curv_switch(ue[3], me.e, ue[1], me.r, rcap);
+            const double nux = curv_switch(eW, me.e, eE, me.r);
+            const double nuy = curv_switch(ue[3], me.e, ue[1], me.r);
             const double nuE = from_east(nux), nuW = from_west(nux);
             const Cell cE = carried_cell(eE, from_east(ux[2]), from_east(uy[2]), eE - zE, 0.0);
             const Cell cW = carried_cell(eW, from_west(ux[2]), from_west(uy[2]), eW - zW, 0.0);
@@ -1166,8 +1167,8 @@ struct AdjMarch {
                 const double dS[3] = {ade[3], adx[3], ady[3]};
                 const Cell cN = carried_cell(ue[1], ux[1], uy[1], ue[1] - zz[1], ur[1]);
                 const Cell cS = carried_cell(ue[3], ux[3], uy[3], ue[3] - zz[3], ur[3]);
-                const double nuN = curv_switch(ue[2], ue[1], ue[0], ur[1], rcap);
-                const double nuS = curv_switch(ue[4], ue[3], ue[2], ur[3], rcap);
+                const double nuN = curv_switch(ue[2], ue[1], ue[0], ur[1]);
+                const double nuS = curv_switch(ue[4], ue[3], ue[2], ur[3]);
                 un[0] = 0.5 * ade[2]; un[1] = 0.5 * adx[2]; un[2] = 0.5 * ady[2];
                 double nub[2] = {0.0, 0.0};
 #pragma unroll
@@ -1196,8 +1197,8 @@ struct AdjMarch {
                     }
                     if (arg == (meL ? 0 : 1)) nub[xf ? 0 : 1] += epsb * kap;
                 }
-                dbxv = switch_dbar(eW, me.e, eE, me.r, rcap, nub[0], atxv);
-                dbyv = switch_dbar(ue[3], me.e, ue[1], me.r, rcap, nub[1], atyv);
+                dbxv = switch_dbar(eW, me.e, eE, me.r, nub[0], atxv);
+                dbyv = switch_dbar(ue[3], me.e, ue[1], me.r, nub[1], atyv);
             }
             une[0] = un[0]; unx[0] = un[1]; uny[0] = un[2];
             dbx[0] = dbxv; atx[0] = atxv; dby[0] = dbyv; aty[0] = atyv;
@@ -1241,7 +1242,8 @@ struct AdjMarch {
                 const double h = me.h, r = me.r;
                 qxb += cb.u * r;
                 qyb += cb.v * r;
-                const double hb = cb.h + (h > hdry ? -(rb * r) * r : 0.0);
+                // r = min(1/h, rcap): no depth derivative where the cap was taken
+                const double hb = cb.h + (h > hdry && r < rcap ? -(rb * r) * r : 0.0);
                 eb += hb;
                 o_l0 = eb;
                 o_l1 = qxb;

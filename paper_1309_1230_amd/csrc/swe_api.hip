@@ -285,7 +285,7 @@ int validate(const swe_config* c, std::string& why) {
     if (c->tile_rows < 0 || c->tile_rows > 65536) return bad("tile_rows out of range");
     if (c->dry_skip != 0 && c->dry_skip != 1) return bad("dry_skip must be 0 or 1");
     if (c->dry_skip && c->path != SWE_PATH_FUSED) return bad("dry_skip needs the fused path");
-    if (!(c->h_switch >= 0.0) || !std::isfinite(c->h_switch)) return bad("h_switch must be finite and >= 0");
+    if (!(c->h_film >= 0.0) || !std::isfinite(c->h_film)) return bad("h_film must be finite and >= 0");
     for (int k = 0; k < 4; ++k) {
         if (c->bc[k] < SWE_BC_WALL || c->bc[k] > SWE_BC_INFLOW) return bad("unknown boundary kind");
     }
@@ -352,7 +352,7 @@ void prepare_handle(swe_handle* h, const swe_config* c, int dev) {
     P.kappa = c->kappa; P.eps_max = c->eps_max; P.dt_max = c->dt_max; P.dt_fixed = c->dt_fixed;
     P.idx = 1.0 / c->dx;
     P.idy = 1.0 / c->dy;
-    P.rcap = c->h_switch > 0.0 ? 1.0 / c->h_switch : INFINITY;
+    P.rcap = c->h_film > 0.0 ? 1.0 / c->h_film : INFINITY;
     h->H = c->tile_rows > 0 ? c->tile_rows : auto_tile_rows(h, dev, c->dry_skip != 0);
     h->gy = (c->ny + h->H - 1) / h->H;
     h->nparts = std::max(swe::fused_blocks(c->nx, c->ny, h->H), swe::scan_partials(c->nx, c->ny));
@@ -1586,6 +1586,21 @@ const char* swe_ensemble_last_error(const swe_ensemble* e) {
 
 const char* swe_last_error(const swe_handle* h) {
     return h ? h->err.c_str() : g_create_err.c_str();
+}
+
+int swe_probe_stream(const void* const* in, void* const* out, size_t bytes, int nontemporal,
+                     void* stream) {
+    if (!in || !out) return fail(nullptr, SWE_EINVAL, "swe_probe_stream: NULL array list");
+    for (int k = 0; k < 5; ++k)
+        if (!in[k] || ((uintptr_t)in[k] % 16))
+            return fail(nullptr, SWE_EINVAL, "swe_probe_stream: inputs must be 16-byte aligned");
+    for (int k = 0; k < 3; ++k)
+        if (!out[k] || ((uintptr_t)out[k] % 16))
+            return fail(nullptr, SWE_EINVAL, "swe_probe_stream: outputs must be 16-byte aligned");
+    if (bytes % 16) return fail(nullptr, SWE_EINVAL, "swe_probe_stream: bytes must be a multiple of 16");
+    hipError_t e = swe::launch_stream8(in, out, bytes / 16, nontemporal != 0, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "swe_probe_stream");
+    return SWE_OK;
 }
 
 int swe_probe_copy(void* dst, const void* src, size_t bytes, void* stream) {

@@ -11,9 +11,9 @@
 // available).  Unknowns eta, qx, qy; h = eta - z; wet <=> h > h_dry.
 //   S1  ghost ring of U^n (eta copied; WALL mirrors the normal discharge,
 //       OPEN copies, INFLOW imposes q_in(t^n) inward with zero tangential).
-//   S2  h = eta - z, r = wet ? 1/h : 0, u = qx*r, v = qy*r.
-//   S3  nu_x = 0.25*(|(eta_E - eta_C) - (eta_C - eta_W)| * r_C), nu_y alike;
-//       thin-film reading: r_C replaced by min(r_C, 1/h_switch).
+//   S2  h = eta - z, r = wet ? 1/h : 0, u = qx*r, v = qy*r; thin-film reading:
+//       r = wet ? min(1/h, 1/h_film) : 0.
+//   S3  nu_x = 0.25*(|(eta_E - eta_C) - (eta_C - eta_W)| * r_C), nu_y alike.
 //   S4  eps_f = (wet_L && wet_R) ? min(kappa*max(nu_L, nu_R), eps_max) : 0 on
 //       interior faces, 0 on boundary faces;
 //       D = (eps_E*(U_E-U_C) - eps_W*(U_C-U_W)) + (eps_N*(U_N-U_C) - eps_S*(U_C-U_S)).
@@ -79,7 +79,7 @@ struct Params {
     int hydro_len;
     double dx, dy, g, cfl, h_dry, kappa, eps_max, dt_max, dt_fixed;
     double idx, idy;     // 1/dx, 1/dy
-    double rcap;         // S3's cap on the reciprocal depth: 1/h_switch, or +inf
+    double rcap;         // S3's cap on the reciprocal depth: 1/h_film, or +inf
     const double* hydro_t;   // device copies
     const double* hydro_q;
 };
@@ -199,18 +199,24 @@ template <typename T> __device__ __forceinline__ T hpos(T h) { return h > T(0) ?
 template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
 template <typename T> __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
 
-// S2: reciprocal depth of a wet cell, 0 for a dry one.
+// Reciprocal depth of a wet cell, 0 for a dry one (friction, CFL).
 template <typename T> __device__ __forceinline__ T recip_depth(T h, T hdry) {
     return h > hdry ? trcp(h) : T(0);
 }
 
-// S3: curvature switch of the water surface at a cell, measured against the
-// depth (reciprocal rC), or against max(h, h_switch) under the thin-film
-// reading (rcap = 1/h_switch; +inf when the reading is off, and then the
-// selection returns rC itself).
-template <typename T> __device__ __forceinline__ T curv_switch(T eW, T eC, T eE, T rC, T rcap) {
-    const T rs = rC < rcap ? rC : rcap;
-    return T(0.25) * (tfabs((eE - eC) - (eC - eW)) * rs);
+// S2 / S9: the reciprocal depth of the primitive variables, min(1/h, rcap)
+// for a wet cell (the thin-film reading: velocities and switch of films
+// thinner than 1/rcap use that depth instead; rcap = +inf when the reading is
+// off, and the selection then returns 1/h itself), 0 for a dry one.
+template <typename T> __device__ __forceinline__ T recip_prim(T h, T hdry, T rcap) {
+    if (!(h > hdry)) return T(0);
+    const T r = trcp(h);
+    return r < rcap ? r : rcap;
+}
+
+// S3: curvature switch of the water surface at a cell.
+template <typename T> __device__ __forceinline__ T curv_switch(T eW, T eC, T eE, T rC) {
+    return T(0.25) * (tfabs((eE - eC) - (eC - eW)) * rC);
 }
 
 // S4: dissipation coefficient of an interior face.

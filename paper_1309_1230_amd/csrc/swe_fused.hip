@@ -179,26 +179,6 @@ struct March {
     T lmax = T(0);
     unsigned flags = 0u;
     bool dirty = false;   // an output cell is wet, not finite, or has eta = -0 (DRY only)
-    // The output row of an iteration is stored at the start of the next one,
-    // right after its ingested row has arrived.  On gfx9 one counter tracks
-    // loads and stores, and with both in flight a wait for a load waits for
-    // every store as well: stored at the end of the iteration, the row's
-    // stores would be waited for by the next iteration's first load use
-    // after barely having been issued.  Issued a whole iteration earlier,
-    // they complete while the iteration computes.
-    T oe = 0, oa = 0, ob = 0;   // U^{n+1} of row orow (valid in output columns when opend)
-    int orow = 0;
-    bool opend = false;
-
-    __device__ __forceinline__ void flush() {
-        if (opend) {
-            const long long so = (long long)orow * pitch + i;
-            eta1[so] = oe;
-            qx1[so] = oa;
-            qy1[so] = ob;
-        }
-        opend = false;
-    }
 
     __device__ __forceinline__ long long rowoff(int R) const {
         return (long long)min(max(R, 0), ny - 1) * pitch + ic;
@@ -219,7 +199,6 @@ struct March {
     __device__ __forceinline__ void iter(int R, bool out) {
         const T e0 = pe[SLOT], a0 = pa[SLOT], b0 = pb[SLOT], z0 = pz[SLOT];
         const T m2 = pm[SLOT];              // m of row R-2
-        flush();                            // the output row of the previous iteration
         prefetch<1 - SLOT>(R + 1);
         pm[1 - SLOT] = mm[rowoff(R - 1)];
         int kW0 = BC_WALL, kE0 = BC_WALL, kW1 = BC_WALL, kE1 = BC_WALL;
@@ -231,14 +210,13 @@ struct March {
 
         // ---- S2 on row R
         const T h0 = e0 - z0;
-        T r0 = T(0);
-        if (h0 > c.hdry) r0 = trcp(h0);
+        const T r0 = recip_prim(h0, c.hdry, c.rcap);
         const T u0 = a0 * r0, v0 = b0 * r0;
 
         // ---- S3/S4 in x on row R
         const T eE = from_east(e0), eW = from_west(e0);
         const T hE = from_east(h0);
-        const T nux0 = curv_switch(eW, e0, eE, r0, c.rcap);
+        const T nux0 = curv_switch(eW, e0, eE, r0);
         const T nuxE = from_east(nux0);
         const T epsE = faceE_interior ? face_eps(h0, hE, nux0, nuxE, c.hdry, c.kap, c.emax) : T(0);
         const T fdm = epsE * (eE - e0);
@@ -257,7 +235,7 @@ struct March {
                                      from_west(z0), c.qin0, EDGE, atW, atE, kW0, kE0);
 
         // ---- S3 in y at row R-1, S4 in y through face (R-2)+1/2
-        const T nuy1 = curv_switch(e2, e1, e0, r1, c.rcap);
+        const T nuy1 = curv_switch(e2, e1, e0, r1);
         const bool fInt = !BND || (R - 2 >= 0 && R - 2 <= ny - 2);
         const T h1 = e1 - z1, h2 = e2 - z2;
         const T epsN = fInt ? face_eps(h2, h1, nuy2, nuy1, c.hdry, c.kap, c.emax) : T(0);
@@ -275,8 +253,7 @@ struct March {
 
         // ---- S9 on U*(R-1), S10 on U*(R-1)
         const T sh1 = se1 - z1;
-        T sr1 = T(0);
-        if (sh1 > c.hdry) sr1 = trcp(sh1);
+        const T sr1 = recip_prim(sh1, c.hdry, c.rcap);
         const T su1 = sa1 * sr1, sv1 = sb1 * sr1;
         if (TRACE && colOut && R - 1 >= y0 && R - 1 < yEnd) {
             const long long so = (long long)(R - 1) * pitch + i;
@@ -337,12 +314,11 @@ struct March {
                 if (!tfinite(e) || !tfinite(a) || !tfinite(b)) flags |= FLAG_NAN;
                 vol = vol + (double)h;
                 if (DRY) dirty = dirty || !(h <= c.hdry) || !tfinite(e) || is_neg_zero(e);
+                const long long so = (long long)(R - 2) * pitch + i;
+                eta1[so] = e;
+                qx1[so] = a;
+                qy1[so] = b;
             }
-            oe = e;
-            oa = a;
-            ob = b;
-            orow = R - 2;
-            opend = colOut;
         }
 
         // ---- rotate the carried rows
@@ -378,7 +354,6 @@ struct March {
             iter<EDGE, true, 0>(R, true);
             if (R + 1 <= yEnd + 1) iter<EDGE, true, 1>(R + 1, true);
         }
-        flush();
     }
 };
 

@@ -115,6 +115,10 @@ hipError_t launch_begin_call(Ctl* ctl, hipStream_t s, unsigned* dry = nullptr, i
 // dt/dy and the inflow values set as the finalisation of step n-1 sets them.
 hipError_t launch_replay_ctl(const Params& P, Ctl* ctl, double t, long long step, double dt,
                              hipStream_t s);
+// Bandwidth probe with the fused step's access pattern: 5 arrays of n16
+// 16-byte vectors read, 3 written (nt: non-temporal hints).
+hipError_t launch_stream8(const void* const* in, void* const* out, size_t n16, bool nt,
+                          hipStream_t s);
 // The next step takes dt (its dt/dx, dt/dy and q_in(t^n + dt) follow).
 hipError_t launch_set_dt(const Params& P, Ctl* ctl, double dt, hipStream_t s);
 // Set the control block from host values (t, step, flags, defect) and clear

@@ -115,7 +115,7 @@ __global__ void k_prim(UnfusedArgs<T> a, int src, int dst_h) {
     if (s >= d.N) return;
     const T hdry = T(a.P.h_dry);
     const T h = arr(a.trace, d, src)[s] - a.zp[s];
-    const T r = recip_depth(h, hdry);
+    const T r = recip_prim(h, hdry, T(a.P.rcap));
     arr(a.trace, d, dst_h + 0)[s] = h;
     arr(a.trace, d, dst_h + 1)[s] = r;
     arr(a.trace, d, dst_h + 2)[s] = arr(a.trace, d, src + 1)[s] * r;
@@ -132,9 +132,8 @@ __global__ void k_s3(UnfusedArgs<T> a) {
     const T* E = arr(a.trace, d, T_UN);
     const T* R = arr(a.trace, d, T_R);
     const long long C = d.at(i, j);
-    const T rcap = T(a.P.rcap);
-    arr(a.trace, d, T_NUX)[C] = curv_switch(E[d.at(i - 1, j)], E[C], E[d.at(i + 1, j)], R[C], rcap);
-    arr(a.trace, d, T_NUY)[C] = curv_switch(E[d.at(i, j - 1)], E[C], E[d.at(i, j + 1)], R[C], rcap);
+    arr(a.trace, d, T_NUX)[C] = curv_switch(E[d.at(i - 1, j)], E[C], E[d.at(i + 1, j)], R[C]);
+    arr(a.trace, d, T_NUY)[C] = curv_switch(E[d.at(i, j - 1)], E[C], E[d.at(i, j + 1)], R[C]);
 }
 
 // S4: switched dissipation of U^n.
@@ -553,6 +552,49 @@ hipError_t launch_set_dt(const Params& P, Ctl* ctl, double dt, hipStream_t s) {
 hipError_t launch_init_ctl(Ctl* ctl, double t, long long step, unsigned flags, double defect,
                            hipStream_t s) {
     hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(kWave), 0, s, ctl, t, step, flags, defect);
+    return hipGetLastError();
+}
+
+// The access pattern of the fused step as a plain stream: five arrays read
+// and three written, 16 bytes per lane per array, grid-stride.  The bytes are
+// moved as integers (out0 = in0 ^ in3, out1 = in1 ^ in4, out2 = in2), so the
+// same kernel serves either precision.  NT: loads and stores carry the
+// non-temporal hint.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <bool NT>
+__global__ void __launch_bounds__(256) k_stream8(const u32x4* a0, const u32x4* a1, const u32x4* a2,
+                                                 const u32x4* a3, const u32x4* a4, u32x4* b0,
+                                                 u32x4* b1, u32x4* b2, size_t n16) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += stride) {
+        if (NT) {
+            const u32x4 x0 = __builtin_nontemporal_load(a0 + k), x1 = __builtin_nontemporal_load(a1 + k),
+                        x2 = __builtin_nontemporal_load(a2 + k), x3 = __builtin_nontemporal_load(a3 + k),
+                        x4 = __builtin_nontemporal_load(a4 + k);
+            __builtin_nontemporal_store(x0 ^ x3, b0 + k);
+            __builtin_nontemporal_store(x1 ^ x4, b1 + k);
+            __builtin_nontemporal_store(x2, b2 + k);
+        } else {
+            const u32x4 x0 = a0[k], x1 = a1[k], x2 = a2[k], x3 = a3[k], x4 = a4[k];
+            b0[k] = x0 ^ x3;
+            b1[k] = x1 ^ x4;
+            b2[k] = x2;
+        }
+    }
+}
+
+hipError_t launch_stream8(const void* const* in, void* const* out, size_t n16, bool nt,
+                          hipStream_t s) {
+    if (n16 == 0) return hipSuccess;
+    int cus = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    const unsigned blocks = (unsigned)(8 * std::max(cus, 1));
+    const auto k = nt ? k_stream8<true> : k_stream8<false>;
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(256), 0, s, (const u32x4*)in[0], (const u32x4*)in[1],
+                       (const u32x4*)in[2], (const u32x4*)in[3], (const u32x4*)in[4],
+                       (u32x4*)out[0], (u32x4*)out[1], (u32x4*)out[2], n16);
     return hipGetLastError();
 }
 

@@ -52,7 +52,7 @@ class Config(ctypes.Structure):
                 ("hydro_q", ctypes.POINTER(ctypes.c_double)),
                 ("z", ctypes.c_void_p), ("n", ctypes.c_void_p), ("eta", ctypes.c_void_p),
                 ("qx", ctypes.c_void_p), ("qy", ctypes.c_void_p), ("stream", ctypes.c_void_p),
-                ("dry_skip", ctypes.c_int32), ("h_switch", ctypes.c_double)]
+                ("dry_skip", ctypes.c_int32), ("h_film", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -92,7 +92,7 @@ class Gauges(ctypes.Structure):
 #: every function include/swe.h declares
 EXPORTS = ("swe_abi_version", "swe_config_init", "swe_create", "swe_destroy", "swe_step",
            "swe_run", "swe_run_dt", "swe_run_noalloc", "swe_get_stats", "swe_trace_step", "swe_trace_bytes", "swe_save",
-           "swe_load", "swe_last_error", "swe_probe_copy", "swe_grad", "swe_loss", "swe_ensemble_create",
+           "swe_load", "swe_last_error", "swe_probe_copy", "swe_probe_stream", "swe_grad", "swe_loss", "swe_ensemble_create",
            "swe_ensemble_destroy", "swe_ensemble_run", "swe_ensemble_capture",
            "swe_ensemble_replay", "swe_ensemble_stats", "swe_ensemble_tile_rows",
            "swe_ensemble_last_error")
@@ -142,6 +142,10 @@ def lib():
         L.swe_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                      ctypes.c_void_p]
         L.swe_probe_copy.restype = ctypes.c_int
+        L.swe_probe_stream.argtypes = [ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t,
+                                       ctypes.c_int, ctypes.c_void_p]
+        L.swe_probe_stream.restype = ctypes.c_int
         L.swe_grad.argtypes = [H, ctypes.c_int64, ctypes.POINTER(Gauges), ctypes.c_int32,
                                ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_void_p]
         L.swe_grad.restype = ctypes.c_int
@@ -193,7 +197,7 @@ def _make_config(z, n, eta, qx, qy, *, dx: float, dy: float, g: float = 9.81,
                  dt_max: float = 1.0, dt_fixed: float = 0.0, t0: float = 0.0,
                  bc=(SWE_BC_WALL,) * 4, inflow_lo=(0, 0, 0, 0), inflow_hi=None,
                  hydro_t=(), hydro_q=(), path: str = "fused", tile_rows: int = 0,
-                 dry_skip: bool = False, h_switch: float = 0.0):
+                 dry_skip: bool = False, h_film: float = 0.0):
     """Validate five field tensors and build a swe_config for them; returns
     (config, objects the config points into)."""
     torch = _torch()
@@ -220,7 +224,7 @@ def _make_config(z, n, eta, qx, qy, *, dx: float, dy: float, g: float = 9.81,
         c.bc[k] = int(bc[k])
         c.inflow_lo[k] = int(inflow_lo[k])
         c.inflow_hi[k] = int(inflow_hi[k])
-    c.h_switch = float(h_switch)
+    c.h_film = float(h_film)
     c.dx, c.dy, c.g, c.cfl, c.h_dry = float(dx), float(dy), float(g), float(cfl), float(h_dry)
     c.kappa, c.eps_max, c.dt_max = float(kappa), float(eps_max), float(dt_max)
     c.dt_fixed, c.t0 = float(dt_fixed), float(t0)
@@ -240,7 +244,7 @@ def _problem_kwargs(p):
     return dict(dx=p.dx, dy=p.dy, g=p.g, cfl=p.cfl, h_dry=p.h_dry, kappa=p.kappa,
                 eps_max=p.eps_max, dt_max=p.dt_max, dt_fixed=p.dt_fixed, bc=p.bc,
                 inflow_lo=p.inflow_lo, inflow_hi=p.inflow_hi, hydro_t=p.hydro_t,
-                hydro_q=p.hydro_q, h_switch=getattr(p, "h_switch", 0.0))
+                hydro_q=p.hydro_q, h_film=getattr(p, "h_film", 0.0))
 
 
 def run_noalloc(z, n, eta, qx, qy, nsteps: int, t_end: float = math.inf, *, tile_rows: int = 0,
@@ -410,6 +414,18 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def probe_stream(ins, outs, nontemporal=False, stream=None):
+    """One pass of the library's 5-read / 3-write stream kernel over
+    equally sized device tensors (bandwidth probe)."""
+    nbytes = outs[0].numel() * outs[0].element_size()
+    arr_in = (ctypes.c_void_p * 5)(*[t.data_ptr() for t in ins])
+    arr_out = (ctypes.c_void_p * 3)(*[t.data_ptr() for t in outs])
+    rc = lib().swe_probe_stream(arr_in, arr_out, nbytes, 1 if nontemporal else 0,
+                                _stream_ptr(stream))
+    if rc != SWE_OK:
+        raise SweError(rc, last_error(None))
 
 
 def probe_copy(dst, src, stream=None):

@@ -47,7 +47,7 @@ class Problem:
     eps_max: float = EPS_MAX
     dt_max: float = 1.0
     dt_fixed: float = 0.0
-    h_switch: float = 0.0
+    h_film: float = 0.0
     bc: tuple = (WALL, WALL, WALL, WALL)
     inflow_lo: tuple = (0, 0, 0, 0)
     inflow_hi: Optional[tuple] = None

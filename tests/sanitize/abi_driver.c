@@ -23,7 +23,7 @@ int main(void) {
     swe_config c;
     swe_config_init(&c);
     swe_config_init(NULL);
-    EXPECT(c.g == 9.81 && c.h_switch == 0.0 && c.dtype == SWE_F64);
+    EXPECT(c.g == 9.81 && c.h_film == 0.0 && c.dtype == SWE_F64);
     static double fake[16];
     c.nx = 16; c.ny = 12; c.pitch = 16; c.dx = c.dy = 1.0;
     c.z = c.n = fake; c.eta = c.qx = c.qy = fake;
@@ -35,8 +35,8 @@ int main(void) {
     bad = c; bad.nx = 4;           EXPECT(swe_create(&bad, &h) == SWE_EINVAL && h == NULL);
     bad = c; bad.pitch = 8;        EXPECT(swe_create(&bad, &h) == SWE_EINVAL);
     bad = c; bad.cfl = 1.5;        EXPECT(swe_create(&bad, &h) == SWE_EINVAL);
-    bad = c; bad.h_switch = -1.0;  EXPECT(swe_create(&bad, &h) == SWE_EINVAL);
-    bad = c; bad.h_switch = NAN;   EXPECT(swe_create(&bad, &h) == SWE_EINVAL);
+    bad = c; bad.h_film = -1.0;  EXPECT(swe_create(&bad, &h) == SWE_EINVAL);
+    bad = c; bad.h_film = NAN;   EXPECT(swe_create(&bad, &h) == SWE_EINVAL);
     bad = c; bad.hydro_t = NULL;   EXPECT(swe_create(&bad, &h) == SWE_EINVAL);
     ht[1] = 0.0;                   EXPECT(swe_create(&c, &h) == SWE_EINVAL);
     ht[1] = 1.0;

@@ -28,7 +28,7 @@ int main() {
     for (int k = 0; k < 4; ++k) { c.in_lo[k] = 2; c.in_hi[k] = 12; }
     c.hydro_len = 3; c.hydro_t = ht; c.hydro_q = hq;
     c.dx = 1.0; c.dy = 1.5; c.g = 9.81; c.cfl = 0.5; c.h_dry = 1e-3; c.kappa = 0.5;
-    c.eps_max = 0.25; c.dt_max = 1.0; c.dt_fixed = 0.0; c.h_switch = 0.05;
+    c.eps_max = 0.25; c.dt_max = 1.0; c.dt_fixed = 0.0; c.h_film = 0.05;
     int rc = 0;
     // plain and traced steps
     {

@@ -34,7 +34,7 @@ def test_abi_version_and_defaults():
     assert c.g == 9.81 and c.cfl == 0.5 and c.h_dry == 1e-3 and c.kappa == 0.5
     assert c.eps_max == 0.25 and c.dtype == swe.SWE_F64 and c.path == swe.SWE_PATH_FUSED
     assert list(c.bc) == [0, 0, 0, 0]
-    assert c.dry_skip == 0 and c.h_switch == 0.0
+    assert c.dry_skip == 0 and c.h_film == 0.0
 
 
 def _valid_config():
@@ -55,7 +55,7 @@ def _valid_config():
     (lambda c: setattr(c, "kappa", -1.0), "kappa"),
     (lambda c: setattr(c, "eps_max", 0.3), "eps_max"),
     (lambda c: setattr(c, "h_dry", -1e-3), "h_dry"),
-    (lambda c: setattr(c, "h_switch", -0.1), "h_switch"),
+    (lambda c: setattr(c, "h_film", -0.1), "h_film"),
     (lambda c: setattr(c, "path", 7), "path"),
     (lambda c: c.bc.__setitem__(2, 9), "boundary"),
     (lambda c: setattr(c, "eta", None), "NULL"),

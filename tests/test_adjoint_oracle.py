@@ -120,15 +120,15 @@ def test_full_gradient_equals_unit_tangents_on_a_small_grid():
         assert abs(gz.ravel()[k] - dz_k) <= 1e-12 * scale
 
 
-# ------------------------------------------------ thin-film switch reading
+# ------------------------------------------------------ thin-film reading
 
-def _channel_flood_case(h_switch, nsteps=600, every=10):
+def _channel_flood_case(h_film, nsteps=600, every=10):
     """The channel flood of the large combined run on a 128 m x 128 m corner
     (128 x 128 cells, dx = 1 m): the inflow overtops the channel and floods
     the land as thin films.  Observations from the true Manning field."""
     c = W.channel_flood(nx=128, ny=128, dx=1.0, nsteps=nsteps, obs_every=every)
     p = c.problem
-    p.h_switch = h_switch
+    p.h_film = h_film
     _, dts = O.run_record(p, nsteps)
     q = p.copy()
     q.n = c.n_true
@@ -140,15 +140,17 @@ def _channel_flood_case(h_switch, nsteps=600, every=10):
     return p, O.Gauges(cells=c.cells, every=every, hobs=np.array(hobs), dts=dts)
 
 
-def test_thin_film_switch_keeps_the_flood_adjoint_bounded():
+def test_thin_film_reading_keeps_the_flood_adjoint_bounded():
     """The plain scheme's discrete adjoint grows without bound on a flood
-    over dry land: its switch is 0.25 |d2 eta| / h, whose depth derivative
-    |d2 eta| / h^2 is enormous in the films at the front, and those terms
-    amplify the adjoint from step to step (max |dJ/dn| ~ 1e17 after 300
-    steps here).  Measuring the curvature against max(h, h_switch) with
-    h_switch = 0.1 m removes them: over 600 steps the gradient stays O(10^2),
-    and it is the derivative of the executed step, as central differences on
-    five cells with the time steps held fixed confirm (relative 1e-5).  The
+    over dry land: S2's reciprocal depth 1/h enters the switch (0.25
+    |d2 eta| / h) and the velocities (q / h), and its depth derivative 1/h^2
+    is enormous in the films at the front; those terms amplify the adjoint
+    from step to step (max |dJ/dn| ~ 1e17 after 300 steps here).  The
+    thin-film reading takes min(1/h, 1/h_film) instead, h_film = 0.1 m: over
+    600 steps the gradient stays O(10^2), and it is the derivative of the
+    executed step, as central differences on five cells with the time steps
+    held fixed confirm (relative 1e-5 on the cells where no kink falls inside
+    the step, at least five of six).  The
     loss is only piecewise smooth (|.|, max and min in S3/S4, the wet/dry
     tests), so the difference step is small, 1e-6 n: at 1e-5 n it already
     straddles kinks in some cells (errors to 3e-4, with the forward and
@@ -161,12 +163,22 @@ def test_thin_film_switch_keeps_the_flood_adjoint_bounded():
     J, gn, gz = O.loss_gradient(p, G)
     assert np.isfinite(J) and np.abs(gn).max() < 1e3 and np.abs(gz).max() < 1e4
     big = np.flatnonzero(np.abs(gn).ravel() >= 1e-2 * np.abs(gn).max())
-    cells = np.random.default_rng(7).choice(big, 5, replace=False)
+    cells = np.random.default_rng(7).choice(big, 6, replace=False)
+    J0 = O.loss(p, G)
+    smooth = 0
     for cell in cells:
         j, i = divmod(int(cell), p.nx)
         d = 1e-6 * p.n[j, i]
         npl, nmi = p.n.copy(), p.n.copy()
         npl[j, i] += d
         nmi[j, i] -= d
-        fd = (O.loss(p, G, nman=npl) - O.loss(p, G, nman=nmi)) / (npl[j, i] - nmi[j, i])
+        Jp, Jm = O.loss(p, G, nman=npl), O.loss(p, G, nman=nmi)
+        fd = (Jp - Jm) / (npl[j, i] - nmi[j, i])
+        # a kink of the piecewise smooth loss inside the step shows as forward
+        # and backward quotients that disagree (the rule of the GPU check)
+        spread = abs((Jp - J0) / (npl[j, i] - p.n[j, i]) - (J0 - Jm) / (p.n[j, i] - nmi[j, i]))
+        if spread > 1e-3 * abs(gn[j, i]):
+            continue
+        smooth += 1
         assert fd == pytest.approx(gn[j, i], rel=1e-5), (i, j)
+    assert smooth >= 5
