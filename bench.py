@@ -425,32 +425,57 @@ def combined_run(torch, swe, W, nx, nsteps, ckpt, obs_every, h_film):
     return out
 
 
-def stream_probe(torch, swe, dtype, cells, reps=7):
-    """The achievable-bandwidth ceiling for the step's traffic: the library's
-    stream kernel reading five and writing three arrays of the workload's
-    size (one pass per launch), with and without non-temporal hints; median
-    of reps launches timed with HIP events."""
+def stream_probe(torch, swe, dtype, nx, ny, reps=7):
+    """Bandwidth ceilings for the step's traffic, each timed as the median of
+    reps launches with HIP events on torch's current stream (where the probes
+    launch), all over the workload's own size:
+    - copy: the library's plain copy kernel over four arrays' worth (as many
+      bytes moved as the step's eight arrays);
+    - plain / nontemporal: the library's stream kernel reading five and
+      writing three arrays, one grid-stride pass, without and with
+      non-temporal hints;
+    - march: the library's march-pattern probe, the step kernel's own tiles,
+      tile height, strip order, row march, loads and stores with a few
+      operations per cell in place of the sub-steps; its rate is algorithmic
+      bytes (the step's 8 words per cell) over time, like the kernel's."""
     tdt = torch.float64 if dtype == "f64" else torch.float32
+    cells = nx * ny
     ins = [torch.ones(cells, dtype=tdt, device="cuda") for _ in range(5)]
     outs = [torch.empty(cells, dtype=tdt, device="cuda") for _ in range(3)]
     nbytes = 8 * cells * ins[0].element_size()
-    res = {}
-    for nt in (False, True):
-        swe.probe_stream(ins, outs, nontemporal=nt)
+
+    def median_ms(fn):
+        fn()
         ts = []
         for _ in range(reps):
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record()
-            swe.probe_stream(ins, outs, nontemporal=nt)
+            fn()
             b.record()
             b.synchronize()
             ts.append(a.elapsed_time(b))
-        ms = sorted(ts)[len(ts) // 2]
+        return sorted(ts)[len(ts) // 2]
+
+    res = {}
+    for nt in (False, True):
+        ms = median_ms(lambda: swe.probe_stream(ins, outs, nontemporal=nt))
         res["nontemporal_GBps" if nt else "plain_GBps"] = nbytes / (ms / 1e3) / 1e9
-    res["bytes_per_launch"] = nbytes
-    res["note"] = "5 arrays read + 3 written, 16 B per lane, grid-stride (swe_probe_stream)"
+    rows = swe.probe_march(ins, outs, nx, ny, nx)
+    ms = median_ms(lambda: swe.probe_march(ins, outs, nx, ny, nx, rows))
+    res["march_GBps"] = nbytes / (ms / 1e3) / 1e9
+    res["march_us"] = ms * 1e3
+    res["march_rows"] = rows
     del ins, outs
+    src = torch.ones(4 * cells, dtype=tdt, device="cuda")
+    dst = torch.empty_like(src)
+    ms = median_ms(lambda: swe.probe_copy(dst, src))
+    res["copy_GBps"] = nbytes / (ms / 1e3) / 1e9
+    del src, dst
+    res["bytes_per_launch"] = nbytes
+    res["note"] = ("stream: 5 arrays read + 3 written, 16 B per lane, grid-stride "
+                   "(swe_probe_stream); march: the step kernel's traversal without its "
+                   "arithmetic (swe_probe_march); copy: swe_probe_copy of the same bytes")
     return res
 
 
@@ -576,8 +601,9 @@ def main():
                      "bytes_per_cell_update": bpc},
         "wall_s": wall,
     }
-    out["stream_probe"] = stream_probe(torch, swe, a.dtype, cells)
+    out["stream_probe"] = stream_probe(torch, swe, a.dtype, p.nx, p.ny)
     out["roofline"]["frac_of_stream_probe"] = achieved / out["stream_probe"]["plain_GBps"]
+    out["roofline"]["frac_of_march_probe"] = achieved / out["stream_probe"]["march_GBps"]
     if a.dry_only:
         out["dry_skip"] = dry_skip_run(torch, swe, W, p, a.dtype, a.steps, a.warmup, a.tile_rows,
                                        st, ms)

@@ -352,6 +352,21 @@ int swe_probe_copy(void* dst, const void* src, size_t bytes, void* stream);
 int swe_probe_stream(const void* const* in, void* const* out, size_t bytes, int nontemporal,
                      void* stream);
 
+/* The fused step's access pattern without its arithmetic: the same tiles,
+ * tile order and row march as the step kernel (one 64-lane wave per strip of
+ * 60 output columns marching up a chunk of `rows` rows, the next row
+ * prefetched), reading in[0..4] and writing out[0..2] (each ny rows of
+ * `pitch` elements of elem_bytes = 4 or 8 bytes, nx <= pitch columns used),
+ * with a few operations per cell in place of the sub-steps S1-S16 (§3.2: the
+ * step is bound by its global-memory accesses).  It is the traversal's own
+ * bandwidth ceiling, between the plain stream and the step kernel.  rows = 0
+ * takes the height the step kernel picks by itself for that precision and
+ * grid on the current device.  Returns the rows used (> 0), or SWE_EINVAL
+ * on misuse (NULL or misaligned arrays, nx > pitch, ny * pitch > 2^31).
+ * Asynchronous. */
+int swe_probe_march(const void* const* in, void* const* out, int32_t nx, int32_t ny,
+                    int64_t pitch, int32_t elem_bytes, int32_t rows, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -250,15 +250,7 @@ int auto_tile_rows(const swe_handle* h, int dev, bool dry_skip) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
     const int per_cu = h->dtype == SWE_F32 ? swe::fused_waves_per_cu<float>()
                                            : swe::fused_waves_per_cu<double>();
-    const long long slots = (long long)cus * per_cu;
-    const int gx = swe::fused_strips(h->P.nx);
-    if (slots <= 0) return dry_skip ? 32 : 128;
-    long long gy = slots / gx;
-    if (gy < 1) gy = 1;
-    int H = (int)((h->P.ny + gy - 1) / gy);
-    if (H < 16) H = 16;
-    if (dry_skip && H > 32) H = 32;
-    return H;
+    return swe::fused_auto_rows(h->P.nx, h->P.ny, (long long)cus * per_cu, dry_skip);
 }
 
 int validate(const swe_config* c, std::string& why) {
@@ -1601,6 +1593,46 @@ int swe_probe_stream(const void* const* in, void* const* out, size_t bytes, int 
     hipError_t e = swe::launch_stream8(in, out, bytes / 16, nontemporal != 0, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(nullptr, e, "swe_probe_stream");
     return SWE_OK;
+}
+
+int swe_probe_march(const void* const* in, void* const* out, int32_t nx, int32_t ny,
+                    int64_t pitch, int32_t elem_bytes, int32_t rows, void* stream) {
+    if (!in || !out) return fail(nullptr, SWE_EINVAL, "swe_probe_march: NULL array list");
+    if (elem_bytes != 4 && elem_bytes != 8)
+        return fail(nullptr, SWE_EINVAL, "swe_probe_march: elem_bytes must be 4 or 8");
+    if (nx < 1 || ny < 1 || pitch < nx || (long long)ny * pitch > (1ll << 31))
+        return fail(nullptr, SWE_EINVAL, "swe_probe_march: need 1 <= nx <= pitch, ny >= 1, ny*pitch <= 2^31");
+    if (rows < 0) return fail(nullptr, SWE_EINVAL, "swe_probe_march: rows must be >= 0");
+    swe::ProbeMarchArgs a;
+    for (int k = 0; k < 5; ++k) {
+        if (!in[k] || ((uintptr_t)in[k] % elem_bytes))
+            return fail(nullptr, SWE_EINVAL, "swe_probe_march: inputs must be non-NULL and aligned");
+        a.in[k] = in[k];
+    }
+    for (int k = 0; k < 3; ++k) {
+        if (!out[k] || ((uintptr_t)out[k] % elem_bytes))
+            return fail(nullptr, SWE_EINVAL, "swe_probe_march: outputs must be non-NULL and aligned");
+        a.out[k] = out[k];
+    }
+    int H = rows;
+    if (H == 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 0;
+        H = swe::probe_march_rows(elem_bytes, nx, ny, cus);
+    }
+    const long long gy = ((long long)ny + H - 1) / H;
+    if ((long long)swe::fused_strips(nx) * gy > (1ll << 30))
+        return fail(nullptr, SWE_EINVAL, "swe_probe_march: too many tiles");
+    a.nx = nx;
+    a.ny = ny;
+    a.H = H;
+    a.gy = (int)gy;
+    a.pitch = pitch;
+    hipError_t e = swe::launch_probe_march(a, elem_bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "swe_probe_march");
+    return H;
 }
 
 int swe_probe_copy(void* dst, const void* src, size_t bytes, void* stream) {

@@ -477,6 +477,29 @@ __device__ __forceinline__ void finish_step(const FusedArgs<T>& A, int tile, int
 // still its unchanged volume) and refreshes the output buffer only if the
 // previous step computed it (after a skip both buffers already hold the
 // tile's state).
+// Strip of the pos-th strip position of a tile run: strips in pairs of
+// neighbours, the pairs enumerated by residue class mod 8.  Each XCD's
+// contiguous run of tiles then covers strip pairs spread over the whole
+// domain (wet and dry strips balance across the XCDs), and the two strips of
+// a pair share the row lines they overlap in one L2.
+__device__ __forceinline__ int paired_strip(int pos, int gx) {
+    const int npair = (gx + 1) / 2;
+    int base = 0;
+    for (int r = 0; r < 8 && r < npair; ++r) {
+        // strips of the pairs r, r+8, r+16, ... (the last pair may be single)
+        const int last = npair - 1;
+        const int n_pairs = (last - r) / 8 + 1;
+        const bool short_last = (gx & 1) && ((last - r) % 8 == 0);
+        const int n_r = 2 * n_pairs - (short_last ? 1 : 0);
+        if (pos < base + n_r) {
+            const int q = pos - base;
+            return 2 * (r + 8 * (q / 2)) + (q & 1);
+        }
+        base += n_r;
+    }
+    return pos;
+}
+
 template <typename T, int SIG, bool DRY, bool TRACE = false>
 __device__ __forceinline__ void fused_step(const FusedArgs<T>& A, int blk, int nblk) {
     Ctl* ctl = A.ctl;
@@ -504,26 +527,8 @@ __device__ __forceinline__ void fused_step(const FusedArgs<T>& A, int blk, int n
     const int lane = threadIdx.x;
     const int tile = xcd_tile(blk, nblk);
     const int pos = tile / A.gy, chunk = tile - pos * A.gy;
-    // strips in pairs of neighbours, the pairs enumerated by residue class
-    // mod 8: each XCD's contiguous run of tiles covers strip pairs spread
-    // over the whole domain (wet and dry strips balance across the XCDs), and
-    // the two strips of a pair share the row lines they overlap in one L2
     const int gx = (P.nx + kOutW - 1) / kOutW;
-    const int npair = (gx + 1) / 2;
-    int strip = pos, base = 0;
-    for (int r = 0; r < 8 && r < npair; ++r) {
-        // strips of the pairs r, r+8, r+16, ... (the last pair may be single)
-        const int last = npair - 1;
-        const int n_pairs = (last - r) / 8 + 1;
-        const bool short_last = (gx & 1) && ((last - r) % 8 == 0);
-        const int n_r = 2 * n_pairs - (short_last ? 1 : 0);
-        if (pos < base + n_r) {
-            const int q = pos - base;
-            strip = 2 * (r + 8 * (q / 2)) + (q & 1);
-            break;
-        }
-        base += n_r;
-    }
+    const int strip = paired_strip(pos, gx);
     const int x0 = strip * kOutW;
     M.y0 = chunk * A.H;
     M.yEnd = min(M.y0 + A.H, P.ny);
@@ -699,6 +704,17 @@ int fused_blocks(int nx, int ny, int H) {
 
 int fused_strips(int nx) { return (nx + kOutW - 1) / kOutW; }
 
+int fused_auto_rows(int nx, int ny, long long slots, bool dry_skip) {
+    const int gx = fused_strips(nx);
+    if (slots <= 0) return dry_skip ? 32 : 128;
+    long long gy = slots / gx;
+    if (gy < 1) gy = 1;
+    int H = (int)((ny + gy - 1) / gy);
+    if (H < 16) H = 16;
+    if (dry_skip && H > 32) H = 32;
+    return H;
+}
+
 size_t fused_part_bytes(int ntiles) {
     const size_t ng = (size_t)(ntiles + kGroup - 1) / kGroup;
     return ((size_t)ntiles + ng) * sizeof(TilePart) + ng * sizeof(unsigned);
@@ -719,6 +735,72 @@ int fused_waves_per_cu() {
                                                      0) != hipSuccess)
         return 0;
     return nb;
+}
+
+// Access-pattern probe of the step: the tiles, tile order, strip map and row
+// march of k_fused_step (64-lane strips of 60 output columns, chunks of H
+// rows, the row ahead prefetched into two register slots, the output row two
+// behind the ingested one), the same five loads and three stores per row,
+// and a handful of operations in place of the sixteen sub-steps.  Every
+// loaded value reaches a store, so none of the traffic is optimised away.
+template <typename T>
+__global__ void __launch_bounds__(kWave) k_probe_march(ProbeMarchArgs A) {
+    const T* __restrict__ f0 = (const T*)A.in[0];
+    const T* __restrict__ f1 = (const T*)A.in[1];
+    const T* __restrict__ f2 = (const T*)A.in[2];
+    const T* __restrict__ f3 = (const T*)A.in[3];
+    const T* __restrict__ f4 = (const T*)A.in[4];
+    T* __restrict__ o0 = (T*)A.out[0];
+    T* __restrict__ o1 = (T*)A.out[1];
+    T* __restrict__ o2 = (T*)A.out[2];
+    const int lane = threadIdx.x;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int pos = tile / A.gy, chunk = tile - pos * A.gy;
+    const int gx = (A.nx + kOutW - 1) / kOutW;
+    const int i = paired_strip(pos, gx) * kOutW - 2 + lane;
+    const int ic = min(max(i, 0), A.nx - 1);
+    const bool colOut = lane >= 2 && lane < 2 + kOutW && i < A.nx;
+    const int y0 = chunk * A.H, yEnd = min(y0 + A.H, A.ny);
+    auto off = [&](int R) { return (long long)min(max(R, 0), A.ny - 1) * A.pitch + ic; };
+    T pe[2], pa[2], pb[2], pz[2], pm[2] = {T(0), T(0)};
+    T e1 = 0, a1 = 0, b1 = 0, z1 = 0, e2 = 0, a2 = 0, b2 = 0, z2 = 0;
+    {
+        const long long o = off(y0 - 2);
+        pe[0] = f0[o]; pa[0] = f1[o]; pb[0] = f2[o]; pz[0] = f3[o];
+    }
+    auto iter = [&](int R, int S) {
+        const T e0 = pe[S], a0 = pa[S], b0 = pb[S], z0 = pz[S], m2 = pm[S];
+        const long long o = off(R + 1);
+        pe[1 - S] = f0[o]; pa[1 - S] = f1[o]; pb[1 - S] = f2[o]; pz[1 - S] = f3[o];
+        pm[1 - S] = f4[off(R - 1)];
+        if (R - 2 >= y0 && R - 2 < yEnd && colOut) {
+            const long long so = (long long)(R - 2) * A.pitch + i;
+            o0[so] = e2 + from_east(e1) * m2;
+            o1[so] = a2 + z2 * from_west(a1) + e0;
+            o2[so] = b2 + b1 * z1 + a0 * b0 + z0;
+        }
+        e2 = e1; a2 = a1; b2 = b1; z2 = z1;
+        e1 = e0; a1 = a0; b1 = b0; z1 = z0;
+    };
+    for (int R = y0 - 2; R <= yEnd + 1; R += 2) {
+        iter(R, 0);
+        iter(R + 1, 1);
+    }
+}
+
+int probe_march_rows(int elem_bytes, int nx, int ny, int cus) {
+    const int per_cu = elem_bytes == 4 ? fused_waves_per_cu<float>() : fused_waves_per_cu<double>();
+    return fused_auto_rows(nx, ny, (long long)cus * per_cu, false);
+}
+
+hipError_t launch_probe_march(const ProbeMarchArgs& a, int elem_bytes, hipStream_t s) {
+    const int gx = (a.nx + kOutW - 1) / kOutW;
+    const int nblk = gx * a.gy;
+    if (elem_bytes == 4)
+        hipLaunchKernelGGL(k_probe_march<float>, dim3(nblk), dim3(kWave), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_probe_march<double>, dim3(nblk), dim3(kWave), 0, s, a);
+    return hipGetLastError();
 }
 
 template hipError_t launch_ensemble<float>(const FusedArgs<float>*, const int*, int, int, int,

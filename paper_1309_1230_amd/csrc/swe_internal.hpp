@@ -61,6 +61,24 @@ int fused_strips(int nx);
 // Resident fused workgroups (one wave each) per compute unit, or 0.
 template <typename T>
 int fused_waves_per_cu();
+// Automatic tile height of the fused step for `slots` resident waves: as
+// many chunks per strip as fit one round of waves, at least 16 rows; with
+// the dry-tile skip at most 32.
+int fused_auto_rows(int nx, int ny, long long slots, bool dry_skip);
+
+// Access-pattern probe of the fused step (k_probe_march): in[0..4] read,
+// out[0..2] written, nx x ny elements at `pitch`, chunks of H rows (gy per
+// strip).
+struct ProbeMarchArgs {
+    const void* in[5];
+    void* out[3];
+    int nx, ny, H, gy;
+    long long pitch;
+};
+hipError_t launch_probe_march(const ProbeMarchArgs& a, int elem_bytes, hipStream_t s);
+// The tile height k_fused_step picks by itself on a device of `cus` compute
+// units for an nx x ny grid of elem_bytes-byte elements.
+int probe_march_rows(int elem_bytes, int nx, int ny, int cus);
 
 // Arguments of the unfused path: the trace block holds the 47 padded arrays
 // in trace order; zp/mp are the padded static fields.

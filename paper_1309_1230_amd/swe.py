@@ -92,7 +92,7 @@ class Gauges(ctypes.Structure):
 #: every function include/swe.h declares
 EXPORTS = ("swe_abi_version", "swe_config_init", "swe_create", "swe_destroy", "swe_step",
            "swe_run", "swe_run_dt", "swe_run_noalloc", "swe_get_stats", "swe_trace_step", "swe_trace_bytes", "swe_save",
-           "swe_load", "swe_last_error", "swe_probe_copy", "swe_probe_stream", "swe_grad", "swe_loss", "swe_ensemble_create",
+           "swe_load", "swe_last_error", "swe_probe_copy", "swe_probe_stream", "swe_probe_march", "swe_grad", "swe_loss", "swe_ensemble_create",
            "swe_ensemble_destroy", "swe_ensemble_run", "swe_ensemble_capture",
            "swe_ensemble_replay", "swe_ensemble_stats", "swe_ensemble_tile_rows",
            "swe_ensemble_last_error")
@@ -146,6 +146,11 @@ def lib():
                                        ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t,
                                        ctypes.c_int, ctypes.c_void_p]
         L.swe_probe_stream.restype = ctypes.c_int
+        L.swe_probe_march.argtypes = [ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_void_p]
+        L.swe_probe_march.restype = ctypes.c_int
         L.swe_grad.argtypes = [H, ctypes.c_int64, ctypes.POINTER(Gauges), ctypes.c_int32,
                                ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_void_p]
         L.swe_grad.restype = ctypes.c_int
@@ -426,6 +431,19 @@ def probe_stream(ins, outs, nontemporal=False, stream=None):
                                 _stream_ptr(stream))
     if rc != SWE_OK:
         raise SweError(rc, last_error(None))
+
+
+def probe_march(ins, outs, nx, ny, pitch, rows=0, stream=None):
+    """One launch of the library's march-pattern probe (the step kernel's
+    tiles, loads and stores without its arithmetic) over device tensors of
+    ny * pitch elements; returns the tile height used."""
+    arr_in = (ctypes.c_void_p * 5)(*[t.data_ptr() for t in ins])
+    arr_out = (ctypes.c_void_p * 3)(*[t.data_ptr() for t in outs])
+    rc = lib().swe_probe_march(arr_in, arr_out, nx, ny, pitch, outs[0].element_size(), rows,
+                               _stream_ptr(stream))
+    if rc <= 0:
+        raise SweError(rc, last_error(None))
+    return rc
 
 
 def probe_copy(dst, src, stream=None):

@@ -98,6 +98,22 @@ def test_probe_copy_rejects_misaligned():
     assert swe.lib().swe_probe_copy(16, 32, 10, None) == swe.SWE_EINVAL
 
 
+def test_probes_reject_bad_arguments():
+    L = swe.lib()
+    P5 = ctypes.c_void_p * 5
+    P3 = ctypes.c_void_p * 3
+    ins, outs = P5(*([4096] * 5)), P3(*([8192] * 3))
+    assert L.swe_probe_stream(None, outs, 64, 0, None) == swe.SWE_EINVAL
+    assert L.swe_probe_stream(ins, outs, 60, 0, None) == swe.SWE_EINVAL
+    assert L.swe_probe_march(None, outs, 64, 64, 64, 8, 0, None) == swe.SWE_EINVAL
+    assert L.swe_probe_march(ins, outs, 64, 64, 64, 3, 0, None) == swe.SWE_EINVAL
+    assert L.swe_probe_march(ins, outs, 65, 64, 64, 8, 0, None) == swe.SWE_EINVAL
+    assert L.swe_probe_march(ins, outs, 64, 64, 64, 8, -1, None) == swe.SWE_EINVAL
+    assert L.swe_probe_march(P5(4096, 4096, 0, 4096, 4096), outs, 64, 64, 64, 8, 0,
+                             None) == swe.SWE_EINVAL
+    assert "swe_probe_march" in swe.last_error(None)
+
+
 def test_create_without_device_reports_edevice():
     import torch
     if torch.cuda.is_available():
