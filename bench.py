@@ -351,9 +351,11 @@ def combined_run(torch, swe, W, nx, nsteps, ckpt, obs_every, h_film):
     state, FP64 adjoint of the gauge-misfit loss with respect to Manning n
     (each step linearised at its FP32 state), checkpoint spacing ckpt.
     Observations come from an FP32 run with the true Manning field.
-    h_film > 0 takes the thin-film reading of the dissipation switch (its
-    curvature measured against max(h, h_film)), without which the discrete
-    adjoint of this flood grows without bound."""
+    h_film > 0 takes the thin-film reading: the reciprocal depth of the
+    primitive variables and of the dissipation switch (S2, S9) is
+    min(1/h, 1/h_film), so films thinner than h_film do not give velocities
+    and switch values of order 1/h.  Without it the discrete adjoint of this
+    flood grows without bound."""
     import dataclasses
     ckpt = ckpt or max(1, int(round(math.sqrt(nsteps))))
     c = W.channel_flood(nx=nx, ny=nx, nsteps=nsteps, obs_every=obs_every)

@@ -312,8 +312,8 @@ int swe_loss(swe_handle* h, int64_t nsteps, const swe_gauges* g, double* loss);
  * time steps and stop independently (t_end, fatal flags).  The ensemble owns
  * one non-blocking stream (cfg->stream is ignored) and the scenarios' scratch.
  * tile_rows > 0 fixes the tile height for every scenario; 0 lets the
- * library's autotuner time the candidate heights 16, 32, 64 and 128 on the
- * ensemble itself (a few steps each, state restored afterwards) and keep the
+ * library's autotuner time the candidate heights 16, 32, 48, 64, 96 and 128 on the
+ * ensemble itself (the best of three short runs each, state restored afterwards) and keep the
  * fastest (cached per set of grid sizes for the life of the process).
  * Errors: as swe_create, plus SWE_EINVAL for mixed dtypes, an unfused path or
  * t0 != 0. */

@@ -197,3 +197,62 @@ def test_dry_skip_handle_gives_the_same_gradient(dtype, keep, monkeypatch):
     (Ja, gna, gza, sa), (Jb, gnb, gzb, sb) = out
     assert Ja == Jb and torch.equal(gna, gnb) and torch.equal(gza, gzb)
     assert sb.cells_skipped > 0 and sa.t == sb.t
+
+
+def south_flood():
+    """The flood scenario turned by 90 degrees: inflow through the south
+    edge, open north edge, walls west and east, so the front climbs through
+    the 16-row chunks of the two interior strips of a 200-column grid."""
+    f = W.flood_scenario(1, 300, 200)
+    z = np.ascontiguousarray(f.z.T)
+    return W.Problem(nx=200, ny=300, dx=f.dx, dy=f.dy, z=z, n=np.ascontiguousarray(f.n.T),
+                     eta=z.copy(), qx=np.zeros((300, 200)), qy=np.zeros((300, 200)),
+                     bc=(W.WALL, W.WALL, W.INFLOW, W.OPEN), hydro_t=f.hydro_t,
+                     hydro_q=f.hydro_q, name="flood_south_200x300")
+
+
+@pytest.mark.parametrize("dtype,keep", [("f32", "1"), ("f64", "1"), ("f64", "0")])
+def test_dry_skip_gradient_with_gauges_the_front_reaches(dtype, keep, monkeypatch):
+    """The checkpointed recompute writes every step of a segment into a slot
+    of its own; a tile left unwritten there (as the dry-tile skip leaves a
+    tile it skipped the step before too) would keep the slot's previous
+    content.  Segments are recomputed last first, so that content is the
+    same step of a later segment.  Here the front climbs from row 9 to row
+    ~54 during the run while the gauges sit in rows 32..47 of the interior
+    strips: those tiles are dry and skippable in the early segments and wet
+    in the late ones, so stale slots would show water at the gauge cells,
+    where the adjoint is not zero, and the gradient would differ.  It must
+    equal the dense handle's bit for bit."""
+    p = south_flood()
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    monkeypatch.setenv("SWE_GRAD_KEEP", keep)
+    k0, nsteps, every, ckpt = 60, 390, 10, 30
+    # gauge cells: the band's cells that the dense run wets by its end
+    ref = swe.Solver.from_problem(p, dtype=tdt, tile_rows=16)
+    ref.run(k0)
+    h0 = (ref.eta - ref.z).double().cpu().numpy()
+    ref.run(nsteps)
+    h1 = (ref.eta - ref.z).double().cpu().numpy()
+    ref.close()
+    band = np.zeros_like(h1, dtype=bool)
+    band[32:48, 62:178] = True
+    assert not (h0[band] > p.h_dry).any(), "the band must start dry"
+    wet_end = np.flatnonzero((band & (h1 > p.h_dry)).ravel())
+    assert len(wet_end) >= 6, len(wet_end)
+    rng = np.random.default_rng(11)
+    cells = rng.choice(wet_end, min(16, len(wet_end)), replace=False)
+    hobs = torch.as_tensor(rng.uniform(0.0, 0.5, (nsteps // every, len(cells))),
+                           dtype=torch.float64, device="cuda")
+    note(f"south flood 200x300 {dtype} keep={keep}: {k0} steps, then swe_grad of {nsteps} "
+         f"steps every {ckpt}, {len(cells)} gauges in the band the front reaches")
+    out = []
+    for dry in (False, True):
+        s = swe.Solver.from_problem(p, dtype=tdt, tile_rows=16, dry_skip=dry)
+        s.run(k0)
+        J, gn, gz = s.grad(nsteps, cells, every, hobs, ckpt)
+        out.append((J, gn, gz, s.stats()))
+        s.close()
+    (Ja, gna, gza, sa), (Jb, gnb, gzb, sb) = out
+    assert sb.cells_skipped > 0 and sa.t == sb.t
+    assert float(gna.abs().max()) > 0.0
+    assert Ja == Jb and torch.equal(gna, gnb) and torch.equal(gza, gzb)
