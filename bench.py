@@ -413,11 +413,17 @@ def combined_run(torch, swe, W, nx, nsteps, ckpt, obs_every, h_film):
            "loss": fin(J), "gradient_finite": finite, "h_film": h_film,
            "max_abs_dJ_dn": fin(float(gn.abs().max())),
            "max_abs_dJ_dz": fin(float(gz.abs().max())),
-           "gradient_note": ("thin-film switch reading (h_film > 0): the gradient is the "
-                             "FP64 linearisation along the FP32 trajectory" if h_film > 0 else
-                             "plain switch: the discrete adjoint grows exponentially through "
+           "gradient_note": ("thin-film reading (h_film > 0): the gradient is the FP64 "
+                             "linearisation along the FP32 trajectory.  On this flood at "
+                             "1024^2 (FP64) it is O(10) and agrees with central differences "
+                             "up to 3000 steps; by 5000 steps wet/dry switching makes the "
+                             "loss itself jump (difference quotients grow like 1/step), so "
+                             "no gradient can be checked there and this run's is a "
+                             "diagnostic" if h_film > 0 else
+                             "plain scheme: the discrete adjoint grows exponentially through "
                              "the wet/dry fronts of this flood, so the gradient is a "
                              "diagnostic"),
+           "gradient_target_met": False,
            "planned_scratch_bytes": planned, "device_free_bytes_before": free0,
            "device_total_bytes": total, "wet_fraction_end": wet,
            "gauges": len(c.cells), "obs_every": obs_every}

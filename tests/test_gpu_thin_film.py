@@ -17,6 +17,8 @@ trajectory: on this flood the FP32 run departs from the FP64 one at the
 fronts (its loss differs by 1.3e-4 relative), and its gradient by 6.8e-4 of
 the largest entry (measured on MI355X).
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -105,3 +107,78 @@ def test_thin_film_flood_gradient_matches_oracle():
     note(f"mixed FP32/FP64 gradient vs oracle: max diff / max |grad| {d:.2e}, "
          f"J {J32:.6e} vs {Jo:.6e}")
     assert d <= 2e-3
+
+
+def test_thin_film_flood_gradient_matches_central_differences():
+    """The combined run's flood at 1024 x 1024 (dx = 1 m), FP64, 2000 steps,
+    h_film = 0.1 m, gauges every 50 steps: dJ/dn against central differences
+    of the loss on the run's own time grid (swe_run_dt), at the four largest
+    entries and four random ones of at least 1e-3 of the largest.
+
+    The flood's loss has kinks packed densely by then (a step sweep on
+    MI355X: at 1e-3 n kinks dominate everywhere, at 1e-5 n two of eight cells
+    still sit on one, at 1e-7 n the one-sided quotients agree to 1e-5 and the
+    central one matches the adjoint to 1e-6 or better, with rounding noise of
+    about 1e-7 absolute).  Step 1e-7 n; a cell whose one-sided quotients
+    differ by more than 1e-3 of the adjoint counts as kinked.  Bar: at most
+    two kinked cells, the others within 1e-4.  (By 5000 steps the wet/dry
+    switching makes the loss jump: the quotients grow like 1/step and change
+    sign, so no gradient can be checked there.)"""
+    nx, nsteps, every = 1024, 2000, 50
+    c = W.channel_flood(nx=nx, ny=nx, nsteps=nsteps, obs_every=every)
+    p = c.problem
+    p.h_film = 0.1
+    ct = torch.as_tensor(c.cells, device="cuda")
+    note(f"channel flood {nx}x{nx}, h_film 0.1: observations, then the first-guess time grid")
+    s = swe.Solver.from_problem(dataclasses.replace(p, n=c.n_true), dtype=torch.float64)
+    obs = []
+    for _ in range(nsteps // every):
+        s.run(every)
+        obs.append(s.eta.reshape(-1)[ct] - s.z.reshape(-1)[ct])
+    s.close()
+    hobs = torch.stack(obs).contiguous()
+    s = swe.Solver.from_problem(p, dtype=torch.float64)
+    dts = np.array([s.step() for _ in range(nsteps)])
+    s.close()
+
+    def loss(n):
+        q = dataclasses.replace(p, n=n)
+        r = swe.Solver.from_problem(q, dtype=torch.float64)
+        zc = r.z.reshape(-1)[ct]
+        J = torch.zeros((), dtype=torch.float64, device="cuda")
+        for k in range(nsteps // every):
+            r.run_dt(dts[k * every:(k + 1) * every])
+            d = r.eta.reshape(-1)[ct] - zc - hobs[k]
+            J = J + (d * d).sum()
+        r.close()
+        return float(J)
+
+    g = swe.Solver.from_problem(p, dtype=torch.float64)
+    J, gn, _ = g.grad(nsteps, c.cells, every, hobs, 45)
+    g.close()
+    gn = gn.cpu().numpy()
+    J0 = loss(p.n)
+    assert J0 == pytest.approx(J, rel=1e-12)
+    assert np.abs(gn).max() < 1e3
+    order = np.argsort(-np.abs(gn).ravel())
+    big = np.flatnonzero(np.abs(gn).ravel() >= 1e-3 * np.abs(gn).max())
+    rng = np.random.default_rng(5)
+    cells = list(order[:4]) + list(rng.choice(big, 4, replace=False))
+    errs, kinks = [], 0
+    for cell in cells:
+        j, i = divmod(int(cell), nx)
+        d = 1e-7 * p.n[j, i]
+        npl, nmi = p.n.copy(), p.n.copy()
+        npl[j, i] += d
+        nmi[j, i] -= d
+        Jp, Jm = loss(npl), loss(nmi)
+        fd = (Jp - Jm) / (npl[j, i] - nmi[j, i])
+        spread = abs((Jp - J0) / (npl[j, i] - p.n[j, i]) - (J0 - Jm) / (p.n[j, i] - nmi[j, i]))
+        kinked = spread > 1e-3 * abs(gn[j, i])
+        kinks += kinked
+        rel = abs(fd - gn[j, i]) / abs(gn[j, i])
+        if not kinked:
+            errs.append(rel)
+        note(f"cell ({i},{j}): adjoint {gn[j, i]:+.8e} central {fd:+.8e} rel {rel:.1e}"
+             f"{'  (kink)' if kinked else ''}")
+    assert kinks <= 2 and max(errs) <= 1e-4
