@@ -79,7 +79,14 @@ typedef struct swe_config {
     int32_t inflow_lo[4];    /* INFLOW face band along each edge: faces k with */
     int32_t inflow_hi[4];    /*   lo <= k < hi (k = j on W/E, k = i on S/N) */
     int32_t hydro_len;       /* points of the hydrograph, 0..4096 (0: q_in = 0) */
-    int32_t tile_rows;       /* rows per workgroup of the fused kernel, 0 = auto */
+    int32_t tile_rows;       /* rows per workgroup of the fused kernel, 0 = auto (as
+                              * many chunks per strip as resident waves allow, at least
+                              * 16 rows).  SWE_FUSED_WAVES=3 (FP64) or 4 (FP32) in the
+                              * environment at swe_create selects the fused kernel's
+                              * occupancy variant, one more resident wave per SIMD than
+                              * its register budget allows (part of the carried state
+                              * spills); a measurement knob with the same results, not
+                              * used with the dry-tile skip */
     int64_t pitch;           /* row pitch of every field in elements, >= nx */
     double dx, dy;           /* cell size (m), > 0 */
     double g;                /* gravity (m/s^2), > 0 */

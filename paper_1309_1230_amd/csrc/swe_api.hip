@@ -27,6 +27,7 @@ struct swe_handle {
     int dtype = SWE_F64;
     int path = SWE_PATH_FUSED;
     int H = 0, gy = 0;
+    bool more_waves = false;   // the fused step's occupancy variant (SWE_FUSED_WAVES)
     size_t elem = 8;
     hipStream_t stream = nullptr;
     int device = 0;
@@ -156,7 +157,7 @@ hipError_t enqueue_step(swe_handle* h, int64_t k, double t_end, bool unfused, do
     a.dry = h->dry;
     a.log_dt = log_dt;
     a.log_t = log_t;
-    return swe::launch_fused<T>(a, sigma, h->stream);
+    return swe::launch_fused<T>(a, sigma, h->stream, h->more_waves);
 }
 
 // Start of a host call: per-call statistics reset and, with the dry-tile
@@ -248,8 +249,8 @@ bool is_device_ptr(const void* p, int device) {
 int auto_tile_rows(const swe_handle* h, int dev, bool dry_skip) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
-    const int per_cu = h->dtype == SWE_F32 ? swe::fused_waves_per_cu<float>()
-                                           : swe::fused_waves_per_cu<double>();
+    const int per_cu = h->dtype == SWE_F32 ? swe::fused_waves_per_cu<float>(h->more_waves)
+                                           : swe::fused_waves_per_cu<double>(h->more_waves);
     return swe::fused_auto_rows(h->P.nx, h->P.ny, (long long)cus * per_cu, dry_skip);
 }
 
@@ -345,6 +346,12 @@ void prepare_handle(swe_handle* h, const swe_config* c, int dev) {
     P.idx = 1.0 / c->dx;
     P.idy = 1.0 / c->dy;
     P.rcap = c->h_film > 0.0 ? 1.0 / c->h_film : INFINITY;
+    // SWE_FUSED_WAVES=3 (FP64) or 4 (FP32) in the environment selects the fused
+    // step's occupancy variant, one resident wave per SIMD more than its
+    // default register budget allows (a measurement knob; same results)
+    if (const char* w = std::getenv("SWE_FUSED_WAVES"))
+        h->more_waves = c->path == SWE_PATH_FUSED && c->dry_skip == 0 &&
+                        std::atoi(w) == (c->dtype == SWE_F32 ? 4 : 3);
     h->H = c->tile_rows > 0 ? c->tile_rows : auto_tile_rows(h, dev, c->dry_skip != 0);
     h->gy = (c->ny + h->H - 1) / h->H;
     h->nparts = std::max(swe::fused_blocks(c->nx, c->ny, h->H), swe::scan_partials(c->nx, c->ny));
@@ -1051,7 +1058,7 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
                     continue;
                 }
             }
-            e = swe::launch_fused<T>(fa, sig, h->stream);
+            e = swe::launch_fused<T>(fa, sig, h->stream, h->more_waves);
         }
         for (int64_t k = s1 - 1; k >= s0 && e == hipSuccess; --k) {
             T* Uk[3];

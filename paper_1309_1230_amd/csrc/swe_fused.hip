@@ -611,6 +611,19 @@ template <int SIG, bool DRY>
 __global__ void __launch_bounds__(kWave, 3) k_fused_step_f32(FusedArgs<float> A) {
     fused_step<float, SIG, DRY>(A, blockIdx.x, gridDim.x);
 }
+// The same steps with one more resident wave per SIMD than the register
+// budget above allows (FP64 3, FP32 4; the state the march carries then
+// partly spills to scratch): the occupancy variant that a launch asks for
+// with `more_waves` (a measurement of what occupancy buys; the results are
+// the same bits, only the register allocation differs).
+template <int SIG>
+__global__ void __launch_bounds__(kWave, 3) k_fused_step_f64_w3(FusedArgs<double> A) {
+    fused_step<double, SIG, false>(A, blockIdx.x, gridDim.x);
+}
+template <int SIG>
+__global__ void __launch_bounds__(kWave, 4) k_fused_step_f32_w4(FusedArgs<float> A) {
+    fused_step<float, SIG, false>(A, blockIdx.x, gridDim.x);
+}
 // The FP64 step that also writes U* and U^d (the forward data of the adjoint).
 template <int SIG>
 __global__ void __launch_bounds__(kWave, 2) k_fused_trace_f64(FusedArgs<double> A) {
@@ -674,14 +687,22 @@ constexpr auto fused_kernel() {
     else
         return &k_fused_step_f32<SIG, DRY>;
 }
+template <typename T, int SIG>
+constexpr auto fused_kernel_more() {
+    if constexpr (sizeof(T) == 8)
+        return &k_fused_step_f64_w3<SIG>;
+    else
+        return &k_fused_step_f32_w4<SIG>;
+}
 
 template <typename T>
-hipError_t launch_fused(const FusedArgs<T>& a, int sigma, hipStream_t s) {
+hipError_t launch_fused(const FusedArgs<T>& a, int sigma, hipStream_t s, bool more_waves) {
     const int gx = (a.P.nx + kOutW - 1) / kOutW;
     const int nblk = gx * a.gy;
     const bool dry = a.dry != nullptr;
-    const auto k = sigma > 0 ? (dry ? fused_kernel<T, 1, true>() : fused_kernel<T, 1, false>())
-                             : (dry ? fused_kernel<T, -1, true>() : fused_kernel<T, -1, false>());
+    auto k = sigma > 0 ? (dry ? fused_kernel<T, 1, true>() : fused_kernel<T, 1, false>())
+                       : (dry ? fused_kernel<T, -1, true>() : fused_kernel<T, -1, false>());
+    if (more_waves && !dry) k = sigma > 0 ? fused_kernel_more<T, 1>() : fused_kernel_more<T, -1>();
     hipLaunchKernelGGL(k, dim3(nblk), dim3(kWave), 0, s, a);
     return hipGetLastError();
 }
@@ -729,11 +750,11 @@ void fused_part_layout(FusedArgs<T>& a, void* buf, int ntiles) {
 }
 
 template <typename T>
-int fused_waves_per_cu() {
+int fused_waves_per_cu(bool more_waves) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fused_kernel<T, 1, false>(), kWave,
-                                                     0) != hipSuccess)
-        return 0;
+    const void* k = more_waves ? (const void*)fused_kernel_more<T, 1>()
+                               : (const void*)fused_kernel<T, 1, false>();
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kWave, 0) != hipSuccess) return 0;
     return nb;
 }
 
@@ -789,7 +810,7 @@ __global__ void __launch_bounds__(kWave) k_probe_march(ProbeMarchArgs A) {
 }
 
 int probe_march_rows(int elem_bytes, int nx, int ny, int cus) {
-    const int per_cu = elem_bytes == 4 ? fused_waves_per_cu<float>() : fused_waves_per_cu<double>();
+    const int per_cu = elem_bytes == 4 ? fused_waves_per_cu<float>(false) : fused_waves_per_cu<double>(false);
     return fused_auto_rows(nx, ny, (long long)cus * per_cu, false);
 }
 
@@ -807,11 +828,11 @@ template hipError_t launch_ensemble<float>(const FusedArgs<float>*, const int*, 
                                            bool, hipStream_t);
 template hipError_t launch_ensemble<double>(const FusedArgs<double>*, const int*, int, int, int,
                                             bool, hipStream_t);
-template hipError_t launch_fused<float>(const FusedArgs<float>&, int, hipStream_t);
-template hipError_t launch_fused<double>(const FusedArgs<double>&, int, hipStream_t);
+template hipError_t launch_fused<float>(const FusedArgs<float>&, int, hipStream_t, bool);
+template hipError_t launch_fused<double>(const FusedArgs<double>&, int, hipStream_t, bool);
 template void fused_part_layout<float>(FusedArgs<float>&, void*, int);
 template void fused_part_layout<double>(FusedArgs<double>&, void*, int);
-template int fused_waves_per_cu<float>();
-template int fused_waves_per_cu<double>();
+template int fused_waves_per_cu<float>(bool);
+template int fused_waves_per_cu<double>(bool);
 
 }  // namespace swe

@@ -39,8 +39,10 @@ struct FusedArgs {
     T* tud[3] = {nullptr, nullptr, nullptr};
 };
 
+// more_waves: the occupancy variant (one more resident wave per SIMD, some
+// of the carried state in scratch; not with the dry-tile skip).
 template <typename T>
-hipError_t launch_fused(const FusedArgs<T>& a, int sigma, hipStream_t s);
+hipError_t launch_fused(const FusedArgs<T>& a, int sigma, hipStream_t s, bool more_waves = false);
 // The FP64 fused step that also writes U* (after S7) and U^d (after S13,
 // before friction) of every cell to a.tus and a.tud.
 hipError_t launch_fused_trace(const FusedArgs<double>& a, int sigma, hipStream_t s);
@@ -60,7 +62,7 @@ void fused_part_layout(FusedArgs<T>& a, void* buf, int ntiles);
 int fused_strips(int nx);
 // Resident fused workgroups (one wave each) per compute unit, or 0.
 template <typename T>
-int fused_waves_per_cu();
+int fused_waves_per_cu(bool more_waves = false);
 // Automatic tile height of the fused step for `slots` resident waves: as
 // many chunks per strip as fit one round of waves, at least 16 rows; with
 // the dry-tile skip at most 32.

@@ -112,6 +112,26 @@ def test_fused_equals_unfused_bitwise(dtype, tile_rows):
     assert sa.defect == pytest.approx(sb.defect, rel=1e-12, abs=1e-12)
 
 
+@pytest.mark.parametrize("dtype,waves", [("f64", "3"), ("f32", "4")])
+def test_occupancy_variant_equals_default_bitwise(dtype, waves, monkeypatch):
+    """The fused kernel's occupancy variant (SWE_FUSED_WAVES: one more
+    resident wave per SIMD, part of the carried state in scratch) is the same
+    code under another register budget: the same bits, at its own automatic
+    tile height and at a fixed one."""
+    p = W.reservoir_release(nx=300, ny=220, dx=60.0, hills=30, seed=1001)
+    for tile_rows in (0, 16):
+        note(f"occupancy variant {dtype} SWE_FUSED_WAVES={waves} H={tile_rows or 'auto'}")
+        a = solver(p, dtype, tile_rows=tile_rows)
+        monkeypatch.setenv("SWE_FUSED_WAVES", waves)
+        b = solver(p, dtype, tile_rows=tile_rows)
+        monkeypatch.delenv("SWE_FUSED_WAVES")
+        sa, sb = a.run(30), b.run(30)
+        for x, y in zip(state(a), state(b)):
+            assert np.array_equal(x, y)
+        assert sa.dt == sb.dt and sa.t == sb.t
+        assert sa.volume == pytest.approx(sb.volume, rel=1e-12)
+
+
 def test_fused_run_to_run_deterministic():
     p = W.reservoir_release(nx=300, ny=220, dx=60.0, hills=30, seed=1001)
     note("run-to-run determinism reservoir300x220")
