@@ -794,10 +794,12 @@ __global__ void __launch_bounds__(kWave) k_probe_march(ProbeMarchArgs A) {
         const long long o = off(R + 1);
         pe[1 - S] = f0[o]; pa[1 - S] = f1[o]; pb[1 - S] = f2[o]; pz[1 - S] = f3[o];
         pm[1 - S] = f4[off(R - 1)];
+        // the shifts run with every lane active (a disabled source lane reads 0)
+        const T e1E = from_east(e1), a1W = from_west(a1);
         if (R - 2 >= y0 && R - 2 < yEnd && colOut) {
             const long long so = (long long)(R - 2) * A.pitch + i;
-            o0[so] = e2 + from_east(e1) * m2;
-            o1[so] = a2 + z2 * from_west(a1) + e0;
+            o0[so] = e2 + e1E * m2;
+            o1[so] = a2 + z2 * a1W + e0;
             o2[so] = b2 + b1 * z1 + a0 * b0 + z0;
         }
         e2 = e1; a2 = a1; b2 = b1; z2 = z1;
