@@ -284,10 +284,10 @@ typedef struct swe_gauges {
  * fits in three quarters of the free device memory, and then recomputes
  * nothing; the buffer stays with the handle for later calls and is released
  * by swe_destroy.  Otherwise, and for FP32 handles, the spacing is
- * round(sqrt(nsteps)).  The reverse step runs as one fused march
- * (SWE_ADJOINT=gather in the environment selects four gather kernels
- * instead).  The gradient is the same bit for bit in every one of these
- * modes.  dJ_dn and dJ_dz (device, FP64, caller-owned, the handle's pitch)
+ * round(sqrt(nsteps)).  The reverse step runs as one fused march with two
+ * waves per tile (SWE_ADJOINT=march1 in the environment selects the one-wave
+ * march, SWE_ADJOINT=gather four gather kernels instead).  The gradient is
+ * the same bit for bit in every one of these modes.  dJ_dn and dJ_dz (device, FP64, caller-owned, the handle's pitch)
  * receive the gradients;
  * *loss (host) receives J.  FP32 handles: the forward run, its checkpoints
  * and the recomputed segments are FP32 (the state trajectory is that of

@@ -904,7 +904,7 @@ struct MarchRow {
 // EDGE: the strip holds the west or the east edge column (its lanes may be
 // ghost or outside columns); otherwise every lane is an interior column and
 // the column tests are compiled out.
-template <bool HOBS, bool EDGE>
+template <bool HOBS, bool EDGE, int PART = 0>
 struct AdjMarch {
     const AdjointArgs& a;
     const int* gmap;
@@ -938,6 +938,15 @@ struct AdjMarch {
     double une[2], unx[2], uny[2];              // U^n adjoint, S12 and S4 terms
     double dbx[2], atx[2], aty[2], dby[3];      // switch derivatives of S3
     MarchRow pf;
+    // PART 1 and 2 (two waves of one workgroup): the rows wave 1 forms and
+    // wave 2 reads, in an LDS ring of 8 rows per field: D-bar of row r
+    // (fields 0..2), the bed's share of row r-1 after S12's flux part, the
+    // U* adjoint of row r-1 (fields 4..6), all filed under r.
+    double* ring = nullptr;
+    int lane = 0;
+    __device__ __forceinline__ double& rg(int f, int r) const {
+        return ring[(f * 8 + (r & 7)) * kWave + lane];
+    }
 
     __device__ AdjMarch(const AdjointArgs& a_, const int* g, const double* h)
         : a(a_), gmap(g), hobs(h) {}
@@ -954,10 +963,13 @@ struct AdjMarch {
         const unsigned o = (unsigned)(jj * (int)a.P.pitch + ii) * 8u;
         const unsigned C = (unsigned)((min(max(R, -1), d.ny) + 1) * d.P2 + ic + 1) * 8u;
         const unsigned NB = (unsigned)d.N * 8u;
-        pf.ue = at_off(a.un[0], o); pf.ux = at_off(a.un[1], o); pf.uy = at_off(a.un[2], o);
+        if (PART != 1) {
+            pf.ue = at_off(a.un[0], o); pf.ux = at_off(a.un[1], o); pf.uy = at_off(a.un[2], o);
+        }
+        pf.z = at_off(a.zp, C);
+        if (PART == 2) return;
         pf.se = at_off(a.us[0], o); pf.sx = at_off(a.us[1], o); pf.sy = at_off(a.us[2], o);
         pf.de = at_off(a.ud[0], o); pf.dx = at_off(a.ud[1], o); pf.dy = at_off(a.ud[2], o);
-        pf.z = at_off(a.zp, C);
         pf.m = at_off(a.mp, C);
         pf.n = at_off(a.nman, o);
         pf.l0 = at_off(LIN, C); pf.l1 = at_off(LIN, C + NB); pf.l2 = at_off(LIN, C + 2 * NB);
@@ -987,12 +999,12 @@ struct AdjMarch {
     }
 
     __device__ __forceinline__ void store_previous(int R) {
-        if (o_fa) {
+        if (PART != 2 && o_fa) {
             const long long C = d.at(i, R - 1);
             GZ[C] = o_gz;
             if (o_wet) GN[C] = o_gn;
         }
-        if (o_e2) {
+        if (PART != 1 && o_e2) {
             const long long C = d.at(i, R - 4);
             LOUT[C] = o_l0;
             LOUT[d.N + C] = o_l1;
@@ -1023,18 +1035,18 @@ struct AdjMarch {
 
         // ---- ingest row R: U^n and U* cells (ghost rule, primitives), bed
         zz[0] = q.z;
-        {
+        if (PART != 1) {
             const Cell c = make_cell<EDGE, BND>(a.P, q.ue, q.ux, q.uy, a.qin0, i, R, q.z, kW, kE);
             ue[0] = c.e; ux[0] = c.qx; uy[0] = c.qy; ur[0] = c.r;
         }
-        {
+        if (PART != 2) {
             const Cell c = make_cell<EDGE, BND>(a.P, q.se, q.sx, q.sy, a.qin1, i, R, q.z, kW, kE);
             se[0] = c.e; sx[0] = c.qx; sy[0] = c.qy; sr[0] = c.r;
         }
 
         // ---- row R: S15, S14, S13, S12's U^n share (with the step reversed
         // before this one's S1 fold and this step's gauge terms)
-        {
+        if (PART != 2) {
             // the west and east ghosts of lambda and of the bed's share are
             // the neighbouring lanes' values of this row
             double lw0 = 0.0, lw1 = 0.0, lw2 = 0.0, le0 = 0.0, le1 = 0.0, le2 = 0.0;
@@ -1092,7 +1104,7 @@ struct AdjMarch {
         }
 
         // ---- row R-1: flux part of S12, S11, S10, S9 (the U* adjoint)
-        {
+        if (PART != 2) {
             const int j = R - 1;
             const double b0 = 0.5 * ade[1], b1 = 0.5 * adx[1], b2 = 0.5 * ady[1];
             const Nbr E = nbr_east(se[1], sx[1], sy[1], sr[1], zz[1], b0, b1, b2);
@@ -1123,8 +1135,28 @@ struct AdjMarch {
             ause[0] = eb; ausx[0] = qxb; ausy[0] = qyb;
         }
 
+        if (PART == 1) {
+            // file this iteration's rows for the second wave
+            rg(0, R) = ade[0]; rg(1, R) = adx[0]; rg(2, R) = ady[0];
+            rg(3, R) = azp[1];
+            rg(4, R) = ause[0]; rg(5, R) = ausx[0]; rg(6, R) = ausy[0];
+        }
+        if (PART == 2) {
+            // the first wave's rows: D-bar of rows R-1..R-3, the bed's share of
+            // row R-3, the U* adjoint of rows R-1..R-3
+#pragma unroll
+            for (int k = 1; k < 4; ++k) {
+                ade[k] = rg(0, R - k); adx[k] = rg(1, R - k); ady[k] = rg(2, R - k);
+            }
+            azp[3] = rg(3, R - 2);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                ause[k] = rg(4, R - k); ausx[k] = rg(5, R - k); ausy[k] = rg(6, R - k);
+            }
+        }
+
         // ---- row R-2: the S8 fold of the U* adjoint
-        {
+        if (PART != 1) {
             const int j = R - 2;
             double we = 0.0, wx = 0.0, wy = 0.0, ee = 0.0, ex = 0.0, ey = 0.0;
             if (EDGE) {
@@ -1147,7 +1179,7 @@ struct AdjMarch {
 
         // ---- row R-2: S4 (nu-bar and the U^n adjoint's first terms), then
         // the switch derivatives of S3
-        {
+        if (PART != 1) {
             const int j = R - 2;
             const Cell me = carried_cell(ue[2], ux[2], uy[2], ue[2] - zz[2], ur[2]);
             const double eW = from_west(ue[2]), eE = from_east(ue[2]);
@@ -1205,7 +1237,7 @@ struct AdjMarch {
         }
 
         // ---- row R-3: S7, S6, S5, S3, S2: lambda^n and the bed's share
-        {
+        if (PART != 1) {
             const int j = R - 3;
             const Nbr E = nbr_east(ue[3], ux[3], uy[3], ur[3], zz[3], fse[1], fsx[1], fsy[1]);
             const double dbW = from_west(dbx[1]), dbE = from_east(dbx[1]);
@@ -1328,8 +1360,9 @@ struct AdjMarch {
         }
     }
 
-    __device__ __forceinline__ void run(int lane, int strip, int chunk, int H, int lout,
+    __device__ __forceinline__ void run(int lane_, int strip, int chunk, int H, int lout,
                                         int zout) {
+        lane = lane_;
         d = pad_of(a.P);
         LIN = wk(a, d, a.lam_slot);
         AZI = wk(a, d, a.azp_slot);
@@ -1353,7 +1386,7 @@ struct AdjMarch {
         // a tile of an interior strip at least five rows from the south and
         // north edges may be a dry tile
         if (!EDGE && j0 - 5 >= 0 && j1 + 4 <= d.ny - 1 && dry_tile(lane)) {
-            dry_rows();
+            if (PART != 2) dry_rows();
             return;
         }
 #pragma unroll
@@ -1373,13 +1406,35 @@ struct AdjMarch {
         // R forms lambda^n of row R-3 (stored by the next iteration).  (Leaving
         // the unneeded phases out of the filling iterations was measured
         // slower: the extra code raises the main loop's register pressure.)
+        if (PART == 0) {
+            prefetch(j0 - 3);
+            // rows that reach the domain's first or last two rows take the
+            // general iteration, the others the interior one
+            int R = j0 - 3;
+            for (; R <= j1 + 2 && R < 5; ++R) iter<true>(R);
+            for (; R <= j1 + 2 && R <= d.ny - 3; ++R) iter<false>(R);
+            for (; R <= j1 + 2; ++R) iter<true>(R);
+            store_previous(j1 + 3);
+            return;
+        }
+        // Two waves: the first forms rows R and R-1 of iteration R, the
+        // second rows R-2 and R-3 of the same iteration one step later, from
+        // the rows the first filed in the ring (zero before any is filed, as
+        // the carried rows are).  One workgroup barrier per step.
+        if (PART == 1)
+            for (int k = 0; k < 7 * 8; ++k) ring[k * kWave + lane] = 0.0;
+        __syncthreads();
         prefetch(j0 - 3);
-        // rows that reach the domain's first or last two rows take the
-        // general iteration, the others the interior one
-        int R = j0 - 3;
-        for (; R <= j1 + 2 && R < 5; ++R) iter<true>(R);
-        for (; R <= j1 + 2 && R <= d.ny - 3; ++R) iter<false>(R);
-        for (; R <= j1 + 2; ++R) iter<true>(R);
+        for (int t = j0 - 3; t <= j1 + 3; ++t) {
+            const int R = PART == 1 ? t : t - 1;
+            if (PART == 1 ? R <= j1 + 2 : R >= j0 - 3) {
+                if (R >= 5 && R <= d.ny - 3)
+                    iter<false>(R);
+                else
+                    iter<true>(R);
+            }
+            __syncthreads();
+        }
         store_previous(j1 + 3);
     }
 };
@@ -1422,6 +1477,51 @@ k_adj_march(AdjointArgs a, const int* gmap, const double* hobs, MarchTiles T, in
         M.run(lane, strip, chunk, H, lout, zout);
     } else {
         AdjMarch<HOBS, false> M(a, gmap, hobs);
+        M.run(lane, strip, chunk, H, lout, zout);
+    }
+}
+
+// The march as a two-wave pipeline (one workgroup of two waves per tile):
+// wave 0 forms rows R and R-1 of each iteration (S15..S9: D-bar, the U*
+// adjoint, dJ/dn and dJ/dz), wave 1 rows R-2 and R-3 (the S8 fold, S4, S3 and
+// S7..S2: lambda^n and the bed's share), one step behind, from the rows wave
+// 0 files in LDS.  Each wave carries about half the rows, so two fit per SIMD
+// (256 registers) where the one-wave march holds one; the sums and their
+// order are the one-wave march's, so the results are the same bits.
+template <bool HOBS>
+__global__ void __launch_bounds__(2 * kWave, 2)
+k_adj_march2(AdjointArgs a, const int* gmap, const double* hobs, MarchTiles T, int lout,
+             int zout) {
+    __shared__ double ring[7 * 8 * kWave];
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    int strip, chunk, H;
+    if (T.se <= 1) {
+        strip = t / T.gye; chunk = t % T.gye; H = T.He;
+    } else if (t < T.gye) {
+        strip = 0; chunk = t; H = T.He;
+    } else if (t < T.gye + (T.se - 1) * T.gy) {
+        strip = 1 + (t - T.gye) / T.gy; chunk = (t - T.gye) % T.gy; H = T.H;
+    } else {
+        const int u = t - T.gye - (T.se - 1) * T.gy;
+        strip = T.se + u / T.gye; chunk = u % T.gye; H = T.He;
+    }
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const bool edge = strip == 0 || strip >= T.se;
+    if (edge && wave == 0) {
+        AdjMarch<HOBS, true, 1> M(a, gmap, hobs);
+        M.ring = ring;
+        M.run(lane, strip, chunk, H, lout, zout);
+    } else if (edge) {
+        AdjMarch<HOBS, true, 2> M(a, gmap, hobs);
+        M.ring = ring;
+        M.run(lane, strip, chunk, H, lout, zout);
+    } else if (wave == 0) {
+        AdjMarch<HOBS, false, 1> M(a, gmap, hobs);
+        M.ring = ring;
+        M.run(lane, strip, chunk, H, lout, zout);
+    } else {
+        AdjMarch<HOBS, false, 2> M(a, gmap, hobs);
+        M.ring = ring;
         M.run(lane, strip, chunk, H, lout, zout);
     }
 }
@@ -1478,17 +1578,25 @@ int adjoint_march_rows(const Params& P, int ncu) {
 }
 
 hipError_t launch_adjoint_march(const AdjointArgs& a, const int* gmap, const double* hobs, int H,
-                                hipStream_t s) {
+                                hipStream_t s, bool two_waves) {
     if (H < 1) return hipErrorInvalidValue;
     const MarchTiles T = march_tiles(a.P, H);
     const int lout = a.lam_slot == kAdjLamSlot[0] ? kAdjLamSlot[1] : kAdjLamSlot[0];
     const int zout = a.azp_slot == kAdjZpSlot[0] ? kAdjZpSlot[1] : kAdjZpSlot[0];
-    if (hobs)
+    if (two_waves) {
+        if (hobs)
+            hipLaunchKernelGGL(k_adj_march2<true>, dim3(T.count()), dim3(2 * kWave), 0, s, a, gmap,
+                               hobs, T, lout, zout);
+        else
+            hipLaunchKernelGGL(k_adj_march2<false>, dim3(T.count()), dim3(2 * kWave), 0, s, a,
+                               gmap, hobs, T, lout, zout);
+    } else if (hobs) {
         hipLaunchKernelGGL(k_adj_march<true>, dim3(T.count()), dim3(kWave), 0, s, a, gmap, hobs,
                            T, lout, zout);
-    else
+    } else {
         hipLaunchKernelGGL(k_adj_march<false>, dim3(T.count()), dim3(kWave), 0, s, a, gmap,
                            hobs, T, lout, zout);
+    }
     return hipGetLastError();
 }
 

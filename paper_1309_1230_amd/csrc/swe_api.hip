@@ -985,12 +985,13 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
     aa.mp = padst.d() + Npad;
     aa.nman = n64;
     aa.work = work.d();
-    // the reverse step runs as one fused march (default) or as the four
-    // gather kernels (SWE_ADJOINT=gather in the environment); both give the
-    // same bits
+    // the reverse step runs as one fused march of two waves per tile
+    // (default), the one-wave march (SWE_ADJOINT=march1 in the environment)
+    // or the four gather kernels (SWE_ADJOINT=gather); all give the same bits
     const char* adj_env = std::getenv("SWE_ADJOINT");
     const bool march =
         !(adj_env && std::strcmp(adj_env, "gather") == 0) && swe::adjoint_march_fits(h->P);
+    const bool march2 = !(adj_env && std::strcmp(adj_env, "march1") == 0);
     int march_rows = 0;
     if (march) {
         int cus = 0;
@@ -1130,7 +1131,7 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
             const double* hrow = obs ? g->hobs + ((k + 1) / g->obs_every - 1) * ng : nullptr;
             if (march) {
                 e = swe::launch_adjoint_march(aa, (const int*)gmap.p, hrow, march_rows,
-                                              h->stream);
+                                              h->stream, march2);
                 // lambda^n and the bed's share are now in the other slot of each pair
                 aa.lam_slot = aa.lam_slot == swe::kAdjLamSlot[0] ? swe::kAdjLamSlot[1]
                                                                  : swe::kAdjLamSlot[0];

@@ -179,11 +179,12 @@ constexpr int kAdjLamSlot[2] = {9, 0}, kAdjZpSlot[2] = {14, 12};
 hipError_t launch_adjoint_step(const AdjointArgs& a, const int* gmap, const double* hobs,
                                hipStream_t s);
 // The same step as one fused reverse march (one wave per strip of columns,
-// chunks of H rows): reads lambda and the bed adjoint from a.lam_slot and
-// a.azp_slot, writes them to the other slot of each pair.  The result is bit
-// for bit the one launch_adjoint_step gives.
+// chunks of H rows; two_waves: a workgroup of two waves per tile, each
+// forming half of the phases, one step apart): reads lambda and the bed
+// adjoint from a.lam_slot and a.azp_slot, writes them to the other slot of
+// each pair.  The result is bit for bit the one launch_adjoint_step gives.
 hipError_t launch_adjoint_march(const AdjointArgs& a, const int* gmap, const double* hobs, int H,
-                                hipStream_t s);
+                                hipStream_t s, bool two_waves = true);
 // Chunk height of the reverse march for a grid on a device with ncu compute
 // units.
 int adjoint_march_rows(const Params& P, int ncu);

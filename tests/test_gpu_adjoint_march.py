@@ -1,7 +1,7 @@
-"""The fused reverse march of the adjoint step against the four gather
-kernels.
+"""The fused reverse march of the adjoint step (the two-wave march, the
+default, and the one-wave march) against the four gather kernels.
 
-Both evaluate the same expressions and sum each cell's terms in the same
+All evaluate the same expressions and sum each cell's terms in the same
 order, so the gradients must agree bit for bit (the gather kernels are in
 turn held to the oracle's reverse-mode gradient in test_gpu_adjoint.py).
 The cases span one and several strips of the march, chunks of its minimum
@@ -40,16 +40,18 @@ def where_differs(a, b):
 
 def check_equal(p, nsteps, every, ncell, ckpt, seed, monkeypatch, dtype=torch.float64):
     g = grads(p, nsteps, every, ncell, ckpt, seed, "gather", monkeypatch, dtype)
-    m = grads(p, nsteps, every, ncell, ckpt, seed, "march", monkeypatch, dtype)
     assert np.isfinite(g[1]).all() and np.isfinite(g[2]).all()
     # over one step n changes only the discharges, which the loss does not see
     assert nsteps == 1 or np.abs(g[1]).max() > 0
     assert np.abs(g[2]).max() > 0
-    assert m[0] == g[0]
-    for k, name in ((1, "dJ/dn"), (2, "dJ/dz")):
-        cells, count = where_differs(m[k], g[k])
-        assert count == 0, (name, count, "first (j, i):", cells,
-                            float(np.abs(m[k] - g[k]).max()), float(np.abs(g[k]).max()))
+    # the two-wave march (default) and the one-wave march
+    for mode in ("march", "march1"):
+        m = grads(p, nsteps, every, ncell, ckpt, seed, mode, monkeypatch, dtype)
+        assert m[0] == g[0], mode
+        for k, name in ((1, "dJ/dn"), (2, "dJ/dz")):
+            cells, count = where_differs(m[k], g[k])
+            assert count == 0, (mode, name, count, "first (j, i):", cells,
+                                float(np.abs(m[k] - g[k]).max()), float(np.abs(g[k]).max()))
 
 
 def rotated(p, bc, lo, hi):
