@@ -1569,8 +1569,9 @@ bool adjoint_march_fits(const Params& P) {
 }
 
 int adjoint_march_rows(const Params& P, int ncu) {
-    // the smallest chunk height (8 .. 256) whose tiles fit one wave per SIMD
-    // (four per compute unit) in one round
+    // the smallest chunk height (8 .. 256) whose tiles fit four per compute
+    // unit in one round: one wave per SIMD for the one-wave march, two (one
+    // two-wave workgroup per SIMD pair of waves) for the two-wave march
     const long long slots = 4LL * std::max(ncu, 1);
     int H = 8;
     while (H < 256 && march_tiles(P, H).count() > slots) ++H;
