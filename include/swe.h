@@ -81,7 +81,7 @@ typedef struct swe_config {
     int32_t hydro_len;       /* points of the hydrograph, 0..4096 (0: q_in = 0) */
     int32_t tile_rows;       /* rows per workgroup of the fused kernel, 0 = auto (as
                               * many chunks per strip as resident waves allow, at least
-                              * 16 rows).  SWE_FUSED_WAVES=3 (FP64) or 4 (FP32) in the
+                              * 6 rows).  SWE_FUSED_WAVES=3 (FP64) or 4 (FP32) in the
                               * environment at swe_create selects the fused kernel's
                               * occupancy variant, one more resident wave per SIMD than
                               * its register budget allows (part of the carried state

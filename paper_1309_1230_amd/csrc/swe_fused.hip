@@ -731,7 +731,7 @@ int fused_auto_rows(int nx, int ny, long long slots, bool dry_skip) {
     long long gy = slots / gx;
     if (gy < 1) gy = 1;
     int H = (int)((ny + gy - 1) / gy);
-    if (H < 16) H = 16;
+    if (H < 6) H = 6;
     if (dry_skip && H > 32) H = 32;
     return H;
 }

@@ -64,7 +64,7 @@ int fused_strips(int nx);
 template <typename T>
 int fused_waves_per_cu(bool more_waves = false);
 // Automatic tile height of the fused step for `slots` resident waves: as
-// many chunks per strip as fit one round of waves, at least 16 rows; with
+// many chunks per strip as fit one round of waves, at least 6 rows; with
 // the dry-tile skip at most 32.
 int fused_auto_rows(int nx, int ny, long long slots, bool dry_skip);
 
