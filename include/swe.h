@@ -285,9 +285,11 @@ typedef struct swe_gauges {
  * nothing; the buffer stays with the handle for later calls and is released
  * by swe_destroy.  Otherwise, and for FP32 handles, the spacing is
  * round(sqrt(nsteps)).  The reverse step runs as one fused march with two
- * waves per tile (SWE_ADJOINT=march1 in the environment selects the one-wave
- * march, SWE_ADJOINT=gather four gather kernels instead).  The gradient is
- * the same bit for bit in every one of these modes.  dJ_dn and dJ_dz (device, FP64, caller-owned, the handle's pitch)
+ * waves per tile that hand rows over through LDS counters, each wait bounded
+ * (SWE_ADJOINT in the environment selects another form: barrier, the same two
+ * waves in step at a workgroup barrier; march1, the one-wave march; gather,
+ * four gather kernels).  The gradient is the same bit for bit in every one of
+ * these modes.  dJ_dn and dJ_dz (device, FP64, caller-owned, the handle's pitch)
  * receive the gradients;
  * *loss (host) receives J.  FP32 handles: the forward run, its checkpoints
  * and the recomputed segments are FP32 (the state trajectory is that of
@@ -296,8 +298,9 @@ typedef struct swe_gauges {
  * are formed in FP64 from the promoted depths.  Memory then holds FP32
  * checkpoints and segment states plus FP64 copies of one step's state, U* and
  * U^d.  Synchronises.  Errors: SWE_EINVAL (arguments, ckpt_every < 0, gauge
- * cells out of range or repeated), SWE_ENOMEM, SWE_EDEVICE, SWE_EUNSTABLE (the forward
- * run raised a fatal flag). */
+ * cells out of range or repeated), SWE_ENOMEM, SWE_EDEVICE (also when a wave of
+ * the march stopped waiting for its partner: the gradient is then not
+ * returned), SWE_EUNSTABLE (the forward run raised a fatal flag). */
 int swe_grad(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_every,
              double* loss, void* dJ_dn, void* dJ_dz);
 

@@ -904,7 +904,7 @@ struct MarchRow {
 // EDGE: the strip holds the west or the east edge column (its lanes may be
 // ghost or outside columns); otherwise every lane is an interior column and
 // the column tests are compiled out.
-template <bool HOBS, bool EDGE, int PART = 0>
+template <bool HOBS, bool EDGE, int PART = 0, bool FLAGS = false>
 struct AdjMarch {
     const AdjointArgs& a;
     const int* gmap;
@@ -946,6 +946,33 @@ struct AdjMarch {
     int lane = 0;
     __device__ __forceinline__ double& rg(int f, int r) const {
         return ring[(f * 8 + (r & 7)) * kWave + lane];
+    }
+    // FLAGS: the waves hand rows over through two progress counters in LDS
+    // (prog[0]: the last row the first wave filed, prog[1]: the last row whose
+    // ring slots the second wave has read) instead of a barrier per step, so
+    // the first wave may run up to five rows ahead.  Every wait is bounded;
+    // a wave whose wait runs out stops waiting (the tile's values are then
+    // not to be trusted) and raises *stall.
+    int* prog = nullptr;
+    int* stall = nullptr;
+    int spin_cap = 0;
+    bool stalled = false;
+    __device__ __forceinline__ void wait_row(int who, int need) {
+        if (stalled) return;
+        for (int n = 0;; ++n) {
+            const int v = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                prog + who, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+            if (v >= need) return;
+            if (n >= spin_cap) {
+                stalled = true;
+                if (lane == 0) __hip_atomic_store(stall, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __device__ __forceinline__ void post_row(int who, int r) {
+        __hip_atomic_store(prog + who, r, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 
     __device__ AdjMarch(const AdjointArgs& a_, const int* g, const double* h)
@@ -1136,14 +1163,19 @@ struct AdjMarch {
         }
 
         if (PART == 1) {
-            // file this iteration's rows for the second wave
+            // file this iteration's rows for the second wave (with FLAGS, once
+            // it has read the slots' previous rows, R-8, last read in its
+            // iteration R-5)
+            if (FLAGS) wait_row(1, R - 5);
             rg(0, R) = ade[0]; rg(1, R) = adx[0]; rg(2, R) = ady[0];
             rg(3, R) = azp[1];
             rg(4, R) = ause[0]; rg(5, R) = ausx[0]; rg(6, R) = ausy[0];
+            if (FLAGS) post_row(0, R);
         }
         if (PART == 2) {
             // the first wave's rows: D-bar of rows R-1..R-3, the bed's share of
             // row R-3, the U* adjoint of rows R-1..R-3
+            if (FLAGS) wait_row(0, R);
 #pragma unroll
             for (int k = 1; k < 4; ++k) {
                 ade[k] = rg(0, R - k); adx[k] = rg(1, R - k); ady[k] = rg(2, R - k);
@@ -1153,6 +1185,7 @@ struct AdjMarch {
             for (int k = 0; k < 3; ++k) {
                 ause[k] = rg(4, R - k); ausx[k] = rg(5, R - k); ausy[k] = rg(6, R - k);
             }
+            if (FLAGS) post_row(1, R);
         }
 
         // ---- row R-2: the S8 fold of the U* adjoint
@@ -1418,13 +1451,27 @@ struct AdjMarch {
             return;
         }
         // Two waves: the first forms rows R and R-1 of iteration R, the
-        // second rows R-2 and R-3 of the same iteration one step later, from
-        // the rows the first filed in the ring (zero before any is filed, as
-        // the carried rows are).  One workgroup barrier per step.
-        if (PART == 1)
+        // second rows R-2 and R-3 of the same iteration after it, from the
+        // rows the first filed in the ring (zero before any is filed, as the
+        // carried rows are).  FLAGS: the progress counters order the two;
+        // otherwise one workgroup barrier per step, the second wave one step
+        // behind.
+        if (PART == 1) {
             for (int k = 0; k < 7 * 8; ++k) ring[k * kWave + lane] = 0.0;
+            if (FLAGS && lane == 0) prog[0] = prog[1] = j0 - 4;
+        }
         __syncthreads();
         prefetch(j0 - 3);
+        if (FLAGS) {
+            for (int R = j0 - 3; R <= j1 + 2; ++R) {
+                if (R >= 5 && R <= d.ny - 3)
+                    iter<false>(R);
+                else
+                    iter<true>(R);
+            }
+            store_previous(j1 + 3);
+            return;
+        }
         for (int t = j0 - 3; t <= j1 + 3; ++t) {
             const int R = PART == 1 ? t : t - 1;
             if (PART == 1 ? R <= j1 + 2 : R >= j0 - 3) {
@@ -1484,15 +1531,19 @@ k_adj_march(AdjointArgs a, const int* gmap, const double* hobs, MarchTiles T, in
 // The march as a two-wave pipeline (one workgroup of two waves per tile):
 // wave 0 forms rows R and R-1 of each iteration (S15..S9: D-bar, the U*
 // adjoint, dJ/dn and dJ/dz), wave 1 rows R-2 and R-3 (the S8 fold, S4, S3 and
-// S7..S2: lambda^n and the bed's share), one step behind, from the rows wave
-// 0 files in LDS.  Each wave carries about half the rows, so two fit per SIMD
-// (256 registers) where the one-wave march holds one; the sums and their
-// order are the one-wave march's, so the results are the same bits.
-template <bool HOBS>
+// S7..S2: lambda^n and the bed's share), behind it, from the rows wave 0
+// files in LDS (FLAGS: ordered by two LDS progress counters, wave 0 up to five
+// rows ahead; otherwise in step at a barrier, one step behind).  Each wave
+// carries about half the rows, so two fit per SIMD (256 registers) where the
+// one-wave march holds one; the sums and their order are the one-wave march's,
+// so the results are the same bits.  The hardware places the two waves of a
+// workgroup on two SIMDs of the compute unit.
+template <bool HOBS, bool FLAGS>
 __global__ void __launch_bounds__(2 * kWave, 2)
 k_adj_march2(AdjointArgs a, const int* gmap, const double* hobs, MarchTiles T, int lout,
-             int zout) {
+             int zout, int* stall, int spin_cap) {
     __shared__ double ring[7 * 8 * kWave];
+    __shared__ int prog[2];
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     int strip, chunk, H;
     if (T.se <= 1) {
@@ -1508,20 +1559,32 @@ k_adj_march2(AdjointArgs a, const int* gmap, const double* hobs, MarchTiles T, i
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const bool edge = strip == 0 || strip >= T.se;
     if (edge && wave == 0) {
-        AdjMarch<HOBS, true, 1> M(a, gmap, hobs);
+        AdjMarch<HOBS, true, 1, FLAGS> M(a, gmap, hobs);
         M.ring = ring;
+        M.prog = prog;
+        M.stall = stall;
+        M.spin_cap = spin_cap;
         M.run(lane, strip, chunk, H, lout, zout);
     } else if (edge) {
-        AdjMarch<HOBS, true, 2> M(a, gmap, hobs);
+        AdjMarch<HOBS, true, 2, FLAGS> M(a, gmap, hobs);
         M.ring = ring;
+        M.prog = prog;
+        M.stall = stall;
+        M.spin_cap = spin_cap;
         M.run(lane, strip, chunk, H, lout, zout);
     } else if (wave == 0) {
-        AdjMarch<HOBS, false, 1> M(a, gmap, hobs);
+        AdjMarch<HOBS, false, 1, FLAGS> M(a, gmap, hobs);
         M.ring = ring;
+        M.prog = prog;
+        M.stall = stall;
+        M.spin_cap = spin_cap;
         M.run(lane, strip, chunk, H, lout, zout);
     } else {
-        AdjMarch<HOBS, false, 2> M(a, gmap, hobs);
+        AdjMarch<HOBS, false, 2, FLAGS> M(a, gmap, hobs);
         M.ring = ring;
+        M.prog = prog;
+        M.stall = stall;
+        M.spin_cap = spin_cap;
         M.run(lane, strip, chunk, H, lout, zout);
     }
 }
@@ -1579,24 +1642,32 @@ int adjoint_march_rows(const Params& P, int ncu) {
 }
 
 hipError_t launch_adjoint_march(const AdjointArgs& a, const int* gmap, const double* hobs, int H,
-                                hipStream_t s, bool two_waves) {
+                                hipStream_t s, MarchMode mode, int* stall, int spin_cap) {
     if (H < 1) return hipErrorInvalidValue;
+    if (mode == MarchMode::flags && !stall) return hipErrorInvalidValue;
     const MarchTiles T = march_tiles(a.P, H);
     const int lout = a.lam_slot == kAdjLamSlot[0] ? kAdjLamSlot[1] : kAdjLamSlot[0];
     const int zout = a.azp_slot == kAdjZpSlot[0] ? kAdjZpSlot[1] : kAdjZpSlot[0];
-    if (two_waves) {
+    const dim3 g(T.count()), b2(2 * kWave);
+    switch (mode) {
+    case MarchMode::flags:
         if (hobs)
-            hipLaunchKernelGGL(k_adj_march2<true>, dim3(T.count()), dim3(2 * kWave), 0, s, a, gmap,
-                               hobs, T, lout, zout);
+            hipLaunchKernelGGL((k_adj_march2<true, true>), g, b2, 0, s, a, gmap, hobs, T, lout, zout, stall, spin_cap);
         else
-            hipLaunchKernelGGL(k_adj_march2<false>, dim3(T.count()), dim3(2 * kWave), 0, s, a,
-                               gmap, hobs, T, lout, zout);
-    } else if (hobs) {
-        hipLaunchKernelGGL(k_adj_march<true>, dim3(T.count()), dim3(kWave), 0, s, a, gmap, hobs,
-                           T, lout, zout);
-    } else {
-        hipLaunchKernelGGL(k_adj_march<false>, dim3(T.count()), dim3(kWave), 0, s, a, gmap,
-                           hobs, T, lout, zout);
+            hipLaunchKernelGGL((k_adj_march2<false, true>), g, b2, 0, s, a, gmap, hobs, T, lout, zout, stall, spin_cap);
+        break;
+    case MarchMode::barrier:
+        if (hobs)
+            hipLaunchKernelGGL((k_adj_march2<true, false>), g, b2, 0, s, a, gmap, hobs, T, lout, zout, stall, spin_cap);
+        else
+            hipLaunchKernelGGL((k_adj_march2<false, false>), g, b2, 0, s, a, gmap, hobs, T, lout, zout, stall, spin_cap);
+        break;
+    case MarchMode::one_wave:
+        if (hobs)
+            hipLaunchKernelGGL(k_adj_march<true>, g, dim3(kWave), 0, s, a, gmap, hobs, T, lout, zout);
+        else
+            hipLaunchKernelGGL(k_adj_march<false>, g, dim3(kWave), 0, s, a, gmap, hobs, T, lout, zout);
+        break;
     }
     return hipGetLastError();
 }

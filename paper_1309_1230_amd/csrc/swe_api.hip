@@ -835,7 +835,7 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
     if ((!store_all && (e = ck.alloc((size_t)nseg * 3 * fe * sizeof(T))) != hipSuccess) ||
         (!store_all && (e = seg.alloc((size_t)C * 3 * fe * sizeof(T))) != hipSuccess) ||
         (e = scratch.alloc(3 * fe * sizeof(double))) != hipSuccess ||
-        (e = work.alloc((size_t)swe::adjoint_work_arrays() * Npad * sizeof(double))) != hipSuccess ||
+        (e = work.alloc((size_t)swe::adjoint_work_arrays() * Npad * sizeof(double) + 256)) != hipSuccess ||
         (e = logs.alloc(2 * (size_t)std::max<int64_t>(nsteps, 1) * sizeof(double))) != hipSuccess ||
         (e = mis.alloc((size_t)std::max<int64_t>(nobs * ng, 1) * sizeof(double))) != hipSuccess ||
         (e = dcells.alloc((size_t)std::max(ng, 1) * sizeof(long long))) != hipSuccess ||
@@ -975,7 +975,10 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
     double J = 0.0;
     for (int64_t k = 0; k < nobs * ng; ++k) J = J + hm[(size_t)k];
     // ---- reverse sweep, segment by segment
-    e = hipMemsetAsync(work.p, 0, (size_t)swe::adjoint_work_arrays() * Npad * sizeof(double), h->stream);
+    e = hipMemsetAsync(work.p, 0, (size_t)swe::adjoint_work_arrays() * Npad * sizeof(double) + 256,
+                       h->stream);
+    // the two-wave march's stall word sits after the work arrays
+    int* stall = (int*)(work.d() + (size_t)swe::adjoint_work_arrays() * Npad);
     Ctl* rc_ctl = (Ctl*)actl.p;
     double* US = fwd.d();
     double* UD = fwd.d() + 3 * fe;
@@ -989,13 +992,22 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
     aa.mp = padst.d() + Npad;
     aa.nman = n64;
     aa.work = work.d();
-    // the reverse step runs as one fused march of two waves per tile
-    // (default), the one-wave march (SWE_ADJOINT=march1 in the environment)
-    // or the four gather kernels (SWE_ADJOINT=gather); all give the same bits
+    // the reverse step runs as one fused march of two waves per tile that
+    // hand rows over through LDS counters (default), the same two waves in
+    // step at a barrier (SWE_ADJOINT=barrier in the environment), the
+    // one-wave march (SWE_ADJOINT=march1) or the four gather kernels
+    // (SWE_ADJOINT=gather); all give the same bits.  SWE_MARCH_SPIN_CAP
+    // lowers the bound on the counter waits (tests of the stall report).
     const char* adj_env = std::getenv("SWE_ADJOINT");
     const bool march =
         !(adj_env && std::strcmp(adj_env, "gather") == 0) && swe::adjoint_march_fits(h->P);
-    const bool march2 = !(adj_env && std::strcmp(adj_env, "march1") == 0);
+    const swe::MarchMode mmode =
+        adj_env && std::strcmp(adj_env, "march1") == 0     ? swe::MarchMode::one_wave
+        : adj_env && std::strcmp(adj_env, "barrier") == 0 ? swe::MarchMode::barrier
+                                                           : swe::MarchMode::flags;
+    int spin_cap = swe::kMarchSpinCap;
+    if (const char* cap_env = std::getenv("SWE_MARCH_SPIN_CAP"))
+        spin_cap = std::max(0, std::min(swe::kMarchSpinCap, std::atoi(cap_env)));
     int march_rows = 0;
     if (march) {
         int cus = 0;
@@ -1135,7 +1147,7 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
             const double* hrow = obs ? g->hobs + ((k + 1) / g->obs_every - 1) * ng : nullptr;
             if (march) {
                 e = swe::launch_adjoint_march(aa, (const int*)gmap.p, hrow, march_rows,
-                                              h->stream, march2);
+                                              h->stream, mmode, stall, spin_cap);
                 // lambda^n and the bed's share are now in the other slot of each pair
                 aa.lam_slot = aa.lam_slot == swe::kAdjLamSlot[0] ? swe::kAdjLamSlot[1]
                                                                  : swe::kAdjLamSlot[0];
@@ -1153,6 +1165,12 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
         e = swe::launch_unpad(h->P, work.d() + (size_t)swe::kAdjGradZ * Npad, (double*)dJ_dz, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "swe_grad: reverse sweep");
+    int stalled = 0;
+    e = hipMemcpy(&stalled, stall, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(h, e, "swe_grad: reverse sweep");
+    if (stalled)
+        return fail(h, SWE_EDEVICE,
+                    "swe_grad: a wave of the reverse march stopped waiting for its partner");
     if (verbose) std::fprintf(stderr, "swe_grad: %.1f ms: reverse sweep done\n", ms_since(t_start));
     *loss = J;
     return SWE_OK;

@@ -179,12 +179,22 @@ constexpr int kAdjLamSlot[2] = {9, 0}, kAdjZpSlot[2] = {14, 12};
 hipError_t launch_adjoint_step(const AdjointArgs& a, const int* gmap, const double* hobs,
                                hipStream_t s);
 // The same step as one fused reverse march (one wave per strip of columns,
-// chunks of H rows; two_waves: a workgroup of two waves per tile, each
-// forming half of the phases, one step apart): reads lambda and the bed
-// adjoint from a.lam_slot and a.azp_slot, writes them to the other slot of
-// each pair.  The result is bit for bit the one launch_adjoint_step gives.
+// chunks of H rows): reads lambda and the bed adjoint from a.lam_slot and
+// a.azp_slot, writes them to the other slot of each pair.  The result is bit
+// for bit the one launch_adjoint_step gives.  one_wave: one wave per tile;
+// barrier: a workgroup of two waves per tile, each forming half of the phases,
+// one step apart, in step at a workgroup barrier; flags: the same two waves
+// handing rows over through LDS progress counters, the first up to five rows
+// ahead.  stall (flags: required, else unused) is a device int the kernel sets
+// to 1 if a wave's wait for the other ran out after spin_cap polls (the values
+// are then wrong); the caller clears it.
+enum class MarchMode { one_wave, barrier, flags };
+// Polls (each about 100 cycles) after which a wave of the flag-synchronised
+// march stops waiting for the other: some 40 ms, far beyond any row's time.
+constexpr int kMarchSpinCap = 1 << 20;
 hipError_t launch_adjoint_march(const AdjointArgs& a, const int* gmap, const double* hobs, int H,
-                                hipStream_t s, bool two_waves = true);
+                                hipStream_t s, MarchMode mode, int* stall,
+                                int spin_cap = kMarchSpinCap);
 // Chunk height of the reverse march for a grid on a device with ncu compute
 // units.
 int adjoint_march_rows(const Params& P, int ncu);

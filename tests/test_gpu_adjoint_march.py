@@ -1,5 +1,6 @@
-"""The fused reverse march of the adjoint step (the two-wave march, the
-default, and the one-wave march) against the four gather kernels.
+"""The fused reverse march of the adjoint step (the two-wave march with its
+waves handing rows over through LDS counters, the default; the same two waves
+in step at a barrier; the one-wave march) against the four gather kernels.
 
 All evaluate the same expressions and sum each cell's terms in the same
 order, so the gradients must agree bit for bit (the gather kernels are in
@@ -44,8 +45,8 @@ def check_equal(p, nsteps, every, ncell, ckpt, seed, monkeypatch, dtype=torch.fl
     # over one step n changes only the discharges, which the loss does not see
     assert nsteps == 1 or np.abs(g[1]).max() > 0
     assert np.abs(g[2]).max() > 0
-    # the two-wave march (default) and the one-wave march
-    for mode in ("march", "march1"):
+    # the two-wave march (default), its barrier form and the one-wave march
+    for mode in ("march", "barrier", "march1"):
         m = grads(p, nsteps, every, ncell, ckpt, seed, mode, monkeypatch, dtype)
         assert m[0] == g[0], mode
         for k, name in ((1, "dJ/dn"), (2, "dJ/dz")):
@@ -98,6 +99,26 @@ def test_march_equals_gather_mixed_fp32(monkeypatch):
     p = W.random_valid_state(130, 100, seed=17)
     note(f"random {p.nx}x{p.ny} f32 forward: 12 steps, march vs gather")
     check_equal(p, 12, 3, 15, 4, seed=9, monkeypatch=monkeypatch, dtype=torch.float32)
+
+
+def test_march_wait_that_runs_out_is_reported(monkeypatch):
+    """The default march's waves wait for each other through LDS counters, each
+    wait bounded.  With the bound lowered from the host to zero polls a wave
+    that finds its partner's row not yet filed stops waiting at once; swe_grad
+    must then fail (SWE_EDEVICE, the stall named) rather than return the
+    values, and the barrier form under the same setting must still agree with
+    the gather kernels.  Every kernel ends normally either way."""
+    p = W.flood_scenario(2, 400, 300)
+    note(f"flood {p.nx}x{p.ny} f64: march with its waits bounded to zero polls")
+    monkeypatch.setenv("SWE_MARCH_SPIN_CAP", "0")
+    with pytest.raises(swe.SweError) as err:
+        grads(p, 30, 3, 40, 7, 5, "march", monkeypatch)
+    assert err.value.code == swe.SWE_EDEVICE
+    assert "stopped waiting" in str(err.value)
+    g = grads(p, 30, 3, 40, 7, 5, "gather", monkeypatch)
+    b = grads(p, 30, 3, 40, 7, 5, "barrier", monkeypatch)
+    assert b[0] == g[0]
+    assert np.array_equal(b[1], g[1]) and np.array_equal(b[2], g[2])
 
 
 def test_march_checkpoint_spacing_and_single_step(monkeypatch):
