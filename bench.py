@@ -604,7 +604,7 @@ def main():
         "hbm_pct": 100.0 * achieved / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(a.dtype),
-                     "kernel": f"k_fused_step_{a.dtype}",
+                     "kernel": f"k_fused_split_{a.dtype}",
                      "bytes_per_launch_algorithmic": bpc * cells,
                      "bytes_per_cell_update": bpc},
         "wall_s": wall,

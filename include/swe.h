@@ -67,7 +67,10 @@ typedef enum swe_path { SWE_PATH_FUSED = 0, SWE_PATH_UNFUSED = 1 } swe_path;
 enum {
     SWE_FLAG_NAN = 1,      /* a non-finite value appeared (fatal) */
     SWE_FLAG_CLIPPED = 2,  /* a negative depth was clipped (informational) */
-    SWE_FLAG_BADDT = 4     /* the next time step is not finite and positive (fatal) */
+    SWE_FLAG_BADDT = 4,    /* the next time step is not finite and positive (fatal) */
+    SWE_FLAG_STALL = 8     /* a wave of the fused step (two waves per tile) stopped waiting
+                              for its partner after its bounded wait: the step's values are
+                              not to be trusted (fatal) */
 };
 
 /* Problem definition.  Fill with swe_config_init, then set the fields. */
@@ -79,14 +82,17 @@ typedef struct swe_config {
     int32_t inflow_lo[4];    /* INFLOW face band along each edge: faces k with */
     int32_t inflow_hi[4];    /*   lo <= k < hi (k = j on W/E, k = i on S/N) */
     int32_t hydro_len;       /* points of the hydrograph, 0..4096 (0: q_in = 0) */
-    int32_t tile_rows;       /* rows per workgroup of the fused kernel, 0 = auto (as
-                              * many chunks per strip as resident waves allow, at least
-                              * 6 rows).  SWE_FUSED_WAVES=3 (FP64) or 4 (FP32) in the
-                              * environment at swe_create selects the fused kernel's
-                              * occupancy variant, one more resident wave per SIMD than
-                              * its register budget allows (part of the carried state
-                              * spills); a measurement knob with the same results, not
-                              * used with the dry-tile skip */
+    int32_t tile_rows;       /* rows per tile of the fused kernel, 0 = auto (as many
+                              * chunks per strip as resident tiles allow, at least 6
+                              * rows).  A tile is one workgroup of two waves, one running
+                              * the predictor half of every row and one the corrector half
+                              * (SWE_FUSED_SPLIT=0 in the environment at swe_create: one
+                              * wave per tile; same results).  SWE_FUSED_WAVES=3 (FP64) or
+                              * 4 (FP32) selects the one-wave kernel's occupancy variant,
+                              * one more resident wave per SIMD than its register budget
+                              * allows (part of the carried state spills); a measurement
+                              * knob with the same results, not used with the dry-tile
+                              * skip */
     int64_t pitch;           /* row pitch of every field in elements, >= nx */
     double dx, dy;           /* cell size (m), > 0 */
     double g;                /* gravity (m/s^2), > 0 */

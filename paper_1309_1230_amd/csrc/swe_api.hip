@@ -28,6 +28,9 @@ struct swe_handle {
     int path = SWE_PATH_FUSED;
     int H = 0, gy = 0;
     bool more_waves = false;   // the fused step's occupancy variant (SWE_FUSED_WAVES)
+    bool split = true;         // two waves per tile (SWE_FUSED_SPLIT=0: one)
+    int spin_cap = swe::kSplitSpinCap;   // the split step's bound on its waits
+    int Ht = 0, gyt = 0;       // tile rows and chunks of the one-wave tracing step (swe_grad)
     size_t elem = 8;
     hipStream_t stream = nullptr;
     int device = 0;
@@ -157,7 +160,8 @@ hipError_t enqueue_step(swe_handle* h, int64_t k, double t_end, bool unfused, do
     a.dry = h->dry;
     a.log_dt = log_dt;
     a.log_t = log_t;
-    return swe::launch_fused<T>(a, sigma, h->stream, h->more_waves);
+    a.spin_cap = h->spin_cap;
+    return swe::launch_fused<T>(a, sigma, h->stream, h->more_waves, h->split);
 }
 
 // Start of a host call: per-call statistics reset and, with the dry-tile
@@ -250,11 +254,15 @@ bool is_device_ptr(const void* p, int device) {
 // against 34 us at 16).  With the dry-tile skip at most 32 rows: smaller
 // tiles follow the wet/dry front more closely, and the skipped ones free
 // their wave slot at once.
-int auto_tile_rows(const swe_handle* h, int dev, bool dry_skip) {
+int auto_tile_rows(const swe_handle* h, int dev, bool dry_skip, bool one_wave = false) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
-    const int per_cu = h->dtype == SWE_F32 ? swe::fused_waves_per_cu<float>(h->more_waves)
-                                           : swe::fused_waves_per_cu<double>(h->more_waves);
+    const int per_cu =
+        h->split && !h->more_waves && !one_wave
+            ? (h->dtype == SWE_F32 ? swe::fused_split_tiles_per_cu<float>()
+                                   : swe::fused_split_tiles_per_cu<double>())
+            : (h->dtype == SWE_F32 ? swe::fused_waves_per_cu<float>(h->more_waves)
+                                   : swe::fused_waves_per_cu<double>(h->more_waves));
     return swe::fused_auto_rows(h->P.nx, h->P.ny, (long long)cus * per_cu, dry_skip);
 }
 
@@ -356,9 +364,21 @@ void prepare_handle(swe_handle* h, const swe_config* c, int dev) {
     if (const char* w = std::getenv("SWE_FUSED_WAVES"))
         h->more_waves = c->path == SWE_PATH_FUSED && c->dry_skip == 0 &&
                         std::atoi(w) == (c->dtype == SWE_F32 ? 4 : 3);
+    // SWE_FUSED_SPLIT=0 in the environment runs the fused step with one wave
+    // per tile instead of two (a measurement knob; same state bits)
+    if (const char* sp = std::getenv("SWE_FUSED_SPLIT")) h->split = std::atoi(sp) != 0;
+    // SWE_SPLIT_SPIN_CAP lowers the split step's bound on its waits (tests of
+    // the stall report)
+    if (const char* cap = std::getenv("SWE_SPLIT_SPIN_CAP"))
+        h->spin_cap = std::max(0, std::min(swe::kSplitSpinCap, std::atoi(cap)));
     h->H = c->tile_rows > 0 ? c->tile_rows : auto_tile_rows(h, dev, c->dry_skip != 0);
     h->gy = (c->ny + h->H - 1) / h->H;
-    h->nparts = std::max(swe::fused_blocks(c->nx, c->ny, h->H), swe::scan_partials(c->nx, c->ny));
+    // swe_grad's tracing step runs one wave per tile, at that form's own
+    // automatic height
+    h->Ht = c->tile_rows > 0 ? c->tile_rows : auto_tile_rows(h, dev, false, true);
+    h->gyt = (c->ny + h->Ht - 1) / h->Ht;
+    h->nparts = std::max({swe::fused_blocks(c->nx, c->ny, h->H), swe::fused_blocks(c->nx, c->ny, h->Ht),
+                          swe::scan_partials(c->nx, c->ny)});
     std::vector<double> hy(2 * (size_t)std::max(1, c->hydro_len), 0.0);
     for (int k = 0; k < c->hydro_len; ++k) {
         hy[k] = c->hydro_t[k];
@@ -929,8 +949,8 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
                     fa.tud[f] = traj_state(k, 6 + f);
                 }
                 swe::fused_part_layout(fa, h->fpart, h->nparts);
-                fa.gy = h->gy;
-                fa.H = h->H;
+                fa.gy = h->gyt;
+                fa.H = h->Ht;
                 fa.log_dt = dtlog + k;
                 fa.log_t = tlog + k;
                 const int sig = ((step0 + k) & 1) ? -1 : 1;
@@ -1063,6 +1083,7 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
             swe::fused_part_layout(fa, h->fpart, h->nparts);
             fa.gy = h->gy;
             fa.H = h->H;
+            fa.spin_cap = h->spin_cap;
             const int sig = ((step0 + k) & 1) ? -1 : 1;
             if constexpr (!mixed) {
                 if (keep) {
@@ -1071,11 +1092,13 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
                         fa.tus[f] = tk + (size_t)f * fe;
                         fa.tud[f] = tk + (size_t)(3 + f) * fe;
                     }
+                    fa.gy = h->gyt;
+                    fa.H = h->Ht;
                     e = swe::launch_fused_trace(fa, sig, h->stream);
                     continue;
                 }
             }
-            e = swe::launch_fused<T>(fa, sig, h->stream, h->more_waves);
+            e = swe::launch_fused<T>(fa, sig, h->stream, h->more_waves, h->split);
         }
         for (int64_t k = s1 - 1; k >= s0 && e == hipSuccess; --k) {
             T* Uk[3];
@@ -1125,8 +1148,8 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
                 ta.m = m64;
                 ta.eta1 = Sc; ta.qx1 = Sc + fe; ta.qy1 = Sc + 2 * fe;
                 swe::fused_part_layout(ta, h->fpart, h->nparts);
-                ta.gy = h->gy;
-                ta.H = h->H;
+                ta.gy = h->gyt;
+                ta.H = h->Ht;
                 for (int f = 0; f < 3; ++f) {
                     ta.tus[f] = US + (size_t)f * fe;
                     ta.tud[f] = UD + (size_t)f * fe;
@@ -1319,6 +1342,7 @@ swe::FusedArgs<T> fused_args_of(swe_handle* h, int parity, double t_end) {
     a.gy = h->gy;
     a.H = h->H;
     a.dry = h->dry;
+    a.spin_cap = h->spin_cap;
     return a;
 }
 
@@ -1364,13 +1388,20 @@ hipError_t ens_enqueue(swe_ensemble* e, int64_t nsteps) {
     const int count = (int)e->h.size();
     bool dry = false;
     for (swe_handle* h : e->h) dry = dry || h->dry != nullptr;
+    // one wave per tile: the two-wave step (SWE_ENSEMBLE_SPLIT=1 in the
+    // environment, FP32 only) measured slower here, 334 against 246 ms for the
+    // 500-step flood ensemble, where the single grid gains 4-6%
+    const char* es = std::getenv("SWE_ENSEMBLE_SPLIT");
+    const bool split = es && std::atoi(es) != 0;
     for (int64_t k = 0; k < nsteps && err == hipSuccess; ++k) {
         const int sigma = ((e->step_host + k) & 1) ? -1 : 1;
         err = e->dtype == SWE_F32
                   ? swe::launch_ensemble<float>((const swe::FusedArgs<float>*)e->args[k & 1],
-                                                e->first, count, e->total, sigma, dry, e->stream)
+                                                e->first, count, e->total, sigma, dry, e->stream,
+                                                split)
                   : swe::launch_ensemble<double>((const swe::FusedArgs<double>*)e->args[k & 1],
-                                                 e->first, count, e->total, sigma, dry, e->stream);
+                                                 e->first, count, e->total, sigma, dry, e->stream,
+                                                 split);
     }
     for (swe_handle* h : e->h)
         if (err == hipSuccess) err = enqueue_copy_back(h);

@@ -44,9 +44,12 @@ namespace swe {
 constexpr int kWave = 64;
 constexpr int BC_WALL = 0, BC_OPEN = 1, BC_INFLOW = 2;
 constexpr int EDGE_W = 0, EDGE_E = 1, EDGE_S = 2, EDGE_N = 3;
-constexpr unsigned FLAG_NAN = 1u, FLAG_CLIPPED = 2u, FLAG_BADDT = 4u;
-constexpr unsigned FLAG_FATAL = FLAG_NAN | FLAG_BADDT;
+constexpr unsigned FLAG_NAN = 1u, FLAG_CLIPPED = 2u, FLAG_BADDT = 4u, FLAG_STALL = 8u;
+constexpr unsigned FLAG_FATAL = FLAG_NAN | FLAG_BADDT | FLAG_STALL;
 constexpr int kMaxHydro = 4096;
+// Polls (each about 100 cycles) after which a wave of the split fused step
+// stops waiting for its partner: some 40 ms, far beyond any row's time.
+constexpr int kSplitSpinCap = 1 << 20;
 
 // Device-resident scalars of one handle.  Written only by the finalisation of
 // a step (one wave, after every block of the step has finished its sweep) and

@@ -137,7 +137,10 @@ __device__ __forceinline__ YFace<T> y_face(const Consts<T>& c, bool bnd, bool so
 // State of one wave's march up its chunk: per-lane constants, the rows and
 // faces carried from one iteration to the next, the prefetched row and the
 // running partial sums.  Rows are named relative to the ingested row R.
-template <typename T, int SIG, bool DRY, bool TRACE = false>
+// The two-wave form of the march: rows of its LDS ring and values per row.
+constexpr int kSplitSlots = 3, kSplitFields = 15;
+
+template <typename T, int SIG, bool DRY, bool TRACE = false, int PART = 0>
 struct March {
     Consts<T> c;
     const Params* P;
@@ -180,6 +183,39 @@ struct March {
     unsigned flags = 0u;
     bool dirty = false;   // an output cell is wet, not finite, or has eta = -0 (DRY only)
 
+    // PART 1 and 2 (two waves of one workgroup): the first wave runs the
+    // predictor half of each iteration (S2..S7), the second the corrector
+    // half (S9..S16 and the stores) from the values the first files in an
+    // LDS ring of kSplitSlots rows (kSplitFields values per lane and row).
+    // Two progress counters order them (prog[0]: the last row the first wave
+    // filed, prog[1]: the last row the second has taken), so the first may
+    // run kSplitSlots - 1 rows ahead.  Every wait is bounded; a wave whose
+    // wait runs out stops waiting and the step raises FLAG_STALL.
+    T* ring = nullptr;
+    int* prog = nullptr;
+    int lane = 0;
+    int spin_cap = 0;
+    bool stalled = false;
+    __device__ __forceinline__ T& rg(int f, int R) const {
+        return ring[(f * kSplitSlots + (R + kSplitSlots) % kSplitSlots) * kWave + lane];
+    }
+    __device__ __forceinline__ void wait_row(int who, int need) {
+        if (stalled) return;
+        for (int n = 0;; ++n) {
+            const int v = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                prog + who, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+            if (v >= need) return;
+            if (n >= spin_cap) {
+                stalled = true;
+                return;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    __device__ __forceinline__ void post_row(int who, int R) {
+        __hip_atomic_store(prog + who, R, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+
     __device__ __forceinline__ long long rowoff(int R) const {
         return (long long)min(max(R, 0), ny - 1) * pitch + ic;
     }
@@ -197,62 +233,102 @@ struct March {
     // when !BND).
     template <bool EDGE, bool BND, int SLOT>
     __device__ __forceinline__ void iter(int R, bool out) {
-        const T e0 = pe[SLOT], a0 = pa[SLOT], b0 = pb[SLOT], z0 = pz[SLOT];
-        const T m2 = pm[SLOT];              // m of row R-2
-        prefetch<1 - SLOT>(R + 1);
-        pm[1 - SLOT] = mm[rowoff(R - 1)];
-        int kW0 = BC_WALL, kE0 = BC_WALL, kW1 = BC_WALL, kE1 = BC_WALL;
+        // the predictor half's values the corrector half reads: U* of row
+        // R-1, the bed of rows R-1 and R-2, U^n and m of row R-2, the x
+        // dissipation of row R-2 and the y dissipation flux through face
+        // (R-2)+1/2
+        T se1, sa1, sb1, z1x, z2x, e2x, a2x, b2x, m2x, dxm, dxa, dxb, pnm, pna, pnb;
+        if constexpr (PART != 2) {
+            const T e0 = pe[SLOT], a0 = pa[SLOT], b0 = pb[SLOT], z0 = pz[SLOT];
+            const T m2 = pm[SLOT];              // m of row R-2
+            prefetch<1 - SLOT>(R + 1);
+            pm[1 - SLOT] = mm[rowoff(R - 1)];
+            int kW0 = BC_WALL, kE0 = BC_WALL;
+            if (EDGE) {
+                const int Rc = min(max(R, 0), ny - 1);
+                kW0 = face_kind(*P, EDGE_W, Rc); kE0 = face_kind(*P, EDGE_E, Rc);
+            }
+
+            // ---- S2 on row R
+            const T h0 = e0 - z0;
+            const T r0 = recip_prim(h0, c.hdry, c.rcap);
+            const T u0 = a0 * r0, v0 = b0 * r0;
+
+            // ---- S3/S4 in x on row R
+            const T eE = from_east(e0), eW = from_west(e0);
+            const T hE = from_east(h0);
+            const T nux0 = curv_switch(eW, e0, eE, r0);
+            const T nuxE = from_east(nux0);
+            const T epsE = faceE_interior ? face_eps(h0, hE, nux0, nuxE, c.hdry, c.kap, c.emax) : T(0);
+            const T fdm = epsE * (eE - e0);
+            const T fda = epsE * (from_east(a0) - a0);
+            const T fdb = epsE * (from_east(b0) - b0);
+            const T dx0m = fdm - from_west(fdm), dx0a = fda - from_west(fda),
+                    dx0b = fdb - from_west(fdb);
+
+            // ---- S5 (+ x pressure of S7) on row R
+            XDiv<T> A0;
+            if (SIG > 0)
+                A0 = x_divergence<T, 1>(c, e0, a0, h0, r0, u0, v0, z0, eE, hE, from_east(z0), c.qin0,
+                                        EDGE, atW, atE, kW0, kE0);
+            else
+                A0 = x_divergence<T, -1>(c, e0, a0, h0, r0, u0, v0, z0, eW, from_west(h0),
+                                         from_west(z0), c.qin0, EDGE, atW, atE, kW0, kE0);
+
+            // ---- S3 in y at row R-1, S4 in y through face (R-2)+1/2
+            const T nuy1 = curv_switch(e2, e1, e0, r1);
+            const bool fInt = !BND || (R - 2 >= 0 && R - 2 <= ny - 2);
+            const T h1 = e1 - z1, h2 = e2 - z2;
+            const T epsN = fInt ? face_eps(h2, h1, nuy2, nuy1, c.hdry, c.kap, c.emax) : T(0);
+            pnm = epsN * (e1 - e2); pna = epsN * (a1 - a2); pnb = epsN * (b1 - b2);
+
+            // ---- S6 through face (R-1)+1/2, S7 predictor of row R-1
+            const bool bndG = BND && ((R - 1 == -1) || (R - 1 == ny - 1));
+            const YFace<T> G0 = y_face<T, SIG>(c, bndG, R - 1 == -1, kS, kN, e1, b1, h1, r1,
+                                               a1 * r1, b1 * r1, z1, e0, b0, h0, r0, u0, v0, z0,
+                                               c.qin0);
+            const T pys = SIG > 0 ? G0.p : G1.p;
+            se1 = (e1 - c.rx * A1.m) - c.ry * (G0.m - G1.m);
+            sa1 = (a1 - c.rx * A1.x) - c.ry * (G0.x - G1.x);
+            sb1 = (b1 - c.rx * A1.y) - c.ry * ((G0.y - G1.y) + pys);
+            z1x = z1; z2x = z2; e2x = e2; a2x = a2; b2x = b2; m2x = m2;
+            dxm = dx2m; dxa = dx2a; dxb = dx2b;
+
+            // ---- rotate the predictor half's carried rows
+            e2 = e1; a2 = a1; b2 = b1; z2 = z1;
+            e1 = e0; a1 = a0; b1 = b0; z1 = z0; r1 = r0;
+            nuy2 = nuy1;
+            dx2m = dx1m; dx2a = dx1a; dx2b = dx1b;
+            dx1m = dx0m; dx1a = dx0a; dx1b = dx0b;
+            A1 = A0;
+            G1 = G0;
+        }
+        if constexpr (PART == 1) {
+            // file row R once the second wave has taken the slot's last row, R - kSplitSlots
+            wait_row(1, R - kSplitSlots);
+            rg(0, R) = se1; rg(1, R) = sa1; rg(2, R) = sb1; rg(3, R) = z1x; rg(4, R) = z2x;
+            rg(5, R) = e2x; rg(6, R) = a2x; rg(7, R) = b2x; rg(8, R) = m2x;
+            rg(9, R) = dxm; rg(10, R) = dxa; rg(11, R) = dxb;
+            rg(12, R) = pnm; rg(13, R) = pna; rg(14, R) = pnb;
+            post_row(0, R);
+            return;
+        }
+        if constexpr (PART == 2) {
+            wait_row(0, R);
+            se1 = rg(0, R); sa1 = rg(1, R); sb1 = rg(2, R); z1x = rg(3, R); z2x = rg(4, R);
+            e2x = rg(5, R); a2x = rg(6, R); b2x = rg(7, R); m2x = rg(8, R);
+            dxm = rg(9, R); dxa = rg(10, R); dxb = rg(11, R);
+            pnm = rg(12, R); pna = rg(13, R); pnb = rg(14, R);
+            post_row(1, R);
+        }
+        int kW1 = BC_WALL, kE1 = BC_WALL;
         if (EDGE) {
-            const int Rc = min(max(R, 0), ny - 1), R1c = min(max(R - 1, 0), ny - 1);
-            kW0 = face_kind(*P, EDGE_W, Rc); kE0 = face_kind(*P, EDGE_E, Rc);
+            const int R1c = min(max(R - 1, 0), ny - 1);
             kW1 = face_kind(*P, EDGE_W, R1c); kE1 = face_kind(*P, EDGE_E, R1c);
         }
 
-        // ---- S2 on row R
-        const T h0 = e0 - z0;
-        const T r0 = recip_prim(h0, c.hdry, c.rcap);
-        const T u0 = a0 * r0, v0 = b0 * r0;
-
-        // ---- S3/S4 in x on row R
-        const T eE = from_east(e0), eW = from_west(e0);
-        const T hE = from_east(h0);
-        const T nux0 = curv_switch(eW, e0, eE, r0);
-        const T nuxE = from_east(nux0);
-        const T epsE = faceE_interior ? face_eps(h0, hE, nux0, nuxE, c.hdry, c.kap, c.emax) : T(0);
-        const T fdm = epsE * (eE - e0);
-        const T fda = epsE * (from_east(a0) - a0);
-        const T fdb = epsE * (from_east(b0) - b0);
-        const T dx0m = fdm - from_west(fdm), dx0a = fda - from_west(fda),
-                dx0b = fdb - from_west(fdb);
-
-        // ---- S5 (+ x pressure of S7) on row R
-        XDiv<T> A0;
-        if (SIG > 0)
-            A0 = x_divergence<T, 1>(c, e0, a0, h0, r0, u0, v0, z0, eE, hE, from_east(z0), c.qin0,
-                                    EDGE, atW, atE, kW0, kE0);
-        else
-            A0 = x_divergence<T, -1>(c, e0, a0, h0, r0, u0, v0, z0, eW, from_west(h0),
-                                     from_west(z0), c.qin0, EDGE, atW, atE, kW0, kE0);
-
-        // ---- S3 in y at row R-1, S4 in y through face (R-2)+1/2
-        const T nuy1 = curv_switch(e2, e1, e0, r1);
-        const bool fInt = !BND || (R - 2 >= 0 && R - 2 <= ny - 2);
-        const T h1 = e1 - z1, h2 = e2 - z2;
-        const T epsN = fInt ? face_eps(h2, h1, nuy2, nuy1, c.hdry, c.kap, c.emax) : T(0);
-        const T pnm = epsN * (e1 - e2), pna = epsN * (a1 - a2), pnb = epsN * (b1 - b2);
-
-        // ---- S6 through face (R-1)+1/2, S7 predictor of row R-1
-        const bool bndG = BND && ((R - 1 == -1) || (R - 1 == ny - 1));
-        const YFace<T> G0 = y_face<T, SIG>(c, bndG, R - 1 == -1, kS, kN, e1, b1, h1, r1,
-                                           a1 * r1, b1 * r1, z1, e0, b0, h0, r0, u0, v0, z0,
-                                           c.qin0);
-        const T pys = SIG > 0 ? G0.p : G1.p;
-        const T se1 = (e1 - c.rx * A1.m) - c.ry * (G0.m - G1.m);
-        const T sa1 = (a1 - c.rx * A1.x) - c.ry * (G0.x - G1.x);
-        const T sb1 = (b1 - c.rx * A1.y) - c.ry * ((G0.y - G1.y) + pys);
-
         // ---- S9 on U*(R-1), S10 on U*(R-1)
-        const T sh1 = se1 - z1;
+        const T sh1 = se1 - z1x;
         const T sr1 = recip_prim(sh1, c.hdry, c.rcap);
         const T su1 = sa1 * sr1, sv1 = sb1 * sr1;
         if (TRACE && colOut && R - 1 >= y0 && R - 1 < yEnd) {
@@ -263,28 +339,28 @@ struct March {
         }
         XDiv<T> B1;
         if (SIG > 0)   // corrector donor direction -1: neighbour on the west
-            B1 = x_divergence<T, -1>(c, se1, sa1, sh1, sr1, su1, sv1, z1, from_west(se1),
-                                     from_west(sh1), from_west(z1), c.qin1, EDGE, atW, atE, kW1,
+            B1 = x_divergence<T, -1>(c, se1, sa1, sh1, sr1, su1, sv1, z1x, from_west(se1),
+                                     from_west(sh1), from_west(z1x), c.qin1, EDGE, atW, atE, kW1,
                                      kE1);
         else
-            B1 = x_divergence<T, 1>(c, se1, sa1, sh1, sr1, su1, sv1, z1, from_east(se1),
-                                    from_east(sh1), from_east(z1), c.qin1, EDGE, atW, atE, kW1,
+            B1 = x_divergence<T, 1>(c, se1, sa1, sh1, sr1, su1, sv1, z1x, from_east(se1),
+                                    from_east(sh1), from_east(z1x), c.qin1, EDGE, atW, atE, kW1,
                                     kE1);
 
         // ---- S11 through face (R-2)+1/2
         const bool bndH = BND && ((R - 2 == -1) || (R - 2 == ny - 1));
-        const T sh2 = se2 - z2;
+        const T sh2 = se2 - z2x;
         const YFace<T> H0 = y_face<T, -SIG>(c, bndH, R - 2 == -1, kS, kN, se2, sb2, sh2, sr2,
-                                            sa2 * sr2, sb2 * sr2, z2, se1, sb1, sh1, sr1, su1, sv1,
-                                            z1, c.qin1);
+                                            sa2 * sr2, sb2 * sr2, z2x, se1, sb1, sh1, sr1, su1, sv1,
+                                            z1x, c.qin1);
 
         if (!BND || out) {
             // ---- S4 total, S12 corrector, S13 .. S16 on row R-2
-            const T Dm = dx2m + (pnm - phm), Da = dx2a + (pna - pha), Db = dx2b + (pnb - phb);
+            const T Dm = dxm + (pnm - phm), Da = dxa + (pna - pha), Db = dxb + (pnb - phb);
             const T pcs = -SIG > 0 ? H0.p : H1.p;
-            const T ce = T(0.5) * (e2 + ((se2 - c.rx * B2.m) - c.ry * (H0.m - H1.m)));
-            const T ca = T(0.5) * (a2 + ((sa2 - c.rx * B2.x) - c.ry * (H0.x - H1.x)));
-            const T cb = T(0.5) * (b2 + ((sb2 - c.rx * B2.y) - c.ry * ((H0.y - H1.y) + pcs)));
+            const T ce = T(0.5) * (e2x + ((se2 - c.rx * B2.m) - c.ry * (H0.m - H1.m)));
+            const T ca = T(0.5) * (a2x + ((sa2 - c.rx * B2.x) - c.ry * (H0.x - H1.x)));
+            const T cb = T(0.5) * (b2x + ((sb2 - c.rx * B2.y) - c.ry * ((H0.y - H1.y) + pcs)));
             T e = ce + Dm, a = ca + Da, b = cb + Db;
             if (TRACE && colOut) {
                 const long long so = (long long)(R - 2) * pitch + i;
@@ -292,19 +368,19 @@ struct March {
                 tud[1][so] = a;
                 tud[2][so] = b;
             }
-            T h = e - z2;
+            T h = e - z2x;
             T lam = T(0);
             if (h > c.hdry) {
                 const T r = trcp(h);
-                manning(c.dt, m2, r, a, b);
+                manning(c.dt, m2x, r, a, b);
                 // wet stays wet through S15 (h is unchanged), so S16 uses r
                 lam = cfl_lambda(h, r, a, b, c.g, c.idx, c.idy);
             } else {
                 if (h < T(0)) {
                     def = def + (colOut ? 0.0 - (double)h : 0.0);
-                    e = z2;
+                    e = z2x;
                     flags |= colOut ? FLAG_CLIPPED : 0u;
-                    h = e - z2;
+                    h = e - z2x;
                 }
                 a = T(0);
                 b = T(0);
@@ -321,15 +397,8 @@ struct March {
             }
         }
 
-        // ---- rotate the carried rows
-        e2 = e1; a2 = a1; b2 = b1; z2 = z1;
-        e1 = e0; a1 = a0; b1 = b0; z1 = z0; r1 = r0;
-        nuy2 = nuy1;
-        dx2m = dx1m; dx2a = dx1a; dx2b = dx1b;
-        dx1m = dx0m; dx1a = dx0a; dx1b = dx0b;
+        // ---- rotate the corrector half's carried rows
         phm = pnm; pha = pna; phb = pnb;
-        A1 = A0;
-        G1 = G0;
         se2 = se1; sa2 = sa1; sb2 = sb1; sr2 = sr1;
         B2 = B1;
         H1 = H0;
@@ -337,7 +406,7 @@ struct March {
 
     template <bool EDGE>
     __device__ __forceinline__ void run() {
-        prefetch<0>(y0 - 2);
+        if constexpr (PART != 2) prefetch<0>(y0 - 2);
         // rows y0-2 .. y0+1 only fill the pipeline: no output row yet; the
         // iteration at row R reads slot (R - y0) mod 2
         for (int R = y0 - 2; R < y0 + 2; R += 2) {
@@ -401,7 +470,7 @@ __device__ __forceinline__ void put_record(TilePart* r, double def, double vol,
 template <typename T>
 __device__ __forceinline__ void finish_step(const FusedArgs<T>& A, int tile, int nblk,
                                             bool lam_is_f32) {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % kWave;
     const int g = tile / kGroup;
     const int gsize = min(kGroup, nblk - g * kGroup);
     wait_stores();
@@ -500,12 +569,16 @@ __device__ __forceinline__ int paired_strip(int pos, int gx) {
     return pos;
 }
 
-template <typename T, int SIG, bool DRY, bool TRACE = false>
-__device__ __forceinline__ void fused_step(const FusedArgs<T>& A, int blk, int nblk) {
+// PART 0: one wave does the whole tile.  PART 1 and 2: the two waves of a
+// workgroup share it (the predictor and the corrector half of every
+// iteration, rows passed through `ring`); the second wave keeps the record.
+template <typename T, int SIG, bool DRY, bool TRACE, int PART>
+__device__ __forceinline__ void fused_tile(const FusedArgs<T>& A, int blk, int nblk, T* ring,
+                                           int* prog, int* note) {
     Ctl* ctl = A.ctl;
     if (step_is_noop(ctl, A.t_end)) return;
     const Params& P = A.P;
-    March<T, SIG, DRY, TRACE> M;
+    March<T, SIG, DRY, TRACE, PART> M;
     if (TRACE)
         for (int f = 0; f < 3; ++f) {
             M.tus[f] = A.tus[f];
@@ -524,7 +597,7 @@ __device__ __forceinline__ void fused_step(const FusedArgs<T>& A, int blk, int n
     M.ny = P.ny;
     M.pitch = P.pitch;
 
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % kWave;
     const int tile = xcd_tile(blk, nblk);
     const int pos = tile / A.gy, chunk = tile - pos * A.gy;
     const int gx = (P.nx + kOutW - 1) / kOutW;
@@ -561,7 +634,7 @@ __device__ __forceinline__ void fused_step(const FusedArgs<T>& A, int blk, int n
             if (lane < 9) f = dprev[(strip + lane % 3 - 1) * A.gy + (chunk + lane / 3 - 1)];
             skip = __ballot(!(f & kDryStill)) == 0ull;
         }
-        if (skip) {
+        if (skip && PART != 1) {
             if (!(dprev[gi] & kDrySkipped) && M.colOut) {
                 for (int r = M.y0; r < M.yEnd; ++r) {
                     const long long o = (long long)r * P.pitch + M.i;
@@ -581,11 +654,35 @@ __device__ __forceinline__ void fused_step(const FusedArgs<T>& A, int blk, int n
         }
     }
 
-    if (!skip) {
+    if (skip) {
+        if (PART != 1) finish_step(A, tile, nblk, sizeof(T) == 4);
+        return;
+    }
+    if (PART != 0) {
+        M.ring = ring;
+        M.prog = prog;
+        M.lane = lane;
+        M.spin_cap = A.spin_cap;
+        if (PART == 1 && lane == 0) {
+            prog[0] = prog[1] = M.y0 - 3;   // no row filed or taken yet
+            *note = 0;
+        }
+        __syncthreads();
+    }
+    {
         if (edge)
             M.template run<true>();
         else
             M.template run<false>();
+        if (PART == 1) {
+            // a stall of this wave reaches the record through the second wave
+            if (M.stalled && lane == 0) __hip_atomic_store(note, 1, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+            return;
+        }
+        if (PART == 2 && (M.stalled || __hip_atomic_load(note, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP)))
+            M.flags |= FLAG_STALL;
         // ---- the workgroup's record (lane 0's reduction order is the fixed one)
         const double vol = wave_sum(M.vol);
         const double def = wave_sum(M.def);
@@ -598,6 +695,24 @@ __device__ __forceinline__ void fused_step(const FusedArgs<T>& A, int blk, int n
         }
     }
     finish_step(A, tile, nblk, sizeof(T) == 4);
+}
+
+template <typename T, int SIG, bool DRY, bool TRACE = false>
+__device__ __forceinline__ void fused_step(const FusedArgs<T>& A, int blk, int nblk) {
+    fused_tile<T, SIG, DRY, TRACE, 0>(A, blk, nblk, nullptr, nullptr, nullptr);
+}
+
+// The two-wave workgroup of a tile: wave 0 the predictor half, wave 1 the
+// corrector half.
+template <typename T, int SIG, bool DRY, bool TRACE = false>
+__device__ __forceinline__ void fused_step_split(const FusedArgs<T>& A, int blk, int nblk) {
+    __shared__ T ring[kSplitFields * kSplitSlots * kWave];
+    __shared__ int prog[2];
+    __shared__ int note;
+    if (threadIdx.x < kWave)
+        fused_tile<T, SIG, DRY, TRACE, 1>(A, blk, nblk, ring, prog, &note);
+    else
+        fused_tile<T, SIG, DRY, TRACE, 2>(A, blk, nblk, ring, prog, &note);
 }
 
 // The two precisions get their own entry points so that each can be given
@@ -628,6 +743,19 @@ __global__ void __launch_bounds__(kWave, 4) k_fused_step_f32_w4(FusedArgs<float>
 template <int SIG>
 __global__ void __launch_bounds__(kWave, 2) k_fused_trace_f64(FusedArgs<double> A) {
     fused_step<double, SIG, false, true>(A, blockIdx.x, gridDim.x);
+}
+// The same steps with two waves per tile, each running half of every
+// iteration: half the carried rows per wave, so more waves fit per SIMD (FP64
+// 3, FP32 4) than one wave per tile allows (2 and 3).  (FP32 at 5 waves per
+// SIMD, 96 registers with a few spilled, was measured no faster.)
+constexpr int kSplitWavesF64 = 3, kSplitWavesF32 = 4;
+template <int SIG, bool DRY>
+__global__ void __launch_bounds__(2 * kWave, kSplitWavesF64) k_fused_split_f64(FusedArgs<double> A) {
+    fused_step_split<double, SIG, DRY>(A, blockIdx.x, gridDim.x);
+}
+template <int SIG, bool DRY>
+__global__ void __launch_bounds__(2 * kWave, kSplitWavesF32) k_fused_split_f32(FusedArgs<float> A) {
+    fused_step_split<float, SIG, DRY>(A, blockIdx.x, gridDim.x);
 }
 
 // Ensemble launch: the workgroups of every scenario in one grid.  Scenario s
@@ -662,22 +790,45 @@ k_ensemble_step_f32(const FusedArgs<float>* args, const int* first, int count) {
     fused_step<float, SIG, DRY>(args[sc], blk, nblk);
 }
 
-template <typename T, int SIG, bool DRY>
+// The same with two waves per tile (the split step), FP32 only: the FP64
+// form, with the ensemble's scenario lookup on top, spills 120-170 bytes per
+// lane at three waves per SIMD, so FP64 ensembles keep one wave per tile.
+template <int SIG, bool DRY>
+__global__ void __launch_bounds__(2 * kWave, kSplitWavesF32)
+k_ensemble_split_f32(const FusedArgs<float>* args, const int* first, int count) {
+    int sc, blk, nblk;
+    ensemble_locate<float>(first, count, sc, blk, nblk);
+    fused_step_split<float, SIG, DRY>(args[sc], blk, nblk);
+}
+
+template <typename T, int SIG, bool DRY, bool SPLIT>
 constexpr auto ensemble_kernel() {
-    if constexpr (sizeof(T) == 8)
+    if constexpr (SPLIT && sizeof(T) == 4) {
+        return &k_ensemble_split_f32<SIG, DRY>;
+    } else if constexpr (sizeof(T) == 8) {
         return &k_ensemble_step_f64<SIG, DRY>;
-    else
+    } else {
         return &k_ensemble_step_f32<SIG, DRY>;
+    }
+}
+
+template <typename T, bool SPLIT>
+static hipError_t launch_ensemble_k(const FusedArgs<T>* args, const int* first, int count,
+                                    int total, int sigma, bool dry, hipStream_t s) {
+    const auto k = sigma > 0 ? (dry ? ensemble_kernel<T, 1, true, SPLIT>() : ensemble_kernel<T, 1, false, SPLIT>())
+                             : (dry ? ensemble_kernel<T, -1, true, SPLIT>() : ensemble_kernel<T, -1, false, SPLIT>());
+    hipLaunchKernelGGL(k, dim3(total), dim3(SPLIT && sizeof(T) == 4 ? 2 * kWave : kWave), 0, s, args,
+                       first, count);
+    return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_ensemble(const FusedArgs<T>* args, const int* first, int count, int total,
-                           int sigma, bool dry, hipStream_t s) {
+                           int sigma, bool dry, hipStream_t s, bool split) {
     if (total <= 0) return hipSuccess;
-    const auto k = sigma > 0 ? (dry ? ensemble_kernel<T, 1, true>() : ensemble_kernel<T, 1, false>())
-                             : (dry ? ensemble_kernel<T, -1, true>() : ensemble_kernel<T, -1, false>());
-    hipLaunchKernelGGL(k, dim3(total), dim3(kWave), 0, s, args, first, count);
-    return hipGetLastError();
+    return split && sizeof(T) == 4
+               ? launch_ensemble_k<T, true>(args, first, count, total, sigma, dry, s)
+               : launch_ensemble_k<T, false>(args, first, count, total, sigma, dry, s);
 }
 
 template <typename T, int SIG, bool DRY>
@@ -694,12 +845,26 @@ constexpr auto fused_kernel_more() {
     else
         return &k_fused_step_f32_w4<SIG>;
 }
+template <typename T, int SIG, bool DRY>
+constexpr auto fused_kernel_split() {
+    if constexpr (sizeof(T) == 8)
+        return &k_fused_split_f64<SIG, DRY>;
+    else
+        return &k_fused_split_f32<SIG, DRY>;
+}
 
 template <typename T>
-hipError_t launch_fused(const FusedArgs<T>& a, int sigma, hipStream_t s, bool more_waves) {
+hipError_t launch_fused(const FusedArgs<T>& a, int sigma, hipStream_t s, bool more_waves,
+                        bool split) {
     const int gx = (a.P.nx + kOutW - 1) / kOutW;
     const int nblk = gx * a.gy;
     const bool dry = a.dry != nullptr;
+    if (split && !more_waves) {
+        const auto k = sigma > 0 ? (dry ? fused_kernel_split<T, 1, true>() : fused_kernel_split<T, 1, false>())
+                                 : (dry ? fused_kernel_split<T, -1, true>() : fused_kernel_split<T, -1, false>());
+        hipLaunchKernelGGL(k, dim3(nblk), dim3(2 * kWave), 0, s, a);
+        return hipGetLastError();
+    }
     auto k = sigma > 0 ? (dry ? fused_kernel<T, 1, true>() : fused_kernel<T, 1, false>())
                        : (dry ? fused_kernel<T, -1, true>() : fused_kernel<T, -1, false>());
     if (more_waves && !dry) k = sigma > 0 ? fused_kernel_more<T, 1>() : fused_kernel_more<T, -1>();
@@ -758,12 +923,22 @@ int fused_waves_per_cu(bool more_waves) {
     return nb;
 }
 
+template <typename T>
+int fused_split_tiles_per_cu() {
+    int nb = 0;
+    const void* k = (const void*)fused_kernel_split<T, 1, false>();
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 2 * kWave, 0) != hipSuccess) return 0;
+    return nb;
+}
+
 // Access-pattern probe of the step: the tiles, tile order, strip map and row
-// march of k_fused_step (64-lane strips of 60 output columns, chunks of H
-// rows, the row ahead prefetched into two register slots, the output row two
-// behind the ingested one), the same five loads and three stores per row,
-// and a handful of operations in place of the sixteen sub-steps.  Every
-// loaded value reaches a store, so none of the traffic is optimised away.
+// march of the one-wave step, k_fused_step (64-lane strips of 60 output
+// columns, chunks of H rows, the row ahead prefetched into two register
+// slots, the output row two behind the ingested one; the split step reads and
+// writes the same rows in the same order, from its first and its second wave),
+// the same five loads and three stores per row, and a handful of operations
+// in place of the sixteen sub-steps.  Every loaded value reaches a store, so
+// none of the traffic is optimised away.
 template <typename T>
 __global__ void __launch_bounds__(kWave) k_probe_march(ProbeMarchArgs A) {
     const T* __restrict__ f0 = (const T*)A.in[0];
@@ -827,14 +1002,16 @@ hipError_t launch_probe_march(const ProbeMarchArgs& a, int elem_bytes, hipStream
 }
 
 template hipError_t launch_ensemble<float>(const FusedArgs<float>*, const int*, int, int, int,
-                                           bool, hipStream_t);
+                                           bool, hipStream_t, bool);
 template hipError_t launch_ensemble<double>(const FusedArgs<double>*, const int*, int, int, int,
-                                            bool, hipStream_t);
-template hipError_t launch_fused<float>(const FusedArgs<float>&, int, hipStream_t, bool);
-template hipError_t launch_fused<double>(const FusedArgs<double>&, int, hipStream_t, bool);
+                                            bool, hipStream_t, bool);
+template hipError_t launch_fused<float>(const FusedArgs<float>&, int, hipStream_t, bool, bool);
+template hipError_t launch_fused<double>(const FusedArgs<double>&, int, hipStream_t, bool, bool);
 template void fused_part_layout<float>(FusedArgs<float>&, void*, int);
 template void fused_part_layout<double>(FusedArgs<double>&, void*, int);
 template int fused_waves_per_cu<float>(bool);
 template int fused_waves_per_cu<double>(bool);
+template int fused_split_tiles_per_cu<float>();
+template int fused_split_tiles_per_cu<double>();
 
 }  // namespace swe

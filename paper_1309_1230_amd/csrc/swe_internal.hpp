@@ -37,21 +37,30 @@ struct FusedArgs {
     // launch_fused_trace only: U* and U^d of every cell (pitched, 3 fields each)
     T* tus[3] = {nullptr, nullptr, nullptr};
     T* tud[3] = {nullptr, nullptr, nullptr};
+    // the split step (two waves per tile): polls after which a wave stops
+    // waiting for the other and the step raises FLAG_STALL
+    int spin_cap = kSplitSpinCap;
 };
 
 // more_waves: the occupancy variant (one more resident wave per SIMD, some
 // of the carried state in scratch; not with the dry-tile skip).
+// split: two waves per tile, one running the predictor half (S2..S7) and one
+// the corrector half (S9..S16) of every row, rows handed over through LDS
+// (not with more_waves); the same state bits as one wave per tile.
 template <typename T>
-hipError_t launch_fused(const FusedArgs<T>& a, int sigma, hipStream_t s, bool more_waves = false);
+hipError_t launch_fused(const FusedArgs<T>& a, int sigma, hipStream_t s, bool more_waves = false,
+                        bool split = false);
 // The FP64 fused step that also writes U* (after S7) and U^d (after S13,
-// before friction) of every cell to a.tus and a.tud.
+// before friction) of every cell to a.tus and a.tud (one wave per tile).
 hipError_t launch_fused_trace(const FusedArgs<double>& a, int sigma, hipStream_t s);
 // One fused step of every scenario of an ensemble in one launch: scenario s
 // owns workgroups first[s] .. first[s+1]-1 of `total` (args, first: device).
 // dry: some scenario has the dry-tile skip on (its args carry the flags).
+// split: two waves per tile (FP32 only; FP64 keeps one wave per tile; a
+// measured variant, not the default).
 template <typename T>
 hipError_t launch_ensemble(const FusedArgs<T>* args, const int* first, int count, int total,
-                           int sigma, bool dry, hipStream_t s);
+                           int sigma, bool dry, hipStream_t s, bool split = false);
 int fused_blocks(int nx, int ny, int H);
 // Bytes of the fused path's partial-result buffer for up to `ntiles` tiles
 // (tile records, group records, group tickets; zero it before first use).
@@ -63,6 +72,9 @@ int fused_strips(int nx);
 // Resident fused workgroups (one wave each) per compute unit, or 0.
 template <typename T>
 int fused_waves_per_cu(bool more_waves = false);
+// Resident two-wave workgroups (tiles) of the split step per compute unit, or 0.
+template <typename T>
+int fused_split_tiles_per_cu();
 // Automatic tile height of the fused step for `slots` resident waves: as
 // many chunks per strip as fit one round of waves, at least 6 rows; with
 // the dry-tile skip at most 32.

@@ -20,7 +20,7 @@ SWE_OK, SWE_EINVAL, SWE_ENOMEM, SWE_EDEVICE, SWE_EUNSTABLE, SWE_EUNSUPPORTED = 0
 SWE_F32, SWE_F64 = 1, 2
 SWE_BC_WALL, SWE_BC_OPEN, SWE_BC_INFLOW = 0, 1, 2
 SWE_PATH_FUSED, SWE_PATH_UNFUSED = 0, 1
-FLAG_NAN, FLAG_CLIPPED, FLAG_BADDT = 1, 2, 4
+FLAG_NAN, FLAG_CLIPPED, FLAG_BADDT, FLAG_STALL = 1, 2, 4, 8
 NTRACE = 47
 TRACE_NAMES = (
     ["S1.eta", "S1.qx", "S1.qy", "S2.h", "S2.r", "S2.u", "S2.v", "S3.nux", "S3.nuy",

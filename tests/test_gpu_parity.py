@@ -132,6 +132,49 @@ def test_occupancy_variant_equals_default_bitwise(dtype, waves, monkeypatch):
         assert sa.volume == pytest.approx(sb.volume, rel=1e-12)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("dry_skip", [False, True])
+def test_split_step_equals_one_wave_bitwise(dtype, dry_skip, monkeypatch):
+    """The fused step runs with two waves per tile by default (one the
+    predictor half of every row, S2..S7, the other the corrector half,
+    S9..S16, rows handed over through LDS).  SWE_FUSED_SPLIT=0 runs the same
+    iteration in one wave per tile.  The two must give the same state, dt, t,
+    volume and defect bits, at the automatic tile height and at short tiles
+    (three rows: every row of a tile is in its pipeline fill)."""
+    p = W.reservoir_release(nx=300, ny=220, dx=60.0, hills=30, seed=1001)
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    for tile_rows in (0, 3, 16):
+        note(f"split vs one wave {dtype} dry_skip={dry_skip} H={tile_rows or 'auto'}")
+        a = swe.Solver.from_problem(p, dtype=dt, tile_rows=tile_rows, dry_skip=dry_skip)
+        monkeypatch.setenv("SWE_FUSED_SPLIT", "0")
+        b = swe.Solver.from_problem(p, dtype=dt, tile_rows=tile_rows, dry_skip=dry_skip)
+        monkeypatch.delenv("SWE_FUSED_SPLIT")
+        sa, sb = a.run(30), b.run(30)
+        for x, y in zip(state(a), state(b)):
+            assert np.array_equal(x, y)
+        assert sa.dt == sb.dt and sa.t == sb.t
+        assert sa.volume == sb.volume and sa.defect == sb.defect
+
+
+def test_split_step_wait_that_runs_out_is_fatal(monkeypatch):
+    """The two waves of a tile wait for each other through LDS counters, each
+    wait bounded.  With the bound lowered from the host to zero polls, a wave
+    that finds its partner's row not yet filed stops waiting at once: the step
+    must raise SWE_FLAG_STALL, which is fatal, so the run fails instead of
+    returning the values.  Every kernel still ends normally."""
+    p = W.reservoir_release(nx=300, ny=220, dx=60.0, hills=30, seed=1001)
+    note("split step with its waits bounded to zero polls")
+    monkeypatch.setenv("SWE_SPLIT_SPIN_CAP", "0")
+    st = solver(p, "f64").run(5, check=False)
+    assert st.flags & swe.FLAG_STALL
+    with pytest.raises(swe.SweError) as err:
+        solver(p, "f64").run(5)
+    assert err.value.code == swe.SWE_EUNSTABLE
+    monkeypatch.delenv("SWE_SPLIT_SPIN_CAP")
+    g = solver(p, "f64")
+    assert g.run(5).flags & swe.FLAG_STALL == 0
+
+
 def test_fused_run_to_run_deterministic():
     p = W.reservoir_release(nx=300, ny=220, dx=60.0, hills=30, seed=1001)
     note("run-to-run determinism reservoir300x220")
