@@ -138,7 +138,7 @@ __device__ __forceinline__ YFace<T> y_face(const Consts<T>& c, bool bnd, bool so
 // faces carried from one iteration to the next, the prefetched row and the
 // running partial sums.  Rows are named relative to the ingested row R.
 // The two-wave form of the march: rows of its LDS ring and values per row.
-constexpr int kSplitSlots = 3, kSplitFields = 15;
+constexpr int kSplitSlots = 3, kSplitFields = 13;
 
 template <typename T, int SIG, bool DRY, bool TRACE = false, int PART = 0>
 struct March {
@@ -162,10 +162,8 @@ struct March {
     // Depths are not carried: h = eta - z is recomputed from the carried
     // eta and z (the same operands, so the same bits) to save registers.
     T e1 = 0, a1 = 0, b1 = 0, z1 = 0, r1 = 0;   // U^n row R-1
-    T e2 = 0, a2 = 0, b2 = 0, z2 = 0;           // U^n row R-2
+    T e2 = 0, a2 = 0, b2 = 0, z2 = 0, r2 = 0;   // U^n row R-2
     T nuy2 = 0;                      // nu_y(R-2)
-    T dx1m = 0, dx1a = 0, dx1b = 0;  // x dissipation of row R-1
-    T dx2m = 0, dx2a = 0, dx2b = 0;  // x dissipation of row R-2
     T phm = 0, pha = 0, phb = 0;     // y dissipation flux through face (R-3)+1/2
     XDiv<T> A1 = {0, 0, 0};          // predictor x part of row R-1
     YFace<T> G1 = {0, 0, 0, 0};      // predictor y face (R-2)+1/2
@@ -234,10 +232,9 @@ struct March {
     template <bool EDGE, bool BND, int SLOT>
     __device__ __forceinline__ void iter(int R, bool out) {
         // the predictor half's values the corrector half reads: U* of row
-        // R-1, the bed of rows R-1 and R-2, U^n and m of row R-2, the x
-        // dissipation of row R-2 and the y dissipation flux through face
-        // (R-2)+1/2
-        T se1, sa1, sb1, z1x, z2x, e2x, a2x, b2x, m2x, dxm, dxa, dxb, pnm, pna, pnb;
+        // R-1, the bed of rows R-1 and R-2, U^n, 1/h and m of row R-2 and the
+        // y dissipation flux through face (R-2)+1/2
+        T se1, sa1, sb1, z1x, z2x, e2x, a2x, b2x, r2x, m2x, pnm, pna, pnb;
         if constexpr (PART != 2) {
             const T e0 = pe[SLOT], a0 = pa[SLOT], b0 = pb[SLOT], z0 = pz[SLOT];
             const T m2 = pm[SLOT];              // m of row R-2
@@ -254,19 +251,10 @@ struct March {
             const T r0 = recip_prim(h0, c.hdry, c.rcap);
             const T u0 = a0 * r0, v0 = b0 * r0;
 
-            // ---- S3/S4 in x on row R
+            // ---- S5 (+ x pressure of S7) on row R (S3/S4 in x on this row
+            // follow in the corrector half, two iterations later)
             const T eE = from_east(e0), eW = from_west(e0);
             const T hE = from_east(h0);
-            const T nux0 = curv_switch(eW, e0, eE, r0);
-            const T nuxE = from_east(nux0);
-            const T epsE = faceE_interior ? face_eps(h0, hE, nux0, nuxE, c.hdry, c.kap, c.emax) : T(0);
-            const T fdm = epsE * (eE - e0);
-            const T fda = epsE * (from_east(a0) - a0);
-            const T fdb = epsE * (from_east(b0) - b0);
-            const T dx0m = fdm - from_west(fdm), dx0a = fda - from_west(fda),
-                    dx0b = fdb - from_west(fdb);
-
-            // ---- S5 (+ x pressure of S7) on row R
             XDiv<T> A0;
             if (SIG > 0)
                 A0 = x_divergence<T, 1>(c, e0, a0, h0, r0, u0, v0, z0, eE, hE, from_east(z0), c.qin0,
@@ -291,15 +279,12 @@ struct March {
             se1 = (e1 - c.rx * A1.m) - c.ry * (G0.m - G1.m);
             sa1 = (a1 - c.rx * A1.x) - c.ry * (G0.x - G1.x);
             sb1 = (b1 - c.rx * A1.y) - c.ry * ((G0.y - G1.y) + pys);
-            z1x = z1; z2x = z2; e2x = e2; a2x = a2; b2x = b2; m2x = m2;
-            dxm = dx2m; dxa = dx2a; dxb = dx2b;
+            z1x = z1; z2x = z2; e2x = e2; a2x = a2; b2x = b2; r2x = r2; m2x = m2;
 
             // ---- rotate the predictor half's carried rows
-            e2 = e1; a2 = a1; b2 = b1; z2 = z1;
+            e2 = e1; a2 = a1; b2 = b1; z2 = z1; r2 = r1;
             e1 = e0; a1 = a0; b1 = b0; z1 = z0; r1 = r0;
             nuy2 = nuy1;
-            dx2m = dx1m; dx2a = dx1a; dx2b = dx1b;
-            dx1m = dx0m; dx1a = dx0a; dx1b = dx0b;
             A1 = A0;
             G1 = G0;
         }
@@ -307,18 +292,16 @@ struct March {
             // file row R once the second wave has taken the slot's last row, R - kSplitSlots
             wait_row(1, R - kSplitSlots);
             rg(0, R) = se1; rg(1, R) = sa1; rg(2, R) = sb1; rg(3, R) = z1x; rg(4, R) = z2x;
-            rg(5, R) = e2x; rg(6, R) = a2x; rg(7, R) = b2x; rg(8, R) = m2x;
-            rg(9, R) = dxm; rg(10, R) = dxa; rg(11, R) = dxb;
-            rg(12, R) = pnm; rg(13, R) = pna; rg(14, R) = pnb;
+            rg(5, R) = e2x; rg(6, R) = a2x; rg(7, R) = b2x; rg(8, R) = r2x; rg(9, R) = m2x;
+            rg(10, R) = pnm; rg(11, R) = pna; rg(12, R) = pnb;
             post_row(0, R);
             return;
         }
         if constexpr (PART == 2) {
             wait_row(0, R);
             se1 = rg(0, R); sa1 = rg(1, R); sb1 = rg(2, R); z1x = rg(3, R); z2x = rg(4, R);
-            e2x = rg(5, R); a2x = rg(6, R); b2x = rg(7, R); m2x = rg(8, R);
-            dxm = rg(9, R); dxa = rg(10, R); dxb = rg(11, R);
-            pnm = rg(12, R); pna = rg(13, R); pnb = rg(14, R);
+            e2x = rg(5, R); a2x = rg(6, R); b2x = rg(7, R); r2x = rg(8, R); m2x = rg(9, R);
+            pnm = rg(10, R); pna = rg(11, R); pnb = rg(12, R);
             post_row(1, R);
         }
         int kW1 = BC_WALL, kE1 = BC_WALL;
@@ -355,6 +338,21 @@ struct March {
                                             z1x, c.qin1);
 
         if (!BND || out) {
+            // ---- S3/S4 in x on row R-2 (every lane active: the shifts read
+            // the neighbouring lanes)
+            const T eE2 = from_east(e2x), eW2 = from_west(e2x);
+            const T h2x = e2x - z2x;
+            const T hE2 = from_east(h2x);
+            const T nux2 = curv_switch(eW2, e2x, eE2, r2x);
+            const T nuxE2 = from_east(nux2);
+            const T epsE = faceE_interior ? face_eps(h2x, hE2, nux2, nuxE2, c.hdry, c.kap, c.emax)
+                                          : T(0);
+            const T fdm = epsE * (eE2 - e2x);
+            const T fda = epsE * (from_east(a2x) - a2x);
+            const T fdb = epsE * (from_east(b2x) - b2x);
+            const T dxm = fdm - from_west(fdm), dxa = fda - from_west(fda),
+                    dxb = fdb - from_west(fdb);
+
             // ---- S4 total, S12 corrector, S13 .. S16 on row R-2
             const T Dm = dxm + (pnm - phm), Da = dxa + (pna - pha), Db = dxb + (pnb - phb);
             const T pcs = -SIG > 0 ? H0.p : H1.p;
@@ -717,7 +715,7 @@ __device__ __forceinline__ void fused_step_split(const FusedArgs<T>& A, int blk,
 
 // The two precisions get their own entry points so that each can be given
 // the register budget of its best occupancy: FP64 holds about twice the live
-// state and runs at 2 waves per SIMD (256 VGPRs), FP32 at 3 (168 VGPRs).
+// state and runs at 2 waves per SIMD (216 VGPRs), FP32 at 4 (128 VGPRs).
 template <int SIG, bool DRY>
 __global__ void __launch_bounds__(kWave, 2) k_fused_step_f64(FusedArgs<double> A) {
     fused_step<double, SIG, DRY>(A, blockIdx.x, gridDim.x);
@@ -782,8 +780,11 @@ k_ensemble_step_f64(const FusedArgs<double>* args, const int* first, int count) 
     ensemble_locate<double>(first, count, sc, blk, nblk);
     fused_step<double, SIG, DRY>(args[sc], blk, nblk);
 }
+// FP32 at four waves per SIMD (128 registers; the single-grid FP32 step fits
+// four without a bound): 90 G against 79 G cell-updates/s at three for the
+// 256-scenario flood ensemble.
 template <int SIG, bool DRY>
-__global__ void __launch_bounds__(kWave, 3)
+__global__ void __launch_bounds__(kWave, 4)
 k_ensemble_step_f32(const FusedArgs<float>* args, const int* first, int count) {
     int sc, blk, nblk;
     ensemble_locate<float>(first, count, sc, blk, nblk);
