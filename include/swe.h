@@ -88,7 +88,7 @@ typedef struct swe_config {
                               * the predictor half of every row and one the corrector half
                               * (SWE_FUSED_SPLIT=0 in the environment at swe_create: one
                               * wave per tile; same results).  SWE_FUSED_WAVES=3 (FP64) or
-                              * 4 (FP32) selects the one-wave kernel's occupancy variant,
+                              * 5 (FP32) selects the one-wave kernel's occupancy variant,
                               * one more resident wave per SIMD than its register budget
                               * allows (part of the carried state spills); a measurement
                               * knob with the same results, not used with the dry-tile

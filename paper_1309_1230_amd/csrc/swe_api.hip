@@ -358,12 +358,12 @@ void prepare_handle(swe_handle* h, const swe_config* c, int dev) {
     P.idx = 1.0 / c->dx;
     P.idy = 1.0 / c->dy;
     P.rcap = c->h_film > 0.0 ? 1.0 / c->h_film : INFINITY;
-    // SWE_FUSED_WAVES=3 (FP64) or 4 (FP32) in the environment selects the fused
+    // SWE_FUSED_WAVES=3 (FP64) or 5 (FP32) in the environment selects the fused
     // step's occupancy variant, one resident wave per SIMD more than its
     // default register budget allows (a measurement knob; same results)
     if (const char* w = std::getenv("SWE_FUSED_WAVES"))
         h->more_waves = c->path == SWE_PATH_FUSED && c->dry_skip == 0 &&
-                        std::atoi(w) == (c->dtype == SWE_F32 ? 4 : 3);
+                        std::atoi(w) == (c->dtype == SWE_F32 ? 5 : 3);
     // SWE_FUSED_SPLIT=0 in the environment runs the fused step with one wave
     // per tile instead of two (a measurement knob; same state bits)
     if (const char* sp = std::getenv("SWE_FUSED_SPLIT")) h->split = std::atoi(sp) != 0;

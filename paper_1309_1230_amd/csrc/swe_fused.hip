@@ -725,7 +725,7 @@ __global__ void __launch_bounds__(kWave, 3) k_fused_step_f32(FusedArgs<float> A)
     fused_step<float, SIG, DRY>(A, blockIdx.x, gridDim.x);
 }
 // The same steps with one more resident wave per SIMD than the register
-// budget above allows (FP64 3, FP32 4; the state the march carries then
+// budget above allows (FP64 3, FP32 5; the state the march carries then
 // partly spills to scratch): the occupancy variant that a launch asks for
 // with `more_waves` (a measurement of what occupancy buys; the results are
 // the same bits, only the register allocation differs).
@@ -734,7 +734,7 @@ __global__ void __launch_bounds__(kWave, 3) k_fused_step_f64_w3(FusedArgs<double
     fused_step<double, SIG, false>(A, blockIdx.x, gridDim.x);
 }
 template <int SIG>
-__global__ void __launch_bounds__(kWave, 4) k_fused_step_f32_w4(FusedArgs<float> A) {
+__global__ void __launch_bounds__(kWave, 5) k_fused_step_f32_w5(FusedArgs<float> A) {
     fused_step<float, SIG, false>(A, blockIdx.x, gridDim.x);
 }
 // The FP64 step that also writes U* and U^d (the forward data of the adjoint).
@@ -744,9 +744,10 @@ __global__ void __launch_bounds__(kWave, 2) k_fused_trace_f64(FusedArgs<double> 
 }
 // The same steps with two waves per tile, each running half of every
 // iteration: half the carried rows per wave, so more waves fit per SIMD (FP64
-// 3, FP32 4) than one wave per tile allows (2 and 3).  (FP32 at 5 waves per
-// SIMD, 96 registers with a few spilled, was measured no faster.)
-constexpr int kSplitWavesF64 = 3, kSplitWavesF32 = 4;
+// 3 at 141 registers, FP32 5 at 88) than one wave per tile allows (2 and 4).
+// (FP64 at 4 waves per SIMD, 128 registers with 48-56 bytes spilled, took 394
+// against 283 us.)
+constexpr int kSplitWavesF64 = 3, kSplitWavesF32 = 5;
 template <int SIG, bool DRY>
 __global__ void __launch_bounds__(2 * kWave, kSplitWavesF64) k_fused_split_f64(FusedArgs<double> A) {
     fused_step_split<double, SIG, DRY>(A, blockIdx.x, gridDim.x);
@@ -844,7 +845,7 @@ constexpr auto fused_kernel_more() {
     if constexpr (sizeof(T) == 8)
         return &k_fused_step_f64_w3<SIG>;
     else
-        return &k_fused_step_f32_w4<SIG>;
+        return &k_fused_step_f32_w5<SIG>;
 }
 template <typename T, int SIG, bool DRY>
 constexpr auto fused_kernel_split() {

@@ -112,7 +112,7 @@ def test_fused_equals_unfused_bitwise(dtype, tile_rows):
     assert sa.defect == pytest.approx(sb.defect, rel=1e-12, abs=1e-12)
 
 
-@pytest.mark.parametrize("dtype,waves", [("f64", "3"), ("f32", "4")])
+@pytest.mark.parametrize("dtype,waves", [("f64", "3"), ("f32", "5")])
 def test_occupancy_variant_equals_default_bitwise(dtype, waves, monkeypatch):
     """The fused kernel's occupancy variant (SWE_FUSED_WAVES: one more
     resident wave per SIMD, part of the carried state in scratch) is the same
