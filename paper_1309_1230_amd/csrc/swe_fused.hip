@@ -137,8 +137,15 @@ __device__ __forceinline__ YFace<T> y_face(const Consts<T>& c, bool bnd, bool so
 // State of one wave's march up its chunk: per-lane constants, the rows and
 // faces carried from one iteration to the next, the prefetched row and the
 // running partial sums.  Rows are named relative to the ingested row R.
-// The two-wave form of the march: rows of its LDS ring and values per row.
-constexpr int kSplitSlots = 3, kSplitFields = 13;
+// The two-wave form of the march: values per row of its LDS ring, and rows
+// of the ring: 3 in FP64 (23 KB a tile, 6 tiles per compute unit); 6 in the
+// dense FP32 step (20 KB: 8 tiles, so 4 waves per SIMD where registers would
+// allow 5, and the first wave may run 5 rows ahead: 156 against 160 us at
+// 4096^2), 3 with the dry-tile skip (its short tiles run 88 against 82 us
+// with 6).
+constexpr int kSplitFields = 13;
+template <typename T, bool DRY>
+constexpr int split_slots() { return sizeof(T) == 4 && !DRY ? 6 : 3; }
 
 template <typename T, int SIG, bool DRY, bool TRACE = false, int PART = 0>
 struct March {
@@ -184,10 +191,10 @@ struct March {
     // PART 1 and 2 (two waves of one workgroup): the first wave runs the
     // predictor half of each iteration (S2..S7), the second the corrector
     // half (S9..S16 and the stores) from the values the first files in an
-    // LDS ring of kSplitSlots rows (kSplitFields values per lane and row).
+    // LDS ring of split_slots<T, DRY>() rows (kSplitFields values per lane and row).
     // Two progress counters order them (prog[0]: the last row the first wave
     // filed, prog[1]: the last row the second has taken), so the first may
-    // run kSplitSlots - 1 rows ahead.  Every wait is bounded; a wave whose
+    // run split_slots<T, DRY>() - 1 rows ahead.  Every wait is bounded; a wave whose
     // wait runs out stops waiting and the step raises FLAG_STALL.
     T* ring = nullptr;
     int* prog = nullptr;
@@ -195,7 +202,8 @@ struct March {
     int spin_cap = 0;
     bool stalled = false;
     __device__ __forceinline__ T& rg(int f, int R) const {
-        return ring[(f * kSplitSlots + (R + kSplitSlots) % kSplitSlots) * kWave + lane];
+        constexpr int NS = split_slots<T, DRY>();
+        return ring[(f * NS + (R + NS) % NS) * kWave + lane];
     }
     __device__ __forceinline__ void wait_row(int who, int need) {
         if (stalled) return;
@@ -289,8 +297,8 @@ struct March {
             G1 = G0;
         }
         if constexpr (PART == 1) {
-            // file row R once the second wave has taken the slot's last row, R - kSplitSlots
-            wait_row(1, R - kSplitSlots);
+            // file row R once the second wave has taken the slot's last row
+            wait_row(1, R - split_slots<T, DRY>());
             rg(0, R) = se1; rg(1, R) = sa1; rg(2, R) = sb1; rg(3, R) = z1x; rg(4, R) = z2x;
             rg(5, R) = e2x; rg(6, R) = a2x; rg(7, R) = b2x; rg(8, R) = r2x; rg(9, R) = m2x;
             rg(10, R) = pnm; rg(11, R) = pna; rg(12, R) = pnb;
@@ -704,7 +712,7 @@ __device__ __forceinline__ void fused_step(const FusedArgs<T>& A, int blk, int n
 // corrector half.
 template <typename T, int SIG, bool DRY, bool TRACE = false>
 __device__ __forceinline__ void fused_step_split(const FusedArgs<T>& A, int blk, int nblk) {
-    __shared__ T ring[kSplitFields * kSplitSlots * kWave];
+    __shared__ T ring[kSplitFields * split_slots<T, DRY>() * kWave];
     __shared__ int prog[2];
     __shared__ int note;
     if (threadIdx.x < kWave)
@@ -744,7 +752,8 @@ __global__ void __launch_bounds__(kWave, 2) k_fused_trace_f64(FusedArgs<double> 
 }
 // The same steps with two waves per tile, each running half of every
 // iteration: half the carried rows per wave, so more waves fit per SIMD (FP64
-// 3 at 141 registers, FP32 5 at 88) than one wave per tile allows (2 and 4).
+// 3 at 141 registers; FP32 88 registers, 4 waves as its ring sets) than one
+// wave per tile allows (2 and 4).
 // (FP64 at 4 waves per SIMD, 128 registers with 48-56 bytes spilled, took 394
 // against 283 us.)
 constexpr int kSplitWavesF64 = 3, kSplitWavesF32 = 5;
