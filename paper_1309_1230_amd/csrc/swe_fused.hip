@@ -198,6 +198,7 @@ struct March {
     // wait runs out stops waiting and the step raises FLAG_STALL.
     T* ring = nullptr;
     int* prog = nullptr;
+    int* note = nullptr;   // the first wave's stall, for the second wave's record
     int lane = 0;
     int spin_cap = 0;
     bool stalled = false;
@@ -213,6 +214,10 @@ struct March {
             if (v >= need) return;
             if (n >= spin_cap) {
                 stalled = true;
+                // noted before any later row is posted, so the second wave's
+                // acquire of that row sees it
+                if (PART == 1 && lane == 0)
+                    __hip_atomic_store(note, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 return;
             }
             __builtin_amdgcn_s_sleep(1);
@@ -667,6 +672,7 @@ __device__ __forceinline__ void fused_tile(const FusedArgs<T>& A, int blk, int n
     if (PART != 0) {
         M.ring = ring;
         M.prog = prog;
+        M.note = note;
         M.lane = lane;
         M.spin_cap = A.spin_cap;
         if (PART == 1 && lane == 0) {
@@ -680,12 +686,8 @@ __device__ __forceinline__ void fused_tile(const FusedArgs<T>& A, int blk, int n
             M.template run<true>();
         else
             M.template run<false>();
-        if (PART == 1) {
-            // a stall of this wave reaches the record through the second wave
-            if (M.stalled && lane == 0) __hip_atomic_store(note, 1, __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-            return;
-        }
+        // a stall of the first wave reaches the record through the second
+        if (PART == 1) return;
         if (PART == 2 && (M.stalled || __hip_atomic_load(note, __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_WORKGROUP)))
             M.flags |= FLAG_STALL;
