@@ -1389,8 +1389,8 @@ hipError_t ens_enqueue(swe_ensemble* e, int64_t nsteps) {
     bool dry = false;
     for (swe_handle* h : e->h) dry = dry || h->dry != nullptr;
     // one wave per tile: the two-wave step (SWE_ENSEMBLE_SPLIT=1 in the
-    // environment, FP32 only) measured slower here, 334 against 246 ms for the
-    // 500-step flood ensemble, where the single grid gains 4-6%
+    // environment, FP32 only) measured slower here, 312 against 228 ms for the
+    // 500-step flood ensemble (short tiles), where the 4096^2 grid gains 4-7%
     const char* es = std::getenv("SWE_ENSEMBLE_SPLIT");
     const bool split = es && std::atoi(es) != 0;
     for (int64_t k = 0; k < nsteps && err == hipSuccess; ++k) {
