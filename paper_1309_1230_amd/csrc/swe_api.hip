@@ -1036,6 +1036,10 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
             cus = 0;
         (void)hipGetLastError();
         march_rows = swe::adjoint_march_rows(h->P, cus);
+        // SWE_MARCH_ROWS fixes the march's chunk height (a measurement knob;
+        // the gradient is the same bits at any height)
+        if (const char* mr = std::getenv("SWE_MARCH_ROWS"))
+            if (std::atoi(mr) > 0) march_rows = std::min(256, std::atoi(mr));
     }
     if (verbose)
         std::fprintf(stderr,
