@@ -376,6 +376,9 @@ void prepare_handle(swe_handle* h, const swe_config* c, int dev) {
     // swe_grad's tracing step runs one wave per tile, at that form's own
     // automatic height
     h->Ht = c->tile_rows > 0 ? c->tile_rows : auto_tile_rows(h, dev, false, true);
+    // SWE_TRACE_ROWS fixes that height (a measurement knob; same bits)
+    if (const char* tr = std::getenv("SWE_TRACE_ROWS"))
+        if (std::atoi(tr) > 0) h->Ht = std::atoi(tr);
     h->gyt = (c->ny + h->Ht - 1) / h->Ht;
     h->nparts = std::max({swe::fused_blocks(c->nx, c->ny, h->H), swe::fused_blocks(c->nx, c->ny, h->Ht),
                           swe::scan_partials(c->nx, c->ny)});
