@@ -295,7 +295,10 @@ typedef struct swe_gauges {
  * (SWE_ADJOINT in the environment selects another form: barrier, the same two
  * waves in step at a workgroup barrier; march1, the one-wave march; gather,
  * four gather kernels).  The gradient is the same bit for bit in every one of
- * these modes.  dJ_dn and dJ_dz (device, FP64, caller-owned, the handle's pitch)
+ * these modes.  Measurement knobs, same bits: SWE_MARCH_ROWS and SWE_TRACE_ROWS
+ * fix the reverse march's and the tracing step's tile heights;
+ * SWE_MARCH_SPIN_CAP lowers the bound on the march's waits (tests of the
+ * stall report).  dJ_dn and dJ_dz (device, FP64, caller-owned, the handle's pitch)
  * receive the gradients;
  * *loss (host) receives J.  FP32 handles: the forward run, its checkpoints
  * and the recomputed segments are FP32 (the state trajectory is that of
