@@ -1631,11 +1631,13 @@ bool adjoint_march_fits(const Params& P) {
     return 3.0 * pad < 4294967296.0 && pit < 4294967296.0;
 }
 
-int adjoint_march_rows(const Params& P, int ncu) {
-    // the smallest chunk height (8 .. 256) whose tiles fit four per compute
-    // unit in one round: one wave per SIMD for the one-wave march, two (one
-    // two-wave workgroup per SIMD pair of waves) for the two-wave march
-    const long long slots = 4LL * std::max(ncu, 1);
+int adjoint_march_rows(const Params& P, int ncu, int per_cu) {
+    // the smallest chunk height (8 .. 256) whose tiles fit per_cu per compute
+    // unit in one round.  Four: one wave per SIMD for the one-wave march, two
+    // (one two-wave workgroup per SIMD pair of waves) for the two-wave march.
+    // Three, when a recompute runs beside the march: two SIMDs then hold one
+    // march wave of 208 registers and have room for one of the tracing step
+    const long long slots = (long long)std::max(per_cu, 1) * std::max(ncu, 1);
     int H = 8;
     while (H < 256 && march_tiles(P, H).count() > slots) ++H;
     return H;

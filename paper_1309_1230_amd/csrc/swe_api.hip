@@ -782,13 +782,43 @@ size_t state_elems(const swe_handle* h) {
 }
 
 template <typename T>
-hipError_t copy_state(swe_handle* h, T* const dst[3], const T* const src[3]) {
+hipError_t copy_state(swe_handle* h, T* const dst[3], const T* const src[3],
+                      hipStream_t st = nullptr) {
     hipError_t e = hipSuccess;
     for (int f = 0; f < 3 && e == hipSuccess; ++f)
         e = hipMemcpyAsync(dst[f], src[f], state_elems(h) * sizeof(T), hipMemcpyDeviceToDevice,
-                           h->stream);
+                           st ? st : h->stream);
     return e;
 }
+
+// A second stream and the events between it and the handle's stream, for the
+// reverse sweep's overlapped segment recompute; it drains its stream before
+// the buffers it writes are freed.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t done[2] = {nullptr, nullptr};   // recompute into buffer b finished
+    hipEvent_t freed[2] = {nullptr, nullptr};  // march out of buffer b finished
+    bool used[2] = {false, false};
+    hipError_t init() {
+        hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+            e = hipEventCreateWithFlags(&done[b], hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&freed[b], hipEventDisableTiming);
+        }
+        return e;
+    }
+    SideStream() = default;
+    SideStream(const SideStream&) = delete;
+    SideStream& operator=(const SideStream&) = delete;
+    ~SideStream() {
+        if (s) (void)hipStreamSynchronize(s);
+        for (int b = 0; b < 2; ++b) {
+            if (done[b]) (void)hipEventDestroy(done[b]);
+            if (freed[b]) (void)hipEventDestroy(freed[b]);
+        }
+        if (s) (void)hipStreamDestroy(s);
+    }
+};
 
 // The discrete adjoint of nsteps steps of handle h, whose state has type T.
 // The forward run, its checkpoints and the recomputed segments are in T; the
@@ -879,6 +909,23 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
         const size_t need = (size_t)C * 6 * fe * sizeof(double);
         if (hipMemGetInfo(&freeb, &totalb) == hipSuccess && need <= freeb / 3)
             keep = segtr.alloc(need) == hipSuccess;
+        (void)hipGetLastError();
+    }
+    // With the kept U* and U^d, the recompute of the segment below runs on a
+    // second stream while the reverse sweep marches the present one, each in
+    // its own pair of segment buffers (the same bits: the same kernels on the
+    // same operands, ordered by events); SWE_GRAD_OVERLAP=0 in the
+    // environment runs them one after the other on the handle's stream
+    DevBuf seg2, segtr2;
+    SideStream side;
+    bool overlap = false;
+    const char* ovl_env = std::getenv("SWE_GRAD_OVERLAP");
+    if (keep && nseg > 1 && !(ovl_env && ovl_env[0] == '0')) {
+        size_t freeb = 0, totalb = 0;
+        const size_t need = (size_t)C * 6 * fe * sizeof(double);
+        overlap = hipMemGetInfo(&freeb, &totalb) == hipSuccess && need <= freeb / 3 &&
+                  seg2.alloc((size_t)C * 3 * fe * sizeof(T)) == hipSuccess &&
+                  segtr2.alloc(need) == hipSuccess && side.init() == hipSuccess;
         (void)hipGetLastError();
     }
     // FP64 views the reverse sweep works on
@@ -1038,7 +1085,7 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
             hipSuccess)
             cus = 0;
         (void)hipGetLastError();
-        march_rows = swe::adjoint_march_rows(h->P, cus);
+        march_rows = swe::adjoint_march_rows(h->P, cus, overlap ? 3 : 4);
         // SWE_MARCH_ROWS fixes the march's chunk height (a measurement knob;
         // the gradient is the same bits at any height)
         if (const char* mr = std::getenv("SWE_MARCH_ROWS"))
@@ -1049,33 +1096,30 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
                      "swe_grad: %.1f ms: forward run of %lld steps done, %lld reverse segments%s\n",
                      ms_since(t_start), (long long)nsteps, (long long)nseg,
                      store_all ? " (trajectory kept)" : "");
-    for (int64_t sg = nseg - 1; sg >= 0 && e == hipSuccess; --sg) {
-        if (verbose && sg < nseg - 1) {
-            e = hipStreamSynchronize(h->stream);
-            std::fprintf(stderr, "swe_grad: %.1f ms: reverse segment %lld of %lld done\n",
-                         ms_since(t_start), (long long)(nseg - 1 - sg), (long long)nseg);
-            if (e != hipSuccess) break;
-        }
+    // the states of segment sg recomputed from its checkpoint into the slots
+    // at segp (with U* and U^d at segtrp when kept), on stream st
+    auto recompute = [&](int64_t sg, void* segp, double* segtrp, hipStream_t st) -> hipError_t {
+        hipError_t r = hipSuccess;
         const int64_t s0 = sg * C, s1 = std::min(s0 + C, nsteps);
-        T *U0[3], *CK[3];
         if (!store_all) {
-            slot(seg.p, 0, U0);
+            T *U0[3], *CK[3];
+            slot(segp, 0, U0);
             slot(ck.p, sg, CK);
-            e = copy_state<T>(h, U0, CK);
+            r = copy_state<T>(h, U0, CK, st);
         }
         // the fused kernel's own finalisation carries dt from step to step.
         // (The recompute runs dense: the dry-tile skip leaves a tile unwritten
         // when the previous step skipped it too, which only a pair of
         // alternating buffers tolerates, not a slot per step.)
-        if (e == hipSuccess && !store_all && (keep || s1 - s0 > 1))
-            e = swe::launch_replay_ctl(h->P, rc_ctl, ht[(size_t)s0], step0 + s0, hdt[(size_t)s0],
-                                       h->stream);
+        if (r == hipSuccess && !store_all && (keep || s1 - s0 > 1))
+            r = swe::launch_replay_ctl(h->P, rc_ctl, ht[(size_t)s0], step0 + s0, hdt[(size_t)s0],
+                                       st);
         const int64_t srec = store_all ? s0 : (keep ? s1 : s1 - 1);   // steps recomputed
-        for (int64_t k = s0; k < srec && e == hipSuccess; ++k) {
+        for (int64_t k = s0; k < srec && r == hipSuccess; ++k) {
             T *Uk[3], *Un[3];
-            slot(seg.p, k - s0, Uk);
+            slot(segp, k - s0, Uk);
             if (k + 1 < s1) {
-                slot(seg.p, k + 1 - s0, Un);
+                slot(segp, k + 1 - s0, Un);
             } else {
                 for (int f = 0; f < 3; ++f) Un[f] = (T*)scratch.p + (size_t)f * fe;
             }
@@ -1094,25 +1138,58 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
             const int sig = ((step0 + k) & 1) ? -1 : 1;
             if constexpr (!mixed) {
                 if (keep) {
-                    double* tk = segtr.d() + (size_t)(k - s0) * 6 * fe;
+                    double* tk = segtrp + (size_t)(k - s0) * 6 * fe;
                     for (int f = 0; f < 3; ++f) {
                         fa.tus[f] = tk + (size_t)f * fe;
                         fa.tud[f] = tk + (size_t)(3 + f) * fe;
                     }
                     fa.gy = h->gyt;
                     fa.H = h->Ht;
-                    e = swe::launch_fused_trace(fa, sig, h->stream);
+                    r = swe::launch_fused_trace(fa, sig, st);
                     continue;
                 }
             }
-            e = swe::launch_fused<T>(fa, sig, h->stream, h->more_waves, h->split);
+            r = swe::launch_fused<T>(fa, sig, st, h->more_waves, h->split);
+        }
+        return r;
+    };
+    // with the overlap, segment sg lives in buffer pair sg & 1 and the side
+    // stream runs one segment ahead of the march
+    auto seg_of = [&](int64_t sg) { return overlap && (sg & 1) ? seg2.p : seg.p; };
+    auto segtr_of = [&](int64_t sg) { return overlap && (sg & 1) ? segtr2.d() : segtr.d(); };
+    if (overlap) {
+        const int b = (int)((nseg - 1) & 1);
+        e = recompute(nseg - 1, seg_of(nseg - 1), segtr_of(nseg - 1), side.s);
+        if (e == hipSuccess) e = hipEventRecord(side.done[b], side.s);
+    }
+    for (int64_t sg = nseg - 1; sg >= 0 && e == hipSuccess; --sg) {
+        if (verbose && sg < nseg - 1) {
+            e = hipStreamSynchronize(h->stream);
+            std::fprintf(stderr, "swe_grad: %.1f ms: reverse segment %lld of %lld done\n",
+                         ms_since(t_start), (long long)(nseg - 1 - sg), (long long)nseg);
+            if (e != hipSuccess) break;
+        }
+        const int64_t s0 = sg * C, s1 = std::min(s0 + C, nsteps);
+        void* const segp = seg_of(sg);
+        double* const segtrp = segtr_of(sg);
+        if (overlap) {
+            if (sg > 0) {
+                // the segment below, into the pair the march of sg + 1 read
+                const int nb = (int)((sg - 1) & 1);
+                if (side.used[nb]) e = hipStreamWaitEvent(side.s, side.freed[nb], 0);
+                if (e == hipSuccess) e = recompute(sg - 1, seg_of(sg - 1), segtr_of(sg - 1), side.s);
+                if (e == hipSuccess) e = hipEventRecord(side.done[nb], side.s);
+            }
+            if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, side.done[sg & 1], 0);
+        } else {
+            e = recompute(sg, segp, segtrp, h->stream);
         }
         for (int64_t k = s1 - 1; k >= s0 && e == hipSuccess; --k) {
             T* Uk[3];
             if (store_all)
                 for (int f = 0; f < 3; ++f) Uk[f] = (T*)traj_state(k, f);
             else
-                slot(seg.p, k - s0, Uk);
+                slot(segp, k - s0, Uk);
             const double* U64[3] = {(const double*)Uk[0], (const double*)Uk[1],
                                     (const double*)Uk[2]};
             if (mixed) {
@@ -1138,7 +1215,7 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
                 UD_k = traj_state(k, 6);
             } else if (keep) {
                 // U* and U^d were kept by the segment's recompute
-                US_k = segtr.d() + (size_t)(k - s0) * 6 * fe;
+                US_k = segtrp + (size_t)(k - s0) * 6 * fe;
                 UD_k = US_k + 3 * fe;
             } else {
                 // the step once more in FP64 with its known dt, writing U* and U^d
@@ -1186,6 +1263,10 @@ int grad_impl(swe_handle* h, int64_t nsteps, const swe_gauges* g, int32_t ckpt_e
             } else {
                 e = swe::launch_adjoint_step(aa, (const int*)gmap.p, hrow, h->stream);
             }
+        }
+        if (overlap && e == hipSuccess) {
+            e = hipEventRecord(side.freed[sg & 1], h->stream);
+            side.used[sg & 1] = true;
         }
     }
     if (e == hipSuccess && nsteps > 0) e = swe::launch_adjoint_finish(aa, h->stream);

@@ -209,7 +209,7 @@ hipError_t launch_adjoint_march(const AdjointArgs& a, const int* gmap, const dou
                                 int spin_cap = kMarchSpinCap);
 // Chunk height of the reverse march for a grid on a device with ncu compute
 // units.
-int adjoint_march_rows(const Params& P, int ncu);
+int adjoint_march_rows(const Params& P, int ncu, int per_cu = 4);
 // Whether the reverse march can address the grid's arrays (below about
 // 13000 x 13000 cells); launch_adjoint_step serves the others.
 bool adjoint_march_fits(const Params& P);

@@ -279,3 +279,29 @@ def test_dry_skip_gradient_with_gauges_the_front_reaches(dtype, keep, monkeypatc
     assert sb.cells_skipped > 0 and sa.t == sb.t
     assert float(gna.abs().max()) > 0.0
     assert Ja == Jb and torch.equal(gna, gnb) and torch.equal(gza, gzb)
+
+
+@pytest.mark.parametrize("ckpt", [1, 2, 4, 7, 15])
+def test_overlapped_recompute_equals_serial(ckpt, monkeypatch):
+    """SWE_GRAD_OVERLAP=1 recomputes the segment below on a second stream
+    while the march sweeps the present one, in two pairs of segment buffers:
+    the same gradient bit for bit, with even, odd and one-segment counts and
+    a ragged last segment, and the same state afterwards."""
+    p = W.random_valid_state(150, 90, seed=8)
+    note(f"overlapped recompute vs serial, checkpoint spacing {ckpt}")
+    outs = {}
+    for ovl in ("0", "1"):
+        monkeypatch.setenv("SWE_GRAD_OVERLAP", ovl)
+        rng = np.random.default_rng(3)
+        cells = rng.choice(p.nx * p.ny, 12, replace=False)
+        hobs = torch.as_tensor(rng.uniform(0.0, 1.0, (5, 12)), dtype=torch.float64,
+                               device="cuda")
+        s = swe.Solver.from_problem(p, dtype=torch.float64)
+        J, gn, gz = s.grad(15, cells, 3, hobs, ckpt)
+        outs[ovl] = (J, gn.cpu().numpy(), gz.cpu().numpy(),
+                     [t.cpu().numpy() for t in (s.eta, s.qx, s.qy)])
+    a, b = outs["0"], outs["1"]
+    assert a[0] == b[0]
+    assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    for x, y in zip(a[3], b[3]):
+        assert np.array_equal(x, y)
