@@ -285,7 +285,13 @@ typedef struct swe_gauges {
  * FP64 handles also keep U* and U^d of each step of the segment being
  * reversed (6 fields per step) when that fits in a third of the free device
  * memory, else each step is replayed once more (SWE_GRAD_KEEP=0 in the
- * environment forces the replay).  ckpt_every = 0: an FP64 handle keeps the
+ * environment forces the replay).  With U* and U^d kept and more than one
+ * segment, the recompute of the next segment runs on a second stream of the
+ * library's while the reverse sweep marches the present one, in a second set
+ * of segment buffers when that also fits in a third of the free memory
+ * (SWE_GRAD_OVERLAP=0 in the environment runs them one after the other on
+ * the handle's stream); the call still returns only when all of it is done.
+ * ckpt_every = 0: an FP64 handle keeps the
  * whole trajectory (U^n, U* and U^d of every step, 9 fields per step) when it
  * fits in three quarters of the free device memory, and then recomputes
  * nothing; the buffer stays with the handle for later calls and is released
